@@ -1,0 +1,157 @@
+"""Metropolis chains over gauge configurations (Sec. 5.1: <W> = sum_G p(G) W(G),
+p(G) = N(G)/N, sampled without a sign problem).
+
+The paper names no sampler; the reading used here is single-link Metropolis:
+a sweep visits links 0 .. 2V-1 in order; Z2 proposes k -> 1-k, Z3 proposes
+k -> (k + 1 + (x2 & 1)) mod 3; the proposal is accepted iff u < N(G')/N(G)
+(strict), with (u, x2) from Philox at counter (chain, sweep, link, 0).
+A cold start has every k = 0; a hot start takes k = x0 mod N from Philox at
+counter (chain, 0xffffffff, link, 1).
+
+Two evaluators of the ratio:
+* ``DefinitionChain``: fresh log-determinant (and, for K > 1, full Pfaffians of
+  every M_nm) of the current and proposed configuration -- the definition;
+* ``WoodburyChain``: maintains G = M^-1, log W and S = N/W; the ratio is
+  det(1 + G_UU dM_UU)^(1/2) S'/S by the matrix determinant lemma, and an
+  accepted flip applies the Woodbury identity
+  G' = G - G[:,U] (dM^-1 + G_UU)^-1 G[U,:].  Every ``refresh_every``
+  accepted flips (checked at the end of a sweep) G, log W and S are recomputed
+  from the link field and the drift of log W is recorded.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import philox
+from .model import Ansatz, rotation
+
+HOT_SWEEP = 0xFFFFFFFF
+
+
+def hot_links(seed: int, chain: int, n_links: int, group: int) -> np.ndarray:
+    x0, _, _, _ = philox.philox_vec(chain, HOT_SWEEP, np.arange(n_links), 1,
+                                    seed & 0xFFFFFFFF, seed >> 32)
+    return (x0 % np.uint64(group)).astype(np.int8)
+
+
+def propose(k: int, step: int, group: int) -> int:
+    return (k + (1 if group == 2 else step)) % group
+
+
+def delta_uu(an: Ansatz, k_old: int, k_new: int) -> np.ndarray:
+    """Change of M(G) on the link Majoranas (out0,out1,in0,in1) when the link changes k_old -> k_new."""
+    x0 = an.gamma_bond[0:2, 2:4]
+    th = 2 * np.pi / an.group
+    x = (rotation(th * k_new) - rotation(th * k_old)) @ x0
+    d = np.zeros((4, 4))
+    d[0:2, 2:4] = x
+    d[2:4, 0:2] = -x.T
+    return d
+
+
+class DefinitionChain:
+    """Metropolis with N(G')/N(G) from scratch for every proposal."""
+
+    def __init__(self, an: Ansatz, seed: int, chain: int, links0=None):
+        self.an, self.seed, self.chain = an, seed, chain
+        self.k = np.zeros(an.lat.n_links, np.int8) if links0 is None else np.array(links0, np.int8)
+        self.sweep_idx = 0
+        self.logn = self._logn(self.k)
+        self.accepts = 0
+
+    def _logn(self, k) -> float:
+        lw = self.an.log_weight(k)
+        if self.an.K == 1:
+            return lw
+        return lw + np.log(self.an.s_factor_def(k).real)
+
+    def sweep(self):
+        an = self.an
+        for ell in range(an.lat.n_links):
+            u, step = philox.draw(self.seed, self.chain, self.sweep_idx, ell)
+            knew = self.k.copy()
+            knew[ell] = propose(int(self.k[ell]), int(step), an.group)
+            ln_new = self._logn(knew)
+            R = np.exp(ln_new - self.logn)
+            if float(u) < R:
+                self.k, self.logn = knew, ln_new
+                self.accepts += 1
+        self.sweep_idx += 1
+
+
+class WoodburyChain:
+    """Metropolis with a maintained inverse G = M(G)^-1, rank-4 Woodbury updates."""
+
+    def __init__(self, an: Ansatz, seed: int, chain: int, links0=None, refresh_every: int = 0):
+        self.an, self.seed, self.chain = an, seed, chain
+        self.k = np.zeros(an.lat.n_links, np.int8) if links0 is None else np.array(links0, np.int8)
+        self.refresh_every = refresh_every
+        self.sweep_idx = 0
+        self.accepts = 0
+        self.proposals = 0
+        self.since_refresh = 0
+        self.drifts = []
+        self.refresh()
+
+    def refresh(self):
+        an = self.an
+        M = an.assemble_M(self.k)
+        sign, ld = np.linalg.slogdet(M)
+        self.G = np.linalg.inv(M)
+        self.logw = 0.5 * ld - 4 * an.lat.V * np.log(2.0)
+        self.S = 1.0 + 0j
+        if an.K > 1:
+            S = an.S
+            self.S = an.s_factor_patch(self.G[np.ix_(S, S)], self.k)
+        self.since_refresh = 0
+
+    def ratio(self, ell: int, k_new: int):
+        """(R, rho, S', dM) for changing link ell to k_new."""
+        an = self.an
+        u = an.lat.link_majoranas(ell)
+        dm = delta_uu(an, int(self.k[ell]), k_new)
+        guu = self.G[np.ix_(u, u)]
+        rho = float(np.linalg.det(np.eye(4) + guu @ dm))
+        s_new = 1.0 + 0j
+        if an.K > 1:
+            S = an.S
+            kw = np.linalg.inv(np.linalg.inv(dm) + guu)
+            gss = self.G[np.ix_(S, S)] - self.G[np.ix_(S, u)] @ kw @ self.G[np.ix_(u, S)]
+            knew = self.k.copy()
+            knew[ell] = k_new
+            s_new = an.s_factor_patch(gss, knew)
+        R = np.sqrt(max(rho, 0.0)) * (s_new.real / self.S.real)
+        return R, rho, s_new, dm
+
+    def accept(self, ell: int, k_new: int, rho: float, s_new, dm):
+        u = self.an.lat.link_majoranas(ell)
+        guu = self.G[np.ix_(u, u)]
+        kw = np.linalg.inv(np.linalg.inv(dm) + guu)
+        self.G = self.G - self.G[:, u] @ kw @ self.G[u, :]
+        self.logw += 0.5 * np.log(rho)
+        self.S = s_new
+        self.k[ell] = k_new
+        self.accepts += 1
+        self.since_refresh += 1
+
+    @property
+    def logn(self) -> float:
+        return self.logw + (np.log(self.S.real) if self.an.K > 1 else 0.0)
+
+    def sweep(self):
+        an = self.an
+        for ell in range(an.lat.n_links):
+            u, step = philox.draw(self.seed, self.chain, self.sweep_idx, ell)
+            k_new = propose(int(self.k[ell]), int(step), an.group)
+            R, rho, s_new, dm = self.ratio(ell, k_new)
+            self.proposals += 1
+            if float(u) < R:
+                self.accept(ell, k_new, rho, s_new, dm)
+        self.sweep_idx += 1
+        if self.refresh_every > 0 and self.since_refresh >= self.refresh_every:
+            lw_acc = self.logw
+            self.refresh()
+            self.drifts.append(abs(lw_acc - self.logw))
+
+    def observables(self) -> np.ndarray:
+        return self.an.observables(self.k)

@@ -1,0 +1,294 @@
+"""Weights, cross terms and observables in covariance form (Sec. 3.2, 5, 5.1, 5.2).
+
+Notation.  Gamma_loc (10x10) splits into the physical block a (2x2), the
+physical-virtual block b (2x8) and the virtual block d (8x8).  Over the lattice
+A = (+)_x a, B = (+)_x b, D = (+)_x d.  The gauge field rotates the two
+Majoranas of the outgoing leg of each link by R(theta) = [[cos, sin], [-sin, cos]],
+theta = 2 pi k / N: this is how exp(i theta n) acts on (c_0, c_1), and Sec. 5
+writes the gauged tensor as Gamma_A(G) = O^T Gamma_A O.  Moving O onto the
+bonds gives the virtual matrix
+    M(G) = D + O(G) Gamma_B O(G)^T          (n x n, n = 8V, real antisymmetric).
+
+* weight (Sec. 3.2, PEPS norm; Sec. 5 with n = m):
+    W(G) = tr(rho_A(G) (rho_B x 1)) = sqrt(det(M/2)) = 2^-4V sqrt(det M),
+  i.e. log W = (1/2) log det M - 4 V ln 2.  The physical block drops out
+  because the projected state is pure (its covariance has determinant 1).
+* physical covariance of the normalised projected state:
+    Gamma_out = A + B M^-1 B^T.
+* cross terms (Sec. 5):
+    N_nm(G) = <psi_n(G)|psi_m(G)> = W(G) <B_m|B_n> Pf(M_nm) / Pf(M_00),
+  with M_nm = D + O Gamma_nm O^T and Gamma_nm the covariance of the transition
+  operator |B_n><B_m| / <B_m|B_n>; N(G) = sum_nm c_n^* c_m N_nm(G).
+* observables: plaquette (Sec. 2.3), Wilson loops (Sec. 5.1), and fermionic
+  two-point functions by Wick's theorem, <c_a c_b> = -i Gamma_out_ab (Sec. 3.2;
+  the printed exponent of (-i) is read as w/2), combined over cross terms as
+  in Sec. 5.2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gaussian
+from .lattice import Lattice
+
+NOBS = 20           # observable slots: plaq, wilson2x2, density, logN, meson r=1..16
+OBS_PLAQ, OBS_WILSON, OBS_DENSITY, OBS_LOGN, OBS_MESON0 = 0, 1, 2, 3, 4
+MAX_MESON = 16
+
+
+def rotation(theta: float) -> np.ndarray:
+    c, s = np.cos(theta), np.sin(theta)
+    return np.array([[c, s], [-s, c]])
+
+
+def link_phase(k: int, group: int) -> complex:
+    return np.exp(2j * np.pi * (int(k) % group) / group)
+
+
+class Ansatz:
+    """Covariance-form evaluator of one (superposed) ansatz on a lattice."""
+
+    def __init__(self, lat: Lattice, gamma_loc, gamma_bond, group: int = 2,
+                 patch_link=None, gamma_bond_k=None, c=None):
+        self.lat = lat
+        self.group = group
+        g = np.asarray(gamma_loc, float)
+        self.a, self.b, self.d = g[0:2, 0:2], g[0:2, 2:10], g[2:10, 2:10]
+        V, n = lat.V, lat.n
+        self.D = np.zeros((n, n))
+        self.A = np.zeros((2 * V, 2 * V))
+        self.B = np.zeros((2 * V, n))
+        for x in range(V):
+            self.D[8 * x:8 * x + 8, 8 * x:8 * x + 8] = self.d
+            self.A[2 * x:2 * x + 2, 2 * x:2 * x + 2] = self.a
+            self.B[2 * x:2 * x + 2, 8 * x:8 * x + 8] = self.b
+        self.gamma_bond = np.asarray(gamma_bond, float)
+        self.K = 1 if patch_link is None else len(patch_link)
+        self.patch_link = np.array([-1] if patch_link is None else patch_link)
+        self.c = np.ones(1, complex) if c is None else np.asarray(c, complex)
+        self._link_states(gamma_bond_k)
+
+    # ----- superposed bonds (Sec. 5: reference bond B_0 and <B_n|B_0> real) -----
+    def _link_states(self, gamma_bond_k):
+        cs2 = gaussian.majorana_matrices(2)
+        self._cs2 = cs2
+        self._trans_cache = {}
+        v0 = gaussian.state_of_covariance(self.gamma_bond, 2, cs2)
+        self.bstate = [v0]
+        for k in range(1, self.K):
+            vk = gaussian.state_of_covariance(np.asarray(gamma_bond_k[k]), 2, cs2)
+            ov = np.vdot(v0, vk)
+            self.bstate.append(vk * (abs(ov) / ov))         # <b_0|b_k> > 0
+        S = []
+        for k in range(1, self.K):
+            S.extend(self.lat.link_majoranas(int(self.patch_link[k])).tolist())
+        self.S = np.array(sorted(set(S)), int)
+
+    def link_transition(self, ell: int, n: int, m: int):
+        """(covariance, overlap <bra|ket>) of link ell in the transition |B_n><B_m|."""
+        key = (int(ell), int(n), int(m))
+        if key not in self._trans_cache:
+            self._trans_cache[key] = self._link_transition(*key)
+        return self._trans_cache[key]
+
+    def _link_transition(self, ell: int, n: int, m: int):
+        ket = self.bstate[n] if (n > 0 and self.patch_link[n] == ell) else self.bstate[0]
+        bra = self.bstate[m] if (m > 0 and self.patch_link[m] == ell) else self.bstate[0]
+        ov = np.vdot(bra, ket)
+        if ket is bra:
+            cov = gaussian.covariance_of_state(ket, 2, self._cs2)
+        else:
+            cov = gaussian.transition_covariance(bra, ket, 2, self._cs2)
+        return cov, ov
+
+    def bond_overlap(self, n: int, m: int) -> complex:
+        """<B_m|B_n>: product over links of the link overlaps."""
+        ov = 1.0 + 0j
+        for ell in set(int(self.patch_link[k]) for k in (n, m) if k > 0):
+            ov *= self.link_transition(ell, n, m)[1]
+        return ov
+
+    # ----- virtual matrices -----
+    def _rot_block(self, gamma4, k: int):
+        o = np.eye(4)
+        o[0:2, 0:2] = rotation(2 * np.pi * (int(k) % self.group) / self.group)
+        return o @ gamma4 @ o.T
+
+    def assemble_M(self, links_k, n: int = 0, m: int = 0) -> np.ndarray:
+        """M_nm(G) = D + O(G) Gamma_nm O(G)^T (n = m = 0: the reference bond)."""
+        lat = self.lat
+        patch = set(int(self.patch_link[k]) for k in (n, m) if k > 0)
+        cplx = bool(patch)
+        M = self.D.astype(complex) if cplx else self.D.copy()
+        for ell in range(lat.n_links):
+            u = lat.link_majoranas(ell)
+            g4 = self.link_transition(ell, n, m)[0] if ell in patch else self.gamma_bond
+            M[np.ix_(u, u)] += self._rot_block(g4, links_k[ell])
+        return M
+
+    def log_weight(self, links_k) -> float:
+        sign, ld = np.linalg.slogdet(self.assemble_M(links_k))
+        if sign <= 0:
+            return -np.inf
+        return 0.5 * ld - 4 * self.lat.V * np.log(2.0)
+
+    def weight(self, links_k) -> float:
+        return float(np.exp(self.log_weight(links_k)))
+
+    def gamma_out(self, Ginv: np.ndarray) -> np.ndarray:
+        return self.A + self.B @ Ginv @ self.B.T
+
+    def cross_ratio_def(self, links_k) -> np.ndarray:
+        """r_nm(G) = Pf(M_nm) / Pf(M_00) by full Pfaffians (the definitional route)."""
+        pf0 = gaussian.pfaffian(self.assemble_M(links_k))
+        r = np.zeros((self.K, self.K), complex)
+        for n in range(self.K):
+            for m in range(self.K):
+                r[n, m] = gaussian.pfaffian(self.assemble_M(links_k, n, m)) / pf0
+        return r
+
+    def bond_overlaps(self) -> np.ndarray:
+        """ov[n, m] = <B_m|B_n>."""
+        if not hasattr(self, "_ov"):
+            self._ov = np.array([[self.bond_overlap(n, m) for m in range(self.K)]
+                                 for n in range(self.K)])
+        return self._ov
+
+    def cross_terms(self, links_k) -> np.ndarray:
+        """N_nm(G) = W(G) <B_m|B_n> Pf(M_nm)/Pf(M_00)."""
+        return self.weight(links_k) * self.bond_overlaps() * self.cross_ratio_def(links_k)
+
+    def norm(self, links_k) -> float:
+        """N(G) = sum_nm c_n^* c_m N_nm(G)."""
+        N = self.cross_terms(links_k)
+        return float(np.real(np.conj(self.c) @ N @ self.c))
+
+    def s_factor_def(self, links_k) -> complex:
+        """S(G) = N(G)/W(G) = sum_nm c_n^* c_m <B_m|B_n> r_nm(G)."""
+        return np.conj(self.c) @ (self.bond_overlaps() * self.cross_ratio_def(links_k)) @ self.c
+
+    # ----- patch route (Woodbury-friendly): only G restricted to the patch Majoranas -----
+    def delta_patch(self, links_k, n: int, m: int) -> np.ndarray:
+        """Delta^nm = (M_nm - M_00) restricted to the patch Majoranas S."""
+        S = self.S
+        pos = {int(v): i for i, v in enumerate(S)}
+        dl = np.zeros((len(S), len(S)), complex)
+        for ell in set(int(self.patch_link[k]) for k in (n, m) if k > 0):
+            u = self.lat.link_majoranas(ell)
+            g4 = self.link_transition(ell, n, m)[0] - self.gamma_bond
+            blk = self._rot_block(g4, links_k[ell])
+            iu = [pos[int(v)] for v in u]
+            dl[np.ix_(iu, iu)] += blk
+        return dl
+
+    def cross_ratio_patch(self, G_SS: np.ndarray, links_k) -> np.ndarray:
+        """r_nm = Pf(M_00 + Delta)/Pf(M_00) = (-1)^(s/2) Pf([[G_SS, I], [-I, Delta_SS]])."""
+        s = len(self.S)
+        r = np.ones((self.K, self.K), complex)
+        for n in range(self.K):
+            for m in range(self.K):
+                if n == 0 and m == 0:
+                    continue
+                blk = np.zeros((2 * s, 2 * s), complex)
+                blk[:s, :s] = G_SS
+                blk[:s, s:] = np.eye(s)
+                blk[s:, :s] = -np.eye(s)
+                blk[s:, s:] = self.delta_patch(links_k, n, m)
+                r[n, m] = (-1) ** (s // 2) * gaussian.pfaffian(blk)
+        return r
+
+    def s_factor_patch(self, G_SS, links_k) -> complex:
+        return np.conj(self.c) @ (self.bond_overlaps() * self.cross_ratio_patch(G_SS, links_k)) @ self.c
+
+    # ----- observables -----
+    def plaquette(self, links_k) -> float:
+        lat, N = self.lat, self.group
+        tot = 0.0
+        for x in range(lat.V):
+            l1, l2, l3, l4 = lat.plaquette_links(x)
+            z = (link_phase(links_k[l1], N) * link_phase(links_k[l2], N)
+                 * np.conj(link_phase(links_k[l3], N)) * np.conj(link_phase(links_k[l4], N)))
+            tot += z.real
+        return tot / lat.V
+
+    def wilson2x2(self, links_k) -> float:
+        """Oriented product around the 2x2 square with lower-left corner x, lattice mean."""
+        lat, N = self.lat, self.group
+        tot = 0.0
+        for x in range(lat.V):
+            z = 1.0 + 0j
+            p = x
+            for _ in range(2):                   # along +e1
+                z *= link_phase(links_k[lat.link(p, 0)], N)
+                p = lat.shift(p, 1, 0)
+            for _ in range(2):                   # along +e2
+                z *= link_phase(links_k[lat.link(p, 1)], N)
+                p = lat.shift(p, 0, 1)
+            for _ in range(2):                   # along -e1
+                p = lat.shift(p, -1, 0)
+                z *= np.conj(link_phase(links_k[lat.link(p, 0)], N))
+            for _ in range(2):                   # along -e2
+                p = lat.shift(p, 0, -1)
+                z *= np.conj(link_phase(links_k[lat.link(p, 1)], N))
+            tot += z.real
+        return tot / lat.V
+
+    def density_from(self, gout: np.ndarray) -> complex:
+        """Lattice mean of <psi_p^+ psi_p> = (1 + Gamma_out[2x, 2x+1]) / 2."""
+        V = self.lat.V
+        return np.mean([(1.0 + gout[2 * x, 2 * x + 1]) / 2.0 for x in range(V)])
+
+    def meson_from(self, gout: np.ndarray, links_k, r: int) -> complex:
+        """(1/V) sum_x 2 Re-part-to-be of [prod_j<r U(x+j e1, e1)] <phi_x^+ phi_{x+r e1}>.
+
+        <phi_x^+ phi_y> = (1/4)[<c_x0 c_y0> + i<c_x0 c_y1> - i<c_x1 c_y0> + <c_x1 c_y1>]
+        with phi = (c_0 + i c_1)/2 and <c_a c_b> = -i Gamma_out_ab.  Returns the
+        (complex, for transition covariances) mean of 2 x (line x bilinear).
+        """
+        lat, N = self.lat, self.group
+        tot = 0.0 + 0j
+        for x in range(lat.V):
+            y = x
+            line = 1.0 + 0j
+            for _ in range(r):
+                line *= link_phase(links_k[lat.link(y, 0)], N)
+                y = lat.shift(y, 1, 0)
+            cc = lambda a, b: -1j * gout[a, b]
+            bil = 0.25 * (cc(2 * x, 2 * y) + 1j * cc(2 * x, 2 * y + 1)
+                          - 1j * cc(2 * x + 1, 2 * y) + cc(2 * x + 1, 2 * y + 1))
+            tot += 2.0 * line * bil
+        return tot / lat.V
+
+    def fermion_obs(self, gout, links_k) -> np.ndarray:
+        out = np.zeros(NOBS, complex)
+        out[OBS_DENSITY] = self.density_from(gout)
+        for r in range(1, min(self.lat.Lx // 2, MAX_MESON) + 1):
+            out[OBS_MESON0 + r - 1] = self.meson_from(gout, links_k, r)
+        return out
+
+    def observables(self, links_k, Ginv=None) -> np.ndarray:
+        """All observable slots for one configuration (Sec. 5.1, 5.2), real parts."""
+        if Ginv is None:
+            Ginv = np.linalg.inv(self.assemble_M(links_k))
+        out = np.zeros(NOBS)
+        out[OBS_PLAQ] = self.plaquette(links_k)
+        out[OBS_WILSON] = self.wilson2x2(links_k)
+        lw = self.log_weight(links_k)
+        if self.K == 1:
+            f = self.fermion_obs(self.gamma_out(Ginv), links_k)
+            out[OBS_LOGN] = lw
+        else:
+            ov = self.bond_overlaps()
+            r = self.cross_ratio_def(links_k)
+            wts = np.conj(self.c)[:, None] * self.c[None, :] * ov * r
+            S = wts.sum()
+            f = np.zeros(NOBS, complex)
+            for n in range(self.K):
+                for m in range(self.K):
+                    Mnm = self.assemble_M(links_k, n, m)
+                    gnm = self.A + self.B @ np.linalg.inv(Mnm) @ self.B.T
+                    f += wts[n, m] / S * self.fermion_obs(gnm, links_k)
+            out[OBS_LOGN] = lw + np.log(S.real)
+        keep = [OBS_DENSITY] + [OBS_MESON0 + i for i in range(MAX_MESON)]
+        out[keep] = f[keep].real
+        return out
