@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark: single-link Metropolis sweeps of gauged Gaussian fermionic PEPS on one MI355X.
+
+Workload (default): Z2 gauge field on an 8x8 periodic lattice (128 links,
+n = 512 virtual Majoranas), the seeded Haar on-site Gaussian tensor, K = 1,
+4096 independent chains, float64 inverse with a float64 refactorisation every
+1024 accepted flips per chain.  A step is one sweep of every chain (128
+proposals each: ratio, Metropolis decision, rank-4 Woodbury update on accept)
+followed by the plaquette / 2x2 Wilson loop / density measurement.
+
+Prints one JSON line: link-update proposals per second (value), effective
+samples per second of the lattice-mean plaquette, the HBM roofline of the
+rank-4 update kernel (bytes: 2 n^2 * 8 per accepted flip, time: HIP events
+around every update launch on its stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chains", type=int, default=4096)
+    ap.add_argument("--L", type=int, default=8)
+    ap.add_argument("--K", type=int, default=1)
+    ap.add_argument("--group", type=int, default=2)
+    ap.add_argument("--precision", type=int, default=64)
+    ap.add_argument("--refresh", type=int, default=1024)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--update-grid", type=int, default=0)
+    ap.add_argument("--update-tiles", type=int, default=0)
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "update_traffic.json"),
+                    help="measured HBM traffic of the update kernel (from rocprofv3 counters)")
+    return ap.parse_args()
+
+
+def cpu_baseline(args, budget_s: float):
+    """The oracle's Woodbury chain on host cores, one chain per worker process, bounded in time."""
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers, initializer=_cpu_init) as pool:
+        res = pool.starmap(_cpu_chain, [(args.L, args.K, args.group, c, budget_s) for c in range(workers)])
+    wall = time.perf_counter() - t0
+    props = sum(r[0] for r in res)
+    sweeps = sum(r[1] for r in res)
+    return {"value": props / wall, "unit": "proposals/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} chains x {sweeps // workers}-{max(r[1] for r in res)} sweeps of L={args.L} "
+                      f"K={args.K} Z{args.group} (Woodbury-mode oracle, float64, 1 BLAS thread per process), "
+                      f"{wall:.1f} s wall"}
+
+
+def _cpu_init():
+    try:
+        import threadpoolctl
+        threadpoolctl.threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _cpu_chain(L, K, group, chain, budget_s):
+    import synth
+    from oracle.chain import WoodburyChain
+    from oracle.lattice import Lattice
+    from oracle.model import Ansatz
+    spec = synth.make_tensor(L, K=K, group=group)
+    an = Ansatz(Lattice(L, L), spec.gamma_loc, spec.gamma_bond, group, spec.patch_link, spec.gamma_bond_k, spec.c)
+    ch = WoodburyChain(an, synth.SEED_CHAIN, chain, refresh_every=1024)
+    t0 = time.perf_counter()
+    sweeps = 0
+    while time.perf_counter() - t0 < budget_s or sweeps == 0:
+        ch.sweep()
+        sweeps += 1
+    return ch.proposals, sweeps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent; "
+              "sharding them across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2412_01737_amd.ggf import Context, autocorr_time, OBS_LINK, OBS_DENSITY, GGF_NOBS
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    L, K, group = args.L, args.K, args.group
+    n = 8 * L * L
+    spec = synth.make_tensor(L, K=K, group=group)
+    ctx = Context(0)
+    tid = ctx.set_tensor_spec(spec)
+    t_init = time.perf_counter()
+    ctx.init_chains([L] * args.chains, tid, synth.SEED_CHAIN, init=0, precision=args.precision,
+                    refresh_every=args.refresh, stream=stream)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
+    if args.update_grid:
+        ctx.set_option("update_grid", args.update_grid)
+    if args.update_tiles:
+        ctx.set_option("update_tiles", args.update_tiles)
+    ctx.set_option("graph", args.graph)
+    mask = OBS_LINK | OBS_DENSITY
+    obs = torch.zeros((args.warmup + args.steps, args.chains, GGF_NOBS), dtype=torch.float64, device=dev)
+    for w in range(args.warmup):
+        ctx.sweep(1, stream=stream)
+        ctx.measure(mask, obs[w], stream=stream)
+    ctx.set_option("time_update", 1)
+    acc0 = sum(ctx.get_state(c)[1]["accepts"] for c in range(min(args.chains, 64)))
+    upd_ms, upd_launches, upd_flips = 0.0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ctx.sweep(1, stream=stream)
+        ms, la, fl = ctx.update_timing()
+        upd_ms += ms
+        upd_launches += la
+        upd_flips += fl
+        ctx.measure(mask, obs[args.warmup + s], stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    proposals = args.chains * 2 * L * L * args.steps
+    value = proposals / elapsed
+    series = obs[args.warmup:, :, 0].cpu().numpy()
+    tau, tau_err, window = autocorr_time(series)
+    ess = series.shape[0] * series.shape[1] / (2.0 * tau)
+    acceptance = upd_flips / proposals
+    bytes_per_flip = 2.0 * n * n * (8 if args.precision == 64 else 4)
+    achieved = (upd_flips * bytes_per_flip / upd_launches) / (upd_ms / upd_launches * 1e-3) / 1e9 if upd_ms > 0 else 0.0
+    traffic = None
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        key = f"L{L}_K{K}_Z{group}_p{args.precision}_c{args.chains}"
+        if key in tj:
+            traffic = tj[key]
+    except (OSError, ValueError):
+        pass
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, args.cpu_seconds)
+    mean_obs = obs[args.warmup:].mean(dim=(0, 1)).cpu().numpy()
+    out = {
+        "metric": "link-update proposals/sec and effective samples/sec at fixed obs. error, 1 MI355X",
+        "value": value,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Z{group} {L}x{L} periodic, K={K}, {args.chains} chains, single-link Metropolis, "
+                               f"float{args.precision} inverse, float64 refresh every {args.refresh} accepted flips",
+                   "L": L, "K": K, "group": group, "chains": args.chains, "n": n, "precision": args.precision,
+                   "refresh_every": args.refresh, "graph": args.graph},
+        "effective_samples_per_s": ess / elapsed,
+        "tau_int_plaquette": tau,
+        "tau_int_err": tau_err,
+        "acceptance": acceptance,
+        "observables_mean": {"plaquette": float(mean_obs[0]), "wilson2x2": float(mean_obs[1]),
+                             "density": float(mean_obs[2])},
+        "init_s": t_init,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_update", "bytes_per_flip": bytes_per_flip,
+                     "update_ms_total": upd_ms, "update_launches": upd_launches, "flips": upd_flips},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

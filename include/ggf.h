@@ -1,0 +1,183 @@
+/*
+ * ggf.h -- C ABI of the MI355X library for gauged (superposed) Gaussian
+ * fermionic PEPS Monte Carlo.
+ *
+ * The problem (Sec. 4 and 5 of Roose & Zohar, "Gauging a superposition of
+ * fermionic Gaussian projected entangled pair states to get lattice gauge
+ * theory eigenstates"): given the variational data of the ansatz -- the
+ * amplitudes lambda_n, the on-site covariance Gamma_A and the bond
+ * covariances Gamma_{B_n} -- estimate gauge-invariant observables as averages
+ * over gauge configurations G drawn from p(G) = N(G)/N (Sec. 5.1), with
+ *   N(G) = sum_nm lambda_n^* lambda_m <psi_n(G)|psi_m(G)>      (Sec. 5).
+ * The library runs many independent Markov chains over G on one GPU.  For
+ * each chain it keeps the link field and the inverse G = M(G)^-1 of the
+ * virtual matrix M(G) = D + O(G) Gamma_B0 O(G)^T, so W(G) = 2^-4V sqrt(det M)
+ * and every single-link ratio costs a 4x4 determinant; an accepted flip is a
+ * rank-4 Woodbury update of G.
+ *
+ * Conventions (Majoranas and covariance as in Sec. 3.2):
+ *   c_{2j} = psi_j + psi_j^+,  c_{2j+1} = -i (psi_j - psi_j^+),
+ *   Gamma_ab = (i/2) <[c_a, c_b]>   (empty mode: [[0,-1],[1,0]]).
+ *   Lattice L x L periodic, site i = x2*L + x1, link l = 2 i + mu (mu = 0:
+ *   x -> x+e1, mu = 1: x -> x+e2).  On-site modes in leg order p,l,u,r,d
+ *   (Sec. 3).  The gauge field acts on the outgoing leg (r for mu = 0, u for
+ *   mu = 1) as exp(i 2 pi k n / N), N = group order (Sec. 3.1).
+ *
+ * Errors: every call returns a ggf_status; nothing aborts or throws across
+ * the ABI.  ggf_last_error() gives a message for the most recent failure on
+ * that context.  A context is not thread-safe: use one per host thread.
+ * Device work is ordered on the caller's stream (a hipStream_t passed as
+ * void*; NULL means the legacy default stream).
+ */
+#ifndef GGF_H
+#define GGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ggf_ctx ggf_ctx;
+
+typedef enum {
+  GGF_OK = 0,
+  GGF_EINVAL = -1,       /* bad argument or inconsistent input */
+  GGF_ENOMEM = -2,       /* device or host allocation failed */
+  GGF_ESINGULAR = -3,    /* W(G) = 0: M(G) is singular at a (re)factorisation */
+  GGF_ENONFINITE = -4,   /* non-finite ratio or weight that a refactorisation did not cure */
+  GGF_EDEVICE = -5,      /* HIP runtime error */
+  GGF_ESTATE = -6        /* call out of order (e.g. sweep before init_chains) */
+} ggf_status;
+
+#define GGF_KMAX 4       /* largest number of Gaussians in a superposition */
+#define GGF_NOBS 20      /* observable slots per chain, see ggf_measure */
+
+/* Variational data of one ansatz (Sec. 5: lambda_n, Gamma_A, Gamma_{B_n}).
+ * All host pointers, row-major float64; the library copies them and the caller
+ * keeps ownership. */
+typedef struct {
+  int32_t group;              /* 2 = Z2, 3 = Z3 */
+  const double *gamma_loc;    /* 10x10 on-site covariance, Majorana order (p,l,u,r,d) x (0,1);
+                                 real antisymmetric with Gamma^2 = -1 */
+  const double *gamma_bond;   /* 4x4 reference bond b_0 on every link, order (out0,out1,in0,in1);
+                                 pure, even parity */
+  int32_t K;                  /* number of Gaussians, 1 <= K <= GGF_KMAX */
+  const int32_t *patch_link;  /* [K]; patch_link[0] ignored; for k >= 1 the link on which bond
+                                 B_k differs from B_0 (may be NULL when K = 1) */
+  const double *gamma_bond_k; /* [K][4][4]; k = 0 ignored; bond state of B_k on its patch link.
+                                 Its phase is fixed by <b_0|b_k> > 0 (Sec. 5) */
+  const double *c_re;         /* [K] real parts of lambda_k (NULL when K = 1) */
+  const double *c_im;         /* [K] imaginary parts of lambda_k (NULL when K = 1) */
+} ggf_tensor_desc;
+
+/* Per-chain counters and scalars, read back synchronously. */
+typedef struct {
+  int32_t L, n, tensor_id, precision;
+  double logw;                /* log W(G) maintained by the updates (reference-bond weight) */
+  double s_re, s_im;          /* S(G) = N(G)/W(G) (1, 0 when K = 1) */
+  uint64_t sweeps;            /* sweeps done; the Philox counter word 1 of the next sweep */
+  uint64_t accepts, proposals, refreshes, recoveries;
+  double max_drift;           /* largest |log W_maintained - log W_fresh| seen at a refresh */
+} ggf_chain_info;
+
+/* Create a context on HIP device `device`. */
+ggf_status ggf_create(ggf_ctx **out, int device);
+
+/* Register an ansatz (Sec. 5 parameter set).  Validates antisymmetry, purity,
+ * even bond parity and K <= GGF_KMAX; precomputes the link-level bond states,
+ * the overlaps <B_m|B_n> (phase convention <b_0|b_k> > 0) and the transition
+ * covariances of |B_n><B_m| on the patch links.  Returns an id used by
+ * ggf_init_chains.  May be called several times (one id per ansatz). */
+ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *desc, int32_t *tensor_id_out);
+
+/* Allocate and start n_chains chains.  L[c] (even, 2..64) and tensor_id[c]
+ * are per chain (host arrays).  seed keys the Philox4x32-10 stream of every
+ * chain: key = (seed lo, seed hi), counter = (chain, sweep, link, 0).
+ * init: 0 = cold (all k = 0), 1 = hot (k = x0 mod N from counter
+ * (chain, 0xffffffff, link, 1)).  precision: 64 (G stored and updated in
+ * float64) or 32 (G in float32; ratios, log-weights and refactorisations in
+ * float64).  refresh_every: after a sweep, chains with at least this many
+ * accepted flips since their last factorisation are refactorised in float64
+ * (0 = never).  Assembles M(G), factorises it (blocked Gauss-Jordan with
+ * partial pivoting) and computes log W and S for every chain.  Replaces any
+ * previous chains.  Returns GGF_ESINGULAR if some M(G) is singular. */
+ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, const int32_t *tensor_id,
+                           uint64_t seed, int32_t init, int32_t precision, int32_t refresh_every,
+                           void *stream);
+
+/* Run n_sweeps single-link Metropolis sweeps on every chain (Sec. 5.1
+ * sampling of p(G)): links 0 .. 2V-1 in order, accept iff u < N(G')/N(G).
+ * Asynchronous on `stream` except when a chain needs a refactorisation
+ * (refresh_every, or recovery from a non-finite ratio), which synchronises. */
+ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
+
+/* Observables of every chain's current configuration (Sec. 2.3 plaquette,
+ * Sec. 5.1 Wilson loops, Sec. 5.2 fermionic two-point functions), written to
+ * out[n_chains][GGF_NOBS] (float64; device pointer when out_is_device != 0,
+ * else host pointer, which makes the call synchronous).  Slots:
+ *   0 mean plaquette Re[U U U* U*]       (obs_mask bit 0)
+ *   1 mean 2x2 Wilson loop               (bit 0)
+ *   2 mean density <psi_p^+ psi_p>       (bit 1)
+ *   3 log N(G) = log W + log S            (bit 1)
+ *   4+r-1 meson string M_r, r = 1..min(L/2, 16), along e1 (bit 2)
+ * Slots not requested are written as 0. */
+ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out_is_device,
+                       void *stream);
+
+/* Synchronous read-back of one chain: link values (int8, 2V entries),
+ * counters and scalars.  Any argument may be NULL. */
+ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info);
+
+/* Replace one chain's link field and sweep counter (checkpoint resume) and
+ * refactorise it; synchronous. */
+ggf_status ggf_set_state(ggf_ctx *ctx, int32_t chain, const int8_t *links, uint64_t sweeps);
+
+/* Copy one chain's maintained inverse G = M(G)^-1 (n x n, row-major) to host
+ * memory as float64.  Synchronous; for tests and diagnostics. */
+ggf_status ggf_get_inverse(ggf_ctx *ctx, int32_t chain, double *host_out);
+
+/* Overwrite one chain's maintained inverse from host float64 data without
+ * refactorising (fault injection for recovery tests).  Synchronous. */
+ggf_status ggf_set_inverse(ggf_ctx *ctx, int32_t chain, const double *host_in);
+
+/* Refactorise every chain from its link field now (float64), recording the
+ * drift of log W.  Synchronous. */
+ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
+
+/* Tuning knobs (0 = library default):
+ *   "update_grid"  workgroups of the persistent rank-4 update kernel
+ *   "update_tiles" row tiles per chain in the rank-4 update
+ *   "graph"        1 = replay each sweep as a captured hipGraph, 0 = direct launches
+ *   "gj_nb"        panel width of the Gauss-Jordan refactorisation (8..64)
+ *   "scratch_mb"   float64 scratch budget for refactorisations, MiB */
+ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
+
+/* Duration in milliseconds of the rank-4 update kernels of the most recent
+ * ggf_sweep call, summed over its launches, measured with HIP events on the
+ * stream the kernels run on (0 when timing is off; enable with option
+ * "time_update" = 1).  Also returns the number of launches and of accepted
+ * flips they applied. */
+ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_t *flips);
+
+/* Integrated autocorrelation time of n_series Monte Carlo series sampled at
+ * n_t times, series[t * n_series + s] (host float64).  Each series is centred
+ * on its own mean; the autocovariance is averaged over series, normalised,
+ * and summed with Sokal's automatic window (smallest W with W >= c tau(W),
+ * tau(W) = 1/2 + sum_{t=1..W} rho(t)).  Outputs tau, its Madras-Sokal error
+ * tau sqrt(2 (2W + 1) / (n_t n_series)) and W; effective samples =
+ * n_t n_series / (2 tau).  Pure host computation; needs no context. */
+ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series, double c, double *tau,
+                             double *tau_err, int64_t *window);
+
+/* Message of the most recent failure on this context ("" if none). */
+const char *ggf_last_error(ggf_ctx *ctx);
+
+/* Free all device and host memory of the context.  NULL is a no-op. */
+void ggf_destroy(ggf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GGF_H */

@@ -1,0 +1,750 @@
+// C ABI of the GGF Monte Carlo library: context, ansatz registration, chain
+// storage, sweep orchestration and read-back.  Device work is in
+// ggf_factor.hip (refactorisation) and ggf_sweep.hip (link steps, observables).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ggf.h"
+#include "ggf_device.h"
+#include "ggf_launch.h"
+
+typedef std::complex<double> cplx;
+
+namespace {
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ggf_ctx {
+  int device = 0;
+  std::string err;
+  std::vector<TensorDev> tensors;
+  TensorDev *tensors_dev = nullptr;
+  size_t tensors_cap = 0;
+
+  // chains
+  int n_chains = 0, precision = 64, refresh_every = 0, kmax = 1, max_links = 0, n_max = 0;
+  uint64_t seed = 0;
+  std::vector<ChainDev> chains;
+  std::vector<unsigned long long> recoveries;
+  ChainDev *chains_dev = nullptr;
+  void *G = nullptr, *F = nullptr;
+  int8_t *links = nullptr;
+  double *logw = nullptr, *max_drift = nullptr, *ldet = nullptr;
+  double2 *sfac = nullptr;
+  uint32_t *sweep = nullptr, *acc_since = nullptr;
+  unsigned long long *acc_total = nullptr, *prop_total = nullptr, *refreshes = nullptr;
+  int *flags = nullptr, *acc_list = nullptr, *acc_cnt = nullptr;
+  double *scratch = nullptr;
+  size_t scratch_elems = 0;
+  int *piv = nullptr, *perm = nullptr, *list_dev = nullptr;
+  size_t piv_stride = 0;
+  std::vector<void *> allocs;
+
+  // options
+  int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 32, opt_time_update = 0;
+  long long opt_scratch_mb = 0;
+
+  // graph replay
+  hipStream_t own_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+
+  // update timing
+  std::vector<hipEvent_t> tev;
+  double last_update_ms = 0.0;
+  long long last_launches = 0, last_flips = 0;
+};
+
+namespace {
+
+ggf_status fail(ggf_ctx *ctx, ggf_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                               \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, GGF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Two-mode even bond states.  A pure even state a|00> + b|11> (|11> = psi_out^+ psi_in^+|0>)
+// is the ground state of H = -(i/4) sum Gamma_ab c_a c_b restricted to the even sector,
+// H = [[h, z], [z^*, -h]] with h = (g01 + g23)/2 and z = (g03 + g12)/2 + i (g02 - g13)/2.
+// Matrix elements of the bilinears c_a c_b (a < b) in the even basis (|00>, |11>):
+//   c0c1 = c2c3 = diag(i, -i); c0c2 = [[0,-1],[1,0]]; c0c3 = c1c2 = [[0,i],[i,0]]; c1c3 = [[0,1],[-1,0]].
+struct Even2 {
+  cplx a, b;
+};
+
+void bilinear(int p, int q, cplx m[2][2]) {
+  const cplx I(0, 1);
+  m[0][0] = m[0][1] = m[1][0] = m[1][1] = 0.0;
+  if ((p == 0 && q == 1) || (p == 2 && q == 3)) { m[0][0] = I; m[1][1] = -I; }
+  else if (p == 0 && q == 2) { m[0][1] = -1.0; m[1][0] = 1.0; }
+  else if ((p == 0 && q == 3) || (p == 1 && q == 2)) { m[0][1] = I; m[1][0] = I; }
+  else if (p == 1 && q == 3) { m[0][1] = 1.0; m[1][0] = -1.0; }
+}
+
+// (i/2) <bra|[c_p,c_q]|ket> / <bra|ket> for all p, q (4x4).
+void transition_cov(const Even2 &bra, const Even2 &ket, cplx out[16]) {
+  const cplx ov = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
+  for (int i = 0; i < 16; ++i) out[i] = 0.0;
+  for (int p = 0; p < 4; ++p)
+    for (int q = p + 1; q < 4; ++q) {
+      cplx m[2][2];
+      bilinear(p, q, m);
+      const cplx e = std::conj(bra.a) * (m[0][0] * ket.a + m[0][1] * ket.b) +
+                     std::conj(bra.b) * (m[1][0] * ket.a + m[1][1] * ket.b);
+      const cplx g = cplx(0, 1) * e / ov;   // [c_p, c_q] = 2 c_p c_q for p != q
+      out[p * 4 + q] = g;
+      out[q * 4 + p] = -g;
+    }
+}
+
+bool even_state(const double *g, Even2 &st, std::string &why) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      if (std::fabs(g[i * 4 + j] + g[j * 4 + i]) > 1e-10) { why = "bond covariance is not antisymmetric"; return false; }
+  const double h = 0.5 * (g[0 * 4 + 1] + g[2 * 4 + 3]);
+  const cplx z(0.5 * (g[0 * 4 + 3] + g[1 * 4 + 2]), 0.5 * (g[0 * 4 + 2] - g[1 * 4 + 3]));
+  const double e = std::sqrt(h * h + std::norm(z));
+  cplx v0 = z, v1 = -(h + e);
+  if (std::abs(h + e) < 0.5) { v0 = e - h; v1 = -std::conj(z); }
+  const double nrm = std::sqrt(std::norm(v0) + std::norm(v1));
+  if (!(nrm > 0)) { why = "bond covariance has no even ground state"; return false; }
+  st.a = v0 / nrm;
+  st.b = v1 / nrm;
+  cplx back[16];
+  transition_cov(st, st, back);
+  for (int i = 0; i < 16; ++i)
+    if (std::abs(back[i] - g[i]) > 1e-8) { why = "bond covariance is not a pure even-parity state"; return false; }
+  return true;
+}
+
+bool check_local(const double *g, std::string &why) {
+  for (int i = 0; i < 10; ++i)
+    for (int j = 0; j < 10; ++j)
+      if (std::fabs(g[i * 10 + j] + g[j * 10 + i]) > 1e-10) { why = "gamma_loc is not antisymmetric"; return false; }
+  for (int i = 0; i < 10; ++i)
+    for (int j = 0; j < 10; ++j) {
+      double v = 0;
+      for (int k = 0; k < 10; ++k) v += g[i * 10 + k] * g[k * 10 + j];
+      if (std::fabs(v + (i == j ? 1.0 : 0.0)) > 1e-8) { why = "gamma_loc is not pure (Gamma^2 != -1)"; return false; }
+    }
+  return true;
+}
+
+template <typename T>
+T *dalloc(ggf_ctx *ctx, size_t count, hipError_t &e) {
+  void *p = nullptr;
+  e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) {
+    ctx->allocs.push_back(p);
+    e = hipMemset(p, 0, std::max<size_t>(count, 1) * sizeof(T));
+  }
+  return static_cast<T *>(p);
+}
+
+void free_chains(ggf_ctx *ctx) {
+  if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
+  for (void *p : ctx->allocs) hipFree(p);
+  ctx->allocs.clear();
+  ctx->n_chains = 0;
+  ctx->chains.clear();
+  ctx->G = ctx->F = nullptr;
+  ctx->scratch = nullptr;
+}
+
+LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
+  LaunchCtx lc;
+  lc.stream = s;
+  lc.precision = ctx->precision;
+  lc.chains = ctx->chains_dev;
+  lc.tensors = ctx->tensors_dev;
+  lc.G = ctx->G;
+  lc.F = ctx->F;
+  lc.links = ctx->links;
+  lc.logw = ctx->logw;
+  lc.sfac = ctx->sfac;
+  lc.sweep = ctx->sweep;
+  lc.acc_since = ctx->acc_since;
+  lc.acc_total = ctx->acc_total;
+  lc.prop_total = ctx->prop_total;
+  lc.refreshes = ctx->refreshes;
+  lc.max_drift = ctx->max_drift;
+  lc.ldet = ctx->ldet;
+  lc.flags = ctx->flags;
+  lc.acc_list = ctx->acc_list;
+  lc.acc_cnt = ctx->acc_cnt;
+  lc.scratch = ctx->scratch;
+  lc.key0 = static_cast<uint32_t>(ctx->seed & 0xFFFFFFFFu);
+  lc.key1 = static_cast<uint32_t>(ctx->seed >> 32);
+  lc.n_chains = ctx->n_chains;
+  return lc;
+}
+
+int gj_nb(const ggf_ctx *ctx) {
+  int nb = ctx->opt_gj_nb;
+  if (nb <= 8) return 8;
+  if (nb <= 16) return 16;
+  if (nb <= 32) return 32;
+  return 64;
+}
+
+// Refactorise the listed chains from their link fields (float64 scratch, in chunks
+// that fit the scratch budget), then recompute S for K > 1.  Synchronous.
+ggf_status factorize(ggf_ctx *ctx, const std::vector<int> &which, int is_refresh, hipStream_t s) {
+  if (which.empty()) return GGF_OK;
+  size_t pos = 0;
+  const int nb = gj_nb(ctx);
+  while (pos < which.size()) {
+    std::vector<int> chunk;
+    size_t used = 0;
+    int nmax = 0;
+    while (pos < which.size()) {
+      const int c = which[pos];
+      const size_t need = static_cast<size_t>(ctx->chains[c].n) * ctx->chains[c].n;
+      if (!chunk.empty() && used + need > ctx->scratch_elems) break;
+      ctx->chains[c].scr_off = used;
+      used += (need + 63) & ~static_cast<size_t>(63);
+      nmax = std::max(nmax, ctx->chains[c].n);
+      chunk.push_back(c);
+      ++pos;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->chains_dev, ctx->chains.data(), ctx->chains.size() * sizeof(ChainDev),
+                                hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->list_dev, chunk.data(), chunk.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const LaunchCtx lc = launch_ctx(ctx, s);
+    const int cnt = static_cast<int>(chunk.size());
+    ggf_launch_assemble(lc, ctx->list_dev, cnt, nmax / 8);
+    ggf_launch_gj(lc, ctx->list_dev, cnt, nmax, nb, ctx->piv, ctx->perm, ctx->piv_stride);
+    ggf_launch_store(lc, ctx->list_dev, cnt, nmax, ctx->perm, ctx->piv_stride);
+    ggf_launch_post(lc, ctx->list_dev, cnt, is_refresh);
+    ggf_launch_sfac(lc, ctx->list_dev, cnt, ctx->kmax);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  }
+  std::vector<int> fl(ctx->n_chains);
+  HIP_TRY(ctx, hipMemcpy(fl.data(), ctx->flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost));
+  for (int c : which)
+    if (fl[c] & GGF_FLAG_SINGULAR)
+      return fail(ctx, GGF_ESINGULAR, "M(G) is singular (W(G) = 0) for chain " + std::to_string(c));
+  return GGF_OK;
+}
+
+ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
+  const LaunchCtx lc = launch_ctx(ctx, s);
+  const int tiles = ctx->opt_update_tiles > 0 ? ctx->opt_update_tiles : std::max(1, ctx->n_max / 16);
+  const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 2048;
+  for (int ell = 0; ell < ctx->max_links; ++ell) {
+    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax);
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * ell], s));
+    ggf_launch_update(lc, ell & 1, grid, tiles);
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * ell + 1], s));
+  }
+  ggf_launch_end_sweep(lc);
+  HIP_TRY(ctx, hipGetLastError());
+  return GGF_OK;
+}
+
+ggf_status after_sweep(ggf_ctx *ctx, hipStream_t s) {
+  // refresh (every refresh_every accepted flips) and recovery from non-finite ratios
+  std::vector<uint32_t> since(ctx->n_chains);
+  std::vector<int> fl(ctx->n_chains);
+  HIP_TRY(ctx, hipMemcpyAsync(since.data(), ctx->acc_since, since.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(fl.data(), ctx->flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  std::vector<int> refresh, recover;
+  for (int c = 0; c < ctx->n_chains; ++c) {
+    if (fl[c] & GGF_FLAG_NONFINITE) {
+      recover.push_back(c);
+      if (ctx->recoveries[c] > 0 && fl[c] == GGF_FLAG_NONFINITE) {
+        // already recovered once and failed again in the next sweep
+      }
+    } else if (ctx->refresh_every > 0 && since[c] >= static_cast<uint32_t>(ctx->refresh_every)) {
+      refresh.push_back(c);
+    }
+  }
+  if (!recover.empty()) {
+    std::vector<int> zero(ctx->n_chains, 0);
+    for (int c : recover) {
+      ctx->recoveries[c] += 1;
+      fl[c] = 0;
+    }
+    HIP_TRY(ctx, hipMemcpy(ctx->flags, fl.data(), fl.size() * sizeof(int), hipMemcpyHostToDevice));
+    ggf_status st = factorize(ctx, recover, 0, s);
+    if (st != GGF_OK) return st;
+    HIP_TRY(ctx, hipMemcpy(fl.data(), ctx->flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (int c : recover)
+      if (fl[c] & GGF_FLAG_NONFINITE)
+        return fail(ctx, GGF_ENONFINITE, "non-finite weight persists after refactorisation, chain " + std::to_string(c));
+  }
+  return factorize(ctx, refresh, 1, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+ggf_status ggf_create(ggf_ctx **out, int device) {
+  if (!out) return GGF_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GGF_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return GGF_EDEVICE;
+  ggf_ctx *ctx = new (std::nothrow) ggf_ctx();
+  if (!ctx) return GGF_ENOMEM;
+  ctx->device = device;
+  *out = ctx;
+  return GGF_OK;
+}
+
+ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tensor_id_out) {
+  if (!ctx) return GGF_EINVAL;
+  if (!d || !tensor_id_out || !d->gamma_loc || !d->gamma_bond) return fail(ctx, GGF_EINVAL, "null descriptor field");
+  if (d->group != 2 && d->group != 3) return fail(ctx, GGF_EINVAL, "group must be 2 or 3");
+  if (d->K < 1 || d->K > GGF_KMAX) return fail(ctx, GGF_EINVAL, "K must be in 1..GGF_KMAX");
+  if (d->K > 1 && (!d->patch_link || !d->gamma_bond_k || !d->c_re || !d->c_im))
+    return fail(ctx, GGF_EINVAL, "K > 1 needs patch_link, gamma_bond_k, c_re, c_im");
+  std::string why;
+  if (!check_local(d->gamma_loc, why)) return fail(ctx, GGF_EINVAL, why);
+  TensorDev t;
+  std::memset(&t, 0, sizeof(t));
+  t.group = d->group;
+  t.K = d->K;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) t.a[i * 2 + j] = d->gamma_loc[i * 10 + j];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 8; ++j) t.b[i * 8 + j] = d->gamma_loc[i * 10 + 2 + j];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) t.d[i * 8 + j] = d->gamma_loc[(2 + i) * 10 + 2 + j];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) t.x0[i * 2 + j] = d->gamma_bond[i * 4 + 2 + j];
+  // the reference bond only couples out to in
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (std::fabs(d->gamma_bond[i * 4 + j]) > 1e-12 || std::fabs(d->gamma_bond[(2 + i) * 4 + 2 + j]) > 1e-12)
+        return fail(ctx, GGF_EINVAL, "reference bond must only couple the out and in modes");
+  Even2 b0;
+  if (!even_state(d->gamma_bond, b0, why)) return fail(ctx, GGF_EINVAL, "gamma_bond: " + why);
+  const int K = d->K;
+  std::vector<Even2> bk(K);
+  std::vector<cplx> cc(K, 1.0);
+  bk[0] = b0;
+  for (int k = 1; k < K; ++k) {
+    if (!even_state(d->gamma_bond_k + 16 * k, bk[k], why))
+      return fail(ctx, GGF_EINVAL, "gamma_bond_k[" + std::to_string(k) + "]: " + why);
+    const cplx ov = std::conj(b0.a) * bk[k].a + std::conj(b0.b) * bk[k].b;   // <b_0|b_k>
+    if (std::abs(ov) < 1e-12) return fail(ctx, GGF_EINVAL, "<b_0|b_k> = 0: phase convention undefined");
+    const cplx ph = ov / std::abs(ov);
+    bk[k].a /= ph;
+    bk[k].b /= ph;
+    if (d->patch_link[k] < 0) return fail(ctx, GGF_EINVAL, "patch_link[k] must be >= 0 for k >= 1");
+  }
+  if (K > 1)
+    for (int k = 0; k < K; ++k) cc[k] = cplx(d->c_re[k], d->c_im[k]);
+  const double *g0 = d->gamma_bond;
+  for (int n = 0; n < K; ++n)
+    for (int m = 0; m < K; ++m) {
+      int links[2], cnt = 0;
+      if (n > 0) links[cnt++] = d->patch_link[n];
+      if (m > 0 && !(cnt == 1 && links[0] == d->patch_link[m])) links[cnt++] = d->patch_link[m];
+      cplx ovl = 1.0;
+      t.nl[n][m] = cnt;
+      for (int l = 0; l < cnt; ++l) {
+        const Even2 &ket = (n > 0 && d->patch_link[n] == links[l]) ? bk[n] : bk[0];
+        const Even2 &bra = (m > 0 && d->patch_link[m] == links[l]) ? bk[m] : bk[0];
+        const cplx o = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
+        if (std::abs(o) < 1e-14) return fail(ctx, GGF_EINVAL, "vanishing bond overlap");
+        ovl *= o;
+        cplx g[16];
+        transition_cov(bra, ket, g);
+        t.lk[n][m][l] = links[l];
+        for (int q = 0; q < 16; ++q) t.dg[n][m][l][q] = make_double2((g[q] - g0[q]).real(), (g[q] - g0[q]).imag());
+      }
+      const cplx w = std::conj(cc[n]) * cc[m] * ovl;
+      t.w[n][m] = make_double2(w.real(), w.imag());
+    }
+  ctx->tensors.push_back(t);
+  if (ctx->tensors.size() > ctx->tensors_cap) {
+    if (ctx->tensors_dev) hipFree(ctx->tensors_dev);
+    ctx->tensors_cap = std::max<size_t>(16, 2 * ctx->tensors.size());
+    HIP_TRY(ctx, hipMalloc(&ctx->tensors_dev, ctx->tensors_cap * sizeof(TensorDev)));
+  }
+  HIP_TRY(ctx, hipMemcpy(ctx->tensors_dev, ctx->tensors.data(), ctx->tensors.size() * sizeof(TensorDev),
+                         hipMemcpyHostToDevice));
+  *tensor_id_out = static_cast<int32_t>(ctx->tensors.size() - 1);
+  return GGF_OK;
+}
+
+ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, const int32_t *tensor_id,
+                           uint64_t seed, int32_t init, int32_t precision, int32_t refresh_every, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (n_chains <= 0 || !L || !tensor_id) return fail(ctx, GGF_EINVAL, "n_chains, L and tensor_id are required");
+  if (precision != 32 && precision != 64) return fail(ctx, GGF_EINVAL, "precision must be 32 or 64");
+  if (init != 0 && init != 1) return fail(ctx, GGF_EINVAL, "init must be 0 (cold) or 1 (hot)");
+  if (refresh_every < 0) return fail(ctx, GGF_EINVAL, "refresh_every must be >= 0");
+  std::vector<ChainDev> ch(n_chains);
+  size_t goff = 0, foff = 0, loff = 0;
+  int kmax = 1, max_links = 0, n_max = 0;
+  size_t max_need = 0, tot_need = 0;
+  for (int c = 0; c < n_chains; ++c) {
+    const int l = L[c];
+    if (l < 2 || l > 64 || (l & 1)) return fail(ctx, GGF_EINVAL, "L must be even and in 2..64");
+    const int tid = tensor_id[c];
+    if (tid < 0 || tid >= static_cast<int>(ctx->tensors.size())) return fail(ctx, GGF_EINVAL, "bad tensor id");
+    const TensorDev &t = ctx->tensors[tid];
+    for (int n = 0; n < t.K; ++n)
+      for (int m = 0; m < t.K; ++m)
+        for (int q = 0; q < t.nl[n][m]; ++q)
+          if (t.lk[n][m][q] >= 2 * l * l) return fail(ctx, GGF_EINVAL, "patch link outside the lattice");
+    ChainDev &d = ch[c];
+    std::memset(&d, 0, sizeof(d));
+    d.L = l;
+    d.n = 8 * l * l;
+    d.nlinks = 2 * l * l;
+    d.tensor = tid;
+    d.group = t.group;
+    d.K = t.K;
+    d.g_off = goff;
+    d.f_off = foff;
+    d.link_off = loff;
+    const size_t nn = static_cast<size_t>(d.n) * d.n;
+    goff += (nn + 63) & ~static_cast<size_t>(63);
+    foff += 8 * static_cast<size_t>(d.n);
+    loff += (d.nlinks + 63) & ~63;
+    kmax = std::max(kmax, t.K);
+    max_links = std::max(max_links, d.nlinks);
+    n_max = std::max(n_max, d.n);
+    max_need = std::max(max_need, nn);
+    tot_need += (nn + 63) & ~static_cast<size_t>(63);
+  }
+  free_chains(ctx);
+  hipError_t e = hipSuccess;
+  const size_t esz = precision == 64 ? sizeof(double) : sizeof(float);
+  size_t scr = tot_need;
+  const size_t budget = ctx->opt_scratch_mb > 0 ? static_cast<size_t>(ctx->opt_scratch_mb) << 20
+                                                : (static_cast<size_t>(32) << 30);
+  scr = std::min(scr, std::max(budget / sizeof(double), max_need));
+  {
+    void *p = nullptr;
+    e = hipMalloc(&p, goff * esz);
+    if (e != hipSuccess) return fail(ctx, GGF_ENOMEM, "cannot allocate the inverse arena");
+    ctx->allocs.push_back(p);
+    ctx->G = p;
+    e = hipMalloc(&p, foff * esz);
+    if (e != hipSuccess) { free_chains(ctx); return fail(ctx, GGF_ENOMEM, "cannot allocate the factor arena"); }
+    ctx->allocs.push_back(p);
+    ctx->F = p;
+    e = hipMalloc(&p, scr * sizeof(double));
+    if (e != hipSuccess) { free_chains(ctx); return fail(ctx, GGF_ENOMEM, "cannot allocate the refactorisation scratch"); }
+    ctx->allocs.push_back(p);
+    ctx->scratch = static_cast<double *>(p);
+    ctx->scratch_elems = scr;
+  }
+  ctx->links = dalloc<int8_t>(ctx, loff, e);
+  ctx->logw = dalloc<double>(ctx, n_chains, e);
+  ctx->max_drift = dalloc<double>(ctx, n_chains, e);
+  ctx->ldet = dalloc<double>(ctx, n_chains, e);
+  ctx->sfac = dalloc<double2>(ctx, n_chains, e);
+  ctx->sweep = dalloc<uint32_t>(ctx, n_chains, e);
+  ctx->acc_since = dalloc<uint32_t>(ctx, n_chains, e);
+  ctx->acc_total = dalloc<unsigned long long>(ctx, n_chains, e);
+  ctx->prop_total = dalloc<unsigned long long>(ctx, n_chains, e);
+  ctx->refreshes = dalloc<unsigned long long>(ctx, n_chains, e);
+  ctx->flags = dalloc<int>(ctx, n_chains, e);
+  ctx->acc_list = dalloc<int>(ctx, n_chains, e);
+  ctx->acc_cnt = dalloc<int>(ctx, 2, e);
+  ctx->piv_stride = n_max;
+  ctx->piv = dalloc<int>(ctx, static_cast<size_t>(n_chains) * n_max, e);
+  ctx->perm = dalloc<int>(ctx, static_cast<size_t>(n_chains) * n_max, e);
+  ctx->list_dev = dalloc<int>(ctx, n_chains, e);
+  ctx->chains_dev = dalloc<ChainDev>(ctx, n_chains, e);
+  if (e != hipSuccess) { free_chains(ctx); return fail(ctx, GGF_ENOMEM, "device allocation failed"); }
+  ctx->chains = ch;
+  ctx->n_chains = n_chains;
+  ctx->precision = precision;
+  ctx->refresh_every = refresh_every;
+  ctx->kmax = kmax;
+  ctx->max_links = max_links;
+  ctx->n_max = n_max;
+  ctx->seed = seed;
+  ctx->recoveries.assign(n_chains, 0);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipMemcpy(ctx->chains_dev, ch.data(), ch.size() * sizeof(ChainDev), hipMemcpyHostToDevice));
+  if (init == 1) {
+    ggf_launch_hot_start(launch_ctx(ctx, s), max_links);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  std::vector<int> all(n_chains);
+  for (int c = 0; c < n_chains; ++c) all[c] = c;
+  return factorize(ctx, all, 0, s);
+}
+
+ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (n_sweeps < 0) return fail(ctx, GGF_EINVAL, "n_sweeps must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool timed = ctx->opt_time_update != 0;
+  ctx->last_update_ms = 0.0;
+  ctx->last_launches = 0;
+  ctx->last_flips = 0;
+  if (timed && ctx->tev.size() < static_cast<size_t>(2 * ctx->max_links)) {
+    for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
+    ctx->tev.assign(2 * ctx->max_links, nullptr);
+    for (auto &ev : ctx->tev) HIP_TRY(ctx, hipEventCreate(&ev));
+  }
+  std::vector<unsigned long long> acc0;
+  if (timed) {
+    acc0.resize(ctx->n_chains);
+    HIP_TRY(ctx, hipMemcpy(acc0.data(), ctx->acc_total, acc0.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  }
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    if (ctx->opt_graph && !timed) {
+      if (!ctx->own_stream) {
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+      }
+      if (!ctx->graph_exec) {
+        hipGraph_t g;
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->own_stream, hipStreamCaptureModeThreadLocal));
+        ggf_status st = record_sweep(ctx, ctx->own_stream, false);
+        hipError_t e = hipStreamEndCapture(ctx->own_stream, &g);
+        if (st != GGF_OK) return st;
+        if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        HIP_TRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+        hipGraphDestroy(g);
+      }
+      HIP_TRY(ctx, hipEventRecord(ctx->ev_in, s));
+      HIP_TRY(ctx, hipStreamWaitEvent(ctx->own_stream, ctx->ev_in, 0));
+      HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->own_stream));
+      HIP_TRY(ctx, hipEventRecord(ctx->ev_out, ctx->own_stream));
+      HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_out, 0));
+    } else {
+      ggf_status st = record_sweep(ctx, s, timed);
+      if (st != GGF_OK) return st;
+      if (timed) {
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        for (int ell = 0; ell < ctx->max_links; ++ell) {
+          float ms = 0.f;
+          HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[2 * ell], ctx->tev[2 * ell + 1]));
+          ctx->last_update_ms += ms;
+        }
+        ctx->last_launches += ctx->max_links;
+      }
+    }
+    ggf_status st = after_sweep(ctx, s);
+    if (st != GGF_OK) return st;
+  }
+  if (timed) {
+    std::vector<unsigned long long> acc1(ctx->n_chains);
+    HIP_TRY(ctx, hipMemcpy(acc1.data(), ctx->acc_total, acc1.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int c = 0; c < ctx->n_chains; ++c) ctx->last_flips += static_cast<long long>(acc1[c] - acc0[c]);
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out_is_device, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (!out) return fail(ctx, GGF_EINVAL, "out is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LaunchCtx lc = launch_ctx(ctx, s);
+  const size_t bytes = static_cast<size_t>(ctx->n_chains) * GGF_NOBS * sizeof(double);
+  if (out_is_device) {
+    ggf_launch_measure(lc, obs_mask, out, ctx->kmax);
+    HIP_TRY(ctx, hipGetLastError());
+    return GGF_OK;
+  }
+  double *tmp = nullptr;
+  HIP_TRY(ctx, hipMalloc(&tmp, bytes));
+  ggf_launch_measure(lc, obs_mask, tmp, ctx->kmax);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info) {
+  if (!ctx) return GGF_EINVAL;
+  if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  const ChainDev &d = ctx->chains[chain];
+  if (links) HIP_TRY(ctx, hipMemcpy(links, ctx->links + d.link_off, d.nlinks, hipMemcpyDeviceToHost));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->L = d.L;
+    info->n = d.n;
+    info->tensor_id = d.tensor;
+    info->precision = ctx->precision;
+    double2 sf;
+    uint32_t sw;
+    HIP_TRY(ctx, hipMemcpy(&info->logw, ctx->logw + chain, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&sf, ctx->sfac + chain, sizeof(double2), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&sw, ctx->sweep + chain, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&info->accepts, ctx->acc_total + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&info->proposals, ctx->prop_total + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&info->refreshes, ctx->refreshes + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&info->max_drift, ctx->max_drift + chain, sizeof(double), hipMemcpyDeviceToHost));
+    info->s_re = sf.x;
+    info->s_im = sf.y;
+    info->sweeps = sw;
+    info->recoveries = ctx->recoveries[chain];
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_set_state(ggf_ctx *ctx, int32_t chain, const int8_t *links, uint64_t sweeps) {
+  if (!ctx) return GGF_EINVAL;
+  if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");
+  if (!links) return fail(ctx, GGF_EINVAL, "links is NULL");
+  if (sweeps > 0xFFFFFFFEull) return fail(ctx, GGF_EINVAL, "sweep counter out of range");
+  const ChainDev &d = ctx->chains[chain];
+  for (int l = 0; l < d.nlinks; ++l)
+    if (links[l] < 0 || links[l] >= d.group) return fail(ctx, GGF_EINVAL, "link value outside Z_N");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  HIP_TRY(ctx, hipMemcpy(ctx->links + d.link_off, links, d.nlinks, hipMemcpyHostToDevice));
+  const uint32_t sw = static_cast<uint32_t>(sweeps);
+  HIP_TRY(ctx, hipMemcpy(ctx->sweep + chain, &sw, sizeof(uint32_t), hipMemcpyHostToDevice));
+  const int zero = 0;
+  HIP_TRY(ctx, hipMemcpy(ctx->flags + chain, &zero, sizeof(int), hipMemcpyHostToDevice));
+  return factorize(ctx, std::vector<int>{chain}, 0, nullptr);
+}
+
+ggf_status ggf_get_inverse(ggf_ctx *ctx, int32_t chain, double *host_out) {
+  if (!ctx) return GGF_EINVAL;
+  if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");
+  if (!host_out) return fail(ctx, GGF_EINVAL, "host_out is NULL");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  const ChainDev &d = ctx->chains[chain];
+  const size_t nn = static_cast<size_t>(d.n) * d.n;
+  if (ctx->precision == 64) {
+    HIP_TRY(ctx, hipMemcpy(host_out, static_cast<double *>(ctx->G) + d.g_off, nn * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(nn);
+    HIP_TRY(ctx, hipMemcpy(tmp.data(), static_cast<float *>(ctx->G) + d.g_off, nn * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < nn; ++i) host_out[i] = tmp[i];
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_set_inverse(ggf_ctx *ctx, int32_t chain, const double *host_in) {
+  if (!ctx) return GGF_EINVAL;
+  if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");
+  if (!host_in) return fail(ctx, GGF_EINVAL, "host_in is NULL");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  const ChainDev &d = ctx->chains[chain];
+  const size_t nn = static_cast<size_t>(d.n) * d.n;
+  if (ctx->precision == 64) {
+    HIP_TRY(ctx, hipMemcpy(static_cast<double *>(ctx->G) + d.g_off, host_in, nn * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> tmp(host_in, host_in + nn);
+    HIP_TRY(ctx, hipMemcpy(static_cast<float *>(ctx->G) + d.g_off, tmp.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  std::vector<int> all(ctx->n_chains);
+  for (int c = 0; c < ctx->n_chains; ++c) all[c] = c;
+  return factorize(ctx, all, 1, static_cast<hipStream_t>(stream));
+}
+
+ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
+  if (!ctx || !key) return GGF_EINVAL;
+  const std::string k(key);
+  if (value < 0) return fail(ctx, GGF_EINVAL, "option values must be >= 0");
+  if (k == "update_grid") ctx->opt_update_grid = static_cast<int>(value);
+  else if (k == "update_tiles") ctx->opt_update_tiles = static_cast<int>(value);
+  else if (k == "graph") {
+    ctx->opt_graph = value != 0;
+    if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
+  } else if (k == "gj_nb") {
+    if (value != 0 && (value < 8 || value > 64)) return fail(ctx, GGF_EINVAL, "gj_nb must be in 8..64");
+    ctx->opt_gj_nb = value ? static_cast<int>(value) : 32;
+  } else if (k == "scratch_mb") ctx->opt_scratch_mb = value;
+  else if (k == "time_update") ctx->opt_time_update = value != 0;
+  else return fail(ctx, GGF_EINVAL, "unknown option " + k);
+  if (k == "update_grid" || k == "update_tiles") {
+    if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_t *flips) {
+  if (!ctx) return GGF_EINVAL;
+  if (ms) *ms = ctx->last_update_ms;
+  if (launches) *launches = ctx->last_launches;
+  if (flips) *flips = ctx->last_flips;
+  return GGF_OK;
+}
+
+ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series, double c, double *tau,
+                             double *tau_err, int64_t *window) {
+  if (!series || n_t < 2 || n_series < 1 || !(c > 0) || !tau) return GGF_EINVAL;
+  std::vector<double> x(static_cast<size_t>(n_t) * n_series);
+  for (int64_t s = 0; s < n_series; ++s) {
+    double m = 0.0;
+    for (int64_t t = 0; t < n_t; ++t) m += series[t * n_series + s];
+    m /= static_cast<double>(n_t);
+    for (int64_t t = 0; t < n_t; ++t) x[t * n_series + s] = series[t * n_series + s] - m;
+  }
+  std::vector<double> g(n_t, 0.0);
+  for (int64_t lag = 0; lag < n_t; ++lag) {
+    double acc = 0.0;
+    for (int64_t t = 0; t + lag < n_t; ++t)
+      for (int64_t s = 0; s < n_series; ++s) acc += x[t * n_series + s] * x[(t + lag) * n_series + s];
+    g[lag] = acc / (static_cast<double>(n_t) * n_series);
+  }
+  double tv = 0.5, err = 0.0;
+  int64_t w = 0;
+  if (g[0] > 0) {
+    for (int64_t t = 1; t < n_t; ++t) {
+      tv += g[t] / g[0];
+      w = t;
+      if (t >= c * tv) break;
+    }
+    tv = std::max(tv, 0.5);
+    err = tv * std::sqrt(2.0 * (2.0 * w + 1.0) / (static_cast<double>(n_t) * n_series));
+  }
+  *tau = tv;
+  if (tau_err) *tau_err = err;
+  if (window) *window = w;
+  return GGF_OK;
+}
+
+const char *ggf_last_error(ggf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void ggf_destroy(ggf_ctx *ctx) {
+  if (!ctx) return;
+  free_chains(ctx);
+  if (ctx->tensors_dev) hipFree(ctx->tensors_dev);
+  for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
+  if (ctx->ev_in) hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) hipEventDestroy(ctx->ev_out);
+  if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+  delete ctx;
+}
+
+}  // extern "C"

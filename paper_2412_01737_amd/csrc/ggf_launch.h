@@ -1,0 +1,48 @@
+// Host-side launch wrappers shared by the kernel translation units and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ggf_device.h"
+
+// Device pointers and scalars every launch needs.
+struct LaunchCtx {
+  hipStream_t stream;
+  int precision;                 // 64 or 32
+  const ChainDev *chains;
+  const TensorDev *tensors;
+  void *G;                       // double* or float*
+  void *F;                       // factor arena, same type as G
+  int8_t *links;
+  double *logw;
+  double2 *sfac;
+  uint32_t *sweep;
+  uint32_t *acc_since;
+  unsigned long long *acc_total;
+  unsigned long long *prop_total;
+  unsigned long long *refreshes;
+  double *max_drift;
+  double *ldet;
+  int *flags;
+  int *acc_list;                 // compacted accepted chains of the current link step
+  int *acc_cnt;                  // [2] double-buffered accepted counts
+  double *scratch;               // float64 refactorisation scratch
+  uint32_t key0, key1;
+  int n_chains;
+};
+
+void ggf_launch_assemble(const LaunchCtx &lc, const int *list, int count, int max_sites);
+void ggf_launch_gj(const LaunchCtx &lc, const int *list, int count, int n_max, int nb, int *piv,
+                   int *perm, size_t piv_stride);
+void ggf_launch_store(const LaunchCtx &lc, const int *list, int count, int n_max, const int *perm,
+                      size_t piv_stride);
+void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_refresh);
+
+// One link step: ratio + decision + factors, then the streaming rank-4 update.
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax);
+void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles);
+void ggf_launch_end_sweep(const LaunchCtx &lc);
+void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);
+void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax);
+void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax);

@@ -1,0 +1,559 @@
+// Sweep and measurement kernels: the single-link Metropolis step (Sec. 5.1
+// sampling of p(G) = N(G)/N) on the maintained inverse G = M(G)^-1.
+//
+// Link step l, per chain (k_ratio, one workgroup per chain):
+//   U = (out0, out1, in0, in1) Majoranas of link l; the proposal changes the
+//   out-in block of M by X = (R(theta') - R(theta)) x0, i.e. dM_UU = [[0, X], [-X^T, 0]];
+//   rho = det(1 + G_UU dM_UU) = (W'/W)^2 by the matrix determinant lemma;
+//   for K > 1, S' = N(G')/W(G') from the patch Pfaffians of every pair (n, m)
+//   of the superposition evaluated on G' restricted to the patch Majoranas
+//   (Woodbury: G'_SS = G_SS + G_SU K G_SU^T);
+//   accept iff u < sqrt(rho) S'/S with u from Philox(chain, sweep, link, 0).
+//   On accept the workgroup writes PT = -G[U,:] and QT = (G[:,U] K)^T,
+//   K = dM (1 + G_UU dM)^-1 = (dM^-1 + G_UU)^-1, and appends the chain to the
+//   step's accepted list.
+// Then the streaming update (k_update) applies G <- G + QT^T PT
+// = G - G[:,U] K G[U,:] to every accepted chain, each element once: read n^2, write n^2.
+#include "ggf_device.h"
+#include "ggf_launch.h"
+
+namespace {
+
+constexpr int kPairLd = 16;   // leading dimension of the per-pair 2s x 2s workspace (s <= 8)
+
+struct PatchSet {
+  int s;
+  int idx[8];
+};
+
+__device__ inline void pair_set(const TensorDev &Tn, int a, int b, int L, PatchSet &ps) {
+  const int nl = Tn.nl[a][b];
+  ps.s = 4 * nl;
+  for (int l = 0; l < nl; ++l) {
+    int u[4];
+    ggf_link_u(Tn.lk[a][b][l], L, u);
+    for (int q = 0; q < 4; ++q) ps.idx[4 * l + q] = u[q];
+  }
+}
+
+// Fill W (2s x 2s, leading dimension 16) with [[G'_SS, 1], [-1, Delta_SS]] for pair (a, b).
+// G'_SS is G restricted to the pair's patch Majoranas, plus the Woodbury term
+// G_SU K G_SU^T of a proposed flip when Kw != nullptr; Delta_SS is the rotated
+// change of the transition covariance on each involved link (link ell_prop
+// taken at its proposed value k_prop).
+template <typename T>
+__device__ inline void build_pair_matrix(const TensorDev &Tn, int a, int b, int L, int group, const T *G, int n,
+                                         const int8_t *lk, const int *U, const double *Kw, int ell_prop,
+                                         int k_prop, double2 *W, PatchSet &ps) {
+  pair_set(Tn, a, b, L, ps);
+  const int s = ps.s, m = 2 * s;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double2 v = make_double2(0.0, 0.0);
+      if (i < s && j < s) v.x = static_cast<double>(G[static_cast<size_t>(ps.idx[i]) * n + ps.idx[j]]);
+      else if (i < s && j == i + s) v.x = 1.0;
+      else if (i >= s && j == i - s) v.x = -1.0;
+      W[i * kPairLd + j] = v;
+    }
+  if (Kw != nullptr) {
+    double p[8][4];
+    for (int i = 0; i < s; ++i)
+      for (int q = 0; q < 4; ++q) p[i][q] = static_cast<double>(G[static_cast<size_t>(ps.idx[i]) * n + U[q]]);
+    for (int i = 0; i < s; ++i) {
+      double t[4];
+      for (int q2 = 0; q2 < 4; ++q2) {
+        double v = 0.0;
+        for (int q = 0; q < 4; ++q) v += p[i][q] * Kw[q * 4 + q2];
+        t[q2] = v;
+      }
+      for (int j = 0; j < s; ++j) {
+        double v = 0.0;
+        for (int q2 = 0; q2 < 4; ++q2) v += t[q2] * p[j][q2];
+        W[i * kPairLd + j].x += v;
+      }
+    }
+  }
+  const int nl = Tn.nl[a][b];
+  for (int l = 0; l < nl; ++l) {
+    const int link = Tn.lk[a][b][l];
+    const int kv = (link == ell_prop) ? k_prop : lk[link];
+    double2 blk[16];
+    ggf_rotate_dg(Tn.dg[a][b][l], kv, group, blk);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) W[(s + 4 * l + i) * kPairLd + s + 4 * l + j] = blk[i * 4 + j];
+  }
+}
+
+// r_ab = Pf(M_ab)/Pf(M_00) = (-1)^(s/2) Pf(W); W is destroyed.
+__device__ inline double2 pair_ratio(double2 *W, int s) {
+  double2 pf = ggf_cpfaffian(W, 2 * s, kPairLd);
+  if ((s / 2) & 1) pf = cscale(pf, -1.0);
+  return pf;
+}
+
+__device__ inline void pair_of(int p, int K, int &a, int &b) {
+  // enumerate a <= b, skipping (0, 0): p = 0 .. K(K+1)/2 - 2
+  int q = p + 1;
+  a = 0;
+  while (q >= K - a) { q -= K - a; ++a; }
+  b = a + q;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity) {
+  extern __shared__ double2 s_work[];
+  __shared__ double s_K[16];
+  __shared__ double s_rho, s_u;
+  __shared__ int s_U[4];
+  __shared__ int s_kn, s_acc;
+  __shared__ double2 s_r[16];
+  const int c = blockIdx.x;
+  if (c == 0 && threadIdx.x == 0) lc.acc_cnt[parity ^ 1] = 0;
+  const ChainDev ch = lc.chains[c];
+  if (ell >= ch.nlinks) return;
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  int8_t *lk = lc.links + ch.link_off;
+  if (threadIdx.x == 0) {
+    int U[4];
+    ggf_link_u(ell, ch.L, U);
+    const int kold = lk[ell];
+    const uint4 x = ggf_philox(make_uint4(static_cast<uint32_t>(c), lc.sweep[c], static_cast<uint32_t>(ell), 0u),
+                               lc.key0, lc.key1);
+    const int kn = (ch.group == 2) ? (1 - kold) : (kold + 1 + static_cast<int>(x.z & 1u)) % 3;
+    double yo[4], yn[4];
+    ggf_bond_block(Tn.x0, kold, ch.group, yo);
+    ggf_bond_block(Tn.x0, kn, ch.group, yn);
+    const double X0 = yn[0] - yo[0], X1 = yn[1] - yo[1], X2 = yn[2] - yo[2], X3 = yn[3] - yo[3];
+    const double dM[16] = {0, 0, X0, X1, 0, 0, X2, X3, -X0, -X2, 0, 0, -X1, -X3, 0, 0};
+    double guu[16];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) guu[a * 4 + b] = static_cast<double>(G[static_cast<size_t>(U[a]) * n + U[b]]);
+    double A[16], Ai[16];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        double v = (a == b) ? 1.0 : 0.0;
+        for (int q = 0; q < 4; ++q) v += guu[a * 4 + q] * dM[q * 4 + b];
+        A[a * 4 + b] = v;
+        Ai[a * 4 + b] = (a == b) ? 1.0 : 0.0;
+      }
+    const double rho = ggf_solve4(A, Ai);      // Ai <- (1 + G_UU dM)^-1
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        double v = 0.0;
+        for (int q = 0; q < 4; ++q) v += dM[a * 4 + q] * Ai[q * 4 + b];
+        s_K[a * 4 + b] = v;
+      }
+    for (int q = 0; q < 4; ++q) s_U[q] = U[q];
+    s_rho = rho;
+    s_kn = kn;
+    s_u = ggf_u53(x.x, x.y);
+  }
+  __syncthreads();
+  const int K = ch.K;
+  const int npairs = K * (K + 1) / 2 - 1;
+  if (K > 1) {
+    if (threadIdx.x < npairs) {
+      int a, b;
+      pair_of(threadIdx.x, K, a, b);
+      PatchSet ps;
+      double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
+      build_pair_matrix(Tn, a, b, ch.L, ch.group, G, n, lk, s_U, s_K, ell, s_kn, W, ps);
+      s_r[threadIdx.x] = pair_ratio(W, ps.s);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double rho = s_rho;
+    double2 snew = make_double2(1.0, 0.0);
+    double sratio = 1.0;
+    if (K > 1) {
+      double sv = Tn.w[0][0].x;
+      for (int p = 0; p < npairs; ++p) {
+        int a, b;
+        pair_of(p, K, a, b);
+        const double2 t = cmul(Tn.w[a][b], s_r[p]);
+        sv += (a == b) ? t.x : 2.0 * t.x;
+      }
+      snew = make_double2(sv, 0.0);
+      sratio = sv / lc.sfac[c].x;
+    }
+    const bool bad = !isfinite(rho) || !isfinite(sratio) || rho < -1e-6;
+    const double R = (rho > 0.0 ? sqrt(rho) : 0.0) * sratio;
+    const bool accept = !bad && (s_u < R);
+    lc.prop_total[c] += 1;
+    if (bad) lc.flags[c] |= GGF_FLAG_NONFINITE;
+    if (accept) {
+      lk[ell] = static_cast<int8_t>(s_kn);
+      lc.logw[c] += 0.5 * log(rho);
+      lc.sfac[c] = snew;
+      lc.acc_since[c] += 1;
+      lc.acc_total[c] += 1;
+      const int slot = atomicAdd(lc.acc_cnt + parity, 1);
+      lc.acc_list[slot] = c;
+    }
+    s_acc = accept ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_acc) return;
+  // Woodbury with the stored rows and columns: G' = G - G[:,U] K G[U,:].
+  // (Substituting -G[U,:]^T for G[:,U] would assume exact antisymmetry; rounding
+  // breaks it and the symmetric part of the error then grows with every flip.)
+  T *PT = static_cast<T *>(lc.F) + ch.f_off;
+  T *QT = PT + 4 * static_cast<size_t>(n);
+  const int u0 = s_U[0], u1 = s_U[1], u2 = s_U[2], u3 = s_U[3];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const T *gj = G + static_cast<size_t>(j) * n;
+    const double c0 = static_cast<double>(gj[u0]), c1 = static_cast<double>(gj[u1]);
+    const double c2 = static_cast<double>(gj[u2]), c3 = static_cast<double>(gj[u3]);
+    PT[j] = static_cast<T>(-static_cast<double>(G[static_cast<size_t>(u0) * n + j]));
+    PT[n + j] = static_cast<T>(-static_cast<double>(G[static_cast<size_t>(u1) * n + j]));
+    PT[2 * n + j] = static_cast<T>(-static_cast<double>(G[static_cast<size_t>(u2) * n + j]));
+    PT[3 * n + j] = static_cast<T>(-static_cast<double>(G[static_cast<size_t>(u3) * n + j]));
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      QT[static_cast<size_t>(b) * n + j] =
+          static_cast<T>(c0 * s_K[0 * 4 + b] + c1 * s_K[1 * 4 + b] + c2 * s_K[2 * 4 + b] + c3 * s_K[3 * 4 + b]);
+  }
+}
+
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+
+__device__ __forceinline__ void upd(double2 &g, double q0, double q1, double q2, double q3, const double2 &p0,
+                                    const double2 &p1, const double2 &p2, const double2 &p3) {
+  g.x = fma(q0, p0.x, fma(q1, p1.x, fma(q2, p2.x, fma(q3, p3.x, g.x))));
+  g.y = fma(q0, p0.y, fma(q1, p1.y, fma(q2, p2.y, fma(q3, p3.y, g.y))));
+}
+__device__ __forceinline__ void upd(float4 &g, float q0, float q1, float q2, float q3, const float4 &p0,
+                                    const float4 &p1, const float4 &p2, const float4 &p3) {
+  g.x = fmaf(q0, p0.x, fmaf(q1, p1.x, fmaf(q2, p2.x, fmaf(q3, p3.x, g.x))));
+  g.y = fmaf(q0, p0.y, fmaf(q1, p1.y, fmaf(q2, p2.y, fmaf(q3, p3.y, g.y))));
+  g.z = fmaf(q0, p0.z, fmaf(q1, p1.z, fmaf(q2, p2.z, fmaf(q3, p3.z, g.z))));
+  g.w = fmaf(q0, p0.w, fmaf(q1, p1.w, fmaf(q2, p2.w, fmaf(q3, p3.w, g.w))));
+}
+
+// Streaming rank-4 update G <- G + sum_b QT[b] (x) PT[b] over the step's accepted chains.
+// Work item = (accepted chain, row tile); a persistent grid strides over items.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(LaunchCtx lc, int parity, int tiles) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VW = Vec16<T>::n;
+  const int nacc = lc.acc_cnt[parity];
+  const int total = nacc * tiles;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int slot = item / tiles;
+    const int tile = item - slot * tiles;
+    const int c = lc.acc_list[slot];
+    const ChainDev ch = lc.chains[c];
+    const int n = ch.n;
+    const int r0 = static_cast<int>((static_cast<long>(tile) * n) / tiles);
+    const int r1 = static_cast<int>((static_cast<long>(tile + 1) * n) / tiles);
+    T *G = static_cast<T *>(lc.G) + ch.g_off;
+    const T *PT = static_cast<const T *>(lc.F) + ch.f_off;
+    const T *QT = PT + 4 * static_cast<size_t>(n);
+    for (int j0 = threadIdx.x * VW; j0 < n; j0 += 256 * VW) {
+      const V p0 = *reinterpret_cast<const V *>(PT + j0);
+      const V p1 = *reinterpret_cast<const V *>(PT + n + j0);
+      const V p2 = *reinterpret_cast<const V *>(PT + 2 * n + j0);
+      const V p3 = *reinterpret_cast<const V *>(PT + 3 * n + j0);
+      int i = r0;
+      for (; i + 4 <= r1; i += 4) {
+        V g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = *reinterpret_cast<const V *>(G + static_cast<size_t>(i + q) * n + j0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          upd(g[q], QT[i + q], QT[n + i + q], QT[2 * n + i + q], QT[3 * n + i + q], p0, p1, p2, p3);
+          *reinterpret_cast<V *>(G + static_cast<size_t>(i + q) * n + j0) = g[q];
+        }
+      }
+      for (; i < r1; ++i) {
+        V g = *reinterpret_cast<const V *>(G + static_cast<size_t>(i) * n + j0);
+        upd(g, QT[i], QT[n + i], QT[2 * n + i], QT[3 * n + i], p0, p1, p2, p3);
+        *reinterpret_cast<V *>(G + static_cast<size_t>(i) * n + j0) = g;
+      }
+    }
+  }
+}
+
+__global__ void k_end_sweep(LaunchCtx lc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < lc.n_chains) lc.sweep[c] += 1u;
+}
+
+__global__ void k_hot_start(LaunchCtx lc, int max_links) {
+  const int c = blockIdx.y;
+  const ChainDev ch = lc.chains[c];
+  for (int ell = blockIdx.x * blockDim.x + threadIdx.x; ell < ch.nlinks; ell += gridDim.x * blockDim.x) {
+    const uint4 x = ggf_philox(make_uint4(static_cast<uint32_t>(c), 0xFFFFFFFFu, static_cast<uint32_t>(ell), 1u),
+                               lc.key0, lc.key1);
+    lc.links[ch.link_off + ell] = static_cast<int8_t>(x.x % static_cast<uint32_t>(ch.group));
+  }
+}
+
+// S(G) = sum_nm lambda_n^* lambda_m <B_m|B_n> r_nm(G) of the committed configuration.
+template <typename T>
+__global__ __launch_bounds__(64) void k_sfac(LaunchCtx lc, const int *list, int count) {
+  extern __shared__ double2 s_work[];
+  __shared__ double2 s_r[16];
+  const int bi = blockIdx.x;
+  if (bi >= count) return;
+  const int c = list[bi];
+  const ChainDev ch = lc.chains[c];
+  const int K = ch.K;
+  if (K == 1) {
+    if (threadIdx.x == 0) lc.sfac[c] = make_double2(1.0, 0.0);
+    return;
+  }
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int npairs = K * (K + 1) / 2 - 1;
+  if (threadIdx.x < npairs) {
+    int a, b;
+    pair_of(threadIdx.x, K, a, b);
+    PatchSet ps;
+    double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
+    build_pair_matrix(Tn, a, b, ch.L, ch.group, G, ch.n, lk, nullptr, nullptr, -1, 0, W, ps);
+    s_r[threadIdx.x] = pair_ratio(W, ps.s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sv = Tn.w[0][0].x;
+    for (int p = 0; p < npairs; ++p) {
+      int a, b;
+      pair_of(p, K, a, b);
+      const double2 t = cmul(Tn.w[a][b], s_r[p]);
+      sv += (a == b) ? t.x : 2.0 * t.x;
+    }
+    lc.sfac[c] = make_double2(sv, 0.0);
+    if (!isfinite(sv)) lc.flags[c] |= GGF_FLAG_NONFINITE;
+  }
+}
+
+__device__ inline double2 link_phase(int k, int group) {
+  if (k == 0) return make_double2(1.0, 0.0);
+  if (group == 2) return make_double2(-1.0, 0.0);
+  double s, co;
+  sincospi(2.0 * k / group, &s, &co);
+  return make_double2(co, s);
+}
+
+__device__ inline double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+// Observables of one chain per workgroup (Sec. 2.3, 5.1, 5.2).  Fermionic
+// two-point functions: Gamma_out = A + B M^-1 B^T (per pair (a, b) of the
+// superposition with M_ab^-1 = G - G_S Y_ab G_S^T, Y_ab = Delta (1 + G_SS Delta)^-1),
+// <c_p c_q> = -i Gamma_out, weights lambda_a^* lambda_b <B_b|B_a> r_ab / S.
+template <typename T>
+__global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, double *out) {
+  __shared__ double2 s_Y[16][64];
+  __shared__ double2 s_om[16];
+  __shared__ int s_S[16][8];
+  __shared__ int s_s[16];
+  __shared__ double red[8];
+  extern __shared__ double2 s_work[];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, K = ch.K, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int npairs = K * K;
+  // per ordered pair: r_ab and Y_ab = Delta (1 + G_SS Delta)^-1, four pairs at a time
+  for (int p0 = 0; p0 < npairs; p0 += 4) {
+    const int pr = p0 + threadIdx.x;
+    if (threadIdx.x < 4 && pr < npairs) {
+      const int a = pr / K, b = pr % K;
+      double2 r = make_double2(1.0, 0.0);
+      int s = 0;
+      if (!(a == 0 && b == 0)) {
+        PatchSet ps;
+        double2 *W = s_work + threadIdx.x * (kPairLd * kPairLd + 64);
+        double2 *C = W + kPairLd * kPairLd;
+        build_pair_matrix(Tn, a, b, L, group, G, n, lk, nullptr, nullptr, -1, 0, W, ps);
+        s = ps.s;
+        for (int i = 0; i < s; ++i)
+          for (int j = 0; j < s; ++j) {
+            double2 v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+            for (int q = 0; q < s; ++q) v = cadd(v, cscale(W[(s + q) * kPairLd + s + j], W[i * kPairLd + q].x));
+            C[i * 8 + j] = v;
+          }
+        int piv[8];
+        if (!ggf_cinvert(C, s, 8, piv)) lc.flags[c] |= GGF_FLAG_NONFINITE;
+        for (int i = 0; i < s; ++i)
+          for (int j = 0; j < s; ++j) {
+            double2 v = make_double2(0.0, 0.0);
+            for (int q = 0; q < s; ++q) v = cadd(v, cmul(W[(s + i) * kPairLd + s + q], C[q * 8 + j]));
+            s_Y[pr][i * 8 + j] = v;
+          }
+        for (int q = 0; q < s; ++q) s_S[pr][q] = ps.idx[q];
+        r = pair_ratio(W, s);
+      }
+      s_s[pr] = s;
+      s_om[pr] = cmul(Tn.w[a][b], r);
+    }
+  }
+  __syncthreads();
+  double Sv = 0.0;
+  for (int p = 0; p < npairs; ++p) Sv += s_om[p].x;
+  const double invS = 1.0 / Sv;
+  double acc[GGF_NOBS_DEV];
+  for (int q = 0; q < GGF_NOBS_DEV; ++q) acc[q] = 0.0;
+  const int nmes = min(L / 2, GGF_MAX_MESON);
+  for (int x = threadIdx.x; x < V; x += blockDim.x) {
+    if (mask & 1u) {
+      const int x1 = ggf_shift(x, L, 1, 0), x2 = ggf_shift(x, L, 0, 1);
+      double2 z = cmul(link_phase(lk[2 * x], group), link_phase(lk[2 * x1 + 1], group));
+      z = cmul(z, cconj(link_phase(lk[2 * x2], group)));
+      z = cmul(z, cconj(link_phase(lk[2 * x + 1], group)));
+      acc[0] += z.x;
+      double2 w = make_double2(1.0, 0.0);
+      int p = x;
+      for (int t = 0; t < 2; ++t) { w = cmul(w, link_phase(lk[2 * p], group)); p = ggf_shift(p, L, 1, 0); }
+      for (int t = 0; t < 2; ++t) { w = cmul(w, link_phase(lk[2 * p + 1], group)); p = ggf_shift(p, L, 0, 1); }
+      for (int t = 0; t < 2; ++t) { p = ggf_shift(p, L, -1, 0); w = cmul(w, cconj(link_phase(lk[2 * p], group))); }
+      for (int t = 0; t < 2; ++t) { p = ggf_shift(p, L, 0, -1); w = cmul(w, cconj(link_phase(lk[2 * p + 1], group))); }
+      acc[1] += w.x;
+    }
+    if (mask & 6u) {
+      // v_x[pair][p][q] = b_p . G[x-block, S_pair q]; base terms b_p G_xy b_q^T computed on the fly
+      for (int r = 0; r <= ((mask & 4u) ? nmes : 0); ++r) {
+        if (r == 0 && !(mask & 2u)) continue;
+        const int y = (r == 0) ? x : ggf_shift(x, L, r, 0);
+        double base[4] = {0, 0, 0, 0};   // (b G_xy b^T)[p][q]
+        for (int i = 0; i < 8; ++i) {
+          const T *grow = G + static_cast<size_t>(8 * x + i) * n + 8 * y;
+          double t0 = 0.0, t1 = 0.0;
+          for (int j = 0; j < 8; ++j) {
+            const double g = static_cast<double>(grow[j]);
+            t0 += g * Tn.b[0 * 8 + j];
+            t1 += g * Tn.b[1 * 8 + j];
+          }
+          base[0] += Tn.b[0 * 8 + i] * t0;
+          base[1] += Tn.b[0 * 8 + i] * t1;
+          base[2] += Tn.b[1 * 8 + i] * t0;
+          base[3] += Tn.b[1 * 8 + i] * t1;
+        }
+        if (r == 0) {
+          base[0] += Tn.a[0]; base[1] += Tn.a[1]; base[2] += Tn.a[2]; base[3] += Tn.a[3];
+        }
+        double2 tot = make_double2(0.0, 0.0);
+        for (int pr = 0; pr < npairs; ++pr) {
+          double2 gm[4] = {make_double2(base[0], 0), make_double2(base[1], 0), make_double2(base[2], 0),
+                           make_double2(base[3], 0)};
+          const int s = s_s[pr];
+          if (s > 0) {
+            double vx[2][8], vy[2][8];
+            for (int q = 0; q < s; ++q) {
+              const int col = s_S[pr][q];
+              double ax0 = 0, ax1 = 0, ay0 = 0, ay1 = 0;
+              for (int i = 0; i < 8; ++i) {
+                const double gx = static_cast<double>(G[static_cast<size_t>(8 * x + i) * n + col]);
+                const double gy = static_cast<double>(G[static_cast<size_t>(8 * y + i) * n + col]);
+                ax0 += Tn.b[i] * gx; ax1 += Tn.b[8 + i] * gx;
+                ay0 += Tn.b[i] * gy; ay1 += Tn.b[8 + i] * gy;
+              }
+              vx[0][q] = ax0; vx[1][q] = ax1; vy[0][q] = ay0; vy[1][q] = ay1;
+            }
+            // + v_x Y v_y^T   (G_Sy = -G_yS^T makes -G_xS Y G_Sy = + v_x Y v_y^T)
+            for (int pp = 0; pp < 2; ++pp)
+              for (int qq = 0; qq < 2; ++qq) {
+                double2 v = make_double2(0, 0);
+                for (int i = 0; i < s; ++i)
+                  for (int j = 0; j < s; ++j) v = cadd(v, cscale(s_Y[pr][i * 8 + j], vx[pp][i] * vy[qq][j]));
+                gm[pp * 2 + qq] = cadd(gm[pp * 2 + qq], v);
+              }
+          }
+          double2 f;
+          if (r == 0) {
+            f = cscale(cadd(make_double2(1.0, 0.0), gm[1]), 0.5);    // (1 + Gamma_out[x0,x1]) / 2
+          } else {
+            // <phi_x^+ phi_y> = 1/4 [<c0c0> + i<c0c1> - i<c1c0> + <c1c1>], <c_p c_q> = -i Gamma
+            const double2 m00 = make_double2(gm[0].y, -gm[0].x), m01 = make_double2(gm[1].y, -gm[1].x);
+            const double2 m10 = make_double2(gm[2].y, -gm[2].x), m11 = make_double2(gm[3].y, -gm[3].x);
+            double2 bil = cadd(m00, m11);
+            bil = cadd(bil, make_double2(-m01.y, m01.x));
+            bil = csub(bil, make_double2(-m10.y, m10.x));
+            f = cscale(bil, 0.5);                                       // 2 * (1/4) * bilinear
+          }
+          tot = cadd(tot, cmul(s_om[pr], f));
+        }
+        if (r == 0) {
+          acc[2] += tot.x * invS;
+        } else {
+          double2 line = make_double2(1.0, 0.0);
+          int p = x;
+          for (int t = 0; t < r; ++t) { line = cmul(line, link_phase(lk[2 * p], group)); p = ggf_shift(p, L, 1, 0); }
+          acc[4 + r - 1] += cmul(line, tot).x * invS;
+        }
+      }
+    }
+  }
+  for (int q = 0; q < GGF_NOBS_DEV; ++q) {
+    const double t = block_sum(acc[q], red);
+    if (threadIdx.x == 0) out[static_cast<size_t>(c) * GGF_NOBS_DEV + q] = t / V;
+  }
+  if (threadIdx.x == 0) out[static_cast<size_t>(c) * GGF_NOBS_DEV + 3] =
+      (mask & 2u) ? lc.logw[c] + (K > 1 ? log(Sv) : 0.0) : 0.0;
+}
+
+}  // namespace
+
+static size_t pair_lds(int kmax) {
+  const int np = kmax * (kmax + 1) / 2 - 1;
+  return np > 0 ? static_cast<size_t>(np) * kPairLd * kPairLd * sizeof(double2) : 0;
+}
+
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax) {
+  const size_t lds = pair_lds(kmax);
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity);
+  else
+    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity);
+}
+
+void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles) {
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_update<double>, dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+  else
+    hipLaunchKernelGGL(k_update<float>, dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+}
+
+void ggf_launch_end_sweep(const LaunchCtx &lc) {
+  hipLaunchKernelGGL(k_end_sweep, dim3((lc.n_chains + 255) / 256), dim3(256), 0, lc.stream, lc);
+}
+
+void ggf_launch_hot_start(const LaunchCtx &lc, int max_links) {
+  hipLaunchKernelGGL(k_hot_start, dim3((max_links + 255) / 256, lc.n_chains), dim3(256), 0, lc.stream, lc,
+                     max_links);
+}
+
+void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax) {
+  const size_t lds = pair_lds(kmax);
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_sfac<double>, dim3(count), dim3(64), lds, lc.stream, lc, list, count);
+  else
+    hipLaunchKernelGGL(k_sfac<float>, dim3(count), dim3(64), lds, lc.stream, lc, list, count);
+}
+
+void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax) {
+  const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_measure<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, mask, out);
+  else
+    hipLaunchKernelGGL(k_measure<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, mask, out);
+}

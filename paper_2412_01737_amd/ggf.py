@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libggf.so (the C ABI declared in include/ggf.h).
+
+Argument marshalling only: every step of the Monte Carlo path runs in the HIP
+library.  Importing this module does not touch the GPU; ``load()`` raises if
+the library has not been built, and nothing here falls back to a CPU path.
+The same names as the C ABI are exported (``ggf_create``, ``ggf_set_tensor``,
+...); ``Context`` wraps them with status checking.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libggf.so")
+
+GGF_OK, GGF_EINVAL, GGF_ENOMEM, GGF_ESINGULAR, GGF_ENONFINITE, GGF_EDEVICE, GGF_ESTATE = 0, -1, -2, -3, -4, -5, -6
+GGF_KMAX = 4
+GGF_NOBS = 20
+OBS_LINK, OBS_DENSITY, OBS_MESON = 1, 2, 4
+OBS_ALL = 7
+_STATUS = {0: "GGF_OK", -1: "GGF_EINVAL", -2: "GGF_ENOMEM", -3: "GGF_ESINGULAR",
+           -4: "GGF_ENONFINITE", -5: "GGF_EDEVICE", -6: "GGF_ESTATE"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class TensorDesc(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_int32), ("gamma_loc", _dp), ("gamma_bond", _dp), ("K", ctypes.c_int32),
+                ("patch_link", _ip), ("gamma_bond_k", _dp), ("c_re", _dp), ("c_im", _dp)]
+
+
+class ChainInfo(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("n", ctypes.c_int32), ("tensor_id", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("logw", ctypes.c_double), ("s_re", ctypes.c_double),
+                ("s_im", ctypes.c_double), ("sweeps", ctypes.c_uint64), ("accepts", ctypes.c_uint64),
+                ("proposals", ctypes.c_uint64), ("refreshes", ctypes.c_uint64), ("recoveries", ctypes.c_uint64),
+                ("max_drift", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = {
+    "ggf_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    "ggf_set_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(TensorDesc), ctypes.POINTER(ctypes.c_int32)]),
+    "ggf_init_chains": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ChainInfo)]),
+    "ggf_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64]),
+    "ggf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
+    "ggf_set_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
+    "ggf_refresh_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ggf_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "ggf_update_timing": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "ggf_autocorr_time": (ctypes.c_int, [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _dp, _dp,
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "ggf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "ggf_destroy": (None, [ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libggf.so and declare every exported symbol; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2412_01737_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def __getattr__(name):
+    if name in EXPORTS:
+        return getattr(load(), name)
+    raise AttributeError(name)
+
+
+class GGFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _stream_ptr(stream) -> int | None:
+    """Raw hipStream_t from None (legacy default stream), an int, or a torch stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Context:
+    """One ggf_ctx on a device; methods mirror the C ABI and raise GGFError on failure."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        st = self._lib.ggf_create(ctypes.byref(h), device)
+        if st != GGF_OK:
+            raise GGFError(st, f"ggf_create(device={device}) failed")
+        self.h = h
+        self.n_chains = 0
+
+    def _check(self, st: int):
+        if st != GGF_OK:
+            raise GGFError(st, self._lib.ggf_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.ggf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tensor(self, group, gamma_loc, gamma_bond, K=1, patch_link=None, gamma_bond_k=None, c=None) -> int:
+        gl, gb = _f64(gamma_loc), _f64(gamma_bond)
+        keep = [gl, gb]
+        d = TensorDesc()
+        d.group, d.K = int(group), int(K)
+        d.gamma_loc = gl.ctypes.data_as(_dp)
+        d.gamma_bond = gb.ctypes.data_as(_dp)
+        if K > 1:
+            pl = np.ascontiguousarray(np.asarray(patch_link, np.int32))
+            gk = _f64(gamma_bond_k)
+            cc = np.asarray(c, complex)
+            cre, cim = _f64(cc.real), _f64(cc.imag)
+            keep += [pl, gk, cre, cim]
+            d.patch_link = pl.ctypes.data_as(_ip)
+            d.gamma_bond_k = gk.ctypes.data_as(_dp)
+            d.c_re = cre.ctypes.data_as(_dp)
+            d.c_im = cim.ctypes.data_as(_dp)
+        tid = ctypes.c_int32()
+        self._check(self._lib.ggf_set_tensor(self.h, ctypes.byref(d), ctypes.byref(tid)))
+        del keep
+        return tid.value
+
+    def set_tensor_spec(self, spec) -> int:
+        """Register a synth.TensorSpec-like object (group, gamma_loc, gamma_bond, K, ...)."""
+        return self.set_tensor(spec.group, spec.gamma_loc, spec.gamma_bond, spec.K, spec.patch_link,
+                               spec.gamma_bond_k, spec.c)
+
+    def init_chains(self, L, tensor_id, seed: int, init: int = 0, precision: int = 64,
+                    refresh_every: int = 0, stream=None):
+        L = np.ascontiguousarray(np.asarray(L, np.int32).reshape(-1))
+        tid = np.ascontiguousarray(np.broadcast_to(np.asarray(tensor_id, np.int32), L.shape))
+        self._check(self._lib.ggf_init_chains(self.h, len(L), L.ctypes.data_as(_ip), tid.ctypes.data_as(_ip),
+                                              int(seed), int(init), int(precision), int(refresh_every),
+                                              _stream_ptr(stream)))
+        self.n_chains = len(L)
+        self.L = L
+
+    def sweep(self, n_sweeps: int = 1, stream=None):
+        self._check(self._lib.ggf_sweep(self.h, int(n_sweeps), _stream_ptr(stream)))
+
+    def measure(self, mask: int = OBS_ALL, out=None, stream=None):
+        """Observables [n_chains, GGF_NOBS]: into a device tensor `out` (async) or a new numpy array."""
+        if out is None:
+            host = np.zeros((self.n_chains, GGF_NOBS))
+            self._check(self._lib.ggf_measure(self.h, int(mask), host.ctypes.data_as(ctypes.c_void_p), 0,
+                                              _stream_ptr(stream)))
+            return host
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        self._check(self._lib.ggf_measure(self.h, int(mask), ctypes.c_void_p(ptr), 1, _stream_ptr(stream)))
+        return out
+
+    def get_state(self, chain: int):
+        info = ChainInfo()
+        self._check(self._lib.ggf_get_state(self.h, int(chain), None, ctypes.byref(info)))
+        links = np.zeros(2 * info.L * info.L, np.int8)
+        self._check(self._lib.ggf_get_state(self.h, int(chain), links.ctypes.data_as(ctypes.c_void_p), None))
+        return links, info.as_dict()
+
+    def set_state(self, chain: int, links, sweeps: int):
+        lk = np.ascontiguousarray(np.asarray(links, np.int8))
+        self._check(self._lib.ggf_set_state(self.h, int(chain), lk.ctypes.data_as(ctypes.c_void_p), int(sweeps)))
+
+    def get_inverse(self, chain: int) -> np.ndarray:
+        L = int(self.L[chain])
+        n = 8 * L * L
+        out = np.zeros((n, n))
+        self._check(self._lib.ggf_get_inverse(self.h, int(chain), out.ctypes.data_as(_dp)))
+        return out
+
+    def set_inverse(self, chain: int, G):
+        g = _f64(G)
+        self._check(self._lib.ggf_set_inverse(self.h, int(chain), g.ctypes.data_as(_dp)))
+
+    def refresh_all(self, stream=None):
+        self._check(self._lib.ggf_refresh_all(self.h, _stream_ptr(stream)))
+
+    def set_option(self, key: str, value: int):
+        self._check(self._lib.ggf_set_option(self.h, key.encode(), int(value)))
+
+    def update_timing(self):
+        ms = ctypes.c_double()
+        la = ctypes.c_int64()
+        fl = ctypes.c_int64()
+        self._check(self._lib.ggf_update_timing(self.h, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(fl)))
+        return ms.value, la.value, fl.value
+
+
+def autocorr_time(series, c: float = 5.0):
+    """(tau, tau_err, window) of series[t, s] (time-major) via ggf_autocorr_time."""
+    x = np.ascontiguousarray(np.asarray(series, np.float64))
+    if x.ndim == 1:
+        x = x[:, None]
+    tau, err, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    st = load().ggf_autocorr_time(x.ctypes.data_as(_dp), x.shape[0], x.shape[1], float(c), ctypes.byref(tau),
+                                  ctypes.byref(err), ctypes.byref(w))
+    if st != GGF_OK:
+        raise GGFError(st, "ggf_autocorr_time: bad arguments")
+    return tau.value, err.value, w.value
