@@ -46,9 +46,50 @@ def parse():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--update-grid", type=int, default=0)
     ap.add_argument("--update-tiles", type=int, default=0)
-    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "update_traffic.json"),
+    ap.add_argument("--update-nt", type=int, default=1)
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "k_update_traffic.json"),
                     help="measured HBM traffic of the update kernel (from rocprofv3 counters)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
+
+
+def copy_probe(nbytes: int):
+    """Project stream probes (ggf_stream_probe) on a buffer of known size.
+
+    Calibrates FETCH_SIZE / WRITE_SIZE per byte moved and measures the
+    achievable copy and read-modify-write bandwidth the update kernel is
+    compared with."""
+    import ctypes
+    import torch
+    from paper_2412_01737_amd.ggf import load
+    lib = load()
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    out = {"bytes": nbytes}
+    for mode, name, moved in ((0, "copy", 2), (1, "copy_nt", 2), (2, "rmw", 2), (3, "rmw_nt", 2)):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st = lib.ggf_stream_probe(mode, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nbytes, 0,
+                                  ctypes.c_void_p(s.cuda_stream))
+        assert st == 0
+        reps = 5
+        ev0.record(s)
+        for _ in range(reps):
+            lib.ggf_stream_probe(mode, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nbytes, 0,
+                                 ctypes.c_void_p(s.cuda_stream))
+        ev1.record(s)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        out[name + "_GBps"] = moved * nbytes / (ms * 1e-3) / 1e9
+    print(json.dumps(out))
+
+
+def source_digest() -> str:
+    """Digest of the update kernel's source; traffic counters are only reported for the kernel they measured."""
+    import hashlib
+    with open(os.path.join(HERE, "paper_2412_01737_amd", "csrc", "ggf_sweep.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def cpu_baseline(args, budget_s: float):
@@ -94,6 +135,9 @@ def _cpu_chain(L, K, group, chain, budget_s):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent; "
               "sharding them across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
@@ -120,13 +164,13 @@ def main():
     if args.update_tiles:
         ctx.set_option("update_tiles", args.update_tiles)
     ctx.set_option("graph", args.graph)
+    ctx.set_option("update_nt", args.update_nt)
     mask = OBS_LINK | OBS_DENSITY
     obs = torch.zeros((args.warmup + args.steps, args.chains, GGF_NOBS), dtype=torch.float64, device=dev)
     for w in range(args.warmup):
         ctx.sweep(1, stream=stream)
         ctx.measure(mask, obs[w], stream=stream)
     ctx.set_option("time_update", 1)
-    acc0 = sum(ctx.get_state(c)[1]["accepts"] for c in range(min(args.chains, 64)))
     upd_ms, upd_launches, upd_flips = 0.0, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -142,8 +186,11 @@ def main():
     proposals = args.chains * 2 * L * L * args.steps
     value = proposals / elapsed
     series = obs[args.warmup:, :, 0].cpu().numpy()
-    tau, tau_err, window = autocorr_time(series)
-    ess = series.shape[0] * series.shape[1] / (2.0 * tau)
+    if series.shape[0] >= 2:
+        tau, tau_err, window = autocorr_time(series)
+        ess_per_s = series.shape[0] * series.shape[1] / (2.0 * tau) / elapsed
+    else:
+        tau = tau_err = ess_per_s = None
     acceptance = upd_flips / proposals
     bytes_per_flip = 2.0 * n * n * (8 if args.precision == 64 else 4)
     achieved = (upd_flips * bytes_per_flip / upd_launches) / (upd_ms / upd_launches * 1e-3) / 1e9 if upd_ms > 0 else 0.0
@@ -152,8 +199,8 @@ def main():
         with open(args.traffic_json) as f:
             tj = json.load(f)
         key = f"L{L}_K{K}_Z{group}_p{args.precision}_c{args.chains}"
-        if key in tj:
-            traffic = tj[key]
+        if key in tj and tj[key].get("source_digest") == source_digest():
+            traffic = tj[key]["bytes_per_launch"]
     except (OSError, ValueError):
         pass
     cpu = None
@@ -177,7 +224,7 @@ def main():
                                f"float{args.precision} inverse, float64 refresh every {args.refresh} accepted flips",
                    "L": L, "K": K, "group": group, "chains": args.chains, "n": n, "precision": args.precision,
                    "refresh_every": args.refresh, "graph": args.graph},
-        "effective_samples_per_s": ess / elapsed,
+        "effective_samples_per_s": ess_per_s,
         "tau_int_plaquette": tau,
         "tau_int_err": tau_err,
         "acceptance": acceptance,

@@ -149,6 +149,7 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
 /* Tuning knobs (0 = library default):
  *   "update_grid"  workgroups of the persistent rank-4 update kernel
  *   "update_tiles" row tiles per chain in the rank-4 update
+ *   "update_nt"    1 (default) = non-temporal loads/stores of G in the rank-4 update, 0 = cached
  *   "graph"        1 = replay each sweep as a captured hipGraph, 0 = direct launches
  *   "gj_nb"        panel width of the Gauss-Jordan refactorisation (8..64)
  *   "scratch_mb"   float64 scratch budget for refactorisations, MiB */
@@ -170,6 +171,13 @@ ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_
  * n_t n_series / (2 tau).  Pure host computation; needs no context. */
 ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series, double c, double *tau,
                              double *tau_err, int64_t *window);
+
+/* Bandwidth probe (diagnostics): mode 0 copies `bytes` from a to b, mode 1 the
+ * same with non-temporal loads/stores, mode 2 updates a in place
+ * (a = a * 1 + 1, read and write), mode 3 the same non-temporal.  a and b are
+ * device pointers (b unused for modes 2, 3); bytes a multiple of 16; grid
+ * workgroups of 256 threads (0 = 4096).  Asynchronous on `stream`. */
+ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_t grid, void *stream);
 
 /* Message of the most recent failure on this context ("" if none). */
 const char *ggf_last_error(ggf_ctx *ctx);

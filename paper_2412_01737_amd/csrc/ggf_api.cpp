@@ -53,7 +53,7 @@ struct ggf_ctx {
   std::vector<void *> allocs;
 
   // options
-  int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 32, opt_time_update = 0;
+  int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 32, opt_time_update = 0, opt_update_nt = 1;
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -254,7 +254,7 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
   for (int ell = 0; ell < ctx->max_links; ++ell) {
     ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * ell], s));
-    ggf_launch_update(lc, ell & 1, grid, tiles);
+    ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * ell + 1], s));
   }
   ggf_launch_end_sweep(lc);
@@ -685,8 +685,9 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
     ctx->opt_gj_nb = value ? static_cast<int>(value) : 32;
   } else if (k == "scratch_mb") ctx->opt_scratch_mb = value;
   else if (k == "time_update") ctx->opt_time_update = value != 0;
+  else if (k == "update_nt") ctx->opt_update_nt = value != 0;
   else return fail(ctx, GGF_EINVAL, "unknown option " + k);
-  if (k == "update_grid" || k == "update_tiles") {
+  if (k == "update_grid" || k == "update_tiles" || k == "update_nt") {
     if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   }
   return GGF_OK;
@@ -732,6 +733,13 @@ ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series
   if (tau_err) *tau_err = err;
   if (window) *window = w;
   return GGF_OK;
+}
+
+ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_t grid, void *stream) {
+  if (!a || (mode < 2 && !b) || bytes % 16 != 0 || grid < 0 || mode < 0 || mode > 3) return GGF_EINVAL;
+  if (ggf_launch_probe(mode, a, b, bytes, grid ? grid : 4096, static_cast<hipStream_t>(stream)) != 0)
+    return GGF_EINVAL;
+  return hipGetLastError() == hipSuccess ? GGF_OK : GGF_EDEVICE;
 }
 
 const char *ggf_last_error(ggf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }

@@ -41,8 +41,9 @@ void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_ref
 
 // One link step: ratio + decision + factors, then the streaming rank-4 update.
 void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax);
-void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles);
+void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt);
 void ggf_launch_end_sweep(const LaunchCtx &lc);
 void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);
 void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax);
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax);
+int ggf_launch_probe(int mode, void *a, void *b, size_t bytes, int grid, hipStream_t s);

@@ -218,34 +218,48 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   }
 }
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec16;
-template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
-template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef d2v type; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef f4v type; static constexpr int n = 4; };
 
-__device__ __forceinline__ void upd(double2 &g, double q0, double q1, double q2, double q3, const double2 &p0,
-                                    const double2 &p1, const double2 &p2, const double2 &p3) {
-  g.x = fma(q0, p0.x, fma(q1, p1.x, fma(q2, p2.x, fma(q3, p3.x, g.x))));
-  g.y = fma(q0, p0.y, fma(q1, p1.y, fma(q2, p2.y, fma(q3, p3.y, g.y))));
+template <typename V, typename S>
+__device__ __forceinline__ void upd(V &g, S q0, S q1, S q2, S q3, const V &p0, const V &p1, const V &p2,
+                                    const V &p3) {
+  g = q0 * p0 + (q1 * p1 + (q2 * p2 + (q3 * p3 + g)));
 }
-__device__ __forceinline__ void upd(float4 &g, float q0, float q1, float q2, float q3, const float4 &p0,
-                                    const float4 &p1, const float4 &p2, const float4 &p3) {
-  g.x = fmaf(q0, p0.x, fmaf(q1, p1.x, fmaf(q2, p2.x, fmaf(q3, p3.x, g.x))));
-  g.y = fmaf(q0, p0.y, fmaf(q1, p1.y, fmaf(q2, p2.y, fmaf(q3, p3.y, g.y))));
-  g.z = fmaf(q0, p0.z, fmaf(q1, p1.z, fmaf(q2, p2.z, fmaf(q3, p3.z, g.z))));
-  g.w = fmaf(q0, p0.w, fmaf(q1, p1.w, fmaf(q2, p2.w, fmaf(q3, p3.w, g.w))));
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V *p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V *p, const V &v) {
+  if (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
 // Streaming rank-4 update G <- G + sum_b QT[b] (x) PT[b] over the step's accepted chains.
 // Work item = (accepted chain, row tile); a persistent grid strides over items.
-template <typename T>
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup w on XCD
+// w mod 8), each with its own L2: every row tile of an accepted chain goes to
+// the same XCD so the chain's factor rows PT/QT are fetched into one L2 only.
+// NT: non-temporal loads/stores of G (each element is touched once per launch).
+template <typename T, bool NT>
 __global__ __launch_bounds__(256) void k_update(LaunchCtx lc, int parity, int tiles) {
   typedef typename Vec16<T>::type V;
   constexpr int VW = Vec16<T>::n;
+  constexpr int kXcd = 8;
   const int nacc = lc.acc_cnt[parity];
-  const int total = nacc * tiles;
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int slot = item / tiles;
-    const int tile = item - slot * tiles;
+  const int xcd = blockIdx.x % kXcd;
+  const int nwg = gridDim.x / kXcd;                 // workgroups per XCD (grid is a multiple of 8)
+  const int nslots = (nacc > xcd) ? (nacc - xcd + kXcd - 1) / kXcd : 0;   // slots xcd, xcd+8, ...
+  const int total = nslots * tiles;
+  for (int item = blockIdx.x / kXcd; item < total; item += nwg) {
+    const int slot = (item / tiles) * kXcd + xcd;
+    const int tile = item - (item / tiles) * tiles;
     const int c = lc.acc_list[slot];
     const ChainDev ch = lc.chains[c];
     const int n = ch.n;
@@ -263,17 +277,17 @@ __global__ __launch_bounds__(256) void k_update(LaunchCtx lc, int parity, int ti
       for (; i + 4 <= r1; i += 4) {
         V g[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = *reinterpret_cast<const V *>(G + static_cast<size_t>(i + q) * n + j0);
+        for (int q = 0; q < 4; ++q) g[q] = ld<NT>(reinterpret_cast<const V *>(G + static_cast<size_t>(i + q) * n + j0));
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           upd(g[q], QT[i + q], QT[n + i + q], QT[2 * n + i + q], QT[3 * n + i + q], p0, p1, p2, p3);
-          *reinterpret_cast<V *>(G + static_cast<size_t>(i + q) * n + j0) = g[q];
+          st<NT>(reinterpret_cast<V *>(G + static_cast<size_t>(i + q) * n + j0), g[q]);
         }
       }
       for (; i < r1; ++i) {
-        V g = *reinterpret_cast<const V *>(G + static_cast<size_t>(i) * n + j0);
+        V g = ld<NT>(reinterpret_cast<const V *>(G + static_cast<size_t>(i) * n + j0));
         upd(g, QT[i], QT[n + i], QT[2 * n + i], QT[3 * n + i], p0, p1, p2, p3);
-        *reinterpret_cast<V *>(G + static_cast<size_t>(i) * n + j0) = g;
+        st<NT>(reinterpret_cast<V *>(G + static_cast<size_t>(i) * n + j0), g);
       }
     }
   }
@@ -526,11 +540,15 @@ void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax) {
     hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity);
 }
 
-void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles) {
-  if (lc.precision == 64)
-    hipLaunchKernelGGL(k_update<double>, dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
-  else
-    hipLaunchKernelGGL(k_update<float>, dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt) {
+  grid = ((grid + 7) / 8) * 8;   // the XCD mapping needs a multiple of 8 workgroups
+  if (lc.precision == 64) {
+    if (nt) hipLaunchKernelGGL((k_update<double, true>), dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+    else hipLaunchKernelGGL((k_update<double, false>), dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+  } else {
+    if (nt) hipLaunchKernelGGL((k_update<float, true>), dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+    else hipLaunchKernelGGL((k_update<float, false>), dim3(grid), dim3(256), 0, lc.stream, lc, parity, tiles);
+  }
 }
 
 void ggf_launch_end_sweep(const LaunchCtx &lc) {

@@ -60,6 +60,8 @@ EXPORTS = {
                                          ctypes.POINTER(ctypes.c_int64)]),
     "ggf_autocorr_time": (ctypes.c_int, [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _dp, _dp,
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "ggf_stream_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_int32, ctypes.c_void_p]),
     "ggf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "ggf_destroy": (None, [ctypes.c_void_p]),
 }
