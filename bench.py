@@ -51,7 +51,46 @@ def parse():
                     help="measured HBM traffic of the update kernel (from rocprofv3 counters)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="derive the update kernel's HBM bytes per launch from rocprofv3 --pmc CSVs, "
+                         "write --traffic-json and exit (no GPU needed)")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30, help="size of the calibration copy (--traffic-from)")
     return ap.parse_args()
+
+
+def traffic_from(args):
+    """HBM bytes per k_update launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch).
+
+    Each counter is scaled by bytes_known / counter_read for a plain copy of
+    --copy-bytes bytes (FETCH_SIZE reads half the bytes of 128-byte requests on
+    this part, WRITE_SIZE reads them in full)."""
+    import csv
+
+    def per_kernel(path, counter, match):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
+        return sum(vals) / len(vals), len(vals)
+
+    fetch, nf = per_kernel(args.traffic_from[0], "FETCH_SIZE", "k_update")
+    write, nw = per_kernel(args.traffic_from[1], "WRITE_SIZE", "k_update")
+    cfetch, _ = per_kernel(args.traffic_from[2], "FETCH_SIZE", "probe_copy")
+    cwrite, _ = per_kernel(args.traffic_from[3], "WRITE_SIZE", "probe_copy")
+    known_kib = args.copy_bytes / 1024.0
+    sf, sw = known_kib / cfetch, known_kib / cwrite
+    rec = {"bytes_per_launch": (fetch * sf + write * sw) * 1024.0,
+           "read_bytes_per_launch": fetch * sf * 1024.0, "write_bytes_per_launch": write * sw * 1024.0,
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+           "fetch_scale": sf, "write_scale": sw, "source_digest": source_digest()}
+    key = f"L{args.L}_K{args.K}_Z{args.group}_p{args.precision}_c{args.chains}"
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+    except (OSError, ValueError):
+        tj = {}
+    tj[key] = rec
+    with open(args.traffic_json, "w") as f:
+        json.dump(tj, f, indent=1)
+    print(json.dumps({key: rec}))
 
 
 def copy_probe(nbytes: int):
@@ -135,6 +174,9 @@ def _cpu_chain(L, K, group, chain, budget_s):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(args)
+        return
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
@@ -155,7 +197,7 @@ def main():
     ctx = Context(0)
     tid = ctx.set_tensor_spec(spec)
     t_init = time.perf_counter()
-    ctx.init_chains([L] * args.chains, tid, synth.SEED_CHAIN, init=0, precision=args.precision,
+    ctx.init_chains([L] * args.chains, tid, synth.SEED_CHAIN, init=1, precision=args.precision,
                     refresh_every=args.refresh, stream=stream)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
