@@ -155,3 +155,54 @@ class WoodburyChain:
 
     def observables(self) -> np.ndarray:
         return self.an.observables(self.k)
+
+
+def block_move(ch: "WoodburyChain", params, P: int, patch: int):
+    """One Metropolis-Hastings block move on a P x P patch (Z2), learned proposal.
+
+    The proposal resamples the patch links from the network's factorised
+    Bernoulli q(.|context) (logits from the float32 forward pass, uniforms
+    from Philox at (chain, sweep, patch, 3 + j)); it is accepted iff
+    u < N(G') q(x|ctx) / (N(G) q(x'|ctx)) with u from (chain, sweep, patch, 2).
+    N is evaluated from scratch for both configurations (the definition) and an
+    accepted move refactorises G.  Returns (proposed, accepted, changed links).
+    """
+    from . import nn
+    an = ch.an
+    if an.group != 2:
+        raise ValueError("block moves are defined for Z2")
+    L = an.lat.Lx
+    pl = nn.patch_links(L, P, patch)
+    z, _ = nn.forward(params, nn.window(ch.k, L, P, patch), np.float32)
+    zl = nn.logits_patch_order(z).astype(np.float64)
+    u_acc, u = nn.draw_block(ch.seed, ch.chain, ch.sweep_idx, patch, len(pl))
+    y_old = ch.k[pl].astype(np.float64)
+    y_new = (u < nn.sigmoid(zl)).astype(np.float64)
+    m = int(np.sum(y_new != y_old))
+    if m == 0:
+        return False, False, 0
+    k_new = ch.k.copy()
+    k_new[pl] = y_new.astype(np.int8)
+
+    def log_n(k):
+        lw = an.log_weight(k)
+        return lw + (np.log(an.s_factor_def(k).real) if an.K > 1 else 0.0)
+
+    R = np.exp(log_n(k_new) - log_n(ch.k) + nn.log_q(zl, y_old) - nn.log_q(zl, y_new))
+    if u_acc < R:
+        ch.k = k_new
+        ch.refresh()
+        return True, True, m
+    return True, False, m
+
+
+def block_sweep(ch: "WoodburyChain", params, P: int):
+    """Block moves on every patch in order, then the sweep counter advances (shared with link sweeps)."""
+    L = ch.an.lat.Lx
+    stats = [0, 0]
+    for p in range((L // P) ** 2):
+        prop, acc, _ = block_move(ch, params, P, p)
+        stats[0] += prop
+        stats[1] += acc
+    ch.sweep_idx += 1
+    return stats
