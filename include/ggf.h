@@ -172,6 +172,61 @@ ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_
 ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series, double c, double *tau,
                              double *tau_err, int64_t *window);
 
+/* ---- Learned block proposal --------------------------------------------
+ * An exact Metropolis-Hastings move on a P x P patch of sites (2 P^2 links) of
+ * Z2 chains, on top of the single-link sampler (Sec. 5.1 leaves the sampler
+ * open).  The patch links are resampled from a factorised Bernoulli whose
+ * logits come from four valid 3x3 convolutions (2 -> 32 -> 32 -> 32 -> 2
+ * channels, tanh, bfloat16 weights, float32 accumulation) over the (P+8)^2
+ * window of the link field around the patch with every image of the patch
+ * masked; forward and reverse proposal probabilities come from one forward
+ * pass and the acceptance uses the true weight N(G).  An accepted move with m
+ * changed links is a rank-4m Woodbury update of G.  Parameters: one float32
+ * vector W1[32][2][3][3], b1[32], W2[32][32][3][3], b2, W3, b3, W4[2][32][3][3],
+ * b4[2] (ggf_nn_nparams() entries).  Patch p of an L x L lattice has origin
+ * (P (p mod L/P), P (p div L/P)); its links are ordered 2 (y P + x) + mu. */
+
+/* Number of network parameters. */
+int32_t ggf_nn_nparams(void);
+
+/* Select the patch side (1, 2 or 4), initialise the weights Glorot-uniform
+ * from Philox at counter (index, 0, 0, 9) keyed by seed (biases 0) and reset
+ * the Adam state.  Synchronous. */
+ggf_status ggf_nn_init(ggf_ctx *ctx, int32_t patch, uint64_t seed);
+
+/* Read (get_host != NULL) and/or replace (set_host != NULL) the float32
+ * parameters; host arrays of ggf_nn_nparams() floats.  Synchronous. */
+ggf_status ggf_nn_params(ggf_ctx *ctx, float *get_host, const float *set_host);
+
+/* Logits of examples (chain[e], patch[e]) of the current chain states into
+ * logits_host[n][2 P^2] (patch link order).  Host arrays; n <= 65536; synchronous. */
+ggf_status ggf_nn_forward(ggf_ctx *ctx, int32_t n, const int32_t *chain, const int32_t *patch, float *logits_host);
+
+/* Mean binary cross-entropy of the examples' current patch links under the
+ * network and its gradient (float32, ggf_nn_nparams() entries; the bfloat16
+ * rounding of the weights is treated as the identity).  Synchronous. */
+ggf_status ggf_nn_grad(ggf_ctx *ctx, int32_t n, const int32_t *chain, const int32_t *patch, float *grad_host,
+                       double *loss_host);
+
+/* `steps` Adam steps (lr, beta 0.9/0.999, eps 1e-8) on batches of `batch`
+ * examples drawn from the current chain states (chain, patch from Philox at
+ * counter (step, example, 0, 8) keyed by seed).  loss_host (may be NULL)
+ * receives the last batch's mean loss, which makes the call synchronous. */
+ggf_status ggf_nn_train(ggf_ctx *ctx, int32_t steps, int32_t batch, float lr, uint64_t seed, double *loss_host,
+                        void *stream);
+
+/* n_sweeps block sweeps: a block move on every patch in order, then the sweep
+ * counter advances (shared with ggf_sweep).  Philox counters: proposal
+ * uniforms (chain, sweep, patch, 3 + l/4), word l mod 4, u = (x + 1/2) 2^-32;
+ * acceptance (chain, sweep, patch, 2).  Requires ggf_nn_init and Z2 chains
+ * whose side is a multiple of P. */
+ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
+
+/* Block moves proposed (at least one link changed) and accepted for a chain,
+ * and the number of links the accepted moves changed.  Synchronous. */
+ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uint64_t *accepts,
+                           uint64_t *links_changed);
+
 /* Bandwidth probe (diagnostics): mode 0 copies `bytes` from a to b, mode 1 the
  * same with non-temporal loads/stores, mode 2 updates a in place
  * (a = a * 1 + 1, read and write), mode 3 the same non-temporal.  a and b are

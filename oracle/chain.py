@@ -164,7 +164,8 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int):
     Bernoulli q(.|context) (logits from the float32 forward pass, uniforms
     from Philox at (chain, sweep, patch, 3 + j)); it is accepted iff
     u < N(G') q(x|ctx) / (N(G) q(x'|ctx)) with u from (chain, sweep, patch, 2).
-    N is evaluated from scratch for both configurations (the definition) and an
+    N is evaluated from scratch for both configurations (fresh determinant; for
+    K > 1 the cross terms from a fresh inverse by the patch lemma) and an
     accepted move refactorises G.  Returns (proposed, accepted, changed links).
     """
     from . import nn
@@ -185,8 +186,13 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int):
     k_new[pl] = y_new.astype(np.int8)
 
     def log_n(k):
-        lw = an.log_weight(k)
-        return lw + (np.log(an.s_factor_def(k).real) if an.K > 1 else 0.0)
+        M = an.assemble_M(k)
+        sign, ld = np.linalg.slogdet(M)
+        lw = 0.5 * ld - 4 * an.lat.V * np.log(2.0)
+        if an.K == 1:
+            return lw
+        G = np.linalg.inv(M)                  # fresh inverse; patch lemma for N/W (pinned to full Pfaffians)
+        return lw + np.log(an.s_factor_patch(G[np.ix_(an.S, an.S)], k).real)
 
     R = np.exp(log_n(k_new) - log_n(ch.k) + nn.log_q(zl, y_old) - nn.log_q(zl, y_new))
     if u_acc < R:

@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libggf.so")
 ARCH = os.environ.get("GGF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ggf_api.cpp", "ggf_factor.hip", "ggf_sweep.hip", "ggf_probe.hip"]
+SOURCES = ["ggf_api.cpp", "ggf_factor.hip", "ggf_sweep.hip", "ggf_probe.hip", "ggf_nn.hip"]
 
 
 def hipcc() -> str:

@@ -14,6 +14,7 @@
 #include "../../include/ggf.h"
 #include "ggf_device.h"
 #include "ggf_launch.h"
+#include "ggf_nn.h"
 
 typedef std::complex<double> cplx;
 
@@ -60,6 +61,21 @@ struct ggf_ctx {
   hipStream_t own_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+
+  // learned block proposal (network state survives re-initialised chains)
+  int nn_P = 0, nn_adam_t = 0, nn_nslices = 256, nn_cap = 0;
+  uint32_t nn_step = 0;
+  float *nn_p = nullptr, *nn_m = nullptr, *nn_v = nullptr, *nn_g = nullptr, *nn_gpart = nullptr, *nn_logits = nullptr;
+  uint16_t *nn_wq = nullptr;
+  double *nn_lpart = nullptr, *nn_loss = nullptr;
+  int *nn_ex_chain = nullptr, *nn_ex_patch = nullptr;
+  std::vector<void *> nn_allocs;
+  // block-move buffers (tied to the chains)
+  double *blk_A = nullptr, *blk_W = nullptr;
+  void *blk_D = nullptr;
+  size_t *blk_doff = nullptr;
+  int *blk_U = nullptr, *blk_r = nullptr;
+  unsigned long long *blk_prop = nullptr, *blk_acc = nullptr;
 
   // update timing
   std::vector<hipEvent_t> tev;
@@ -164,6 +180,11 @@ void free_chains(ggf_ctx *ctx) {
   if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   for (void *p : ctx->allocs) hipFree(p);
   ctx->allocs.clear();
+  ctx->blk_A = ctx->blk_W = nullptr;
+  ctx->blk_D = nullptr;
+  ctx->blk_doff = nullptr;
+  ctx->blk_U = ctx->blk_r = nullptr;
+  ctx->blk_prop = ctx->blk_acc = nullptr;
   ctx->n_chains = 0;
   ctx->chains.clear();
   ctx->G = ctx->F = nullptr;
@@ -295,6 +316,71 @@ ggf_status after_sweep(ggf_ctx *ctx, hipStream_t s) {
         return fail(ctx, GGF_ENONFINITE, "non-finite weight persists after refactorisation, chain " + std::to_string(c));
   }
   return factorize(ctx, refresh, 1, s);
+}
+
+NNArgs nn_args(ggf_ctx *ctx) {
+  NNArgs n;
+  n.P = ctx->nn_P;
+  n.wq = ctx->nn_wq;
+  n.params = ctx->nn_p;
+  n.chains = ctx->chains_dev;
+  n.links = ctx->links;
+  return n;
+}
+
+// All chains must be Z2 lattices tiled by P x P patches.
+ggf_status nn_check_chains(ggf_ctx *ctx) {
+  if (ctx->nn_P == 0) return fail(ctx, GGF_ESTATE, "ggf_nn_init has not been called");
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  for (const ChainDev &c : ctx->chains) {
+    if (c.group != 2) return fail(ctx, GGF_EINVAL, "the learned block proposal is defined for Z2 chains");
+    if (c.L % ctx->nn_P != 0) return fail(ctx, GGF_EINVAL, "lattice side is not a multiple of the patch side");
+  }
+  return GGF_OK;
+}
+
+ggf_status nn_examples(ggf_ctx *ctx, int32_t n, const int32_t *chain, const int32_t *patch) {
+  if (n <= 0 || !chain || !patch) return fail(ctx, GGF_EINVAL, "examples are required");
+  for (int e = 0; e < n; ++e) {
+    if (chain[e] < 0 || chain[e] >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "example chain out of range");
+    const int npx = ctx->chains[chain[e]].L / ctx->nn_P;
+    if (patch[e] < 0 || patch[e] >= npx * npx) return fail(ctx, GGF_EINVAL, "example patch out of range");
+  }
+  if (n > ctx->nn_cap) return fail(ctx, GGF_EINVAL, "too many examples (capacity 65536)");
+  HIP_TRY(ctx, hipMemcpy(ctx->nn_ex_chain, chain, n * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->nn_ex_patch, patch, n * sizeof(int), hipMemcpyHostToDevice));
+  return GGF_OK;
+}
+
+ggf_status block_buffers(ggf_ctx *ctx) {
+  if (ctx->blk_A) return GGF_OK;
+  hipError_t e = hipSuccess;
+  const size_t esz = ctx->precision == 64 ? sizeof(double) : sizeof(float);
+  std::vector<size_t> off(ctx->n_chains);
+  size_t tot = 0;
+  for (int c = 0; c < ctx->n_chains; ++c) {
+    off[c] = tot;
+    tot += static_cast<size_t>(GGF_BLOCK_RMAX) * ctx->chains[c].n;
+  }
+  const size_t rr = static_cast<size_t>(GGF_BLOCK_RMAX) * GGF_BLOCK_RMAX;
+  ctx->blk_A = dalloc<double>(ctx, rr * ctx->n_chains, e);
+  ctx->blk_W = dalloc<double>(ctx, rr * ctx->n_chains, e);
+  ctx->blk_doff = dalloc<size_t>(ctx, ctx->n_chains, e);
+  ctx->blk_U = dalloc<int>(ctx, static_cast<size_t>(GGF_BLOCK_RMAX) * ctx->n_chains, e);
+  ctx->blk_r = dalloc<int>(ctx, ctx->n_chains, e);
+  ctx->blk_prop = dalloc<unsigned long long>(ctx, 3 * static_cast<size_t>(ctx->n_chains), e);   // proposed, accepted, links
+  ctx->blk_acc = ctx->blk_prop;
+  if (e == hipSuccess) {
+    void *p = nullptr;
+    e = hipMalloc(&p, tot * esz);
+    if (e == hipSuccess) {
+      ctx->allocs.push_back(p);
+      ctx->blk_D = p;
+    }
+  }
+  if (e != hipSuccess) return fail(ctx, GGF_ENOMEM, "cannot allocate block-move buffers");
+  HIP_TRY(ctx, hipMemcpy(ctx->blk_doff, off.data(), off.size() * sizeof(size_t), hipMemcpyHostToDevice));
+  return GGF_OK;
 }
 
 }  // namespace
@@ -735,6 +821,179 @@ ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series
   return GGF_OK;
 }
 
+int32_t ggf_nn_nparams(void) { return GGF_NN_NPARAMS; }
+
+ggf_status ggf_nn_init(ggf_ctx *ctx, int32_t patch, uint64_t seed) {
+  if (!ctx) return GGF_EINVAL;
+  if (patch != 1 && patch != 2 && patch != 4) return fail(ctx, GGF_EINVAL, "patch side must be 1, 2 or 4");
+  if (!ctx->nn_p) {
+    hipError_t e = hipSuccess;
+    auto grab = [&](size_t bytes) -> void * {
+      void *p = nullptr;
+      if (e == hipSuccess) e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+      if (e == hipSuccess) { ctx->nn_allocs.push_back(p); e = hipMemset(p, 0, std::max<size_t>(bytes, 16)); }
+      return p;
+    };
+    ctx->nn_cap = 65536;
+    ctx->nn_p = static_cast<float *>(grab(GGF_NN_NPARAMS * sizeof(float)));
+    ctx->nn_m = static_cast<float *>(grab(GGF_NN_NPARAMS * sizeof(float)));
+    ctx->nn_v = static_cast<float *>(grab(GGF_NN_NPARAMS * sizeof(float)));
+    ctx->nn_g = static_cast<float *>(grab(GGF_NN_NPARAMS * sizeof(float)));
+    ctx->nn_gpart = static_cast<float *>(grab(static_cast<size_t>(ctx->nn_nslices) * GGF_NN_NPARAMS * sizeof(float)));
+    ctx->nn_wq = static_cast<uint16_t *>(grab(GGF_NN_NPARAMS * sizeof(uint16_t)));
+    ctx->nn_lpart = static_cast<double *>(grab(ctx->nn_nslices * sizeof(double)));
+    ctx->nn_loss = static_cast<double *>(grab(sizeof(double)));
+    ctx->nn_ex_chain = static_cast<int *>(grab(ctx->nn_cap * sizeof(int)));
+    ctx->nn_ex_patch = static_cast<int *>(grab(ctx->nn_cap * sizeof(int)));
+    ctx->nn_logits = static_cast<float *>(grab(static_cast<size_t>(ctx->nn_cap) * 32 * sizeof(float)));
+    if (e != hipSuccess) return fail(ctx, GGF_ENOMEM, "cannot allocate network buffers");
+  }
+  // Glorot-uniform weights from Philox at counter (index, 0, 0, 9), zero biases
+  std::vector<float> p(GGF_NN_NPARAMS, 0.0f);
+  const int layers[4][2] = {{2, 32}, {32, 32}, {32, 32}, {32, 2}};
+  int off = 0;
+  for (int l = 0; l < 4; ++l) {
+    const int ci = layers[l][0], co = layers[l][1], cnt = co * ci * 9;
+    const double a = std::sqrt(6.0 / (9.0 * ci + 9.0 * co));
+    for (int i = 0; i < cnt; ++i) {
+      const uint4 x = ggf_philox(make_uint4(static_cast<uint32_t>(off + i), 0u, 0u, 9u),
+                                 static_cast<uint32_t>(seed & 0xFFFFFFFFu), static_cast<uint32_t>(seed >> 32));
+      const double u = (static_cast<double>(x.x) + 0.5) * 0x1.0p-32;
+      p[off + i] = static_cast<float>((2.0 * u - 1.0) * a);
+    }
+    off += cnt + co;
+  }
+  ctx->nn_P = patch;
+  ctx->nn_adam_t = 0;
+  ctx->nn_step = 0;
+  HIP_TRY(ctx, hipMemcpy(ctx->nn_p, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemset(ctx->nn_m, 0, GGF_NN_NPARAMS * sizeof(float)));
+  HIP_TRY(ctx, hipMemset(ctx->nn_v, 0, GGF_NN_NPARAMS * sizeof(float)));
+  ggf_nn_quantize_launch(ctx->nn_p, ctx->nn_wq, nullptr);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  return GGF_OK;
+}
+
+ggf_status ggf_nn_params(ggf_ctx *ctx, float *get_host, const float *set_host) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->nn_P == 0) return fail(ctx, GGF_ESTATE, "ggf_nn_init has not been called");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  if (get_host) HIP_TRY(ctx, hipMemcpy(get_host, ctx->nn_p, GGF_NN_NPARAMS * sizeof(float), hipMemcpyDeviceToHost));
+  if (set_host) {
+    HIP_TRY(ctx, hipMemcpy(ctx->nn_p, set_host, GGF_NN_NPARAMS * sizeof(float), hipMemcpyHostToDevice));
+    ggf_nn_quantize_launch(ctx->nn_p, ctx->nn_wq, nullptr);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipDeviceSynchronize());
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_nn_forward(ggf_ctx *ctx, int32_t n, const int32_t *chain, const int32_t *patch, float *logits_host) {
+  if (!ctx) return GGF_EINVAL;
+  ggf_status st = nn_check_chains(ctx);
+  if (st != GGF_OK) return st;
+  if (!logits_host) return fail(ctx, GGF_EINVAL, "logits_host is NULL");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  if ((st = nn_examples(ctx, n, chain, patch)) != GGF_OK) return st;
+  ggf_nn_forward_launch(nn_args(ctx), ctx->nn_ex_chain, ctx->nn_ex_patch, n, ctx->nn_logits, nullptr);
+  HIP_TRY(ctx, hipGetLastError());
+  const size_t np = 2 * ctx->nn_P * ctx->nn_P;
+  HIP_TRY(ctx, hipMemcpy(logits_host, ctx->nn_logits, n * np * sizeof(float), hipMemcpyDeviceToHost));
+  return GGF_OK;
+}
+
+ggf_status ggf_nn_grad(ggf_ctx *ctx, int32_t n, const int32_t *chain, const int32_t *patch, float *grad_host,
+                       double *loss_host) {
+  if (!ctx) return GGF_EINVAL;
+  ggf_status st = nn_check_chains(ctx);
+  if (st != GGF_OK) return st;
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  if ((st = nn_examples(ctx, n, chain, patch)) != GGF_OK) return st;
+  ggf_nn_grad_launch(nn_args(ctx), ctx->nn_ex_chain, ctx->nn_ex_patch, n, ctx->nn_gpart, ctx->nn_nslices,
+                     ctx->nn_lpart, ctx->nn_g, ctx->nn_loss, nullptr);
+  HIP_TRY(ctx, hipGetLastError());
+  if (grad_host) HIP_TRY(ctx, hipMemcpy(grad_host, ctx->nn_g, GGF_NN_NPARAMS * sizeof(float), hipMemcpyDeviceToHost));
+  if (loss_host) HIP_TRY(ctx, hipMemcpy(loss_host, ctx->nn_loss, sizeof(double), hipMemcpyDeviceToHost));
+  return GGF_OK;
+}
+
+ggf_status ggf_nn_train(ggf_ctx *ctx, int32_t steps, int32_t batch, float lr, uint64_t seed, double *loss_host,
+                        void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  ggf_status st = nn_check_chains(ctx);
+  if (st != GGF_OK) return st;
+  if (steps < 0 || batch <= 0 || batch > ctx->nn_cap || !(lr > 0)) return fail(ctx, GGF_EINVAL, "bad training arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int npatch = 1 << 30;
+  for (const ChainDev &c : ctx->chains) npatch = std::min(npatch, (c.L / ctx->nn_P) * (c.L / ctx->nn_P));
+  for (int t = 0; t < steps; ++t) {
+    ggf_nn_examples_launch(ctx->nn_ex_chain, ctx->nn_ex_patch, batch, ctx->nn_step++,
+                           static_cast<uint32_t>(seed & 0xFFFFFFFFu), static_cast<uint32_t>(seed >> 32),
+                           ctx->n_chains, npatch, s);
+    ggf_nn_grad_launch(nn_args(ctx), ctx->nn_ex_chain, ctx->nn_ex_patch, batch, ctx->nn_gpart, ctx->nn_nslices,
+                       ctx->nn_lpart, ctx->nn_g, ctx->nn_loss, s);
+    ggf_nn_adam_launch(ctx->nn_p, ctx->nn_wq, ctx->nn_m, ctx->nn_v, ctx->nn_g, lr, ++ctx->nn_adam_t, s);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  if (loss_host) {
+    HIP_TRY(ctx, hipMemcpyAsync(loss_host, ctx->nn_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  ggf_status st = nn_check_chains(ctx);
+  if (st != GGF_OK) return st;
+  if (n_sweeps < 0) return fail(ctx, GGF_EINVAL, "n_sweeps must be >= 0");
+  if ((st = block_buffers(ctx)) != GGF_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int max_np = 0;
+  for (const ChainDev &c : ctx->chains) max_np = std::max(max_np, (c.L / ctx->nn_P) * (c.L / ctx->nn_P));
+  BlockLaunch bl;
+  bl.lc = launch_ctx(ctx, s);
+  bl.nn = nn_args(ctx);
+  bl.A = ctx->blk_A;
+  bl.Wf = ctx->blk_W;
+  bl.D = ctx->blk_D;
+  bl.d_off = ctx->blk_doff;
+  bl.U = ctx->blk_U;
+  bl.rcnt = ctx->blk_r;
+  bl.bprop = ctx->blk_prop;
+  bl.bacc = ctx->blk_acc;
+  bl.kmax = ctx->kmax;
+  const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 1024;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    for (int p = 0; p < max_np; ++p) {
+      bl.patch = p;
+      bl.parity = p & 1;
+      ggf_block_decide_launch(bl, s);
+      ggf_block_update_launch(bl, grid, s);
+    }
+    ggf_launch_end_sweep(bl.lc);
+    HIP_TRY(ctx, hipGetLastError());
+    if ((st = after_sweep(ctx, s)) != GGF_OK) return st;
+  }
+  return GGF_OK;
+}
+
+ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uint64_t *accepts,
+                           uint64_t *links_changed) {
+  if (!ctx) return GGF_EINVAL;
+  if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  uint64_t v[3] = {0, 0, 0};
+  if (ctx->blk_prop)
+    for (int q = 0; q < 3; ++q)
+      HIP_TRY(ctx, hipMemcpy(&v[q], ctx->blk_prop + 3 * chain + q, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  if (proposals) *proposals = v[0];
+  if (accepts) *accepts = v[1];
+  if (links_changed) *links_changed = v[2];
+  return GGF_OK;
+}
+
 ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_t grid, void *stream) {
   if (!a || (mode < 2 && !b) || bytes % 16 != 0 || grid < 0 || mode < 0 || mode > 3) return GGF_EINVAL;
   if (ggf_launch_probe(mode, a, b, bytes, grid ? grid : 4096, static_cast<hipStream_t>(stream)) != 0)
@@ -747,6 +1006,7 @@ const char *ggf_last_error(ggf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null
 void ggf_destroy(ggf_ctx *ctx) {
   if (!ctx) return;
   free_chains(ctx);
+  for (void *p : ctx->nn_allocs) hipFree(p);
   if (ctx->tensors_dev) hipFree(ctx->tensors_dev);
   for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
   if (ctx->ev_in) hipEventDestroy(ctx->ev_in);

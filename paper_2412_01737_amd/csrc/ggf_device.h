@@ -49,11 +49,15 @@ struct ChainDev {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // mixed with the other counter words and the key, key bumped by Weyl constants.
-__device__ __forceinline__ uint4 ggf_philox(uint4 c, uint32_t k0, uint32_t k1) {
+__host__ __device__ __forceinline__ uint32_t ggf_mulhi(uint32_t a, uint32_t b) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(a) * b) >> 32);
+}
+
+__host__ __device__ __forceinline__ uint4 ggf_philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = ggf_mulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = ggf_mulhi(0xCD9E8D57u, c.z);
     c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
@@ -61,7 +65,7 @@ __device__ __forceinline__ uint4 ggf_philox(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
-__device__ __forceinline__ double ggf_u53(uint32_t x0, uint32_t x1) {
+__host__ __device__ __forceinline__ double ggf_u53(uint32_t x0, uint32_t x1) {
   const uint64_t bits = ((static_cast<uint64_t>(x1) << 32) | x0) >> 11;
   return static_cast<double>(bits) * 0x1.0p-53;
 }

@@ -16,88 +16,9 @@
 // = G - G[:,U] K G[U,:] to every accepted chain, each element once: read n^2, write n^2.
 #include "ggf_device.h"
 #include "ggf_launch.h"
+#include "ggf_pair.h"
 
 namespace {
-
-constexpr int kPairLd = 16;   // leading dimension of the per-pair 2s x 2s workspace (s <= 8)
-
-struct PatchSet {
-  int s;
-  int idx[8];
-};
-
-__device__ inline void pair_set(const TensorDev &Tn, int a, int b, int L, PatchSet &ps) {
-  const int nl = Tn.nl[a][b];
-  ps.s = 4 * nl;
-  for (int l = 0; l < nl; ++l) {
-    int u[4];
-    ggf_link_u(Tn.lk[a][b][l], L, u);
-    for (int q = 0; q < 4; ++q) ps.idx[4 * l + q] = u[q];
-  }
-}
-
-// Fill W (2s x 2s, leading dimension 16) with [[G'_SS, 1], [-1, Delta_SS]] for pair (a, b).
-// G'_SS is G restricted to the pair's patch Majoranas, plus the Woodbury term
-// G_SU K G_SU^T of a proposed flip when Kw != nullptr; Delta_SS is the rotated
-// change of the transition covariance on each involved link (link ell_prop
-// taken at its proposed value k_prop).
-template <typename T>
-__device__ inline void build_pair_matrix(const TensorDev &Tn, int a, int b, int L, int group, const T *G, int n,
-                                         const int8_t *lk, const int *U, const double *Kw, int ell_prop,
-                                         int k_prop, double2 *W, PatchSet &ps) {
-  pair_set(Tn, a, b, L, ps);
-  const int s = ps.s, m = 2 * s;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
-      double2 v = make_double2(0.0, 0.0);
-      if (i < s && j < s) v.x = static_cast<double>(G[static_cast<size_t>(ps.idx[i]) * n + ps.idx[j]]);
-      else if (i < s && j == i + s) v.x = 1.0;
-      else if (i >= s && j == i - s) v.x = -1.0;
-      W[i * kPairLd + j] = v;
-    }
-  if (Kw != nullptr) {
-    double p[8][4];
-    for (int i = 0; i < s; ++i)
-      for (int q = 0; q < 4; ++q) p[i][q] = static_cast<double>(G[static_cast<size_t>(ps.idx[i]) * n + U[q]]);
-    for (int i = 0; i < s; ++i) {
-      double t[4];
-      for (int q2 = 0; q2 < 4; ++q2) {
-        double v = 0.0;
-        for (int q = 0; q < 4; ++q) v += p[i][q] * Kw[q * 4 + q2];
-        t[q2] = v;
-      }
-      for (int j = 0; j < s; ++j) {
-        double v = 0.0;
-        for (int q2 = 0; q2 < 4; ++q2) v += t[q2] * p[j][q2];
-        W[i * kPairLd + j].x += v;
-      }
-    }
-  }
-  const int nl = Tn.nl[a][b];
-  for (int l = 0; l < nl; ++l) {
-    const int link = Tn.lk[a][b][l];
-    const int kv = (link == ell_prop) ? k_prop : lk[link];
-    double2 blk[16];
-    ggf_rotate_dg(Tn.dg[a][b][l], kv, group, blk);
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) W[(s + 4 * l + i) * kPairLd + s + 4 * l + j] = blk[i * 4 + j];
-  }
-}
-
-// r_ab = Pf(M_ab)/Pf(M_00) = (-1)^(s/2) Pf(W); W is destroyed.
-__device__ inline double2 pair_ratio(double2 *W, int s) {
-  double2 pf = ggf_cpfaffian(W, 2 * s, kPairLd);
-  if ((s / 2) & 1) pf = cscale(pf, -1.0);
-  return pf;
-}
-
-__device__ inline void pair_of(int p, int K, int &a, int &b) {
-  // enumerate a <= b, skipping (0, 0): p = 0 .. K(K+1)/2 - 2
-  int q = p + 1;
-  a = 0;
-  while (q >= K - a) { q -= K - a; ++a; }
-  b = a + q;
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity) {
@@ -218,8 +139,6 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   }
 }
 
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f4v __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { typedef d2v type; static constexpr int n = 2; };
 template <> struct Vec16<float> { typedef f4v type; static constexpr int n = 4; };
@@ -296,6 +215,7 @@ __global__ __launch_bounds__(256) void k_update(LaunchCtx lc, int parity, int ti
 __global__ void k_end_sweep(LaunchCtx lc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < lc.n_chains) lc.sweep[c] += 1u;
+  if (c < 2) lc.acc_cnt[c] = 0;   // every sweep starts with both accepted counters cleared
 }
 
 __global__ void k_hot_start(LaunchCtx lc, int max_links) {

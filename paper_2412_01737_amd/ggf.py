@@ -60,6 +60,16 @@ EXPORTS = {
                                          ctypes.POINTER(ctypes.c_int64)]),
     "ggf_autocorr_time": (ctypes.c_int, [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _dp, _dp,
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "ggf_nn_nparams": (ctypes.c_int32, []),
+    "ggf_nn_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
+    "ggf_nn_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "ggf_nn_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, ctypes.POINTER(ctypes.c_float)]),
+    "ggf_nn_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, ctypes.POINTER(ctypes.c_float), _dp]),
+    "ggf_nn_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                                    _dp, ctypes.c_void_p]),
+    "ggf_block_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_block_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "ggf_stream_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_int32, ctypes.c_void_p]),
     "ggf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -216,6 +226,57 @@ class Context:
 
     def set_option(self, key: str, value: int):
         self._check(self._lib.ggf_set_option(self.h, key.encode(), int(value)))
+
+    # ---- learned block proposal ----
+    def nn_init(self, patch: int, seed: int):
+        self._check(self._lib.ggf_nn_init(self.h, int(patch), int(seed)))
+        self.patch = int(patch)
+
+    def nn_params(self, set_params=None) -> np.ndarray:
+        out = np.zeros(self._lib.ggf_nn_nparams(), np.float32)
+        sp = None
+        if set_params is not None:
+            sp = np.ascontiguousarray(np.asarray(set_params, np.float32))
+        self._check(self._lib.ggf_nn_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            None if sp is None else sp.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        if sp is not None:
+            return sp.copy()
+        return out
+
+    def _examples(self, chains, patches):
+        c = np.ascontiguousarray(np.asarray(chains, np.int32))
+        p = np.ascontiguousarray(np.asarray(patches, np.int32))
+        return c, p
+
+    def nn_forward(self, chains, patches) -> np.ndarray:
+        c, p = self._examples(chains, patches)
+        out = np.zeros((len(c), 2 * self.patch * self.patch), np.float32)
+        self._check(self._lib.ggf_nn_forward(self.h, len(c), c.ctypes.data_as(_ip), p.ctypes.data_as(_ip),
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def nn_grad(self, chains, patches):
+        c, p = self._examples(chains, patches)
+        g = np.zeros(self._lib.ggf_nn_nparams(), np.float32)
+        loss = ctypes.c_double()
+        self._check(self._lib.ggf_nn_grad(self.h, len(c), c.ctypes.data_as(_ip), p.ctypes.data_as(_ip),
+                                          g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+        return loss.value, g
+
+    def nn_train(self, steps: int, batch: int, lr: float, seed: int, stream=None) -> float:
+        loss = ctypes.c_double()
+        self._check(self._lib.ggf_nn_train(self.h, int(steps), int(batch), float(lr), int(seed), ctypes.byref(loss),
+                                           _stream_ptr(stream)))
+        return loss.value
+
+    def block_sweep(self, n_sweeps: int = 1, stream=None):
+        self._check(self._lib.ggf_block_sweep(self.h, int(n_sweeps), _stream_ptr(stream)))
+
+    def block_stats(self, chain: int):
+        """(proposed, accepted, links changed by accepted moves) of one chain's block moves."""
+        p, a, m = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._lib.ggf_block_stats(self.h, int(chain), ctypes.byref(p), ctypes.byref(a), ctypes.byref(m)))
+        return p.value, a.value, m.value
 
     def update_timing(self):
         ms = ctypes.c_double()

@@ -1,0 +1,158 @@
+"""GPU parity of the learned block proposal against the oracle (through the C ABI).
+
+* network logits within 2e-5 of the oracle's float32 forward (same bf16 weights);
+* gradients of the mean cross-entropy within 1e-3 relative of the oracle's
+  float64 back-propagation;
+* one Adam step against the closed form;
+* block Metropolis-Hastings moves: link fields bit-exact against the oracle's
+  definitional block move (fresh determinants) after every sweep, mixed with
+  single-link sweeps; log W and G within float64 tolerance; K = 1 and K = 2.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import ansatz_for, gpu_context, oracle_chain, say, spec_for
+from oracle import nn
+from oracle.chain import block_sweep
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    p = (nn.init_params(seed) + scale * rng.standard_normal(nn.n_params())).astype(np.float32)
+    p[-2:] = [0.3, -0.4]
+    return p
+
+
+@pytest.mark.parametrize("L,P", [(8, 4), (4, 2), (2, 1), (16, 4)])
+def test_forward_matches_oracle(L, P):
+    say(f"nn forward L={L} P={P}")
+    spec = spec_for(L)
+    ctx = gpu_context([spec], [L] * 3, init=1)
+    ctx.nn_init(P, 11)
+    params = ctx.nn_params(_params(3))
+    npatch = (L // P) ** 2
+    ch = [0, 1, 2, 1]
+    pa = [0, npatch - 1, npatch // 2, 1 % npatch]
+    z = ctx.nn_forward(ch, pa)
+    for e in range(len(ch)):
+        links, _ = ctx.get_state(ch[e])
+        zr, _ = nn.forward(params, nn.window(links, L, P, pa[e]), np.float32)
+        assert np.abs(z[e] - nn.logits_patch_order(zr)).max() < 2e-5
+
+
+def test_init_matches_oracle():
+    spec = spec_for(8)
+    ctx = gpu_context([spec], [8])
+    ctx.nn_init(4, 1234)
+    assert np.array_equal(ctx.nn_params(), nn.init_params(1234))
+
+
+@pytest.mark.parametrize("P", [4, 2])
+def test_gradient_matches_oracle(P):
+    say(f"nn grad P={P}")
+    L = 8
+    spec = spec_for(L)
+    ctx = gpu_context([spec], [L] * 4, init=1)
+    ctx.nn_init(P, 5)
+    params = ctx.nn_params(_params(7))
+    rng = np.random.default_rng(1)
+    ch = rng.integers(0, 4, 24)
+    pa = rng.integers(0, (L // P) ** 2, 24)
+    loss, g = ctx.nn_grad(ch, pa)
+    ex = []
+    for c, p in zip(ch, pa):
+        links, _ = ctx.get_state(int(c))
+        ex.append((nn.window(links, L, P, int(p)), links[nn.patch_links(L, P, int(p))].astype(float)))
+    lref, gref = nn.loss_and_grad(params, ex)
+    assert abs(loss - lref) < 1e-4 * abs(lref)
+    assert np.linalg.norm(g - gref) < 1e-3 * np.linalg.norm(gref)
+    big = np.abs(gref) > 1e-2 * np.abs(gref).max()
+    assert np.abs(g[big] - gref[big]).max() < 1e-3 * np.abs(gref).max()
+
+
+def test_adam_step_matches_closed_form():
+    L, P = 8, 4
+    ctx = gpu_context([spec_for(L)], [L] * 2, init=1)
+    ctx.nn_init(P, 9)
+    p0 = ctx.nn_params()
+    ctx.nn_train(1, 16, 1e-2, 77)
+    p1 = ctx.nn_params()
+    # first Adam step moves a parameter by lr * g / (|g| + eps): never more than lr,
+    # and lr to within 1e-4 relative wherever |g| >> eps
+    d = np.abs(p0 - p1).astype(np.float64)
+    assert d.max() <= 1e-2 * (1 + 1e-5)
+    assert np.mean(np.abs(d - 1e-2) < 1e-6) > 0.9
+
+
+@pytest.mark.parametrize("L,P,K,mix,bias,init", [
+    (8, 4, 1, False, -1.5, 0),    # about 6 of 32 links proposed to change: ranks up to ~40
+    (8, 4, 2, True, -3.0, 0),
+    (4, 2, 1, True, 0.0, 1),
+    (8, 2, 1, False, -0.5, 1),
+])
+def test_block_moves_bit_exact(L, P, K, mix, bias, init):
+    say(f"block moves L={L} P={P} K={K} mix={mix} bias={bias}")
+    spec = synth.make_tensor(2, K=K)
+    ctx = gpu_context([spec], [L] * 2, init=init)
+    ctx.nn_init(P, 21)
+    p = _params(13, 0.02)
+    p[-2:] = bias
+    params = ctx.nn_params(p)
+    orc = [oracle_chain(spec, L, c, init=init)[1] for c in range(2)]
+    for s in range(4):
+        if mix and s % 2 == 1:
+            ctx.sweep(1)
+            for oc in orc:
+                oc.sweep()
+        else:
+            ctx.block_sweep(1)
+            for oc in orc:
+                block_sweep(oc, params, P)
+        for c, oc in enumerate(orc):
+            links, info = ctx.get_state(c)
+            assert np.array_equal(links, oc.k), (s, c)
+            assert info["sweeps"] == oc.sweep_idx
+    an = ansatz_for(spec, L)
+    for c, oc in enumerate(orc):
+        links, info = ctx.get_state(c)
+        assert abs(info["logw"] - an.log_weight(links)) < 1e-9 * abs(info["logw"])
+        G = ctx.get_inverse(c)
+        Gt = np.linalg.inv(an.assemble_M(links))
+        assert np.abs(G - Gt).max() < 1e-9 * np.abs(Gt).max()
+        if K > 1:
+            assert abs(info["s_re"] - an.s_factor_def(links).real) < 1e-8 * abs(info["s_re"])
+    props = sum(ctx.block_stats(c)[0] for c in range(2))
+    accs = sum(ctx.block_stats(c)[1] for c in range(2))
+    assert props > 0 and accs > 0
+
+
+def test_training_learns_the_conditional_and_moves_blocks():
+    """Online training on samples the plain sampler generates lowers the cross-entropy of the
+    patch conditional; the trained network's block moves are accepted and change several links
+    per accepted rank-4m update (one pass over G for m links, where single-link moves need m)."""
+    say("training L=8 P=2")
+    L, P, nc = 8, 2, 64
+    ctx = gpu_context([spec_for(L)], [L] * nc, init=1)
+    ctx.sweep(5)
+    ctx.nn_init(P, 3)
+
+    def block_rates():
+        p0 = np.array([ctx.block_stats(c) for c in range(nc)])
+        ctx.block_sweep(2)
+        d = np.array([ctx.block_stats(c) for c in range(nc)]) - p0
+        return d[:, 1].sum() / max(1, d[:, 0].sum()), d[:, 2].sum() / max(1, d[:, 1].sum())
+
+    acc0, links0 = block_rates()
+    loss0 = ctx.nn_grad(list(range(nc)), [0] * nc)[0]
+    for _ in range(6):
+        ctx.sweep(2)
+        ctx.nn_train(40, 256, 3e-3, 99)
+    loss1 = ctx.nn_grad(list(range(nc)), [0] * nc)[0]
+    acc1, links1 = block_rates()
+    say(f"cross-entropy {loss0:.3f} -> {loss1:.3f} nats/patch; block acceptance untrained {acc0:.3f} "
+        f"({links0:.2f} links/accept), trained {acc1:.3f} ({links1:.2f} links/accept)")
+    assert loss1 < 0.8 * loss0
+    assert acc1 > 0.05 and links1 > 1.5
