@@ -92,7 +92,7 @@ ggf_status ggf_create(ggf_ctx **out, int device);
  * ggf_init_chains.  May be called several times (one id per ansatz). */
 ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *desc, int32_t *tensor_id_out);
 
-/* Allocate and start n_chains chains.  L[c] (even, 2..64) and tensor_id[c]
+/* Allocate and start n_chains chains.  L[c] (even, 2..32, so n = 8 L^2 <= 8192) and tensor_id[c]
  * are per chain (host arrays).  seed keys the Philox4x32-10 stream of every
  * chain: key = (seed lo, seed hi), counter = (chain, sweep, link, 0).
  * init: 0 = cold (all k = 0), 1 = hot (k = x0 mod N from counter
@@ -151,7 +151,8 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *   "update_tiles" row tiles per chain in the rank-4 update
  *   "update_nt"    1 (default) = non-temporal loads/stores of G in the rank-4 update, 0 = cached
  *   "graph"        1 = replay each sweep as a captured hipGraph, 0 = direct launches
- *   "gj_nb"        panel width of the Gauss-Jordan refactorisation (8..64)
+ *   "gj_nb"        column-block width of the Gauss-Jordan refactorisation (8..256, rounded up to a
+ *                  power of 2; 0 = 128 for n >= 1024, else 64)
  *   "scratch_mb"   float64 scratch budget for refactorisations, MiB */
 ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
 

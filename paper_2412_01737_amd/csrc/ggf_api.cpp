@@ -49,12 +49,14 @@ struct ggf_ctx {
   int *flags = nullptr, *acc_list = nullptr, *acc_cnt = nullptr;
   double *scratch = nullptr;
   size_t scratch_elems = 0;
+  double *ybuf = nullptr;        // pivot-row snapshots of the Gauss-Jordan update
+  size_t ybuf_elems = 0;
   int *piv = nullptr, *perm = nullptr, *list_dev = nullptr;
   size_t piv_stride = 0;
   std::vector<void *> allocs;
 
   // options
-  int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 32, opt_time_update = 0, opt_update_nt = 1;
+  int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 0, opt_time_update = 0, opt_update_nt = 1;
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -189,6 +191,9 @@ void free_chains(ggf_ctx *ctx) {
   ctx->chains.clear();
   ctx->G = ctx->F = nullptr;
   ctx->scratch = nullptr;
+  if (ctx->ybuf) hipFree(ctx->ybuf);
+  ctx->ybuf = nullptr;
+  ctx->ybuf_elems = 0;
 }
 
 LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
@@ -219,12 +224,11 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   return lc;
 }
 
-int gj_nb(const ggf_ctx *ctx) {
-  int nb = ctx->opt_gj_nb;
-  if (nb <= 8) return 8;
-  if (nb <= 16) return 16;
-  if (nb <= 32) return 32;
-  return 64;
+int gj_nb(const ggf_ctx *ctx, int n_max) {
+  const int want = ctx->opt_gj_nb > 0 ? ctx->opt_gj_nb : (n_max >= 1024 ? 128 : 64);
+  int nb = 8;
+  while (nb < want && nb < 256) nb *= 2;   // power of two, 8..256
+  return nb;
 }
 
 // Refactorise the listed chains from their link fields (float64 scratch, in chunks
@@ -232,10 +236,12 @@ int gj_nb(const ggf_ctx *ctx) {
 ggf_status factorize(ggf_ctx *ctx, const std::vector<int> &which, int is_refresh, hipStream_t s) {
   if (which.empty()) return GGF_OK;
   size_t pos = 0;
-  const int nb = gj_nb(ctx);
+  int all_nmax = 0;
+  for (int c : which) all_nmax = std::max(all_nmax, ctx->chains[c].n);
+  const int nb = gj_nb(ctx, all_nmax);
   while (pos < which.size()) {
     std::vector<int> chunk;
-    size_t used = 0;
+    size_t used = 0, yused = 0;
     int nmax = 0;
     while (pos < which.size()) {
       const int c = which[pos];
@@ -243,6 +249,8 @@ ggf_status factorize(ggf_ctx *ctx, const std::vector<int> &which, int is_refresh
       if (!chunk.empty() && used + need > ctx->scratch_elems) break;
       ctx->chains[c].scr_off = used;
       used += (need + 63) & ~static_cast<size_t>(63);
+      ctx->chains[c].y_off = yused;
+      yused += static_cast<size_t>(nb) * ctx->chains[c].n;
       nmax = std::max(nmax, ctx->chains[c].n);
       chunk.push_back(c);
       ++pos;
@@ -253,7 +261,14 @@ ggf_status factorize(ggf_ctx *ctx, const std::vector<int> &which, int is_refresh
     const LaunchCtx lc = launch_ctx(ctx, s);
     const int cnt = static_cast<int>(chunk.size());
     ggf_launch_assemble(lc, ctx->list_dev, cnt, nmax / 8);
-    ggf_launch_gj(lc, ctx->list_dev, cnt, nmax, nb, ctx->piv, ctx->perm, ctx->piv_stride);
+    if (yused > ctx->ybuf_elems) {
+      if (ctx->ybuf) hipFree(ctx->ybuf);
+      ctx->ybuf = nullptr;
+      ctx->ybuf_elems = 0;
+      HIP_TRY(ctx, hipMalloc(&ctx->ybuf, yused * sizeof(double)));
+      ctx->ybuf_elems = yused;
+    }
+    ggf_launch_gj(lc, ctx->list_dev, cnt, nmax, nb, ctx->piv, ctx->perm, ctx->piv_stride, ctx->ybuf);
     ggf_launch_store(lc, ctx->list_dev, cnt, nmax, ctx->perm, ctx->piv_stride);
     ggf_launch_post(lc, ctx->list_dev, cnt, is_refresh);
     ggf_launch_sfac(lc, ctx->list_dev, cnt, ctx->kmax);
@@ -491,7 +506,7 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
   size_t max_need = 0, tot_need = 0;
   for (int c = 0; c < n_chains; ++c) {
     const int l = L[c];
-    if (l < 2 || l > 64 || (l & 1)) return fail(ctx, GGF_EINVAL, "L must be even and in 2..64");
+    if (l < 2 || l > 32 || (l & 1)) return fail(ctx, GGF_EINVAL, "L must be even and in 2..32");
     const int tid = tensor_id[c];
     if (tid < 0 || tid >= static_cast<int>(ctx->tensors.size())) return fail(ctx, GGF_EINVAL, "bad tensor id");
     const TensorDev &t = ctx->tensors[tid];
@@ -767,8 +782,8 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
     ctx->opt_graph = value != 0;
     if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   } else if (k == "gj_nb") {
-    if (value != 0 && (value < 8 || value > 64)) return fail(ctx, GGF_EINVAL, "gj_nb must be in 8..64");
-    ctx->opt_gj_nb = value ? static_cast<int>(value) : 32;
+    if (value != 0 && (value < 8 || value > 256)) return fail(ctx, GGF_EINVAL, "gj_nb must be in 8..256");
+    ctx->opt_gj_nb = static_cast<int>(value);
   } else if (k == "scratch_mb") ctx->opt_scratch_mb = value;
   else if (k == "time_update") ctx->opt_time_update = value != 0;
   else if (k == "update_nt") ctx->opt_update_nt = value != 0;

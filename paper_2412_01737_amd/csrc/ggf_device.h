@@ -4,7 +4,7 @@
 //   * G arena: every chain's inverse G = M(G)^-1, n x n row-major, float64 or
 //     float32, chain c at element offset ChainDev::g_off (256-byte aligned).
 //   * factor arena: per chain 8 n elements (same type as G): PT[4][n] = -G[U,:]
-//     and QT[4][n] = (P K)^T of the last accepted flip, consumed by the
+//     and QT[4][n] = (G[:,U] K)^T of the last accepted flip, consumed by the
 //     streaming update kernel.
 //   * link arena: int8 link values, chain c at ChainDev::link_off.
 //   * per-chain scalars (SoA): log W, S = N/W (complex), sweep counter,
@@ -40,6 +40,7 @@ struct ChainDev {
   size_t f_off;     // element offset of the factor buffer (8 n elements)
   size_t link_off;  // byte offset of the link values
   size_t scr_off;   // element offset in the float64 refactorisation scratch (set per batch)
+  size_t y_off;     // element offset of the pivot-row snapshot of the Gauss-Jordan update (set per batch)
 };
 
 // Status flag bits per chain.

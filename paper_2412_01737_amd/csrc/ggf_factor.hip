@@ -6,13 +6,17 @@
 // the bonds): per site the 8x8 virtual block d, per link the 2x2 out-in block
 // R(theta_link) x0 and its negative transpose.  log W = (1/2) log|det M| - 4V ln 2.
 //
-// Gauss-Jordan, panel width nb: the panel kernel runs the unblocked in-place
-// elimination on the n x nb panel (pivot rows recorded, the eliminated column
-// replaced by the corresponding column of the partial inverse); the update
-// kernel applies the panel's row swaps to every other column, then
-//   x <- (x with the nb pivot rows zeroed) + Z x[pivot rows],
-// Z the n x nb panel -- a rank-nb update, so all work is GEMM-shaped.  The
-// final column un-permutation is folded into the store of G.
+// Gauss-Jordan in column blocks of width nb.  Each block panel is factored
+// recursively: its left half, the left half's transform applied to the right
+// half, the right half, the right half's transform applied to the left half,
+// down to base panels of 8 columns held in registers (pivot rows recorded, each
+// eliminated column replaced by the corresponding column of the partial
+// inverse).  A panel's transform on any other columns is its row swaps
+// followed by  x <- (x with the pivot rows zeroed) + Z x[pivot rows],  Z the
+// panel columns -- a rank-w update done as a register-blocked float64 GEMM.
+// The final column un-permutation is folded into the store of G.
+#include <algorithm>
+
 #include "ggf_device.h"
 #include "ggf_launch.h"
 
@@ -69,89 +73,128 @@ __global__ __launch_bounds__(256) void k_assemble(const int *__restrict__ list, 
   }
 }
 
-// Unblocked Gauss-Jordan on the panel columns [j, j+nbe) of one chain per workgroup.
-__global__ __launch_bounds__(256) void k_gj_panel(const int *__restrict__ list, int count,
-                                                  const ChainDev *__restrict__ chains,
-                                                  double *__restrict__ scr, int *__restrict__ piv,
-                                                  size_t piv_stride, double *__restrict__ ldet,
-                                                  int *__restrict__ flags, int j, int nb) {
+// Base panel of the recursive factorisation: unblocked Gauss-Jordan on at most
+// BW columns [j, j+w) of one chain, the panel held in registers (thread t owns
+// rows t, t + T, ..., at most RPT of them).  Per column: block argmax of |A[r][k]|
+// over rows r >= k (wave shuffles, then LDS), swap of rows k and p through LDS,
+// scaling of the pivot row (its pivot entry replaced by 1/pv), elimination of the
+// other rows (their entry in column k replaced by -f/pv).
+template <int RPT, int BW>
+__global__ __launch_bounds__(1024) void k_gj_base(const int *__restrict__ list, int count,
+                                                  const ChainDev *__restrict__ chains, double *__restrict__ scr,
+                                                  int *__restrict__ piv, size_t piv_stride, double *__restrict__ ldet,
+                                                  int *__restrict__ flags, int j, int w) {
   const int b = blockIdx.x;
   if (b >= count) return;
   const int c = list[b];
   const ChainDev ch = chains[c];
   const int n = ch.n;
   if (j >= n) return;
-  const int nbe = min(nb, n - j);
+  const int we = min(w, n - j);
+  const int T = blockDim.x;
   double *A = scr + ch.scr_off;
   int *pv_rows = piv + static_cast<size_t>(b) * piv_stride;
-  __shared__ double s_best[256];
-  __shared__ int s_idx[256];
-  __shared__ double s_rowk[64];
-  __shared__ double s_pv;
+  __shared__ double s_rk[BW], s_rp[BW], s_bv[16];
+  __shared__ int s_bi[16];
   __shared__ int s_p;
+  __shared__ double s_pv;
+  double v[RPT][BW];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = threadIdx.x + q * T;
+#pragma unroll
+    for (int t = 0; t < BW; ++t) v[q][t] = (r < n && t < we) ? A[static_cast<size_t>(r) * n + j + t] : 0.0;
+  }
   double acc_ldet = (j == 0) ? 0.0 : ldet[c];
   bool singular = false;
-  for (int kk = 0; kk < nbe; ++kk) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = T >> 6;
+#pragma unroll
+  for (int kk = 0; kk < BW; ++kk) {
+    if (kk >= we) break;
     const int k = j + kk;
-    // pivot search over rows >= k in column k
     double best = -1.0;
     int bi = n;
-    for (int r = k + threadIdx.x; r < n; r += blockDim.x) {
-      const double v = fabs(A[static_cast<size_t>(r) * n + k]);
-      if (v > best) { best = v; bi = r; }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = threadIdx.x + q * T;
+      const double a = fabs(v[q][kk]);
+      if (r >= k && r < n && (a > best || (a == best && r < bi))) { best = a; bi = r; }
     }
-    s_best[threadIdx.x] = best;
-    s_idx[threadIdx.x] = bi;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { s_bv[wv] = best; s_bi[wv] = bi; }
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) {
-        const double ob = s_best[threadIdx.x + off];
-        const int oi = s_idx[threadIdx.x + off];
-        if (ob > s_best[threadIdx.x] || (ob == s_best[threadIdx.x] && oi < s_idx[threadIdx.x])) {
-          s_best[threadIdx.x] = ob;
-          s_idx[threadIdx.x] = oi;
-        }
+    if (threadIdx.x == 0) {
+      double bb = s_bv[0];
+      int ii = s_bi[0];
+      for (int q = 1; q < nw; ++q)
+        if (s_bv[q] > bb || (s_bv[q] == bb && s_bi[q] < ii)) { bb = s_bv[q]; ii = s_bi[q]; }
+      s_p = (ii < n && bb > 0.0) ? ii : k;    // no finite nonzero pivot: keep order, flag below
+      pv_rows[k] = s_p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != k) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = threadIdx.x + q * T;
+        if (r == k)
+          for (int t = 0; t < BW; ++t) s_rk[t] = v[q][t];
+        if (r == p)
+          for (int t = 0; t < BW; ++t) s_rp[t] = v[q][t];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = threadIdx.x + q * T;
+        if (r == k)
+          for (int t = 0; t < BW; ++t) v[q][t] = s_rp[t];
+        if (r == p)
+          for (int t = 0; t < BW; ++t) v[q][t] = s_rk[t];
       }
       __syncthreads();
     }
-    // no finite nonzero candidate: keep the row order (in-range pivot), flag singular
-    const int p = (s_idx[0] < n && s_best[0] > 0.0) ? s_idx[0] : k;
-    if (threadIdx.x == 0) pv_rows[k] = p;
-    if (p != k && threadIdx.x < nbe) {
-      double *rk = A + static_cast<size_t>(k) * n + j;
-      double *rp = A + static_cast<size_t>(p) * n + j;
-      const double t = rk[threadIdx.x];
-      rk[threadIdx.x] = rp[threadIdx.x];
-      rp[threadIdx.x] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_pv = A[static_cast<size_t>(k) * n + k];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (threadIdx.x + q * T == k) s_pv = v[q][kk];
     __syncthreads();
     const double pv = s_pv;
-    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {   // singular column: skip it, indices stay valid
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
       singular = true;
       __syncthreads();
       continue;
     }
     acc_ldet += log(fabs(pv));
-    if (threadIdx.x < nbe) {
-      double *rk = A + static_cast<size_t>(k) * n + j;
-      const double v = (threadIdx.x == kk) ? 1.0 / pv : rk[threadIdx.x] / pv;
-      rk[threadIdx.x] = v;
-      s_rowk[threadIdx.x] = v;
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-      if (r == k) continue;
-      double *ar = A + static_cast<size_t>(r) * n + j;
-      const double f = ar[kk];
-      if (f == 0.0) continue;
-      for (int t = 0; t < nbe; ++t) {
-        const double old = (t == kk) ? 0.0 : ar[t];
-        ar[t] = old - f * s_rowk[t];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (threadIdx.x + q * T == k) {
+#pragma unroll
+        for (int t = 0; t < BW; ++t) {
+          v[q][t] = (t == kk ? 1.0 : v[q][t]) / pv;
+          s_rk[t] = v[q][t];
+        }
       }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = threadIdx.x + q * T;
+      if (r == k || r >= n) continue;
+      const double f = v[q][kk];
+#pragma unroll
+      for (int t = 0; t < BW; ++t) v[q][t] = (t == kk ? 0.0 : v[q][t]) - f * s_rk[t];
     }
     __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = threadIdx.x + q * T;
+    if (r < n)
+#pragma unroll
+      for (int t = 0; t < BW; ++t)
+        if (t < we) A[static_cast<size_t>(r) * n + j + t] = v[q][t];
   }
   if (threadIdx.x == 0) {
     ldet[c] = acc_ldet;
@@ -159,52 +202,128 @@ __global__ __launch_bounds__(256) void k_gj_panel(const int *__restrict__ list, 
   }
 }
 
-// Rank-nb update of all columns outside the panel, 64 columns per workgroup.
-template <int NB>
-__global__ __launch_bounds__(256) void k_gj_update(const int *__restrict__ list, int count,
-                                                   const ChainDev *__restrict__ chains,
-                                                   double *__restrict__ scr,
-                                                   const int *__restrict__ piv, size_t piv_stride,
-                                                   int j, int nb) {
+// Apply the panel's row swaps to every column outside the panel (each column
+// independently, swaps in order) and snapshot the nb pivot rows into Y, so the
+// update can overwrite them while other tiles still read them.
+__global__ __launch_bounds__(256) void k_gj_swapcopy(const int *__restrict__ list, int count,
+                                                     const ChainDev *__restrict__ chains, double *__restrict__ scr,
+                                                     const int *__restrict__ piv, size_t piv_stride,
+                                                     double *__restrict__ ybuf, int pj, int pw, int c_lo, int c_hi) {
   const int b = blockIdx.y;
   if (b >= count) return;
   const ChainDev ch = chains[list[b]];
   const int n = ch.n;
-  if (j >= n) return;
-  const int c0 = blockIdx.x * 64;
-  if (c0 >= n) return;
-  const int nbe = min(nb, n - j);
+  if (pj >= n) return;
+  const int col = c_lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= min(c_hi, n)) return;
+  const int pwe = min(pw, n - pj);
+  if (col >= pj && col < pj + pwe) return;     // the panel's own columns
   double *A = scr + ch.scr_off;
   const int *pr = piv + static_cast<size_t>(b) * piv_stride;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int col = c0 + lane;
-  const bool active = col < n && !(col >= j && col < j + nbe);
-  if (wave == 0 && active) {
-    for (int t = 0; t < nbe; ++t) {
-      const int r2 = pr[j + t];
-      if (r2 != j + t) {
-        double *x1 = A + static_cast<size_t>(j + t) * n + col;
-        double *x2 = A + static_cast<size_t>(r2) * n + col;
-        const double tmp = *x1;
-        *x1 = *x2;
-        *x2 = tmp;
-      }
+  double *Y = ybuf + ch.y_off;
+  for (int t = 0; t < pwe; ++t) {
+    const int r2 = pr[pj + t];
+    if (r2 != pj + t) {
+      double *x1 = A + static_cast<size_t>(pj + t) * n + col;
+      double *x2 = A + static_cast<size_t>(r2) * n + col;
+      const double tmp = *x1;
+      *x1 = *x2;
+      *x2 = tmp;
     }
   }
-  __syncthreads();
-  double y[NB];
+  for (int t = 0; t < pwe; ++t) Y[static_cast<size_t>(t) * n + col] = A[static_cast<size_t>(pj + t) * n + col];
+}
+
+// Rank-w update X <- (X with the pivot rows zeroed) + Z Y on columns [c_lo, c_hi)
+// outside the panel, as a register-blocked float64 GEMM: a workgroup owns a
+// 128 x 128 tile, each thread an 8 x 8 block (rows ty + 16 a, columns tx + 16 c),
+// the accumulators start from X, and K is staged through LDS in chunks of 16
+// with the next chunk's global loads in flight during the current chunk's FMAs.
+// Z = the panel columns (final), Y = the snapshot of the pivot rows.
+constexpr int kGT = 128, kGK = 16;
+__global__ __launch_bounds__(256) void k_gj_gemm(const int *__restrict__ list, int count,
+                                                 const ChainDev *__restrict__ chains, double *__restrict__ scr,
+                                                 const double *__restrict__ ybuf, int pj, int pw, int c_lo, int c_hi) {
+  const int b = blockIdx.z;
+  if (b >= count) return;
+  const ChainDev ch = chains[list[b]];
+  const int n = ch.n;
+  if (pj >= n) return;
+  const int hi = min(c_hi, n);
+  const int r0 = blockIdx.y * kGT, c0 = c_lo + blockIdx.x * kGT;
+  if (r0 >= n || c0 >= hi) return;
+  const int pwe = min(pw, n - pj);
+  if (c0 >= pj && c0 + kGT <= pj + pwe) return;     // tile entirely inside the panel
+  double *A = scr + ch.scr_off;
+  const double *Y = ybuf + ch.y_off;
+  __shared__ double sZ[kGK][kGT + 1];
+  __shared__ double sY[kGK][kGT + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[8][8];
 #pragma unroll
-  for (int t = 0; t < NB; ++t) y[t] = (active && t < nbe) ? A[static_cast<size_t>(j + t) * n + col] : 0.0;
-  __syncthreads();
-  if (!active) return;
-  for (int r = wave; r < n; r += 4) {
-    const double *z = A + static_cast<size_t>(r) * n + j;   // panel row r (uniform per wave)
-    double x = (r >= j && r < j + nbe) ? 0.0 : A[static_cast<size_t>(r) * n + col];
+  for (int a = 0; a < 8; ++a) {
+    const int r = r0 + ty + 16 * a;
+    const bool blockrow = r >= pj && r < pj + pwe;
 #pragma unroll
-    for (int t = 0; t < NB; ++t)
-      if (t < nbe) x = fma(z[t], y[t], x);
-    A[static_cast<size_t>(r) * n + col] = x;
+    for (int c = 0; c < 8; ++c) {
+      const int col = c0 + tx + 16 * c;
+      const bool ok = r < n && col < hi && !(col >= pj && col < pj + pwe) && !blockrow;
+      acc[a][c] = ok ? A[static_cast<size_t>(r) * n + col] : 0.0;
+    }
+  }
+  // staging map: Z chunk by (row q = t/2, k half kh = 8 (t&1)), Y chunk by (k = t/16 .. , col)
+  const int zq = threadIdx.x >> 1, zk = (threadIdx.x & 1) * 8;
+  double zreg[8], yreg[8];
+  auto load_chunk = [&](int k0) {
+    const int rr = r0 + zq;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int kk = zk + i;
+      zreg[i] = (k0 + kk < pwe && rr < n) ? A[static_cast<size_t>(rr) * n + pj + k0 + kk] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int t = threadIdx.x + 256 * i;
+      const int kk = t / kGT, q = t - kk * kGT;
+      const int cc = c0 + q;
+      yreg[i] = (k0 + kk < pwe && cc < hi) ? Y[static_cast<size_t>(k0 + kk) * n + cc] : 0.0;
+    }
+  };
+  load_chunk(0);
+  for (int k0 = 0; k0 < pwe; k0 += kGK) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sZ[zk + i][zq] = zreg[i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int t = threadIdx.x + 256 * i;
+      sY[t / kGT][t % kGT] = yreg[i];
+    }
+    __syncthreads();
+    if (k0 + kGK < pwe) load_chunk(k0 + kGK);
+#pragma unroll
+    for (int kk = 0; kk < kGK; ++kk) {
+      double zr[8], yc[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) zr[a] = sZ[kk][ty + 16 * a];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) yc[c] = sY[kk][tx + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[a][c] = fma(zr[a], yc[c], acc[a][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int r = r0 + ty + 16 * a;
+    if (r >= n) continue;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int col = c0 + tx + 16 * c;
+      if (col >= hi || (col >= pj && col < pj + pwe)) continue;
+      A[static_cast<size_t>(r) * n + col] = acc[a][c];
+    }
   }
 }
 
@@ -272,21 +391,58 @@ void ggf_launch_assemble(const LaunchCtx &lc, const int *list, int count, int ma
                      lc.links, lc.scratch);
 }
 
-void ggf_launch_gj(const LaunchCtx &lc, const int *list, int count, int n_max, int nb, int *piv,
-                   int *perm, size_t piv_stride) {
-  for (int j = 0; j < n_max; j += nb) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(count), dim3(256), 0, lc.stream, list, count, lc.chains,
-                       lc.scratch, piv, piv_stride, lc.ldet, lc.flags, j, nb);
-    dim3 grid((n_max + 63) / 64, count);
-    if (nb <= 16)
-      hipLaunchKernelGGL(k_gj_update<16>, grid, dim3(256), 0, lc.stream, list, count, lc.chains,
-                         lc.scratch, piv, piv_stride, j, nb);
-    else if (nb <= 32)
-      hipLaunchKernelGGL(k_gj_update<32>, grid, dim3(256), 0, lc.stream, list, count, lc.chains,
-                         lc.scratch, piv, piv_stride, j, nb);
+namespace {
+
+struct GJRun {
+  const LaunchCtx &lc;
+  const int *list;
+  int count, n_max;
+  int *piv;
+  size_t piv_stride;
+  double *ybuf;
+};
+
+// Apply the transform of panel [pj, pj+pw) (its row swaps, then the rank-pw update) to columns [c_lo, c_hi).
+void gj_apply(const GJRun &g, int pj, int pw, int c_lo, int c_hi) {
+  const int width = c_hi - c_lo;
+  hipLaunchKernelGGL(k_gj_swapcopy, dim3((width + 255) / 256, g.count), dim3(256), 0, g.lc.stream, g.list, g.count,
+                     g.lc.chains, g.lc.scratch, g.piv, g.piv_stride, g.ybuf, pj, pw, c_lo, c_hi);
+  dim3 grid((width + kGT - 1) / kGT, (g.n_max + kGT - 1) / kGT, g.count);
+  hipLaunchKernelGGL(k_gj_gemm, grid, dim3(256), 0, g.lc.stream, g.list, g.count, g.lc.chains, g.lc.scratch, g.ybuf,
+                     pj, pw, c_lo, c_hi);
+}
+
+// Factor the panel columns [j, j+w): recursively, left half, its transform on the right half,
+// right half, its transform on the left half; base panels of 8 columns held in registers.
+void gj_panel(const GJRun &g, int j, int w) {
+  // base panels in registers: <= 4 rows x 8 columns per thread up to n = 4096, 8 x 4 above
+  const int T = g.n_max <= 1024 ? 256 : 1024;
+  const int bw = g.n_max <= 4096 ? 8 : 4;
+  if (w <= bw) {
+    if (g.n_max <= 4096)
+      hipLaunchKernelGGL((k_gj_base<4, 8>), dim3(g.count), dim3(T), 0, g.lc.stream, g.list, g.count, g.lc.chains,
+                         g.lc.scratch, g.piv, g.piv_stride, g.lc.ldet, g.lc.flags, j, w);
     else
-      hipLaunchKernelGGL(k_gj_update<64>, grid, dim3(256), 0, lc.stream, list, count, lc.chains,
-                         lc.scratch, piv, piv_stride, j, nb);
+      hipLaunchKernelGGL((k_gj_base<8, 4>), dim3(g.count), dim3(T), 0, g.lc.stream, g.list, g.count, g.lc.chains,
+                         g.lc.scratch, g.piv, g.piv_stride, g.lc.ldet, g.lc.flags, j, w);
+    return;
+  }
+  const int h = w / 2;
+  gj_panel(g, j, h);
+  gj_apply(g, j, h, j + h, j + w);
+  gj_panel(g, j + h, w - h);
+  gj_apply(g, j + h, w - h, j, j + h);
+}
+
+}  // namespace
+
+void ggf_launch_gj(const LaunchCtx &lc, const int *list, int count, int n_max, int nb, int *piv,
+                   int *perm, size_t piv_stride, double *ybuf) {
+  const GJRun g{lc, list, count, n_max, piv, piv_stride, ybuf};
+  for (int j = 0; j < n_max; j += nb) {
+    const int w = std::min(nb, n_max - j);
+    gj_panel(g, j, w);
+    gj_apply(g, j, w, 0, n_max);
   }
   hipLaunchKernelGGL(k_gj_perm, dim3(count), dim3(64), 0, lc.stream, list, count, lc.chains, piv,
                      piv_stride, perm);

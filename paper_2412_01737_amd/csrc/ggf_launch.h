@@ -34,7 +34,7 @@ struct LaunchCtx {
 
 void ggf_launch_assemble(const LaunchCtx &lc, const int *list, int count, int max_sites);
 void ggf_launch_gj(const LaunchCtx &lc, const int *list, int count, int n_max, int nb, int *piv,
-                   int *perm, size_t piv_stride);
+                   int *perm, size_t piv_stride, double *ybuf);
 void ggf_launch_store(const LaunchCtx &lc, const int *list, int count, int n_max, const int *perm,
                       size_t piv_stride);
 void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_refresh);

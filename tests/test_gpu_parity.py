@@ -198,7 +198,7 @@ def test_invalid_inputs_rejected():
     with pytest.raises(GGFError):
         ctx.set_tensor(5, spec.gamma_loc, spec.gamma_bond)
     tid = ctx.set_tensor_spec(spec)
-    for L in (3, 0, 66):
+    for L in (3, 0, 34):
         with pytest.raises(GGFError):
             ctx.init_chains([L], [tid], 1)
     with pytest.raises(GGFError):
