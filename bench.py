@@ -33,14 +33,20 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--chains", type=int, default=4096)
-    ap.add_argument("--L", type=int, default=8)
-    ap.add_argument("--K", type=int, default=1)
-    ap.add_argument("--group", type=int, default=2)
-    ap.add_argument("--precision", type=int, default=64)
-    ap.add_argument("--refresh", type=int, default=1024)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2: 8x8 Z2 K=1 4096 chains float64 (default, the headline workload); "
+                         "c3: 16x16 Z2 K=3 2048 chains float32 + float64 refresh; "
+                         "c4: 8192 chains, L in {6,8,12,16,20}, K in {1,2,4}, Z2/Z3, float32 + refresh, "
+                         "graph-replayed autotuned sweeps")
+    ap.add_argument("--autotune", type=int, default=0, help="sweeps per autotuner candidate (0 = off)")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--chains", type=int, default=None)
+    ap.add_argument("--L", type=int, default=None)
+    ap.add_argument("--K", type=int, default=None)
+    ap.add_argument("--group", type=int, default=None)
+    ap.add_argument("--precision", type=int, default=None)
+    ap.add_argument("--refresh", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
@@ -55,7 +61,16 @@ def parse():
                     help="derive the update kernel's HBM bytes per launch from rocprofv3 --pmc CSVs, "
                          "write --traffic-json and exit (no GPU needed)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30, help="size of the calibration copy (--traffic-from)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    presets = {
+        "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=1024),
+        "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64),
+        "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64),
+    }
+    for k, v in presets[args.workload].items():
+        if getattr(args, k) is None:
+            setattr(args, k, v)
+    return args
 
 
 def traffic_from(args):
@@ -192,21 +207,37 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     L, K, group = args.L, args.K, args.group
-    n = 8 * L * L
-    spec = synth.make_tensor(L, K=K, group=group)
     ctx = Context(0)
-    tid = ctx.set_tensor_spec(spec)
+    if args.workload == "c4":
+        Ls, Ks, groups = synth.mixed_batch(args.chains)
+        ids = {}
+        for kk in synth.MIX_K:
+            for gg in synth.MIX_GROUP:
+                # patch links drawn on the smallest lattice exist on every lattice of the batch
+                ids[(kk, gg)] = ctx.set_tensor_spec(synth.make_tensor(min(synth.MIX_L), K=int(kk), group=int(gg)))
+        Lc = Ls
+        tids = np.array([ids[(int(k), int(g))] for k, g in zip(Ks, groups)], np.int32)
+    else:
+        Lc = np.full(args.chains, L, np.int32)
+        tids = ctx.set_tensor_spec(synth.make_tensor(L, K=K, group=group))
+    n_c = 8 * Lc.astype(np.int64) ** 2
+    n = int(n_c.max())
     t_init = time.perf_counter()
-    ctx.init_chains([L] * args.chains, tid, synth.SEED_CHAIN, init=1, precision=args.precision,
+    ctx.init_chains(Lc, tids, synth.SEED_CHAIN, init=1, precision=args.precision,
                     refresh_every=args.refresh, stream=stream)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
+    tuned = None
+    if args.autotune:
+        tuned = ctx.autotune(args.autotune, os.path.join(HERE, "paper_2412_01737_amd", "autotune_cache.txt"),
+                             stream=stream)
     if args.update_grid:
         ctx.set_option("update_grid", args.update_grid)
     if args.update_tiles:
         ctx.set_option("update_tiles", args.update_tiles)
     ctx.set_option("graph", args.graph)
-    ctx.set_option("update_nt", args.update_nt)
+    if not args.autotune:
+        ctx.set_option("update_nt", args.update_nt)
     mask = OBS_LINK | OBS_DENSITY
     obs = torch.zeros((args.warmup + args.steps, args.chains, GGF_NOBS), dtype=torch.float64, device=dev)
     for w in range(args.warmup):
@@ -225,7 +256,7 @@ def main():
         ctx.measure(mask, obs[args.warmup + s], stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    proposals = args.chains * 2 * L * L * args.steps
+    proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
     value = proposals / elapsed
     series = obs[args.warmup:, :, 0].cpu().numpy()
     if series.shape[0] >= 2:
@@ -234,7 +265,13 @@ def main():
     else:
         tau = tau_err = ess_per_s = None
     acceptance = upd_flips / proposals
-    bytes_per_flip = 2.0 * n * n * (8 if args.precision == 64 else 4)
+    esz = 8 if args.precision == 64 else 4
+    if args.workload == "c4":
+        # flips per chain are not tracked by the timer: weight each chain's bytes by its accepted flips
+        acc = np.array([ctx.get_state(c)[1]["accepts"] for c in range(args.chains)], np.float64)
+        bytes_per_flip = float((acc * 2.0 * n_c.astype(np.float64) ** 2 * esz).sum() / max(acc.sum(), 1.0))
+    else:
+        bytes_per_flip = 2.0 * n * n * esz
     achieved = (upd_flips * bytes_per_flip / upd_launches) / (upd_ms / upd_launches * 1e-3) / 1e9 if upd_ms > 0 else 0.0
     traffic = None
     try:
@@ -246,7 +283,7 @@ def main():
     except (OSError, ValueError):
         pass
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "c4":
         cpu = cpu_baseline(args, args.cpu_seconds)
     mean_obs = obs[args.warmup:].mean(dim=(0, 1)).cpu().numpy()
     out = {
@@ -262,10 +299,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"Z{group} {L}x{L} periodic, K={K}, {args.chains} chains, single-link Metropolis, "
-                               f"float{args.precision} inverse, float64 refresh every {args.refresh} accepted flips",
-                   "L": L, "K": K, "group": group, "chains": args.chains, "n": n, "precision": args.precision,
-                   "refresh_every": args.refresh, "graph": args.graph},
+        "config": {"workload": (f"Z{group} {L}x{L} periodic, K={K}, {args.chains} chains, single-link Metropolis, "
+                                f"float{args.precision} inverse, float64 refresh every {args.refresh} accepted flips")
+                   if args.workload != "c4" else
+                   (f"{args.chains} chains, L in {{6,8,12,16,20}}, K in {{1,2,4}}, Z2/Z3 (uniform from seed), "
+                    f"single-link Metropolis, float{args.precision} inverse, float64 refresh every {args.refresh} "
+                    f"accepted flips"),
+                   "name": args.workload, "L": L, "K": K, "group": group, "chains": args.chains, "n_max": n,
+                   "precision": args.precision, "refresh_every": args.refresh, "graph": args.graph,
+                   "autotuned": list(tuned) if tuned else None},
         "effective_samples_per_s": ess_per_s,
         "tau_int_plaquette": tau,
         "tau_int_err": tau_err,

@@ -156,6 +156,19 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *   "scratch_mb"   float64 scratch budget for refactorisations, MiB */
 ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
 
+/* Pick the launch shape of the rank-4 update (grid, rows per work item,
+ * non-temporal G access) by timing candidates on live sweeps: each candidate
+ * runs `sweeps_per_candidate` real Metropolis sweeps (they advance the chains,
+ * so call it during burn-in; results do not depend on the launch shape) and
+ * the update time per accepted flip is measured with HIP events.  With
+ * cache_path != NULL the choice is looked up in / appended to that text file,
+ * keyed by (n_max, precision, K_max, n_chains); a cached choice skips the
+ * timing.  The chosen values are left set as the "update_grid",
+ * "update_tiles" and "update_nt" options and returned through best[3]
+ * (may be NULL).  Synchronous. */
+ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *cache_path, int64_t *best,
+                        void *stream);
+
 /* Duration in milliseconds of the rank-4 update kernels of the most recent
  * ggf_sweep call, summed over its launches, measured with HIP events on the
  * stream the kernels run on (0 when timing is off; enable with option

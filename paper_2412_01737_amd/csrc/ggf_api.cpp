@@ -794,6 +794,67 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
   return GGF_OK;
 }
 
+ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *cache_path, int64_t *best,
+                        void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (sweeps_per_candidate < 1) return fail(ctx, GGF_EINVAL, "sweeps_per_candidate must be >= 1");
+  char key[128];
+  std::snprintf(key, sizeof(key), "n%d_p%d_K%d_c%d", ctx->n_max, ctx->precision, ctx->kmax, ctx->n_chains);
+  long long choice[3] = {0, 0, 1};
+  bool found = false;
+  if (cache_path) {
+    if (FILE *f = std::fopen(cache_path, "r")) {
+      char k[128];
+      long long g, t, nt;
+      while (std::fscanf(f, "%127s %lld %lld %lld", k, &g, &t, &nt) == 4)
+        if (std::strcmp(k, key) == 0) { choice[0] = g; choice[1] = t; choice[2] = nt; found = true; }
+      std::fclose(f);
+    }
+  }
+  if (!found) {
+    const int saved_time = ctx->opt_time_update, saved_graph = ctx->opt_graph;
+    ctx->opt_time_update = 1;
+    double best_cost = 1e300;
+    const int grids[3] = {1024, 2048, 4096};
+    const int rows[3] = {8, 16, 32};
+    for (int nt = 1; nt >= 0; --nt)
+      for (int gi = 0; gi < 3; ++gi)
+        for (int ri = 0; ri < 3; ++ri) {
+          ctx->opt_update_grid = grids[gi];
+          ctx->opt_update_tiles = std::max(1, ctx->n_max / rows[ri]);
+          ctx->opt_update_nt = nt;
+          ggf_status st = ggf_sweep(ctx, sweeps_per_candidate, stream);
+          if (st != GGF_OK) return st;
+          if (ctx->last_flips <= 0) continue;
+          const double cost = ctx->last_update_ms / static_cast<double>(ctx->last_flips);
+          if (cost < best_cost) {
+            best_cost = cost;
+            choice[0] = grids[gi];
+            choice[1] = ctx->opt_update_tiles;
+            choice[2] = nt;
+          }
+        }
+    ctx->opt_time_update = saved_time;
+    ctx->opt_graph = saved_graph;
+    if (cache_path && choice[0] > 0) {
+      if (FILE *f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %lld %lld %lld\n", key, choice[0], choice[1], choice[2]);
+        std::fclose(f);
+      }
+    }
+  }
+  if (choice[0] > 0) {
+    ctx->opt_update_grid = static_cast<int>(choice[0]);
+    ctx->opt_update_tiles = static_cast<int>(choice[1]);
+    ctx->opt_update_nt = static_cast<int>(choice[2]);
+    if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
+  }
+  if (best)
+    for (int q = 0; q < 3; ++q) best[q] = choice[q];
+  return GGF_OK;
+}
+
 ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_t *flips) {
   if (!ctx) return GGF_EINVAL;
   if (ms) *ms = ctx->last_update_ms;

@@ -56,6 +56,8 @@ EXPORTS = {
     "ggf_set_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "ggf_refresh_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "ggf_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "ggf_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.c_void_p]),
     "ggf_update_timing": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]),
     "ggf_autocorr_time": (ctypes.c_int, [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _dp, _dp,
@@ -277,6 +279,14 @@ class Context:
         p, a, m = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self._lib.ggf_block_stats(self.h, int(chain), ctypes.byref(p), ctypes.byref(a), ctypes.byref(m)))
         return p.value, a.value, m.value
+
+    def autotune(self, sweeps_per_candidate: int = 1, cache_path: str | None = None, stream=None):
+        """Choose the update launch shape on live sweeps; returns (grid, tiles, non_temporal)."""
+        best = (ctypes.c_int64 * 3)()
+        self._check(self._lib.ggf_autotune(self.h, int(sweeps_per_candidate),
+                                           None if cache_path is None else cache_path.encode(), best,
+                                           _stream_ptr(stream)))
+        return tuple(best)
 
     def update_timing(self):
         ms = ctypes.c_double()
