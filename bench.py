@@ -33,11 +33,18 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: 8x8 Z2 K=1 4096 chains float64 (default, the headline workload); "
                          "c3: 16x16 Z2 K=3 2048 chains float32 + float64 refresh; "
                          "c4: 8192 chains, L in {6,8,12,16,20}, K in {1,2,4}, Z2/Z3, float32 + refresh, "
-                         "graph-replayed autotuned sweeps")
+                         "graph-replayed autotuned sweeps; "
+                         "c5: 32x32 Z2 K=2 256 chains, learned 4x4-patch block proposal trained online on the "
+                         "plain sampler, float32 + float64 refresh, vs the plain float64 single-link sampler")
+    ap.add_argument("--train-chains", type=int, default=32, help="c5: chains of the plain sampler the net trains on")
+    ap.add_argument("--train-sweeps", type=int, default=3, help="c5: plain-sampler sweeps of online training")
+    ap.add_argument("--train-steps", type=int, default=40, help="c5: Adam steps after each training sweep")
+    ap.add_argument("--plain-chains", type=int, default=64, help="c5: chains of the float64 single-link comparison")
+    ap.add_argument("--plain-steps", type=int, default=4, help="c5: timed sweeps of the float64 single-link comparison")
     ap.add_argument("--autotune", type=int, default=0, help="sweeps per autotuner candidate (0 = off)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
@@ -66,6 +73,7 @@ def parse():
         "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=1024),
         "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64),
         "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64),
+        "c5": dict(steps=8, warmup=1, chains=256, L=32, K=2, group=2, precision=32, refresh=4096),
     }
     for k, v in presets[args.workload].items():
         if getattr(args, k) is None:
@@ -187,6 +195,142 @@ def _cpu_chain(L, K, group, chain, budget_s):
     return ch.proposals, sweeps
 
 
+NN_SEED = 7
+ALU_PEAK_F32_TFLOPS = 157.3
+
+
+def run_c5(args):
+    """Learned block proposal (4x4-site patches) vs the plain float64 single-link sampler, one GPU.
+
+    1. Online training: a plain float32 single-link sampler on --train-chains
+       chains; after each of its sweeps the network takes --train-steps Adam
+       steps on (window, patch) examples of its current link fields.
+    2. The learned sampler: --chains chains, one block sweep = one
+       Metropolis-Hastings block move on every patch, float32 inverse with a
+       float64 refactorisation every --refresh changed links; the plaquette
+       is measured after every sweep.
+    3. The plain float64 single-link sampler on the same GPU (--plain-chains
+       chains, --plain-steps sweeps), measured the same way.
+    Effective samples per second = chains * sweeps / (2 tau_int) / wall time."""
+    import torch
+    import synth
+    from paper_2412_01737_amd.ggf import Context, autocorr_time, OBS_LINK, GGF_NOBS
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    L, K, group, P = args.L, args.K, args.group, 4
+    n = 8 * L * L
+    spec = synth.make_tensor(L, K=K, group=group)
+
+    t0 = time.perf_counter()
+    tr = Context(0)
+    tid = tr.set_tensor_spec(spec)
+    tr.init_chains([L] * args.train_chains, tid, synth.SEED_CHAIN + 1, init=1, precision=32,
+                   refresh_every=args.refresh, stream=stream)
+    tr.nn_init(P, NN_SEED)
+    losses = []
+    for sw in range(args.train_sweeps):
+        tr.sweep(1, stream=stream)
+        losses.append(tr.nn_train(args.train_steps, 512, 3e-3, NN_SEED + 1 + sw, stream=stream))
+        log(f"c5 training sweep {sw + 1}/{args.train_sweeps}: loss {losses[-1]:.4f} nats/patch")
+    params = tr.nn_params()
+    tr.close()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    def sampler(chains, precision, refresh, learned, steps, warmup):
+        ctx = Context(0)
+        tid = ctx.set_tensor_spec(spec)
+        ti = time.perf_counter()
+        ctx.init_chains([L] * chains, tid, synth.SEED_CHAIN, init=1, precision=precision,
+                        refresh_every=refresh, stream=stream)
+        if learned:
+            ctx.nn_init(P, NN_SEED)
+            ctx.nn_params(params)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - ti
+        step = (lambda: ctx.block_sweep(1, stream=stream)) if learned else (lambda: ctx.sweep(1, stream=stream))
+        for w in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"c5 {'learned' if learned else 'plain'} warmup sweep {w + 1}/{warmup}")
+        before = [ctx.block_stats(c) for c in range(chains)] if learned else None
+        acc_before = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) if not learned else 0
+        ctx.set_option("time_update", 1)
+        obs = torch.zeros((steps, chains, GGF_NOBS), dtype=torch.float64, device=dev)
+        upd_ms, launches, changed = 0.0, 0, 0
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for s in range(steps):
+            step()
+            ms, la, fl = ctx.update_timing()
+            upd_ms, launches, changed = upd_ms + ms, launches + la, changed + fl
+            ctx.measure(OBS_LINK, obs[s], stream=stream)
+            log(f"c5 {'learned' if learned else 'plain'} sweep {s + 1}/{steps}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - ts
+        series = obs[:, :, 0].cpu().numpy()
+        tau, tau_err, _ = autocorr_time(series)
+        rec = {"chains": chains, "sweeps": steps, "s_per_sweep": elapsed / steps, "init_s": t_init,
+               "tau_int_plaquette": tau, "tau_int_err": tau_err,
+               "effective_samples_per_s": steps * chains / (2.0 * tau) / elapsed,
+               "plaquette_mean": float(series.mean()), "update_ms_total": upd_ms, "update_launches": launches,
+               "links_changed": changed}
+        if learned:
+            after = [ctx.block_stats(c) for c in range(chains)]
+            prop = sum(a[0] - b[0] for a, b in zip(after, before))
+            acc = sum(a[1] - b[1] for a, b in zip(after, before))
+            rec.update(acceptance=acc / max(prop, 1), links_per_accepted_move=changed / max(acc, 1),
+                       link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
+        else:
+            acc = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) - acc_before
+            rec.update(acceptance=acc / (chains * steps * 2 * L * L),
+                       link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
+        ctx.close()
+        torch.cuda.synchronize()
+        return rec
+
+    learned = sampler(args.chains, args.precision, args.refresh, True, args.steps, args.warmup)
+    plain = sampler(args.plain_chains, 64, 1024, False, args.plain_steps, 1)
+    # block update: G -= (G[:,U] W) D with rank r = 4 m per accepted move of m changed links
+    flops = 2.0 * n * n * 4.0 * learned["links_changed"]
+    achieved = flops / (learned["update_ms_total"] * 1e-3) / 1e12 if learned["update_ms_total"] > 0 else 0.0
+    out = {
+        "metric": "link-update proposals/sec and effective samples/sec at fixed obs. error, 1 MI355X",
+        "value": learned["effective_samples_per_s"],
+        "unit": "effective samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": learned["s_per_sweep"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"Z{group} {L}x{L} periodic, K={K}, {args.chains} chains, learned 4x4-patch block "
+                                f"proposal (4-layer 3x3 conv, 32 channels, bf16 weights), float32 inverse, float64 "
+                                f"refresh every {args.refresh} changed links; vs the plain float64 single-link "
+                                f"sampler on {args.plain_chains} chains"),
+                   "name": "c5", "L": L, "K": K, "group": group, "chains": args.chains, "n": n, "patch": P,
+                   "precision": args.precision, "refresh_every": args.refresh},
+        "learned": learned,
+        "plain_f64_single_link": plain,
+        "ess_ratio_learned_vs_plain": learned["effective_samples_per_s"] / plain["effective_samples_per_s"],
+        "training": {"chains": args.train_chains, "sweeps": args.train_sweeps, "adam_steps_per_sweep": args.train_steps,
+                     "loss_nats_per_patch": losses, "seconds": t_train},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": None, "kernel": "k_block_update",
+                     "flops_per_changed_link": 8.0 * n * n},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -199,6 +343,9 @@ def main():
         print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent; "
               "sharding them across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c5":
+        run_c5(args)
+        return
     import torch
     import synth
     from paper_2412_01737_amd.ggf import Context, autocorr_time, OBS_LINK, OBS_DENSITY, GGF_NOBS

@@ -169,11 +169,12 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
 ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *cache_path, int64_t *best,
                         void *stream);
 
-/* Duration in milliseconds of the rank-4 update kernels of the most recent
- * ggf_sweep call, summed over its launches, measured with HIP events on the
- * stream the kernels run on (0 when timing is off; enable with option
- * "time_update" = 1).  Also returns the number of launches and of accepted
- * flips they applied. */
+/* Duration in milliseconds of the update kernels of the most recent
+ * ggf_sweep or ggf_block_sweep call, summed over its launches, measured with
+ * HIP events on the stream the kernels run on (0 when timing is off; enable
+ * with option "time_update" = 1).  Also returns the number of launches and
+ * the number of link changes they applied (accepted flips for ggf_sweep, sum
+ * of changed links over accepted block moves for ggf_block_sweep). */
 ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_t *flips);
 
 /* Integrated autocorrelation time of n_series Monte Carlo series sampled at

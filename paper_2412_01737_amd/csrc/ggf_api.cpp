@@ -1041,16 +1041,46 @@ ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   bl.bacc = ctx->blk_acc;
   bl.kmax = ctx->kmax;
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 1024;
+  const bool timed = ctx->opt_time_update != 0;
+  ctx->last_update_ms = 0.0;
+  ctx->last_launches = 0;
+  ctx->last_flips = 0;
+  if (timed && ctx->tev.size() < static_cast<size_t>(2 * max_np)) {
+    for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
+    ctx->tev.assign(2 * max_np, nullptr);
+    for (auto &ev : ctx->tev) HIP_TRY(ctx, hipEventCreate(&ev));
+  }
+  std::vector<unsigned long long> chg0;
+  if (timed) {
+    chg0.resize(3 * static_cast<size_t>(ctx->n_chains));
+    HIP_TRY(ctx, hipMemcpy(chg0.data(), ctx->blk_prop, chg0.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  }
   for (int sw = 0; sw < n_sweeps; ++sw) {
     for (int p = 0; p < max_np; ++p) {
       bl.patch = p;
       bl.parity = p & 1;
       ggf_block_decide_launch(bl, s);
+      if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * p], s));
       ggf_block_update_launch(bl, grid, s);
+      if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * p + 1], s));
     }
     ggf_launch_end_sweep(bl.lc);
     HIP_TRY(ctx, hipGetLastError());
+    if (timed) {
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      for (int p = 0; p < max_np; ++p) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[2 * p], ctx->tev[2 * p + 1]));
+        ctx->last_update_ms += ms;
+      }
+      ctx->last_launches += max_np;
+    }
     if ((st = after_sweep(ctx, s)) != GGF_OK) return st;
+  }
+  if (timed) {
+    std::vector<unsigned long long> chg1(chg0.size());
+    HIP_TRY(ctx, hipMemcpy(chg1.data(), ctx->blk_prop, chg1.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int c = 0; c < ctx->n_chains; ++c) ctx->last_flips += static_cast<long long>(chg1[3 * c + 2] - chg0[3 * c + 2]);
   }
   return GGF_OK;
 }
