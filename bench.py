@@ -274,7 +274,7 @@ def run_c5(args):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - ts
         series = obs[:, :, 0].cpu().numpy()
-        tau, tau_err, _ = autocorr_time(series)
+        tau, tau_err = autocorr_time(series)[:2] if steps >= 2 else (float("nan"), float("nan"))
         rec = {"chains": chains, "sweeps": steps, "s_per_sweep": elapsed / steps, "init_s": t_init,
                "tau_int_plaquette": tau, "tau_int_err": tau_err,
                "effective_samples_per_s": steps * chains / (2.0 * tau) / elapsed,
@@ -295,7 +295,7 @@ def run_c5(args):
         return rec
 
     learned = sampler(args.chains, args.precision, args.refresh, True, args.steps, args.warmup)
-    plain = sampler(args.plain_chains, 64, 1024, False, args.plain_steps, 1)
+    plain = sampler(args.plain_chains, 64, 1024, False, args.plain_steps, 1) if args.plain_steps > 0 else None
     # block update: G -= (G[:,U] W) D with rank r = 4 m per accepted move of m changed links
     flops = 2.0 * n * n * 4.0 * learned["links_changed"]
     achieved = flops / (learned["update_ms_total"] * 1e-3) / 1e12 if learned["update_ms_total"] > 0 else 0.0
@@ -320,7 +320,8 @@ def run_c5(args):
                    "precision": args.precision, "refresh_every": args.refresh},
         "learned": learned,
         "plain_f64_single_link": plain,
-        "ess_ratio_learned_vs_plain": learned["effective_samples_per_s"] / plain["effective_samples_per_s"],
+        "ess_ratio_learned_vs_plain": (learned["effective_samples_per_s"] / plain["effective_samples_per_s"]
+                                       if plain else None),
         "training": {"chains": args.train_chains, "sweeps": args.train_sweeps, "adam_steps_per_sweep": args.train_steps,
                      "loss_nats_per_patch": losses, "seconds": t_train},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",

@@ -92,6 +92,7 @@ def test_adam_step_matches_closed_form():
     (8, 4, 2, True, -3.0, 0),
     (4, 2, 1, True, 0.0, 1),
     (8, 2, 1, False, -0.5, 1),
+    (6, 2, 1, False, -1.0, 1),    # n = 288: ragged 64 x 128 update tiles
 ])
 def test_block_moves_bit_exact(L, P, K, mix, bias, init):
     say(f"block moves L={L} P={P} K={K} mix={mix} bias={bias}")
@@ -127,6 +128,33 @@ def test_block_moves_bit_exact(L, P, K, mix, bias, init):
     props = sum(ctx.block_stats(c)[0] for c in range(2))
     accs = sum(ctx.block_stats(c)[1] for c in range(2))
     assert props > 0 and accs > 0
+
+
+def test_block_moves_fp32_with_refresh():
+    """Float32 inverse, matrix-core float32 block updates, float64 refactorisation every 8 changed links."""
+    say("block moves fp32 L=12 P=4 K=2")
+    L, P, K = 12, 4, 2
+    spec = synth.make_tensor(2, K=K)
+    ctx = gpu_context([spec], [L] * 2, init=0, precision=32, refresh_every=8)
+    ctx.nn_init(P, 21)
+    p = _params(13, 0.02)
+    p[-2:] = -1.5
+    params = ctx.nn_params(p)
+    orc = [oracle_chain(spec, L, c, init=0)[1] for c in range(2)]
+    for s in range(3):
+        ctx.block_sweep(1)
+        for oc in orc:
+            block_sweep(oc, params, P)
+        for c, oc in enumerate(orc):
+            assert np.array_equal(ctx.get_state(c)[0], oc.k), (s, c)
+    an = ansatz_for(spec, L)
+    for c in range(2):
+        links, info = ctx.get_state(c)
+        assert info["refreshes"] >= 1
+        assert abs(info["logw"] - an.log_weight(links)) < 1e-5 * abs(info["logw"])
+        Gt = np.linalg.inv(an.assemble_M(links))
+        assert np.abs(ctx.get_inverse(c) - Gt).max() < 1e-4 * np.abs(Gt).max()
+    assert sum(ctx.block_stats(c)[1] for c in range(2)) > 0
 
 
 def test_training_learns_the_conditional_and_moves_blocks():
