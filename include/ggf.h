@@ -152,7 +152,7 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *   "update_nt"    1 (default) = non-temporal loads/stores of G in the rank-4 update, 0 = cached
  *   "graph"        1 = replay each sweep as a captured hipGraph, 0 = direct launches
  *   "gj_nb"        column-block width of the Gauss-Jordan refactorisation (8..256, rounded up to a
- *                  power of 2; 0 = 128 for n >= 1024, else 64)
+ *                  power of 2; 0 = 256 for n >= 2048, 128 for n >= 512, else 64)
  *   "scratch_mb"   float64 scratch budget for refactorisations, MiB */
 ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
 

@@ -225,7 +225,8 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
 }
 
 int gj_nb(const ggf_ctx *ctx, int n_max) {
-  const int want = ctx->opt_gj_nb > 0 ? ctx->opt_gj_nb : (n_max >= 1024 ? 128 : 64);
+  // measured on the float64 matrix-core update: 256 wins from n = 2048 up, 128 at n = 512
+  const int want = ctx->opt_gj_nb > 0 ? ctx->opt_gj_nb : (n_max >= 2048 ? 256 : n_max >= 512 ? 128 : 64);
   int nb = 8;
   while (nb < want && nb < 256) nb *= 2;   // power of two, 8..256
   return nb;

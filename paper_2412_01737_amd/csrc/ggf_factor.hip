@@ -235,13 +235,18 @@ __global__ __launch_bounds__(256) void k_gj_swapcopy(const int *__restrict__ lis
 }
 
 // Rank-w update X <- (X with the pivot rows zeroed) + Z Y on columns [c_lo, c_hi)
-// outside the panel, as a register-blocked float64 GEMM: a workgroup owns a
-// 128 x 128 tile, each thread an 8 x 8 block (rows ty + 16 a, columns tx + 16 c),
-// the accumulators start from X, and K is staged through LDS in chunks of 16
-// with the next chunk's global loads in flight during the current chunk's FMAs.
+// outside the panel, on the float64 matrix cores: a workgroup owns a 128 x 128
+// tile, wave (wr, wc) its 64 x 64 quarter as 4 x 4 blocks of 16 x 16; K is
+// staged through LDS in chunks of 16 with the next chunk's global loads in
+// flight during the current chunk's products, and X is added in the epilogue
+// (two workgroups per CU overlap one's epilogue with the other's products).
+// In a 16x16x4 float64 instruction lane (li, g) = (lane % 16, lane / 16) gives
+// Z[row li][k g] and Y[k g][col li] and holds X[rows g + 4 e][col li], so the
+// accumulator loads and stores cover 128 contiguous bytes of a row per 16 lanes.
 // Z = the panel columns (final), Y = the snapshot of the pivot rows.
 constexpr int kGT = 128, kGK = 16;
-__global__ __launch_bounds__(256) void k_gj_gemm(const int *__restrict__ list, int count,
+typedef double gj_acc_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list, int count,
                                                  const ChainDev *__restrict__ chains, double *__restrict__ scr,
                                                  const double *__restrict__ ybuf, int pj, int pw, int c_lo, int c_hi) {
   const int b = blockIdx.z;
@@ -258,20 +263,15 @@ __global__ __launch_bounds__(256) void k_gj_gemm(const int *__restrict__ list, i
   const double *Y = ybuf + ch.y_off;
   __shared__ double sZ[kGK][kGT + 1];
   __shared__ double sY[kGK][kGT + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[8][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+  gj_acc_t acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int r = r0 + ty + 16 * a;
-    const bool blockrow = r >= pj && r < pj + pwe;
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int col = c0 + tx + 16 * c;
-      const bool ok = r < n && col < hi && !(col >= pj && col < pj + pwe) && !blockrow;
-      acc[a][c] = ok ? A[static_cast<size_t>(r) * n + col] : 0.0;
-    }
-  }
-  // staging map: Z chunk by (row q = t/2, k half kh = 8 (t&1)), Y chunk by (k = t/16 .. , col)
+    for (int c = 0; c < 4; ++c) acc[a][c] = static_cast<gj_acc_t>(0.0);
+  // staging map: Z chunk by (row q = t/2, k half kh = 8 (t&1)), Y chunk by (k = t/128, col)
   const int zq = threadIdx.x >> 1, zk = (threadIdx.x & 1) * 8;
   double zreg[8], yreg[8];
   auto load_chunk = [&](int k0) {
@@ -301,30 +301,32 @@ __global__ __launch_bounds__(256) void k_gj_gemm(const int *__restrict__ list, i
     __syncthreads();
     if (k0 + kGK < pwe) load_chunk(k0 + kGK);
 #pragma unroll
-    for (int kk = 0; kk < kGK; ++kk) {
-      double zr[8], yc[8];
+    for (int k4 = 0; k4 < kGK; k4 += 4) {
+      double zo[4], yo[4];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) zr[a] = sZ[kk][ty + 16 * a];
+      for (int a = 0; a < 4; ++a) zo[a] = sZ[k4 + g][wr + 16 * a + li];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) yc[c] = sY[kk][tx + 16 * c];
+      for (int c = 0; c < 4; ++c) yo[c] = sY[k4 + g][wc + 16 * c + li];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[a][c] = fma(zr[a], yc[c], acc[a][c]);
+        for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(zo[a], yo[c], acc[a][c], 0, 0, 0);
     }
     __syncthreads();
   }
+  // epilogue: X (zero on the pivot rows) + Z Y, columns of the panel untouched
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int r = r0 + ty + 16 * a;
-    if (r >= n) continue;
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int col = c0 + tx + 16 * c;
-      if (col >= hi || (col >= pj && col < pj + pwe)) continue;
-      A[static_cast<size_t>(r) * n + col] = acc[a][c];
-    }
-  }
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + wr + 16 * a + g + 4 * e, col = c0 + wc + 16 * c + li;
+        if (r < n && col < hi && !(col >= pj && col < pj + pwe)) {
+          double *x = A + static_cast<size_t>(r) * n + col;
+          *x = (r >= pj && r < pj + pwe) ? acc[a][c][e] : *x + acc[a][c][e];
+        }
+      }
 }
 
 // Column permutation that undoes the row pivoting: result column q = panel-ordered column arr[q].

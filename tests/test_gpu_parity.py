@@ -115,6 +115,25 @@ def test_fp32_updates_with_fp64_refresh():
         assert info["max_drift"] < 1e-3
 
 
+@pytest.mark.parametrize("nb", [8, 64, 128, 256])
+def test_refactorisation_panel_widths(nb):
+    """Blocked Gauss-Jordan with every panel width (recursive base panels, matrix-core update) at n = 2048."""
+    say(f"refactorisation nb={nb} L=16")
+    L = 16
+    spec = spec_for(L)
+    from paper_2412_01737_amd.ggf import Context
+    ctx = Context(0)
+    ctx.set_option("gj_nb", nb)
+    tid = ctx.set_tensor_spec(spec)
+    ctx.init_chains([L], tid, synth.SEED_CHAIN, init=1, precision=64)
+    an = ansatz_for(spec, L)
+    links, info = ctx.get_state(0)
+    M = an.assemble_M(links)
+    Gt = np.linalg.inv(M)
+    assert abs(info["logw"] - an.log_weight(links)) < 1e-10 * abs(info["logw"])
+    assert np.abs(ctx.get_inverse(0) - Gt).max() < 1e-10 * np.abs(Gt).max()
+
+
 def test_checkpoint_resume_bit_exact():
     say("checkpoint resume L=4 Z3")
     spec = spec_for(4, 1, 3)
