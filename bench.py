@@ -68,6 +68,10 @@ def parse():
                     help="derive the update kernel's HBM bytes per launch from rocprofv3 --pmc CSVs, "
                          "write --traffic-json and exit (no GPU needed)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30, help="size of the calibration copy (--traffic-from)")
+    ap.add_argument("--block-traffic-from", nargs=5,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "BENCH_JSON"),
+                    help="derive the block update's HBM bytes per accepted move from rocprofv3 --pmc CSVs of a "
+                         "--workload c5 run and that run's JSON line, write profiles/k_block_traffic.json and exit")
     args = ap.parse_args()
     presets = {
         "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=1024),
@@ -116,6 +120,55 @@ def traffic_from(args):
     print(json.dumps({key: rec}))
 
 
+def block_traffic_from(args):
+    """HBM bytes per accepted block move of k_block_prep + k_block_gemm, from FETCH_SIZE / WRITE_SIZE.
+
+    Counters are scaled by the copy calibration as in traffic_from; the number of
+    accepted moves per launch comes from the profiled run's own JSON line."""
+    import csv
+
+    def per_kernel(path, counter, match):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
+        return vals
+
+    f_csv, w_csv, cf_csv, cw_csv, bench_json = args.block_traffic_from
+    cfetch = sum(per_kernel(cf_csv, "FETCH_SIZE", "probe_copy")) / len(per_kernel(cf_csv, "FETCH_SIZE", "probe_copy"))
+    cwrite = sum(per_kernel(cw_csv, "WRITE_SIZE", "probe_copy")) / len(per_kernel(cw_csv, "WRITE_SIZE", "probe_copy"))
+    known_kib = args.copy_bytes / 1024.0
+    sf, sw = known_kib / cfetch, known_kib / cwrite
+    rec = None
+    for line in open(bench_json):
+        if line.startswith("{") and '"learned"' in line:
+            rec = json.loads(line)
+    learned = rec["learned"]
+    moves_per_launch = learned["accepted_moves"] / learned["update_launches"]
+    out = {"source_digest": source_digest("ggf_block.inc"), "moves_per_launch": moves_per_launch,
+           "fetch_scale": sf, "write_scale": sw}
+    total = 0.0
+    for k in ("k_block_prep", "k_block_gemm"):
+        fv, wv = per_kernel(f_csv, "FETCH_SIZE", k), per_kernel(w_csv, "WRITE_SIZE", k)
+        rd = sum(fv) / len(fv) * sf * 1024.0
+        wr = sum(wv) / len(wv) * sw * 1024.0
+        out[k] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr, "dispatches": [len(fv), len(wv)]}
+        total += rd + wr
+    n = rec["config"]["n"]
+    esz = 4 if rec["config"]["precision"] == 32 else 8
+    out["bytes_per_accepted_move"] = total / moves_per_launch
+    out["algorithmic_bytes_per_accepted_move"] = 2.0 * n * n * esz
+    key = f"L{rec['config']['L']}_K{rec['config']['K']}_Z{rec['config']['group']}_p{rec['config']['precision']}"
+    path = os.path.join(HERE, "profiles", "k_block_traffic.json")
+    try:
+        with open(path) as f:
+            tj = json.load(f)
+    except (OSError, ValueError):
+        tj = {}
+    tj[key] = out
+    with open(path, "w") as f:
+        json.dump(tj, f, indent=1)
+    print(json.dumps({key: out}))
+
+
 def copy_probe(nbytes: int):
     """Project stream probes (ggf_stream_probe) on a buffer of known size.
 
@@ -147,10 +200,10 @@ def copy_probe(nbytes: int):
     print(json.dumps(out))
 
 
-def source_digest() -> str:
-    """Digest of the update kernel's source; traffic counters are only reported for the kernel they measured."""
+def source_digest(name: str = "ggf_sweep.hip") -> str:
+    """Digest of a kernel source file; traffic counters are only reported for the kernel they measured."""
     import hashlib
-    with open(os.path.join(HERE, "paper_2412_01737_amd", "csrc", "ggf_sweep.hip"), "rb") as f:
+    with open(os.path.join(HERE, "paper_2412_01737_amd", "csrc", name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -196,7 +249,7 @@ def _cpu_chain(L, K, group, chain, budget_s):
 
 
 NN_SEED = 7
-ALU_PEAK_F32_TFLOPS = 157.3
+MFMA_PEAK_F32_TFLOPS = 157.3
 
 
 def run_c5(args):
@@ -284,7 +337,7 @@ def run_c5(args):
             after = [ctx.block_stats(c) for c in range(chains)]
             prop = sum(a[0] - b[0] for a, b in zip(after, before))
             acc = sum(a[1] - b[1] for a, b in zip(after, before))
-            rec.update(acceptance=acc / max(prop, 1), links_per_accepted_move=changed / max(acc, 1),
+            rec.update(acceptance=acc / max(prop, 1), links_per_accepted_move=changed / max(acc, 1), accepted_moves=acc,
                        link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
         else:
             acc = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) - acc_before
@@ -296,9 +349,24 @@ def run_c5(args):
 
     learned = sampler(args.chains, args.precision, args.refresh, True, args.steps, args.warmup)
     plain = sampler(args.plain_chains, 64, 1024, False, args.plain_steps, 1) if args.plain_steps > 0 else None
-    # block update: G -= (G[:,U] W) D with rank r = 4 m per accepted move of m changed links
+    # block update G -= G[:,U] W G[U,:] per accepted move of m changed links (rank r = 4 m):
+    # algorithmic bytes = one read and one write of G (2 n^2 * 4), flops = 2 n^2 r; at r ~ 64 the
+    # arithmetic intensity (~16 flop/B) is below the float32 matrix-core ridge (157.3 / 8 ~ 19.7)
+    esz = 4 if args.precision == 32 else 8
+    upd_s = learned["update_ms_total"] * 1e-3
+    bytes_moved = 2.0 * n * n * esz * learned["accepted_moves"]
     flops = 2.0 * n * n * 4.0 * learned["links_changed"]
-    achieved = flops / (learned["update_ms_total"] * 1e-3) / 1e12 if learned["update_ms_total"] > 0 else 0.0
+    achieved = bytes_moved / upd_s / 1e9 if upd_s > 0 else 0.0
+    tflops = flops / upd_s / 1e12 if upd_s > 0 else 0.0
+    traffic = None
+    try:
+        with open(os.path.join(HERE, "profiles", "k_block_traffic.json")) as f:
+            tj = json.load(f).get(f"L{L}_K{K}_Z{group}_p{args.precision}")
+        if tj and tj["source_digest"] == source_digest("ggf_block.inc"):
+            # measured bytes per accepted move x accepted moves per launch of this run
+            traffic = tj["bytes_per_accepted_move"] * learned["accepted_moves"] / learned["update_launches"]
+    except (OSError, ValueError, KeyError):
+        pass
     out = {
         "metric": "link-update proposals/sec and effective samples/sec at fixed obs. error, 1 MI355X",
         "value": learned["effective_samples_per_s"],
@@ -324,8 +392,11 @@ def run_c5(args):
                                        if plain else None),
         "training": {"chains": args.train_chains, "sweeps": args.train_sweeps, "adam_steps_per_sweep": args.train_steps,
                      "loss_nats_per_patch": losses, "seconds": t_train},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": None, "kernel": "k_block_update",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_block_prep + k_block_gemm",
+                     "algorithmic_bytes_per_launch": bytes_moved / max(learned["update_launches"], 1),
+                     "bytes_per_accepted_move": 2.0 * n * n * esz,
+                     "tflops": tflops, "mfma_peak_tflops": MFMA_PEAK_F32_TFLOPS,
                      "flops_per_changed_link": 8.0 * n * n},
         "cpu_baseline": None,
     }
@@ -336,6 +407,9 @@ def main():
     args = parse()
     if args.traffic_from:
         traffic_from(args)
+        return
+    if args.block_traffic_from:
+        block_traffic_from(args)
         return
     if args.copy_probe:
         copy_probe(args.copy_probe)

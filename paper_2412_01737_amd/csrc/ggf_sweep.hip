@@ -192,15 +192,33 @@ __global__ __launch_bounds__(256) void k_update(LaunchCtx lc, int parity, int ti
       const V p1 = *reinterpret_cast<const V *>(PT + n + j0);
       const V p2 = *reinterpret_cast<const V *>(PT + 2 * n + j0);
       const V p3 = *reinterpret_cast<const V *>(PT + 3 * n + j0);
+      // rows in groups of 4, the next group's G and QT loads issued before this group's stores
       int i = r0;
-      for (; i + 4 <= r1; i += 4) {
-        V g[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = ld<NT>(reinterpret_cast<const V *>(G + static_cast<size_t>(i + q) * n + j0));
+      V ga[4];
+      T qa[4][4];
+      auto fetch = [&](int i0, V (&g)[4], T (&qq)[4][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          upd(g[q], QT[i + q], QT[n + i + q], QT[2 * n + i + q], QT[3 * n + i + q], p0, p1, p2, p3);
-          st<NT>(reinterpret_cast<V *>(G + static_cast<size_t>(i + q) * n + j0), g[q]);
+          g[q] = ld<NT>(reinterpret_cast<const V *>(G + static_cast<size_t>(i0 + q) * n + j0));
+#pragma unroll
+          for (int b = 0; b < 4; ++b) qq[q][b] = QT[b * n + i0 + q];
+        }
+      };
+      if (i + 4 <= r1) fetch(i, ga, qa);
+      for (; i + 4 <= r1; i += 4) {
+        V gb[4];
+        T qb[4][4];
+        if (i + 8 <= r1) fetch(i + 4, gb, qb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          upd(ga[q], qa[q][0], qa[q][1], qa[q][2], qa[q][3], p0, p1, p2, p3);
+          st<NT>(reinterpret_cast<V *>(G + static_cast<size_t>(i + q) * n + j0), ga[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ga[q] = gb[q];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) qa[q][b] = qb[q][b];
         }
       }
       for (; i < r1; ++i) {
