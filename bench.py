@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--delay", type=int, default=None,
+                    help="window of delayed updates in link steps (0 = one rank-4 pass per accepted flip; "
+                         "default: the library's)")
     ap.add_argument("--update-grid", type=int, default=0)
     ap.add_argument("--update-tiles", type=int, default=0)
     ap.add_argument("--update-nt", type=int, default=1)
@@ -458,6 +461,8 @@ def main():
     if args.update_tiles:
         ctx.set_option("update_tiles", args.update_tiles)
     ctx.set_option("graph", args.graph)
+    if args.delay is not None:
+        ctx.set_option("delay", args.delay)
     if not args.autotune:
         ctx.set_option("update_nt", args.update_nt)
     mask = OBS_LINK | OBS_DENSITY

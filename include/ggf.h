@@ -153,7 +153,12 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *   "graph"        1 = replay each sweep as a captured hipGraph, 0 = direct launches
  *   "gj_nb"        column-block width of the Gauss-Jordan refactorisation (8..256, rounded up to a
  *                  power of 2; 0 = 256 for n >= 2048, 128 for n >= 512, else 64)
- *   "scratch_mb"   float64 scratch budget for refactorisations, MiB */
+ *   "scratch_mb"   float64 scratch budget for refactorisations, MiB
+ *   "delay"        window of delayed updates in link steps: 8, 16, 24 or 32 (the accepted
+ *                  flips of a window are kept as pending factors G_cur = G - X Y^T and applied
+ *                  by one matrix-core rank-4F update at its end), 0 = one rank-4 streaming
+ *                  update per link step, -1 (default) = 16.  Takes effect at the next sweep;
+ *                  G as read through the ABI never has pending flips. */
 ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
 
 /* Pick the launch shape of the rank-4 update (grid, rows per work item,

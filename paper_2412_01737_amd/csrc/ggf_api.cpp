@@ -57,6 +57,7 @@ struct ggf_ctx {
 
   // options
   int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 0, opt_time_update = 0, opt_update_nt = 1;
+  int opt_delay = -1;            // window of delayed updates in link steps (0 = immediate, -1 = automatic)
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -79,8 +80,15 @@ struct ggf_ctx {
   int *blk_U = nullptr, *blk_r = nullptr;
   unsigned long long *blk_prop = nullptr, *blk_acc = nullptr;
 
+  // delayed-update buffers (tied to the chains): X, Y arenas of width 4 * dly_F
+  void *dly_X = nullptr, *dly_Y = nullptr;
+  size_t *dly_off = nullptr;
+  int *dly_pend = nullptr, *all_list = nullptr, *all_cnt = nullptr;
+  int dly_F = 0;
+
   // update timing
   std::vector<hipEvent_t> tev;
+  int timed_launches = 0;        // event pairs recorded by the last record_sweep
   double last_update_ms = 0.0;
   long long last_launches = 0, last_flips = 0;
 };
@@ -184,6 +192,10 @@ void free_chains(ggf_ctx *ctx) {
   ctx->allocs.clear();
   ctx->blk_A = ctx->blk_W = nullptr;
   ctx->blk_C = ctx->blk_D = nullptr;
+  ctx->dly_X = ctx->dly_Y = nullptr;
+  ctx->dly_off = nullptr;
+  ctx->dly_pend = ctx->all_list = ctx->all_cnt = nullptr;
+  ctx->dly_F = 0;
   ctx->blk_doff = nullptr;
   ctx->blk_U = ctx->blk_r = nullptr;
   ctx->blk_prop = ctx->blk_acc = nullptr;
@@ -218,6 +230,11 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.acc_list = ctx->acc_list;
   lc.acc_cnt = ctx->acc_cnt;
   lc.scratch = ctx->scratch;
+  lc.X = ctx->dly_X;
+  lc.Y = ctx->dly_Y;
+  lc.x_off = ctx->dly_off;
+  lc.pend = ctx->dly_pend;
+  lc.dld = 0;                     // set by record_sweep when the window is delayed
   lc.key0 = static_cast<uint32_t>(ctx->seed & 0xFFFFFFFFu);
   lc.key1 = static_cast<uint32_t>(ctx->seed >> 32);
   lc.n_chains = ctx->n_chains;
@@ -284,16 +301,80 @@ ggf_status factorize(ggf_ctx *ctx, const std::vector<int> &which, int is_refresh
   return GGF_OK;
 }
 
+// Window length of delayed updates: the option, else 16 link steps (rank-64
+// flushes), 0 = immediate rank-4 updates.  Multiples of 8 keep the partial last
+// window of a sweep (2 L^2 link steps) at a rank that is a multiple of 32.
+int delay_window(const ggf_ctx *ctx) {
+  const int want = ctx->opt_delay >= 0 ? ctx->opt_delay : 16;
+  return want;
+}
+
+// Allocate the pending-factor arenas for window F (X, Y: n x 4F per chain).
+ggf_status delay_buffers(ggf_ctx *ctx, int F) {
+  if (F == 0 || ctx->dly_F == F) return GGF_OK;
+  hipError_t e = hipSuccess;
+  if (ctx->dly_F != 0) {
+    // another window width: nothing is pending between sweeps, so the arenas are simply replaced
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    for (void *p : {ctx->dly_X, ctx->dly_Y}) {
+      ctx->allocs.erase(std::remove(ctx->allocs.begin(), ctx->allocs.end(), p), ctx->allocs.end());
+      HIP_TRY(ctx, hipFree(p));
+    }
+    ctx->dly_X = ctx->dly_Y = nullptr;
+    ctx->dly_F = 0;
+  }
+  const size_t esz = ctx->precision == 64 ? sizeof(double) : sizeof(float);
+  std::vector<size_t> off(ctx->n_chains);
+  size_t tot = 0;
+  for (int c = 0; c < ctx->n_chains; ++c) {
+    off[c] = tot;
+    tot += static_cast<size_t>(4 * F) * ctx->chains[c].n;
+  }
+  std::vector<int> all(ctx->n_chains);
+  for (int c = 0; c < ctx->n_chains; ++c) all[c] = c;
+  const int cnt[2] = {ctx->n_chains, ctx->n_chains};
+  if (!ctx->dly_off) {
+    ctx->dly_off = dalloc<size_t>(ctx, ctx->n_chains, e);
+    ctx->dly_pend = dalloc<int>(ctx, ctx->n_chains, e);
+    ctx->all_list = dalloc<int>(ctx, ctx->n_chains, e);
+    ctx->all_cnt = dalloc<int>(ctx, 2, e);
+  }
+  for (void **dst : {&ctx->dly_X, &ctx->dly_Y}) {
+    if (e != hipSuccess) break;
+    void *p = nullptr;
+    e = hipMalloc(&p, tot * esz);
+    if (e == hipSuccess) {
+      ctx->allocs.push_back(p);
+      *dst = p;
+    }
+  }
+  if (e != hipSuccess) return fail(ctx, GGF_ENOMEM, "cannot allocate delayed-update buffers");
+  HIP_TRY(ctx, hipMemcpy(ctx->dly_off, off.data(), off.size() * sizeof(size_t), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->all_list, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->all_cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice));
+  ctx->dly_F = F;
+  return GGF_OK;
+}
+
 ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
-  const LaunchCtx lc = launch_ctx(ctx, s);
+  LaunchCtx lc = launch_ctx(ctx, s);
   const int tiles = ctx->opt_update_tiles > 0 ? ctx->opt_update_tiles : std::max(1, ctx->n_max / 16);
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 2048;
+  const int F = delay_window(ctx);
+  if (F > 0 && ctx->dly_F != F) return fail(ctx, GGF_ESTATE, "delayed-update buffers are not allocated");
+  lc.dld = 4 * F;
+  int k = 0;
   for (int ell = 0; ell < ctx->max_links; ++ell) {
-    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax);
-    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * ell], s));
-    ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
-    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * ell + 1], s));
+    const int t = F > 0 ? ell % F : 0;
+    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax, t);
+    if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
+    if (F > 0) ggf_launch_flush(lc, ctx->all_list, ctx->all_cnt, 512);
+    else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
+    ++k;
   }
+  ctx->timed_launches = timed ? k : 0;
   ggf_launch_end_sweep(lc);
   HIP_TRY(ctx, hipGetLastError());
   return GGF_OK;
@@ -604,6 +685,8 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
   if (n_sweeps < 0) return fail(ctx, GGF_EINVAL, "n_sweeps must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  ggf_status dst = delay_buffers(ctx, delay_window(ctx));
+  if (dst != GGF_OK) return dst;
   const bool timed = ctx->opt_time_update != 0;
   ctx->last_update_ms = 0.0;
   ctx->last_launches = 0;
@@ -645,12 +728,12 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
       if (st != GGF_OK) return st;
       if (timed) {
         HIP_TRY(ctx, hipStreamSynchronize(s));
-        for (int ell = 0; ell < ctx->max_links; ++ell) {
+        for (int k = 0; k < ctx->timed_launches; ++k) {
           float ms = 0.f;
-          HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[2 * ell], ctx->tev[2 * ell + 1]));
+          HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[2 * k], ctx->tev[2 * k + 1]));
           ctx->last_update_ms += ms;
         }
-        ctx->last_launches += ctx->max_links;
+        ctx->last_launches += ctx->timed_launches;
       }
     }
     ggf_status st = after_sweep(ctx, s);
@@ -789,8 +872,12 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
   } else if (k == "scratch_mb") ctx->opt_scratch_mb = value;
   else if (k == "time_update") ctx->opt_time_update = value != 0;
   else if (k == "update_nt") ctx->opt_update_nt = value != 0;
-  else return fail(ctx, GGF_EINVAL, "unknown option " + k);
-  if (k == "update_grid" || k == "update_tiles" || k == "update_nt") {
+  else if (k == "delay") {
+    if (!(value == -1 || value == 0 || (value % 8 == 0 && value >= 8 && value <= 32)))
+      return fail(ctx, GGF_EINVAL, "delay must be -1 (automatic), 0 (immediate) or 8, 16, 24, 32 link steps");
+    ctx->opt_delay = static_cast<int>(value);
+  } else return fail(ctx, GGF_EINVAL, "unknown option " + k);
+  if (k == "update_grid" || k == "update_tiles" || k == "update_nt" || k == "delay") {
     if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   }
   return GGF_OK;

@@ -28,6 +28,13 @@ struct LaunchCtx {
   int *acc_list;                 // compacted accepted chains of the current link step
   int *acc_cnt;                  // [2] double-buffered accepted counts
   double *scratch;               // float64 refactorisation scratch
+  // delayed updates (dld > 0): pending factors of the current window of link
+  // steps, G_cur = G - X Y^T, chain c's X and Y n x dld row-major at x_off[c];
+  // pend[c] = 1 + the window slot of the chain's last accepted flip (0: none)
+  void *X, *Y;
+  const size_t *x_off;
+  int *pend;
+  int dld;
   uint32_t key0, key1;
   int n_chains;
 };
@@ -39,8 +46,13 @@ void ggf_launch_store(const LaunchCtx &lc, const int *list, int count, int n_max
                       size_t piv_stride);
 void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_refresh);
 
-// One link step: ratio + decision + factors, then the streaming rank-4 update.
-void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax);
+// One link step: ratio + decision + factors, then the streaming rank-4 update
+// (or, with delayed updates, the factors of window slot t).
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t);
+// Delayed updates: G -= X Y^T for every chain with a pending flip in the window
+// (matrix-core GEMM of rank 4 * pend[c] rounded up to 16); all_list holds 0..n_chains-1
+// and all_cnt[0] = n_chains.
+void ggf_launch_flush(const LaunchCtx &lc, const int *all_list, int *all_cnt, int grid);
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt);
 void ggf_launch_end_sweep(const LaunchCtx &lc);
 void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);

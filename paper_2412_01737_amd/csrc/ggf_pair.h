@@ -12,6 +12,31 @@ namespace {
 
 constexpr int kPairLd = 16;   // leading dimension of the per-pair 2s x 2s workspace (s <= 8)
 
+// Read access to the current inverse G_cur = G - X Y^T: X and Y hold the
+// pending Woodbury factors of the accepted flips of the current window of link
+// steps (row-major n x ld, r columns in use; r = 0 when nothing is pending).
+template <typename T>
+struct GView {
+  const T *G;
+  int n;
+  const T *X, *Y;
+  int ld, r;
+  __device__ double at(int a, int b) const {
+    double v = static_cast<double>(G[static_cast<size_t>(a) * n + b]);
+    if (r > 0) {
+      const T *xa = X + static_cast<size_t>(a) * ld;
+      const T *yb = Y + static_cast<size_t>(b) * ld;
+      for (int s = 0; s < r; ++s) v -= static_cast<double>(xa[s]) * static_cast<double>(yb[s]);
+    }
+    return v;
+  }
+};
+
+template <typename T>
+__device__ inline GView<T> plain_view(const T *G, int n) {
+  return GView<T>{G, n, nullptr, nullptr, 0, 0};
+}
+
 struct PatchSet {
   int s;
   int idx[8];
@@ -33,7 +58,7 @@ __device__ inline void pair_set(const TensorDev &Tn, int a, int b, int L, PatchS
 // change of the transition covariance on each involved link (link ell_prop
 // taken at its proposed value k_prop).
 template <typename T>
-__device__ inline void build_pair_matrix(const TensorDev &Tn, int a, int b, int L, int group, const T *G, int n,
+__device__ inline void build_pair_matrix(const TensorDev &Tn, int a, int b, int L, int group, const GView<T> &G,
                                          const int8_t *lk, const int *U, const double *Kw, int ell_prop,
                                          int k_prop, double2 *W, PatchSet &ps) {
   pair_set(Tn, a, b, L, ps);
@@ -41,7 +66,7 @@ __device__ inline void build_pair_matrix(const TensorDev &Tn, int a, int b, int 
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) {
       double2 v = make_double2(0.0, 0.0);
-      if (i < s && j < s) v.x = static_cast<double>(G[static_cast<size_t>(ps.idx[i]) * n + ps.idx[j]]);
+      if (i < s && j < s) v.x = G.at(ps.idx[i], ps.idx[j]);
       else if (i < s && j == i + s) v.x = 1.0;
       else if (i >= s && j == i - s) v.x = -1.0;
       W[i * kPairLd + j] = v;
@@ -49,7 +74,7 @@ __device__ inline void build_pair_matrix(const TensorDev &Tn, int a, int b, int 
   if (Kw != nullptr) {
     double p[8][4];
     for (int i = 0; i < s; ++i)
-      for (int q = 0; q < 4; ++q) p[i][q] = static_cast<double>(G[static_cast<size_t>(ps.idx[i]) * n + U[q]]);
+      for (int q = 0; q < 4; ++q) p[i][q] = G.at(ps.idx[i], U[q]);
     for (int i = 0; i < s; ++i) {
       double t[4];
       for (int q2 = 0; q2 < 4; ++q2) {

@@ -14,31 +14,74 @@
 //   step's accepted list.
 // Then the streaming update (k_update) applies G <- G + QT^T PT
 // = G - G[:,U] K G[U,:] to every accepted chain, each element once: read n^2, write n^2.
+//
+// Delayed updates (lc.dld > 0): the flips of a window of F link steps are not
+// applied at once.  Step t of the window reads the current inverse as
+// G - X Y^T (X, Y: n x 4F, slots 0..t-1 filled); on accept the workgroup writes
+// slot t: X[:, 4t..4t+3] = G_cur[:,U] K and Y[:, 4t..4t+3] = G_cur[U,:]^T, so that
+// G_cur' = G_cur - G_cur[:,U] K G_cur[U,:]; a rejected or absent step writes
+// zeros.  At the end of the window one matrix-core GEMM applies G -= X Y^T
+// (rank 4F): one pass over G per window instead of one per accepted flip.
 #include "ggf_device.h"
 #include "ggf_launch.h"
 #include "ggf_pair.h"
 
 namespace {
 
+constexpr int kDelaySlotsMax = 32;   // window length F <= 32 (rank 4F <= 128)
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity) {
+__global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity, int t) {
   extern __shared__ double2 s_work[];
   __shared__ double s_K[16];
+  __shared__ double s_guu[16];
+  __shared__ double s_xu[4][4 * kDelaySlotsMax], s_yu[4][4 * kDelaySlotsMax];   // X[U,:r], Y[U,:r]
   __shared__ double s_rho, s_u;
-  __shared__ int s_U[4];
   __shared__ int s_kn, s_acc;
   __shared__ double2 s_r[16];
   const int c = blockIdx.x;
   if (c == 0 && threadIdx.x == 0) lc.acc_cnt[parity ^ 1] = 0;
   const ChainDev ch = lc.chains[c];
-  if (ell >= ch.nlinks) return;
-  const TensorDev &Tn = lc.tensors[ch.tensor];
   const int n = ch.n;
+  const bool delayed = lc.dld > 0;
+  const int ld = lc.dld, r = delayed ? 4 * t : 0;
+  T *X = delayed ? static_cast<T *>(lc.X) + lc.x_off[c] : nullptr;
+  T *Y = delayed ? static_cast<T *>(lc.Y) + lc.x_off[c] : nullptr;
+  // a step without an accepted flip leaves zeros in its slot of the window
+  auto zero_slot = [&]() {
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        X[static_cast<size_t>(j) * ld + r + q] = static_cast<T>(0);
+        Y[static_cast<size_t>(j) * ld + r + q] = static_cast<T>(0);
+      }
+  };
+  if (ell >= ch.nlinks) {
+    if (delayed) {
+      if (t == 0 && threadIdx.x == 0) lc.pend[c] = 0;
+      zero_slot();
+    }
+    return;
+  }
+  const TensorDev &Tn = lc.tensors[ch.tensor];
   const T *G = static_cast<const T *>(lc.G) + ch.g_off;
   int8_t *lk = lc.links + ch.link_off;
+  int U[4];
+  ggf_link_u(ell, ch.L, U);
+  for (int i = threadIdx.x; i < 4 * r; i += blockDim.x) {
+    const int q = i / r, s = i - q * r;
+    s_xu[q][s] = static_cast<double>(X[static_cast<size_t>(U[q]) * ld + s]);
+    s_yu[q][s] = static_cast<double>(Y[static_cast<size_t>(U[q]) * ld + s]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int a = threadIdx.x >> 2, b = threadIdx.x & 3;
+    double v = static_cast<double>(G[static_cast<size_t>(U[a]) * n + U[b]]);
+    for (int s = 0; s < r; ++s) v -= s_xu[a][s] * s_yu[b][s];
+    s_guu[threadIdx.x] = v;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    int U[4];
-    ggf_link_u(ell, ch.L, U);
     const int kold = lk[ell];
     const uint4 x = ggf_philox(make_uint4(static_cast<uint32_t>(c), lc.sweep[c], static_cast<uint32_t>(ell), 0u),
                                lc.key0, lc.key1);
@@ -48,14 +91,11 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     ggf_bond_block(Tn.x0, kn, ch.group, yn);
     const double X0 = yn[0] - yo[0], X1 = yn[1] - yo[1], X2 = yn[2] - yo[2], X3 = yn[3] - yo[3];
     const double dM[16] = {0, 0, X0, X1, 0, 0, X2, X3, -X0, -X2, 0, 0, -X1, -X3, 0, 0};
-    double guu[16];
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) guu[a * 4 + b] = static_cast<double>(G[static_cast<size_t>(U[a]) * n + U[b]]);
     double A[16], Ai[16];
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
         double v = (a == b) ? 1.0 : 0.0;
-        for (int q = 0; q < 4; ++q) v += guu[a * 4 + q] * dM[q * 4 + b];
+        for (int q = 0; q < 4; ++q) v += s_guu[a * 4 + q] * dM[q * 4 + b];
         A[a * 4 + b] = v;
         Ai[a * 4 + b] = (a == b) ? 1.0 : 0.0;
       }
@@ -66,7 +106,6 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
         for (int q = 0; q < 4; ++q) v += dM[a * 4 + q] * Ai[q * 4 + b];
         s_K[a * 4 + b] = v;
       }
-    for (int q = 0; q < 4; ++q) s_U[q] = U[q];
     s_rho = rho;
     s_kn = kn;
     s_u = ggf_u53(x.x, x.y);
@@ -80,7 +119,8 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
       pair_of(threadIdx.x, K, a, b);
       PatchSet ps;
       double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
-      build_pair_matrix(Tn, a, b, ch.L, ch.group, G, n, lk, s_U, s_K, ell, s_kn, W, ps);
+      const GView<T> gv{G, n, X, Y, ld, r};
+      build_pair_matrix(Tn, a, b, ch.L, ch.group, gv, lk, U, s_K, ell, s_kn, W, ps);
       s_r[threadIdx.x] = pair_ratio(W, ps.s);
     }
     __syncthreads();
@@ -94,8 +134,8 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
       for (int p = 0; p < npairs; ++p) {
         int a, b;
         pair_of(p, K, a, b);
-        const double2 t = cmul(Tn.w[a][b], s_r[p]);
-        sv += (a == b) ? t.x : 2.0 * t.x;
+        const double2 tt = cmul(Tn.w[a][b], s_r[p]);
+        sv += (a == b) ? tt.x : 2.0 * tt.x;
       }
       snew = make_double2(sv, 0.0);
       sratio = sv / lc.sfac[c].x;
@@ -111,19 +151,58 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
       lc.sfac[c] = snew;
       lc.acc_since[c] += 1;
       lc.acc_total[c] += 1;
-      const int slot = atomicAdd(lc.acc_cnt + parity, 1);
-      lc.acc_list[slot] = c;
+      if (delayed) {
+        lc.pend[c] = t + 1;
+      } else {
+        const int slot = atomicAdd(lc.acc_cnt + parity, 1);
+        lc.acc_list[slot] = c;
+      }
+    } else if (delayed && t == 0) {
+      lc.pend[c] = 0;
     }
     s_acc = accept ? 1 : 0;
   }
   __syncthreads();
+  const int u0 = U[0], u1 = U[1], u2 = U[2], u3 = U[3];
+  if (delayed) {
+    if (!s_acc) {
+      zero_slot();
+      return;
+    }
+    // slot t: X = G_cur[:,U] K, Y = G_cur[U,:]^T, with G_cur = G - X Y^T over slots 0..t-1
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const T *gj = G + static_cast<size_t>(j) * n;
+      double gc[4] = {static_cast<double>(gj[u0]), static_cast<double>(gj[u1]), static_cast<double>(gj[u2]),
+                      static_cast<double>(gj[u3])};
+      double gr[4] = {static_cast<double>(G[static_cast<size_t>(u0) * n + j]),
+                      static_cast<double>(G[static_cast<size_t>(u1) * n + j]),
+                      static_cast<double>(G[static_cast<size_t>(u2) * n + j]),
+                      static_cast<double>(G[static_cast<size_t>(u3) * n + j])};
+      T *xj = X + static_cast<size_t>(j) * ld;
+      T *yj = Y + static_cast<size_t>(j) * ld;
+      for (int s = 0; s < r; ++s) {
+        const double xs = static_cast<double>(xj[s]), ys = static_cast<double>(yj[s]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          gc[q] -= xs * s_yu[q][s];
+          gr[q] -= s_xu[q][s] * ys;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        xj[r + b] = static_cast<T>(gc[0] * s_K[0 * 4 + b] + gc[1] * s_K[1 * 4 + b] + gc[2] * s_K[2 * 4 + b] +
+                                   gc[3] * s_K[3 * 4 + b]);
+        yj[r + b] = static_cast<T>(gr[b]);
+      }
+    }
+    return;
+  }
   if (!s_acc) return;
   // Woodbury with the stored rows and columns: G' = G - G[:,U] K G[U,:].
   // (Substituting -G[U,:]^T for G[:,U] would assume exact antisymmetry; rounding
   // breaks it and the symmetric part of the error then grows with every flip.)
   T *PT = static_cast<T *>(lc.F) + ch.f_off;
   T *QT = PT + 4 * static_cast<size_t>(n);
-  const int u0 = s_U[0], u1 = s_U[1], u2 = s_U[2], u3 = s_U[3];
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const T *gj = G + static_cast<size_t>(j) * n;
     const double c0 = static_cast<double>(gj[u0]), c1 = static_cast<double>(gj[u1]);
@@ -269,7 +348,7 @@ __global__ __launch_bounds__(64) void k_sfac(LaunchCtx lc, const int *list, int 
     pair_of(threadIdx.x, K, a, b);
     PatchSet ps;
     double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
-    build_pair_matrix(Tn, a, b, ch.L, ch.group, G, ch.n, lk, nullptr, nullptr, -1, 0, W, ps);
+    build_pair_matrix(Tn, a, b, ch.L, ch.group, plain_view(G, ch.n), lk, nullptr, nullptr, -1, 0, W, ps);
     s_r[threadIdx.x] = pair_ratio(W, ps.s);
   }
   __syncthreads();
@@ -336,7 +415,7 @@ __global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, do
         PatchSet ps;
         double2 *W = s_work + threadIdx.x * (kPairLd * kPairLd + 64);
         double2 *C = W + kPairLd * kPairLd;
-        build_pair_matrix(Tn, a, b, L, group, G, n, lk, nullptr, nullptr, -1, 0, W, ps);
+        build_pair_matrix(Tn, a, b, L, group, plain_view(G, n), lk, nullptr, nullptr, -1, 0, W, ps);
         s = ps.s;
         for (int i = 0; i < s; ++i)
           for (int j = 0; j < s; ++j) {
@@ -470,12 +549,12 @@ static size_t pair_lds(int kmax) {
   return np > 0 ? static_cast<size_t>(np) * kPairLd * kPairLd * sizeof(double2) : 0;
 }
 
-void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax) {
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t) {
   const size_t lds = pair_lds(kmax);
   if (lc.precision == 64)
-    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity);
+    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t);
   else
-    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity);
+    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t);
 }
 
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt) {

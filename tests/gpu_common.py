@@ -23,10 +23,14 @@ def spec_for(L, K=1, group=2):
     return synth.make_tensor(L, K=K, group=group)
 
 
-def gpu_context(specs, Ls, seed=synth.SEED_CHAIN, init=0, precision=64, refresh_every=0, tensor_ids=None):
-    """Context with one chain per entry of Ls; specs: one spec per distinct tensor."""
+def gpu_context(specs, Ls, seed=synth.SEED_CHAIN, init=0, precision=64, refresh_every=0, tensor_ids=None,
+                delay=None):
+    """Context with one chain per entry of Ls; specs: one spec per distinct tensor; delay: window of delayed
+    updates in link steps (None = the library's default)."""
     from paper_2412_01737_amd.ggf import Context
     ctx = Context(0)
+    if delay is not None:
+        ctx.set_option("delay", delay)
     ids = [ctx.set_tensor_spec(s) for s in specs]
     tids = [ids[0]] * len(Ls) if tensor_ids is None else [ids[t] for t in tensor_ids]
     ctx.init_chains(Ls, tids, seed, init=init, precision=precision, refresh_every=refresh_every)

@@ -171,14 +171,55 @@ def test_recovery_from_corrupted_inverse():
     assert ctx.get_state(0)[1]["recoveries"] == 0
 
 
-def test_uneven_batch_mixed_lattices():
+@pytest.mark.parametrize("delay", [0, 8, 24, 32])
+def test_delayed_update_windows(delay):
+    """Flips applied in windows of `delay` link steps (one rank-4 pass per accepted flip when 0) on 6x6 Z3 K=2:
+    72 link steps give full and partial windows; decisions, log W, S and G against the oracle's one-flip-at-a-time
+    Woodbury chain."""
+    L, K, group, chains, sweeps = 6, 2, 3, 3, 3
+    say(f"delayed updates window={delay} L={L} K={K} Z{group}")
+    spec = spec_for(L, K, group)
+    ctx = gpu_context([spec], [L] * chains, init=1, delay=delay)
+    orc = [oracle_chain(spec, L, c, init=1)[1] for c in range(chains)]
+    for s in range(sweeps):
+        ctx.sweep(1)
+        for c, oc in enumerate(orc):
+            oc.sweep()
+            assert np.array_equal(ctx.get_state(c)[0], oc.k), f"chain {c} sweep {s}"
+    for c, oc in enumerate(orc):
+        _, info = ctx.get_state(c)
+        assert abs(info["logw"] - oc.logw) <= 1e-10 * abs(oc.logw)
+        assert abs(info["s_re"] - oc.S.real) <= 1e-9 * abs(oc.S.real)
+        G = ctx.get_inverse(c)
+        assert np.abs(G - oc.G).max() <= 1e-9 * np.abs(oc.G).max()
+
+
+def test_delay_window_changes_between_sweeps():
+    """The window may change between sweeps (nothing is pending at a sweep's end)."""
+    say("delay window changes")
+    L = 4
+    spec = spec_for(L, 2, 2)
+    ctx = gpu_context([spec], [L] * 2, init=1, delay=8)
+    orc = [oracle_chain(spec, L, c, init=1)[1] for c in range(2)]
+    for s, d in enumerate([8, 32, 0, 16]):
+        ctx.set_option("delay", d)
+        ctx.sweep(1)
+        for c, oc in enumerate(orc):
+            oc.sweep()
+            assert np.array_equal(ctx.get_state(c)[0], oc.k), f"chain {c} sweep {s} window {d}"
+    G = ctx.get_inverse(1)
+    assert np.abs(G - orc[1].G).max() <= 1e-9 * np.abs(orc[1].G).max()
+
+
+@pytest.mark.parametrize("delay", [0, 8])
+def test_uneven_batch_mixed_lattices(delay):
     """One context, chains of different L, K and group, lock-step over the longest sweep."""
-    say("uneven batch")
+    say(f"uneven batch window={delay}")
     # patch links drawn on the 2x2 lattice exist on every lattice of the batch
     specs = [spec_for(2, 1, 2), spec_for(2, 2, 3), spec_for(2, 3, 2)]
     Ls = [2, 4, 6, 4, 6, 2]
     tids = [0, 1, 2, 0, 1, 2]
-    ctx = gpu_context(specs, Ls, tensor_ids=tids, init=1)
+    ctx = gpu_context(specs, Ls, tensor_ids=tids, init=1, delay=delay)
     orc = [oracle_chain(specs[t], L, c, init=1)[1] for c, (L, t) in enumerate(zip(Ls, tids))]
     for _ in range(3):
         ctx.sweep(1)
@@ -222,6 +263,9 @@ def test_invalid_inputs_rejected():
             ctx.init_chains([L], [tid], 1)
     with pytest.raises(GGFError):
         ctx.init_chains([4], [tid + 7], 1)
+    for bad_delay in (12, 40, -2):
+        with pytest.raises(GGFError):
+            ctx.set_option("delay", bad_delay)
     ctx.init_chains([2], [tid], 1)
     ctx.sweep(0)
     with pytest.raises(GGFError):
