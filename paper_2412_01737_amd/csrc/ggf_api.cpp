@@ -366,10 +366,10 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
   int k = 0;
   for (int ell = 0; ell < ctx->max_links; ++ell) {
     const int t = F > 0 ? ell % F : 0;
-    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax, t);
+    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax, t, ctx->n_max);
     if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
-    if (F > 0) ggf_launch_flush(lc, ctx->all_list, ctx->all_cnt, 512);
+    if (F > 0) ggf_launch_flush(lc, ctx->all_list, ctx->all_cnt, 1024);
     else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
     ++k;

@@ -48,7 +48,7 @@ void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_ref
 
 // One link step: ratio + decision + factors, then the streaming rank-4 update
 // (or, with delayed updates, the factors of window slot t).
-void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t);
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int n_max);
 // Delayed updates: G -= X Y^T for every chain with a pending flip in the window
 // (matrix-core GEMM of rank 4 * pend[c] rounded up to 16); all_list holds 0..n_chains-1
 // and all_cnt[0] = n_chains.

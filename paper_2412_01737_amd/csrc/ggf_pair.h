@@ -14,27 +14,25 @@ constexpr int kPairLd = 16;   // leading dimension of the per-pair 2s x 2s works
 
 // Read access to the current inverse G_cur = G - X Y^T: X and Y hold the
 // pending Woodbury factors of the accepted flips of the current window of link
-// steps (row-major n x ld, r columns in use; r = 0 when nothing is pending).
+// steps, stored slot-major (column s of X is X[s * n .. s * n + n), r columns in
+// use; r = 0 when nothing is pending).
 template <typename T>
 struct GView {
   const T *G;
   int n;
   const T *X, *Y;
-  int ld, r;
+  int r;
   __device__ double at(int a, int b) const {
     double v = static_cast<double>(G[static_cast<size_t>(a) * n + b]);
-    if (r > 0) {
-      const T *xa = X + static_cast<size_t>(a) * ld;
-      const T *yb = Y + static_cast<size_t>(b) * ld;
-      for (int s = 0; s < r; ++s) v -= static_cast<double>(xa[s]) * static_cast<double>(yb[s]);
-    }
+    for (int s = 0; s < r; ++s)
+      v -= static_cast<double>(X[static_cast<size_t>(s) * n + a]) * static_cast<double>(Y[static_cast<size_t>(s) * n + b]);
     return v;
   }
 };
 
 template <typename T>
 __device__ inline GView<T> plain_view(const T *G, int n) {
-  return GView<T>{G, n, nullptr, nullptr, 0, 0};
+  return GView<T>{G, n, nullptr, nullptr, 0};
 }
 
 struct PatchSet {

@@ -17,7 +17,8 @@
 //
 // Delayed updates (lc.dld > 0): the flips of a window of F link steps are not
 // applied at once.  Step t of the window reads the current inverse as
-// G - X Y^T (X, Y: n x 4F, slots 0..t-1 filled); on accept the workgroup writes
+// G - X Y^T (X, Y: 4F columns of length n stored one after another, slots
+// 0..t-1 filled); on accept the workgroup writes
 // slot t: X[:, 4t..4t+3] = G_cur[:,U] K and Y[:, 4t..4t+3] = G_cur[U,:]^T, so that
 // G_cur' = G_cur - G_cur[:,U] K G_cur[U,:]; a rejected or absent step writes
 // zeros.  At the end of the window one matrix-core GEMM applies G -= X Y^T
@@ -44,16 +45,16 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   const ChainDev ch = lc.chains[c];
   const int n = ch.n;
   const bool delayed = lc.dld > 0;
-  const int ld = lc.dld, r = delayed ? 4 * t : 0;
+  const int r = delayed ? 4 * t : 0;
   T *X = delayed ? static_cast<T *>(lc.X) + lc.x_off[c] : nullptr;
   T *Y = delayed ? static_cast<T *>(lc.Y) + lc.x_off[c] : nullptr;
   // a step without an accepted flip leaves zeros in its slot of the window
   auto zero_slot = [&]() {
-    for (int j = threadIdx.x; j < n; j += blockDim.x)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        X[static_cast<size_t>(j) * ld + r + q] = static_cast<T>(0);
-        Y[static_cast<size_t>(j) * ld + r + q] = static_cast<T>(0);
+    for (int q = 0; q < 4; ++q)
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        X[static_cast<size_t>(r + q) * n + j] = static_cast<T>(0);
+        Y[static_cast<size_t>(r + q) * n + j] = static_cast<T>(0);
       }
   };
   if (ell >= ch.nlinks) {
@@ -70,8 +71,8 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   ggf_link_u(ell, ch.L, U);
   for (int i = threadIdx.x; i < 4 * r; i += blockDim.x) {
     const int q = i / r, s = i - q * r;
-    s_xu[q][s] = static_cast<double>(X[static_cast<size_t>(U[q]) * ld + s]);
-    s_yu[q][s] = static_cast<double>(Y[static_cast<size_t>(U[q]) * ld + s]);
+    s_xu[q][s] = static_cast<double>(X[static_cast<size_t>(s) * n + U[q]]);
+    s_yu[q][s] = static_cast<double>(Y[static_cast<size_t>(s) * n + U[q]]);
   }
   __syncthreads();
   if (threadIdx.x < 16) {
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
       pair_of(threadIdx.x, K, a, b);
       PatchSet ps;
       double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
-      const GView<T> gv{G, n, X, Y, ld, r};
+      const GView<T> gv{G, n, X, Y, r};
       build_pair_matrix(Tn, a, b, ch.L, ch.group, gv, lk, U, s_K, ell, s_kn, W, ps);
       s_r[threadIdx.x] = pair_ratio(W, ps.s);
     }
@@ -178,21 +179,26 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
                       static_cast<double>(G[static_cast<size_t>(u1) * n + j]),
                       static_cast<double>(G[static_cast<size_t>(u2) * n + j]),
                       static_cast<double>(G[static_cast<size_t>(u3) * n + j])};
-      T *xj = X + static_cast<size_t>(j) * ld;
-      T *yj = Y + static_cast<size_t>(j) * ld;
-      for (int s = 0; s < r; ++s) {
-        const double xs = static_cast<double>(xj[s]), ys = static_cast<double>(yj[s]);
+      for (int s0 = 0; s0 < r; s0 += 4) {     // r is a multiple of 4: four slots' loads in flight
+        double xs[4], ys[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          gc[q] -= xs * s_yu[q][s];
-          gr[q] -= s_xu[q][s] * ys;
+        for (int d = 0; d < 4; ++d) {
+          xs[d] = static_cast<double>(X[static_cast<size_t>(s0 + d) * n + j]);
+          ys[d] = static_cast<double>(Y[static_cast<size_t>(s0 + d) * n + j]);
         }
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            gc[q] -= xs[d] * s_yu[q][s0 + d];
+            gr[q] -= s_xu[q][s0 + d] * ys[d];
+          }
       }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        xj[r + b] = static_cast<T>(gc[0] * s_K[0 * 4 + b] + gc[1] * s_K[1 * 4 + b] + gc[2] * s_K[2 * 4 + b] +
-                                   gc[3] * s_K[3 * 4 + b]);
-        yj[r + b] = static_cast<T>(gr[b]);
+        X[static_cast<size_t>(r + b) * n + j] = static_cast<T>(
+            gc[0] * s_K[0 * 4 + b] + gc[1] * s_K[1 * 4 + b] + gc[2] * s_K[2 * 4 + b] + gc[3] * s_K[3 * 4 + b]);
+        Y[static_cast<size_t>(r + b) * n + j] = static_cast<T>(gr[b]);
       }
     }
     return;
@@ -549,12 +555,16 @@ static size_t pair_lds(int kmax) {
   return np > 0 ? static_cast<size_t>(np) * kPairLd * kPairLd * sizeof(double2) : 0;
 }
 
-void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t) {
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int n_max) {
   const size_t lds = pair_lds(kmax);
+  // (one wave per chain was measured slower on 8x8 float64: the pending-factor reads of an
+  // accepted flip need the full workgroup)
+  const int threads = 256;
+  (void)n_max;
   if (lc.precision == 64)
-    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t);
+    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(threads), lds, lc.stream, lc, ell, parity, t);
   else
-    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t);
+    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(threads), lds, lc.stream, lc, ell, parity, t);
 }
 
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt) {
