@@ -5,14 +5,18 @@ Workload (default): Z2 gauge field on an 8x8 periodic lattice (128 links,
 n = 512 virtual Majoranas), the seeded Haar on-site Gaussian tensor, K = 1,
 4096 independent chains, float64 inverse with a float64 refactorisation every
 1024 accepted flips per chain.  A step is one sweep of every chain (128
-proposals each: ratio, Metropolis decision, rank-4 Woodbury update on accept)
-followed by the plaquette / 2x2 Wilson loop / density measurement.
+proposals each: ratio and Metropolis decision on the current inverse, the
+Woodbury factors of an accepted flip kept pending, and one matrix-core flush
+of the pending flips per window of 16 link steps) followed by the plaquette /
+2x2 Wilson loop / density measurement.
 
 Prints one JSON line: link-update proposals per second (value), effective
 samples per second of the lattice-mean plaquette, the HBM roofline of the
-rank-4 update kernel (bytes: 2 n^2 * 8 per accepted flip, time: HIP events
-around every update launch on its stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+dominant kernel (the window flush: one read and one write of every chain's G
+per window; time: HIP events around every flush launch on its stream; with
+--delay 0 the rank-4 update, 2 n^2 * 8 bytes per accepted flip), the time of
+the ratio kernels, and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -77,10 +81,10 @@ def parse():
                          "--workload c5 run and that run's JSON line, write profiles/k_block_traffic.json and exit")
     args = ap.parse_args()
     presets = {
-        "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=1024),
-        "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64),
-        "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64),
-        "c5": dict(steps=8, warmup=1, chains=256, L=32, K=2, group=2, precision=32, refresh=4096),
+        "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=1024, delay=16),
+        "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64, delay=16),
+        "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64, delay=16),
+        "c5": dict(steps=8, warmup=1, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
     }
     for k, v in presets[args.workload].items():
         if getattr(args, k) is None:
@@ -101,8 +105,9 @@ def traffic_from(args):
                 if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
         return sum(vals) / len(vals), len(vals)
 
-    fetch, nf = per_kernel(args.traffic_from[0], "FETCH_SIZE", "k_update")
-    write, nw = per_kernel(args.traffic_from[1], "WRITE_SIZE", "k_update")
+    kernel = "k_flush" if args.delay > 0 else "k_update"
+    fetch, nf = per_kernel(args.traffic_from[0], "FETCH_SIZE", kernel)
+    write, nw = per_kernel(args.traffic_from[1], "WRITE_SIZE", kernel)
     cfetch, _ = per_kernel(args.traffic_from[2], "FETCH_SIZE", "probe_copy")
     cwrite, _ = per_kernel(args.traffic_from[3], "WRITE_SIZE", "probe_copy")
     known_kib = args.copy_bytes / 1024.0
@@ -110,8 +115,9 @@ def traffic_from(args):
     rec = {"bytes_per_launch": (fetch * sf + write * sw) * 1024.0,
            "read_bytes_per_launch": fetch * sf * 1024.0, "write_bytes_per_launch": write * sw * 1024.0,
            "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
-           "fetch_scale": sf, "write_scale": sw, "source_digest": source_digest()}
-    key = f"L{args.L}_K{args.K}_Z{args.group}_p{args.precision}_c{args.chains}"
+           "fetch_scale": sf, "write_scale": sw, "kernel": kernel,
+           "source_digest": source_digest(KERNEL_SOURCE[kernel])}
+    key = traffic_key(args)
     try:
         with open(args.traffic_json) as f:
             tj = json.load(f)
@@ -203,6 +209,14 @@ def copy_probe(nbytes: int):
     print(json.dumps(out))
 
 
+KERNEL_SOURCE = {"k_update": "ggf_sweep.hip", "k_flush": "ggf_block.inc"}
+
+
+def traffic_key(args) -> str:
+    key = f"L{args.L}_K{args.K}_Z{args.group}_p{args.precision}_c{args.chains}"
+    return key + (f"_flush{args.delay}" if args.delay > 0 else "")
+
+
 def source_digest(name: str = "ggf_sweep.hip") -> str:
     """Digest of a kernel source file; traffic counters are only reported for the kernel they measured."""
     import hashlib
@@ -284,6 +298,7 @@ def run_c5(args):
 
     t0 = time.perf_counter()
     tr = Context(0)
+    tr.set_option("delay", args.delay)
     tid = tr.set_tensor_spec(spec)
     tr.init_chains([L] * args.train_chains, tid, synth.SEED_CHAIN + 1, init=1, precision=32,
                    refresh_every=args.refresh, stream=stream)
@@ -300,6 +315,7 @@ def run_c5(args):
 
     def sampler(chains, precision, refresh, learned, steps, warmup):
         ctx = Context(0)
+        ctx.set_option("delay", args.delay)
         tid = ctx.set_tensor_spec(spec)
         ti = time.perf_counter()
         ctx.init_chains([L] * chains, tid, synth.SEED_CHAIN, init=1, precision=precision,
@@ -386,7 +402,7 @@ def run_c5(args):
         "config": {"workload": (f"Z{group} {L}x{L} periodic, K={K}, {args.chains} chains, learned 4x4-patch block "
                                 f"proposal (4-layer 3x3 conv, 32 channels, bf16 weights), float32 inverse, float64 "
                                 f"refresh every {args.refresh} changed links; vs the plain float64 single-link "
-                                f"sampler on {args.plain_chains} chains"),
+                                f"sampler (delayed updates, window {args.delay}) on {args.plain_chains} chains"),
                    "name": "c5", "L": L, "K": K, "group": group, "chains": args.chains, "n": n, "patch": P,
                    "precision": args.precision, "refresh_every": args.refresh},
         "learned": learned,
@@ -461,8 +477,7 @@ def main():
     if args.update_tiles:
         ctx.set_option("update_tiles", args.update_tiles)
     ctx.set_option("graph", args.graph)
-    if args.delay is not None:
-        ctx.set_option("delay", args.delay)
+    ctx.set_option("delay", args.delay)
     if not args.autotune:
         ctx.set_option("update_nt", args.update_nt)
     mask = OBS_LINK | OBS_DENSITY
@@ -472,6 +487,7 @@ def main():
         ctx.measure(mask, obs[w], stream=stream)
     ctx.set_option("time_update", 1)
     upd_ms, upd_launches, upd_flips = 0.0, 0, 0
+    rat_ms, rat_launches = 0.0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -480,6 +496,9 @@ def main():
         upd_ms += ms
         upd_launches += la
         upd_flips += fl
+        ms, la = ctx.ratio_timing()
+        rat_ms += ms
+        rat_launches += la
         ctx.measure(mask, obs[args.warmup + s], stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -499,13 +518,26 @@ def main():
         bytes_per_flip = float((acc * 2.0 * n_c.astype(np.float64) ** 2 * esz).sum() / max(acc.sum(), 1.0))
     else:
         bytes_per_flip = 2.0 * n * n * esz
-    achieved = (upd_flips * bytes_per_flip / upd_launches) / (upd_ms / upd_launches * 1e-3) / 1e9 if upd_ms > 0 else 0.0
+    F = args.delay
+    if F > 0:
+        # delayed updates: the dominant kernel is the window flush, one read and one write of
+        # each chain's G per window in which the chain has a pending flip (at these acceptances,
+        # every window it has link steps in); the X, Y operand reads are not counted
+        nl_c = 2 * Lc.astype(np.int64) ** 2
+        windows = -(-int(nl_c.max()) // F)
+        share = np.minimum(-(-nl_c // F), windows) / windows
+        bytes_per_launch = float((share * 2.0 * n_c.astype(np.float64) ** 2 * esz).sum())
+        kernel = "k_flush"
+    else:
+        bytes_per_launch = upd_flips * bytes_per_flip / max(upd_launches, 1)
+        kernel = "k_update"
+    achieved = bytes_per_launch / (upd_ms / upd_launches * 1e-3) / 1e9 if upd_ms > 0 else 0.0
     traffic = None
     try:
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        key = f"L{L}_K{K}_Z{group}_p{args.precision}_c{args.chains}"
-        if key in tj and tj[key].get("source_digest") == source_digest():
+        key = traffic_key(args)
+        if key in tj and tj[key].get("source_digest") == source_digest(KERNEL_SOURCE[kernel]):
             traffic = tj[key]["bytes_per_launch"]
     except (OSError, ValueError):
         pass
@@ -534,7 +566,7 @@ def main():
                     f"accepted flips"),
                    "name": args.workload, "L": L, "K": K, "group": group, "chains": args.chains, "n_max": n,
                    "precision": args.precision, "refresh_every": args.refresh, "graph": args.graph,
-                   "autotuned": list(tuned) if tuned else None},
+                   "delay_window": F, "autotuned": list(tuned) if tuned else None},
         "effective_samples_per_s": ess_per_s,
         "tau_int_plaquette": tau,
         "tau_int_err": tau_err,
@@ -544,8 +576,9 @@ def main():
         "init_s": t_init,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_update", "bytes_per_flip": bytes_per_flip,
+                     "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "update_ms_total": upd_ms, "update_launches": upd_launches, "flips": upd_flips},
+        "kernels_ms_per_step": {kernel: upd_ms / args.steps, "k_ratio": rat_ms / args.steps},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -182,6 +182,12 @@ ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *
  * of changed links over accepted block moves for ggf_block_sweep). */
 ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_t *flips);
 
+/* Duration in milliseconds of the ratio / decision kernels (one launch per link
+ * step: ratio, Metropolis decision and, on accept, the update factors) of the
+ * most recent ggf_sweep call, measured like ggf_update_timing (0 when timing
+ * is off), and the number of launches. */
+ggf_status ggf_ratio_timing(ggf_ctx *ctx, double *ms, int64_t *launches);
+
 /* Integrated autocorrelation time of n_series Monte Carlo series sampled at
  * n_t times, series[t * n_series + s] (host float64).  Each series is centred
  * on its own mean; the autocovariance is averaged over series, normalised,

@@ -87,8 +87,10 @@ struct ggf_ctx {
   int dly_F = 0;
 
   // update timing
-  std::vector<hipEvent_t> tev;
-  int timed_launches = 0;        // event pairs recorded by the last record_sweep
+  std::vector<hipEvent_t> tev, rev;   // update / ratio kernel events
+  int timed_launches = 0;        // update event pairs recorded by the last record_sweep
+  double last_ratio_ms = 0.0;
+  long long last_ratio_launches = 0;
   double last_update_ms = 0.0;
   long long last_launches = 0, last_flips = 0;
 };
@@ -366,10 +368,12 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
   int k = 0;
   for (int ell = 0; ell < ctx->max_links; ++ell) {
     const int t = F > 0 ? ell % F : 0;
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell], s));
     ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax, t, ctx->n_max);
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell + 1], s));
     if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
-    if (F > 0) ggf_launch_flush(lc, ctx->all_list, ctx->all_cnt, 1024);
+    if (F > 0) ggf_launch_flush(lc, ctx->all_list, ctx->all_cnt, 1024, ctx->n_max);
     else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
     ++k;
@@ -691,10 +695,16 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   ctx->last_update_ms = 0.0;
   ctx->last_launches = 0;
   ctx->last_flips = 0;
-  if (timed && ctx->tev.size() < static_cast<size_t>(2 * ctx->max_links)) {
+  ctx->last_ratio_ms = 0.0;
+  ctx->last_ratio_launches = 0;
+  if (timed && (ctx->tev.size() < static_cast<size_t>(2 * ctx->max_links) ||
+                ctx->rev.size() < static_cast<size_t>(2 * ctx->max_links))) {
     for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
+    for (hipEvent_t ev : ctx->rev) hipEventDestroy(ev);
     ctx->tev.assign(2 * ctx->max_links, nullptr);
+    ctx->rev.assign(2 * ctx->max_links, nullptr);
     for (auto &ev : ctx->tev) HIP_TRY(ctx, hipEventCreate(&ev));
+    for (auto &ev : ctx->rev) HIP_TRY(ctx, hipEventCreate(&ev));
   }
   std::vector<unsigned long long> acc0;
   if (timed) {
@@ -734,6 +744,12 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
           ctx->last_update_ms += ms;
         }
         ctx->last_launches += ctx->timed_launches;
+        for (int ell = 0; ell < ctx->max_links; ++ell) {
+          float ms = 0.f;
+          HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->rev[2 * ell], ctx->rev[2 * ell + 1]));
+          ctx->last_ratio_ms += ms;
+        }
+        ctx->last_ratio_launches += ctx->max_links;
       }
     }
     ggf_status st = after_sweep(ctx, s);
@@ -949,6 +965,13 @@ ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_
   if (ms) *ms = ctx->last_update_ms;
   if (launches) *launches = ctx->last_launches;
   if (flips) *flips = ctx->last_flips;
+  return GGF_OK;
+}
+
+ggf_status ggf_ratio_timing(ggf_ctx *ctx, double *ms, int64_t *launches) {
+  if (!ctx) return GGF_EINVAL;
+  if (ms) *ms = ctx->last_ratio_ms;
+  if (launches) *launches = ctx->last_ratio_launches;
   return GGF_OK;
 }
 

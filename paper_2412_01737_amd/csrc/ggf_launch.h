@@ -52,7 +52,7 @@ void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t,
 // Delayed updates: G -= X Y^T for every chain with a pending flip in the window
 // (matrix-core GEMM of rank 4 * pend[c] rounded up to 16); all_list holds 0..n_chains-1
 // and all_cnt[0] = n_chains.
-void ggf_launch_flush(const LaunchCtx &lc, const int *all_list, int *all_cnt, int grid);
+void ggf_launch_flush(const LaunchCtx &lc, const int *all_list, int *all_cnt, int grid, int n_max);
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt);
 void ggf_launch_end_sweep(const LaunchCtx &lc);
 void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);

@@ -16,13 +16,26 @@ constexpr int kPairLd = 16;   // leading dimension of the per-pair 2s x 2s works
 // pending Woodbury factors of the accepted flips of the current window of link
 // steps, stored slot-major (column s of X is X[s * n .. s * n + n), r columns in
 // use; r = 0 when nothing is pending).
+// Entries whose both indices are among the nc Majoranas cidx[] are served from
+// `cache` (nc x nc, leading dimension 16, already corrected for the pending flips).
 template <typename T>
 struct GView {
   const T *G;
   int n;
   const T *X, *Y;
   int r;
+  const double *cache = nullptr;
+  const int *cidx = nullptr;
+  int nc = 0;
   __device__ double at(int a, int b) const {
+    if (nc > 0) {
+      int pa = -1, pb = -1;
+      for (int i = 0; i < nc; ++i) {
+        if (cidx[i] == a) pa = i;
+        if (cidx[i] == b) pb = i;
+      }
+      if (pa >= 0 && pb >= 0) return cache[pa * 16 + pb];
+    }
     double v = static_cast<double>(G[static_cast<size_t>(a) * n + b]);
     for (int s = 0; s < r; ++s)
       v -= static_cast<double>(X[static_cast<size_t>(s) * n + a]) * static_cast<double>(Y[static_cast<size_t>(s) * n + b]);

@@ -35,7 +35,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity, int t) {
   extern __shared__ double2 s_work[];
   __shared__ double s_K[16];
-  __shared__ double s_guu[16];
+  __shared__ double s_GI[16 * 16];     // current inverse on the link's and the patch links' Majoranas
+  __shared__ int s_I[16];
+  __shared__ int s_nI;
   __shared__ double s_xu[4][4 * kDelaySlotsMax], s_yu[4][4 * kDelaySlotsMax];   // X[U,:r], Y[U,:r]
   __shared__ double s_rho, s_u;
   __shared__ int s_kn, s_acc;
@@ -74,12 +76,36 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     s_xu[q][s] = static_cast<double>(X[static_cast<size_t>(s) * n + U[q]]);
     s_yu[q][s] = static_cast<double>(Y[static_cast<size_t>(s) * n + U[q]]);
   }
+  const int K = ch.K;
+  const int npairs = K * (K + 1) / 2 - 1;
+  if (threadIdx.x == 0) {
+    // index set: U first, then the Majoranas of every patch link of the superposition
+    int m = 0;
+    for (int q = 0; q < 4; ++q) s_I[m++] = U[q];
+    for (int p = 0; p < npairs; ++p) {
+      int a, b;
+      pair_of(p, K, a, b);
+      for (int l = 0; l < Tn.nl[a][b]; ++l) {
+        int u4[4];
+        ggf_link_u(Tn.lk[a][b][l], ch.L, u4);
+        for (int q = 0; q < 4; ++q) {
+          bool seen = false;
+          for (int i = 0; i < m; ++i) seen |= s_I[i] == u4[q];
+          if (!seen && m < 16) s_I[m++] = u4[q];
+        }
+      }
+    }
+    s_nI = m;
+  }
   __syncthreads();
-  if (threadIdx.x < 16) {
-    const int a = threadIdx.x >> 2, b = threadIdx.x & 3;
-    double v = static_cast<double>(G[static_cast<size_t>(U[a]) * n + U[b]]);
-    for (int s = 0; s < r; ++s) v -= s_xu[a][s] * s_yu[b][s];
-    s_guu[threadIdx.x] = v;
+  const int nI = s_nI;
+  for (int e = threadIdx.x; e < nI * nI; e += blockDim.x) {
+    const int i = e / nI, j = e - i * nI;
+    const int a = s_I[i], b = s_I[j];
+    double v = static_cast<double>(G[static_cast<size_t>(a) * n + b]);
+    for (int s = 0; s < r; ++s)
+      v -= static_cast<double>(X[static_cast<size_t>(s) * n + a]) * static_cast<double>(Y[static_cast<size_t>(s) * n + b]);
+    s_GI[i * 16 + j] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -96,7 +122,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
         double v = (a == b) ? 1.0 : 0.0;
-        for (int q = 0; q < 4; ++q) v += s_guu[a * 4 + q] * dM[q * 4 + b];
+        for (int q = 0; q < 4; ++q) v += s_GI[a * 16 + q] * dM[q * 4 + b];
         A[a * 4 + b] = v;
         Ai[a * 4 + b] = (a == b) ? 1.0 : 0.0;
       }
@@ -112,15 +138,16 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     s_u = ggf_u53(x.x, x.y);
   }
   __syncthreads();
-  const int K = ch.K;
-  const int npairs = K * (K + 1) / 2 - 1;
   if (K > 1) {
     if (threadIdx.x < npairs) {
       int a, b;
       pair_of(threadIdx.x, K, a, b);
       PatchSet ps;
       double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
-      const GView<T> gv{G, n, X, Y, r};
+      GView<T> gv{G, n, X, Y, r};
+      gv.cache = s_GI;
+      gv.cidx = s_I;
+      gv.nc = nI;
       build_pair_matrix(Tn, a, b, ch.L, ch.group, gv, lk, U, s_K, ell, s_kn, W, ps);
       s_r[threadIdx.x] = pair_ratio(W, ps.s);
     }

@@ -60,6 +60,7 @@ EXPORTS = {
                                     ctypes.c_void_p]),
     "ggf_update_timing": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "ggf_ratio_timing": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "ggf_autocorr_time": (ctypes.c_int, [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _dp, _dp,
                                          ctypes.POINTER(ctypes.c_int64)]),
     "ggf_nn_nparams": (ctypes.c_int32, []),
@@ -287,6 +288,13 @@ class Context:
                                            None if cache_path is None else cache_path.encode(), best,
                                            _stream_ptr(stream)))
         return tuple(best)
+
+    def ratio_timing(self):
+        """(ms, launches) of the ratio / decision kernels of the last timed sweep call."""
+        ms = ctypes.c_double()
+        la = ctypes.c_int64()
+        self._check(self._lib.ggf_ratio_timing(self.h, ctypes.byref(ms), ctypes.byref(la)))
+        return ms.value, la.value
 
     def update_timing(self):
         ms = ctypes.c_double()
