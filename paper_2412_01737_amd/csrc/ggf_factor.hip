@@ -244,8 +244,11 @@ __global__ __launch_bounds__(256) void k_gj_swapcopy(const int *__restrict__ lis
 // Z[row li][k g] and Y[k g][col li] and holds X[rows g + 4 e][col li], so the
 // accumulator loads and stores cover 128 contiguous bytes of a row per 16 lanes.
 // Z = the panel columns (final), Y = the snapshot of the pivot rows.
+// TC = columns per workgroup tile (32, 64 or 128): narrow tiles for the updates
+// inside a panel, whose width is the panel half being applied.
 constexpr int kGT = 128, kGK = 16;
 typedef double gj_acc_t __attribute__((ext_vector_type(4)));
+template <int TC>
 __global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list, int count,
                                                  const ChainDev *__restrict__ chains, double *__restrict__ scr,
                                                  const double *__restrict__ ybuf, int pj, int pw, int c_lo, int c_hi) {
@@ -255,25 +258,26 @@ __global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list
   const int n = ch.n;
   if (pj >= n) return;
   const int hi = min(c_hi, n);
-  const int r0 = blockIdx.y * kGT, c0 = c_lo + blockIdx.x * kGT;
+  constexpr int CB = TC / 32;                          // 16-column blocks per wave
+  const int r0 = blockIdx.y * kGT, c0 = c_lo + blockIdx.x * TC;
   if (r0 >= n || c0 >= hi) return;
   const int pwe = min(pw, n - pj);
-  if (c0 >= pj && c0 + kGT <= pj + pwe) return;     // tile entirely inside the panel
+  if (c0 >= pj && c0 + TC <= pj + pwe) return;      // tile entirely inside the panel
   double *A = scr + ch.scr_off;
   const double *Y = ybuf + ch.y_off;
   __shared__ double sZ[kGK][kGT + 1];
-  __shared__ double sY[kGK][kGT + 1];
+  __shared__ double sY[kGK][TC + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
-  gj_acc_t acc[4][4];
+  const int wr = 64 * (w >> 1), wc = (TC / 2) * (w & 1);
+  gj_acc_t acc[4][CB];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = static_cast<gj_acc_t>(0.0);
+    for (int c = 0; c < CB; ++c) acc[a][c] = static_cast<gj_acc_t>(0.0);
   // staging map: Z chunk by (row q = t/2, k half kh = 8 (t&1)), Y chunk by (k = t/128, col)
   const int zq = threadIdx.x >> 1, zk = (threadIdx.x & 1) * 8;
-  double zreg[8], yreg[8];
+  double zreg[8], yreg[TC / 16];
   auto load_chunk = [&](int k0) {
     const int rr = r0 + zq;
 #pragma unroll
@@ -282,9 +286,9 @@ __global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list
       zreg[i] = (k0 + kk < pwe && rr < n) ? A[static_cast<size_t>(rr) * n + pj + k0 + kk] : 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < TC / 16; ++i) {
       const int t = threadIdx.x + 256 * i;
-      const int kk = t / kGT, q = t - kk * kGT;
+      const int kk = t / TC, q = t - kk * TC;
       const int cc = c0 + q;
       yreg[i] = (k0 + kk < pwe && cc < hi) ? Y[static_cast<size_t>(k0 + kk) * n + cc] : 0.0;
     }
@@ -294,23 +298,23 @@ __global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list
 #pragma unroll
     for (int i = 0; i < 8; ++i) sZ[zk + i][zq] = zreg[i];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < TC / 16; ++i) {
       const int t = threadIdx.x + 256 * i;
-      sY[t / kGT][t % kGT] = yreg[i];
+      sY[t / TC][t % TC] = yreg[i];
     }
     __syncthreads();
     if (k0 + kGK < pwe) load_chunk(k0 + kGK);
 #pragma unroll
     for (int k4 = 0; k4 < kGK; k4 += 4) {
-      double zo[4], yo[4];
+      double zo[4], yo[CB];
 #pragma unroll
       for (int a = 0; a < 4; ++a) zo[a] = sZ[k4 + g][wr + 16 * a + li];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) yo[c] = sY[k4 + g][wc + 16 * c + li];
+      for (int c = 0; c < CB; ++c) yo[c] = sY[k4 + g][wc + 16 * c + li];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(zo[a], yo[c], acc[a][c], 0, 0, 0);
+        for (int c = 0; c < CB; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(zo[a], yo[c], acc[a][c], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = r0 + wr + 16 * a + g + 4 * e, col = c0 + wc + 16 * c + li;
@@ -409,9 +413,16 @@ void gj_apply(const GJRun &g, int pj, int pw, int c_lo, int c_hi) {
   const int width = c_hi - c_lo;
   hipLaunchKernelGGL(k_gj_swapcopy, dim3((width + 255) / 256, g.count), dim3(256), 0, g.lc.stream, g.list, g.count,
                      g.lc.chains, g.lc.scratch, g.piv, g.piv_stride, g.ybuf, pj, pw, c_lo, c_hi);
-  dim3 grid((width + kGT - 1) / kGT, (g.n_max + kGT - 1) / kGT, g.count);
-  hipLaunchKernelGGL(k_gj_gemm, grid, dim3(256), 0, g.lc.stream, g.list, g.count, g.lc.chains, g.lc.scratch, g.ybuf,
-                     pj, pw, c_lo, c_hi);
+  const dim3 rows(1, (g.n_max + kGT - 1) / kGT, g.count);
+  if (width <= 32)
+    hipLaunchKernelGGL(k_gj_gemm<32>, dim3((width + 31) / 32, rows.y, rows.z), dim3(256), 0, g.lc.stream, g.list,
+                       g.count, g.lc.chains, g.lc.scratch, g.ybuf, pj, pw, c_lo, c_hi);
+  else if (width <= 64)
+    hipLaunchKernelGGL(k_gj_gemm<64>, dim3((width + 63) / 64, rows.y, rows.z), dim3(256), 0, g.lc.stream, g.list,
+                       g.count, g.lc.chains, g.lc.scratch, g.ybuf, pj, pw, c_lo, c_hi);
+  else
+    hipLaunchKernelGGL(k_gj_gemm<128>, dim3((width + 127) / 128, rows.y, rows.z), dim3(256), 0, g.lc.stream,
+                       g.list, g.count, g.lc.chains, g.lc.scratch, g.ybuf, pj, pw, c_lo, c_hi);
 }
 
 // Factor the panel columns [j, j+w): recursively, left half, its transform on the right half,
