@@ -80,11 +80,10 @@ struct ggf_ctx {
   int *blk_U = nullptr, *blk_r = nullptr;
   unsigned long long *blk_prop = nullptr, *blk_acc = nullptr;
 
-  // delayed-update buffers (tied to the chains): X, Y arenas of width 4 * dly_F
-  void *dly_X = nullptr, *dly_Y = nullptr;
-  size_t *dly_off = nullptr;
-  int *dly_pend = nullptr, *all_list = nullptr, *all_cnt = nullptr;
-  int dly_F = 0;
+  // delayed-update state (tied to the chains; with the block-move buffers): link changes of
+  // the pending flips, window list counters
+  double *dly_dX = nullptr;
+  int *dly_cnt = nullptr;
 
   // update timing
   std::vector<hipEvent_t> tev, rev;   // update / ratio kernel events
@@ -194,10 +193,8 @@ void free_chains(ggf_ctx *ctx) {
   ctx->allocs.clear();
   ctx->blk_A = ctx->blk_W = nullptr;
   ctx->blk_C = ctx->blk_D = nullptr;
-  ctx->dly_X = ctx->dly_Y = nullptr;
-  ctx->dly_off = nullptr;
-  ctx->dly_pend = ctx->all_list = ctx->all_cnt = nullptr;
-  ctx->dly_F = 0;
+  ctx->dly_dX = nullptr;
+  ctx->dly_cnt = nullptr;
   ctx->blk_doff = nullptr;
   ctx->blk_U = ctx->blk_r = nullptr;
   ctx->blk_prop = ctx->blk_acc = nullptr;
@@ -232,11 +229,13 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.acc_list = ctx->acc_list;
   lc.acc_cnt = ctx->acc_cnt;
   lc.scratch = ctx->scratch;
-  lc.X = ctx->dly_X;
-  lc.Y = ctx->dly_Y;
-  lc.x_off = ctx->dly_off;
-  lc.pend = ctx->dly_pend;
-  lc.dld = 0;                     // set by record_sweep when the window is delayed
+  lc.dly = 0;                      // set by record_sweep when the window is delayed
+  lc.dU = ctx->blk_U;
+  lc.dr = ctx->blk_r;
+  lc.dcnt = ctx->dly_cnt;
+  lc.dBinv = ctx->blk_A;
+  lc.dW = ctx->blk_W;
+  lc.dX = ctx->dly_dX;
   lc.key0 = static_cast<uint32_t>(ctx->seed & 0xFFFFFFFFu);
   lc.key1 = static_cast<uint32_t>(ctx->seed >> 32);
   lc.n_chains = ctx->n_chains;
@@ -311,50 +310,19 @@ int delay_window(const ggf_ctx *ctx) {
   return want;
 }
 
-// Allocate the pending-factor arenas for window F (X, Y: n x 4F per chain).
+ggf_status block_buffers(ggf_ctx *ctx);
+
+// State of delayed updates: the block-move buffers (window inverse, W, pending
+// Majoranas, operands of the window flush) plus the pending link changes and the
+// window-list counters; independent of the window length.
 ggf_status delay_buffers(ggf_ctx *ctx, int F) {
-  if (F == 0 || ctx->dly_F == F) return GGF_OK;
+  if (F == 0 || ctx->dly_cnt) return GGF_OK;
+  ggf_status st = block_buffers(ctx);
+  if (st != GGF_OK) return st;
   hipError_t e = hipSuccess;
-  if (ctx->dly_F != 0) {
-    // another window width: nothing is pending between sweeps, so the arenas are simply replaced
-    HIP_TRY(ctx, hipDeviceSynchronize());
-    for (void *p : {ctx->dly_X, ctx->dly_Y}) {
-      ctx->allocs.erase(std::remove(ctx->allocs.begin(), ctx->allocs.end(), p), ctx->allocs.end());
-      HIP_TRY(ctx, hipFree(p));
-    }
-    ctx->dly_X = ctx->dly_Y = nullptr;
-    ctx->dly_F = 0;
-  }
-  const size_t esz = ctx->precision == 64 ? sizeof(double) : sizeof(float);
-  std::vector<size_t> off(ctx->n_chains);
-  size_t tot = 0;
-  for (int c = 0; c < ctx->n_chains; ++c) {
-    off[c] = tot;
-    tot += static_cast<size_t>(4 * F) * ctx->chains[c].n;
-  }
-  std::vector<int> all(ctx->n_chains);
-  for (int c = 0; c < ctx->n_chains; ++c) all[c] = c;
-  const int cnt[2] = {ctx->n_chains, ctx->n_chains};
-  if (!ctx->dly_off) {
-    ctx->dly_off = dalloc<size_t>(ctx, ctx->n_chains, e);
-    ctx->dly_pend = dalloc<int>(ctx, ctx->n_chains, e);
-    ctx->all_list = dalloc<int>(ctx, ctx->n_chains, e);
-    ctx->all_cnt = dalloc<int>(ctx, 2, e);
-  }
-  for (void **dst : {&ctx->dly_X, &ctx->dly_Y}) {
-    if (e != hipSuccess) break;
-    void *p = nullptr;
-    e = hipMalloc(&p, tot * esz);
-    if (e == hipSuccess) {
-      ctx->allocs.push_back(p);
-      *dst = p;
-    }
-  }
+  ctx->dly_dX = dalloc<double>(ctx, static_cast<size_t>(GGF_BLOCK_RMAX) * ctx->n_chains, e);
+  ctx->dly_cnt = dalloc<int>(ctx, 2, e);
   if (e != hipSuccess) return fail(ctx, GGF_ENOMEM, "cannot allocate delayed-update buffers");
-  HIP_TRY(ctx, hipMemcpy(ctx->dly_off, off.data(), off.size() * sizeof(size_t), hipMemcpyHostToDevice));
-  HIP_TRY(ctx, hipMemcpy(ctx->all_list, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(ctx, hipMemcpy(ctx->all_cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice));
-  ctx->dly_F = F;
   return GGF_OK;
 }
 
@@ -363,17 +331,18 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
   const int tiles = ctx->opt_update_tiles > 0 ? ctx->opt_update_tiles : std::max(1, ctx->n_max / 16);
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 2048;
   const int F = delay_window(ctx);
-  if (F > 0 && ctx->dly_F != F) return fail(ctx, GGF_ESTATE, "delayed-update buffers are not allocated");
-  lc.dld = 4 * F;
+  if (F > 0 && !ctx->dly_cnt) return fail(ctx, GGF_ESTATE, "delayed-update buffers are not allocated");
+  lc.dly = F;
   int k = 0;
   for (int ell = 0; ell < ctx->max_links; ++ell) {
     const int t = F > 0 ? ell % F : 0;
+    const int wp = F > 0 ? (ell / F) & 1 : 0;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell], s));
-    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax, t, ctx->n_max);
+    ggf_launch_ratio(lc, ell, ell & 1, ctx->kmax, t, wp);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell + 1], s));
     if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
-    if (F > 0) ggf_launch_flush(lc, ctx->all_list, ctx->all_cnt, 1024, ctx->n_max);
+    if (F > 0) ggf_launch_window_flush(lc, wp, ctx->blk_C, ctx->blk_D, ctx->blk_doff, 1024);
     else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
     ++k;

@@ -28,13 +28,15 @@ struct LaunchCtx {
   int *acc_list;                 // compacted accepted chains of the current link step
   int *acc_cnt;                  // [2] double-buffered accepted counts
   double *scratch;               // float64 refactorisation scratch
-  // delayed updates (dld > 0): pending factors of the current window of link
-  // steps, G_cur = G - X Y^T, chain c's X and Y n x dld row-major at x_off[c];
-  // pend[c] = 1 + the window slot of the chain's last accepted flip (0: none)
-  void *X, *Y;
-  const size_t *x_off;
-  int *pend;
-  int dld;
+  // delayed updates (dly = window length F > 0): the flips accepted so far in
+  // the window are the Majoranas A (dU, 4 per flip, dr[c] of them) with their
+  // link changes dX (2x2 per flip); the current inverse is
+  // G - G[:,A] W G[A,:], W = dM_A Binv, Binv = (1 + G_AA dM_A)^-1 (float64,
+  // dBinv with leading dimension GGF_BLOCK_RMAX, dW with leading dimension dr[c]);
+  // chains with a flip pending are listed in acc_list, dcnt[window parity] of them
+  int dly;
+  int *dU, *dr, *dcnt;
+  double *dBinv, *dW, *dX;
   uint32_t key0, key1;
   int n_chains;
 };
@@ -48,11 +50,11 @@ void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_ref
 
 // One link step: ratio + decision + factors, then the streaming rank-4 update
 // (or, with delayed updates, the factors of window slot t).
-void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int n_max);
-// Delayed updates: G -= X Y^T for every chain with a pending flip in the window
-// (matrix-core GEMM of rank 4 * pend[c] rounded up to 16); all_list holds 0..n_chains-1
-// and all_cnt[0] = n_chains.
-void ggf_launch_flush(const LaunchCtx &lc, const int *all_list, int *all_cnt, int grid, int n_max);
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int wp);
+// Delayed updates, end of a window of parity wp: G -= G[:,A] W G[A,:] for every
+// listed chain (the block-update kernels; C, D: per-chain n x 128 operand buffers
+// at d_off[c]).
+void ggf_launch_window_flush(const LaunchCtx &lc, int wp, void *C, void *D, const size_t *d_off, int grid);
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt);
 void ggf_launch_end_sweep(const LaunchCtx &lc);
 void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);

@@ -12,18 +12,15 @@ namespace {
 
 constexpr int kPairLd = 16;   // leading dimension of the per-pair 2s x 2s workspace (s <= 8)
 
-// Read access to the current inverse G_cur = G - X Y^T: X and Y hold the
-// pending Woodbury factors of the accepted flips of the current window of link
-// steps, stored slot-major (column s of X is X[s * n .. s * n + n), r columns in
-// use; r = 0 when nothing is pending).
+// Read access to the current inverse on the Majoranas a pair Pfaffian needs.
 // Entries whose both indices are among the nc Majoranas cidx[] are served from
-// `cache` (nc x nc, leading dimension 16, already corrected for the pending flips).
+// `cache` (nc x nc, leading dimension 16; the link-step kernel stores there the
+// inverse corrected for the flips pending in its window); other entries are
+// read from G.
 template <typename T>
 struct GView {
   const T *G;
   int n;
-  const T *X, *Y;
-  int r;
   const double *cache = nullptr;
   const int *cidx = nullptr;
   int nc = 0;
@@ -36,16 +33,13 @@ struct GView {
       }
       if (pa >= 0 && pb >= 0) return cache[pa * 16 + pb];
     }
-    double v = static_cast<double>(G[static_cast<size_t>(a) * n + b]);
-    for (int s = 0; s < r; ++s)
-      v -= static_cast<double>(X[static_cast<size_t>(s) * n + a]) * static_cast<double>(Y[static_cast<size_t>(s) * n + b]);
-    return v;
+    return static_cast<double>(G[static_cast<size_t>(a) * n + b]);
   }
 };
 
 template <typename T>
 __device__ inline GView<T> plain_view(const T *G, int n) {
-  return GView<T>{G, n, nullptr, nullptr, 0};
+  return GView<T>{G, n};
 }
 
 struct PatchSet {

@@ -15,67 +15,51 @@
 // Then the streaming update (k_update) applies G <- G + QT^T PT
 // = G - G[:,U] K G[U,:] to every accepted chain, each element once: read n^2, write n^2.
 //
-// Delayed updates (lc.dld > 0): the flips of a window of F link steps are not
-// applied at once.  Step t of the window reads the current inverse as
-// G - X Y^T (X, Y: 4F columns of length n stored one after another, slots
-// 0..t-1 filled); on accept the workgroup writes
-// slot t: X[:, 4t..4t+3] = G_cur[:,U] K and Y[:, 4t..4t+3] = G_cur[U,:]^T, so that
-// G_cur' = G_cur - G_cur[:,U] K G_cur[U,:]; a rejected or absent step writes
-// zeros.  At the end of the window one matrix-core GEMM applies G -= X Y^T
-// (rank 4F): one pass over G per window instead of one per accepted flip.
+// Delayed updates (lc.dly = F > 0): the flips of a window of F link steps are
+// not applied at once.  With A the Majoranas of the flips accepted so far in the
+// window and dM_A their block-diagonal change, the current inverse is
+//   G_cur = G - G[:,A] W G[A,:],  W = dM_A Binv,  Binv = (1 + G_AA dM_A)^-1
+// (block Woodbury; the same chain as one update per flip).  A link step only
+// needs G_cur on the link's and the patch links' Majoranas I, i.e. G_II, G_IA
+// and G_AI gathered from the unchanged G; an accepted flip borders Binv by its 4
+// rows and columns (Schur complement S = 1 + G_cur,UU dM, whose determinant is
+// rho).  At the end of the window the block-update kernels apply the whole
+// window as one rank-|A| matrix-core update of G.
 #include "ggf_device.h"
 #include "ggf_launch.h"
+#include "ggf_nn.h"
 #include "ggf_pair.h"
 
 namespace {
 
-constexpr int kDelaySlotsMax = 32;   // window length F <= 32 (rank 4F <= 128)
+constexpr int kDelayMax = GGF_BLOCK_RMAX;   // Majoranas pending in a window (4 per flip; the block-update rank limit)
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity, int t) {
-  extern __shared__ double2 s_work[];
-  __shared__ double s_K[16];
-  __shared__ double s_GI[16 * 16];     // current inverse on the link's and the patch links' Majoranas
+__global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity, int t, int wp) {
+  extern __shared__ double2 s_work[];   // pair workspaces, then (delayed) G_IA, G_AI and a scratch block
+  __shared__ double s_K[16], s_Ai[16], s_dM[16];
+  __shared__ double s_GI[16 * 16];      // current inverse on the Majoranas I (U first)
   __shared__ int s_I[16];
   __shared__ int s_nI;
-  __shared__ double s_xu[4][4 * kDelaySlotsMax], s_yu[4][4 * kDelaySlotsMax];   // X[U,:r], Y[U,:r]
   __shared__ double s_rho, s_u;
   __shared__ int s_kn, s_acc;
   __shared__ double2 s_r[16];
   const int c = blockIdx.x;
-  if (c == 0 && threadIdx.x == 0) lc.acc_cnt[parity ^ 1] = 0;
+  const bool delayed = lc.dly > 0;
+  if (c == 0 && threadIdx.x == 0) {
+    if (!delayed) lc.acc_cnt[parity ^ 1] = 0;
+    else if (t == 0) lc.dcnt[wp ^ 1] = 0;          // the other window's list was flushed already
+  }
   const ChainDev ch = lc.chains[c];
   const int n = ch.n;
-  const bool delayed = lc.dld > 0;
-  const int r = delayed ? 4 * t : 0;
-  T *X = delayed ? static_cast<T *>(lc.X) + lc.x_off[c] : nullptr;
-  T *Y = delayed ? static_cast<T *>(lc.Y) + lc.x_off[c] : nullptr;
-  // a step without an accepted flip leaves zeros in its slot of the window
-  auto zero_slot = [&]() {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        X[static_cast<size_t>(r + q) * n + j] = static_cast<T>(0);
-        Y[static_cast<size_t>(r + q) * n + j] = static_cast<T>(0);
-      }
-  };
-  if (ell >= ch.nlinks) {
-    if (delayed) {
-      if (t == 0 && threadIdx.x == 0) lc.pend[c] = 0;
-      zero_slot();
-    }
-    return;
-  }
+  const int a = (delayed && t > 0) ? lc.dr[c] : 0;  // pending Majoranas of this chain
+  if (delayed && t == 0 && threadIdx.x == 0) lc.dr[c] = 0;
+  if (ell >= ch.nlinks) return;
   const TensorDev &Tn = lc.tensors[ch.tensor];
   const T *G = static_cast<const T *>(lc.G) + ch.g_off;
   int8_t *lk = lc.links + ch.link_off;
   int U[4];
   ggf_link_u(ell, ch.L, U);
-  for (int i = threadIdx.x; i < 4 * r; i += blockDim.x) {
-    const int q = i / r, s = i - q * r;
-    s_xu[q][s] = static_cast<double>(X[static_cast<size_t>(s) * n + U[q]]);
-    s_yu[q][s] = static_cast<double>(Y[static_cast<size_t>(s) * n + U[q]]);
-  }
   const int K = ch.K;
   const int npairs = K * (K + 1) / 2 - 1;
   if (threadIdx.x == 0) {
@@ -83,11 +67,11 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     int m = 0;
     for (int q = 0; q < 4; ++q) s_I[m++] = U[q];
     for (int p = 0; p < npairs; ++p) {
-      int a, b;
-      pair_of(p, K, a, b);
-      for (int l = 0; l < Tn.nl[a][b]; ++l) {
+      int pa, pb;
+      pair_of(p, K, pa, pb);
+      for (int l = 0; l < Tn.nl[pa][pb]; ++l) {
         int u4[4];
-        ggf_link_u(Tn.lk[a][b][l], ch.L, u4);
+        ggf_link_u(Tn.lk[pa][pb][l], ch.L, u4);
         for (int q = 0; q < 4; ++q) {
           bool seen = false;
           for (int i = 0; i < m; ++i) seen |= s_I[i] == u4[q];
@@ -99,12 +83,32 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   }
   __syncthreads();
   const int nI = s_nI;
+  // delayed-window work arrays after the pair workspaces: G_IA (16 x a), G_AI (a x 16), scratch (16 x a)
+  const int lda = 4 * lc.dly;            // >= a + 4: pending Majoranas of a full window
+  double *s_GIA = reinterpret_cast<double *>(s_work + (npairs > 0 ? npairs * kPairLd * kPairLd : 0));
+  double *s_GAI = s_GIA + 16 * lda;
+  double *s_T = s_GAI + 16 * lda;
+  const int *A = delayed ? lc.dU + static_cast<size_t>(c) * kDelayMax : nullptr;
+  if (a > 0) {
+    for (int e = threadIdx.x; e < nI * a; e += blockDim.x) {
+      const int i = e / a, p = e - i * a;
+      s_GIA[i * lda + p] = static_cast<double>(G[static_cast<size_t>(s_I[i]) * n + A[p]]);
+      s_GAI[p * 16 + i] = static_cast<double>(G[static_cast<size_t>(A[p]) * n + s_I[i]]);
+    }
+    __syncthreads();
+    const double *W = lc.dW + static_cast<size_t>(c) * kDelayMax * kDelayMax;   // a x a, leading dimension a
+    for (int e = threadIdx.x; e < nI * a; e += blockDim.x) {
+      const int i = e / a, q = e - i * a;
+      double v = 0.0;
+      for (int p = 0; p < a; ++p) v += s_GIA[i * lda + p] * W[p * a + q];
+      s_T[i * lda + q] = v;                           // (G_IA W)[i][q]
+    }
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < nI * nI; e += blockDim.x) {
     const int i = e / nI, j = e - i * nI;
-    const int a = s_I[i], b = s_I[j];
-    double v = static_cast<double>(G[static_cast<size_t>(a) * n + b]);
-    for (int s = 0; s < r; ++s)
-      v -= static_cast<double>(X[static_cast<size_t>(s) * n + a]) * static_cast<double>(Y[static_cast<size_t>(s) * n + b]);
+    double v = static_cast<double>(G[static_cast<size_t>(s_I[i]) * n + s_I[j]]);
+    for (int q = 0; q < a; ++q) v -= s_T[i * lda + q] * s_GAI[q * 16 + j];
     s_GI[i * 16 + j] = v;
   }
   __syncthreads();
@@ -118,21 +122,25 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     ggf_bond_block(Tn.x0, kn, ch.group, yn);
     const double X0 = yn[0] - yo[0], X1 = yn[1] - yo[1], X2 = yn[2] - yo[2], X3 = yn[3] - yo[3];
     const double dM[16] = {0, 0, X0, X1, 0, 0, X2, X3, -X0, -X2, 0, 0, -X1, -X3, 0, 0};
-    double A[16], Ai[16];
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) {
-        double v = (a == b) ? 1.0 : 0.0;
-        for (int q = 0; q < 4; ++q) v += s_GI[a * 16 + q] * dM[q * 4 + b];
-        A[a * 4 + b] = v;
-        Ai[a * 4 + b] = (a == b) ? 1.0 : 0.0;
+    double Am[16], Ai[16];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double v = (i == j) ? 1.0 : 0.0;
+        for (int q = 0; q < 4; ++q) v += s_GI[i * 16 + q] * dM[q * 4 + j];
+        Am[i * 4 + j] = v;
+        Ai[i * 4 + j] = (i == j) ? 1.0 : 0.0;
       }
-    const double rho = ggf_solve4(A, Ai);      // Ai <- (1 + G_UU dM)^-1
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) {
+    const double rho = ggf_solve4(Am, Ai);      // Ai <- (1 + G_UU dM)^-1
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
         double v = 0.0;
-        for (int q = 0; q < 4; ++q) v += dM[a * 4 + q] * Ai[q * 4 + b];
-        s_K[a * 4 + b] = v;
+        for (int q = 0; q < 4; ++q) v += dM[i * 4 + q] * Ai[q * 4 + j];
+        s_K[i * 4 + j] = v;
       }
+    for (int q = 0; q < 16; ++q) {
+      s_Ai[q] = Ai[q];
+      s_dM[q] = dM[q];
+    }
     s_rho = rho;
     s_kn = kn;
     s_u = ggf_u53(x.x, x.y);
@@ -140,16 +148,16 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   __syncthreads();
   if (K > 1) {
     if (threadIdx.x < npairs) {
-      int a, b;
-      pair_of(threadIdx.x, K, a, b);
+      int pa, pb;
+      pair_of(threadIdx.x, K, pa, pb);
       PatchSet ps;
-      double2 *W = s_work + threadIdx.x * kPairLd * kPairLd;
-      GView<T> gv{G, n, X, Y, r};
+      double2 *Wp = s_work + threadIdx.x * kPairLd * kPairLd;
+      GView<T> gv{G, n};
       gv.cache = s_GI;
       gv.cidx = s_I;
       gv.nc = nI;
-      build_pair_matrix(Tn, a, b, ch.L, ch.group, gv, lk, U, s_K, ell, s_kn, W, ps);
-      s_r[threadIdx.x] = pair_ratio(W, ps.s);
+      build_pair_matrix(Tn, pa, pb, ch.L, ch.group, gv, lk, U, s_K, ell, s_kn, Wp, ps);
+      s_r[threadIdx.x] = pair_ratio(Wp, ps.s);
     }
     __syncthreads();
   }
@@ -160,17 +168,17 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     if (K > 1) {
       double sv = Tn.w[0][0].x;
       for (int p = 0; p < npairs; ++p) {
-        int a, b;
-        pair_of(p, K, a, b);
-        const double2 tt = cmul(Tn.w[a][b], s_r[p]);
-        sv += (a == b) ? tt.x : 2.0 * tt.x;
+        int pa, pb;
+        pair_of(p, K, pa, pb);
+        const double2 tt = cmul(Tn.w[pa][pb], s_r[p]);
+        sv += (pa == pb) ? tt.x : 2.0 * tt.x;
       }
       snew = make_double2(sv, 0.0);
       sratio = sv / lc.sfac[c].x;
     }
     const bool bad = !isfinite(rho) || !isfinite(sratio) || rho < -1e-6;
     const double R = (rho > 0.0 ? sqrt(rho) : 0.0) * sratio;
-    const bool accept = !bad && (s_u < R);
+    const bool accept = !bad && (s_u < R) && (a + 4 <= kDelayMax || !delayed);
     lc.prop_total[c] += 1;
     if (bad) lc.flags[c] |= GGF_FLAG_NONFINITE;
     if (accept) {
@@ -180,60 +188,129 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
       lc.acc_since[c] += 1;
       lc.acc_total[c] += 1;
       if (delayed) {
-        lc.pend[c] = t + 1;
+        if (a == 0) {
+          const int slot = atomicAdd(lc.dcnt + wp, 1);
+          lc.acc_list[slot] = c;
+        }
       } else {
         const int slot = atomicAdd(lc.acc_cnt + parity, 1);
         lc.acc_list[slot] = c;
       }
-    } else if (delayed && t == 0) {
-      lc.pend[c] = 0;
     }
     s_acc = accept ? 1 : 0;
   }
   __syncthreads();
-  const int u0 = U[0], u1 = U[1], u2 = U[2], u3 = U[3];
+  if (!s_acc) return;
   if (delayed) {
-    if (!s_acc) {
-      zero_slot();
-      return;
-    }
-    // slot t: X = G_cur[:,U] K, Y = G_cur[U,:]^T, with G_cur = G - X Y^T over slots 0..t-1
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const T *gj = G + static_cast<size_t>(j) * n;
-      double gc[4] = {static_cast<double>(gj[u0]), static_cast<double>(gj[u1]), static_cast<double>(gj[u2]),
-                      static_cast<double>(gj[u3])};
-      double gr[4] = {static_cast<double>(G[static_cast<size_t>(u0) * n + j]),
-                      static_cast<double>(G[static_cast<size_t>(u1) * n + j]),
-                      static_cast<double>(G[static_cast<size_t>(u2) * n + j]),
-                      static_cast<double>(G[static_cast<size_t>(u3) * n + j])};
-      for (int s0 = 0; s0 < r; s0 += 4) {     // r is a multiple of 4: four slots' loads in flight
-        double xs[4], ys[4];
+    // border Binv (a x a, leading dimension kDelayMax) by the flip's rows and columns:
+    //   B' = [[B, b12], [b21, S]],  b12 = G_AU dM,  b21 = G_UA dM_A,  S = 1 + G_cur,UU dM (S^-1 = s_Ai),
+    //   B'^-1 = [[Binv + u S^-1 v, -u S^-1], [-S^-1 v, S^-1]],  u = Binv b12,  v = b21 Binv,
+    // then W' = dM_A' B'^-1 with leading dimension a + 4.
+    double *Binv = lc.dBinv + static_cast<size_t>(c) * kDelayMax * kDelayMax;
+    double *W = lc.dW + static_cast<size_t>(c) * kDelayMax * kDelayMax;
+    double *dXc = lc.dX + static_cast<size_t>(c) * kDelayMax;   // 4 values (X of dM) per pending flip
+    int *Ac = lc.dU + static_cast<size_t>(c) * kDelayMax;
+    double *b12 = s_T;                   // a x 4
+    double *b21 = b12 + 4 * lda;         // 4 x a
+    double *uu = b21 + 4 * lda;          // a x 4: u
+    double *uS = uu + 4 * lda;           // a x 4: u S^-1
+    double *Sv = uS + 4 * lda;           // 4 x a: S^-1 v
+    if (a > 0) {
+      for (int e = threadIdx.x; e < 4 * a; e += blockDim.x) {
+        const int p = e >> 2, y = e & 3;
+        double v = 0.0;
+        for (int x = 0; x < 4; ++x) v += s_GAI[p * 16 + x] * s_dM[x * 4 + y];
+        b12[p * 4 + y] = v;
+        const int xq = e / a, pp = e - xq * a;
+        const int blk = pp & ~3, col = pp & 3;
+        const double *X = dXc + blk;
+        const double dMb[16] = {0, 0, X[0], X[1], 0, 0, X[2], X[3], -X[0], -X[2], 0, 0, -X[1], -X[3], 0, 0};
+        double w = 0.0;
+        for (int z = 0; z < 4; ++z) w += s_GIA[xq * lda + blk + z] * dMb[z * 4 + col];
+        b21[xq * lda + pp] = w;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < a; i += blockDim.x) {
+        double u4[4] = {0, 0, 0, 0};
+        const double *bi = Binv + static_cast<size_t>(i) * kDelayMax;
+        for (int j = 0; j < a; ++j) {
+          const double bij = bi[j];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          xs[d] = static_cast<double>(X[static_cast<size_t>(s0 + d) * n + j]);
-          ys[d] = static_cast<double>(Y[static_cast<size_t>(s0 + d) * n + j]);
+          for (int x = 0; x < 4; ++x) u4[x] += bij * b12[j * 4 + x];
         }
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
+        for (int y = 0; y < 4; ++y) {
+          uu[i * 4 + y] = u4[y];
+          double v = 0.0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            gc[q] -= xs[d] * s_yu[q][s0 + d];
-            gr[q] -= s_xu[q][s0 + d] * ys[d];
-          }
+          for (int x = 0; x < 4; ++x) v += u4[x] * s_Ai[x * 4 + y];
+          uS[i * 4 + y] = v;
+        }
       }
+      for (int j = threadIdx.x; j < a; j += blockDim.x) {
+        double v4[4] = {0, 0, 0, 0};
+        for (int i = 0; i < a; ++i) {
+          const double bij = Binv[static_cast<size_t>(i) * kDelayMax + j];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        X[static_cast<size_t>(r + b) * n + j] = static_cast<T>(
-            gc[0] * s_K[0 * 4 + b] + gc[1] * s_K[1 * 4 + b] + gc[2] * s_K[2 * 4 + b] + gc[3] * s_K[3 * 4 + b]);
-        Y[static_cast<size_t>(r + b) * n + j] = static_cast<T>(gr[b]);
+          for (int y = 0; y < 4; ++y) v4[y] += b21[y * lda + i] * bij;
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          double v = 0.0;
+#pragma unroll
+          for (int y = 0; y < 4; ++y) v += s_Ai[x * 4 + y] * v4[y];
+          Sv[x * lda + j] = v;
+        }
       }
+      __syncthreads();
+    }
+    const int a2 = a + 4;
+    for (int e = threadIdx.x; e < a2 * a2; e += blockDim.x) {
+      const int i = e / a2, j = e - i * a2;
+      double *bij = Binv + static_cast<size_t>(i) * kDelayMax + j;
+      if (i < a && j < a) {
+        double v = *bij;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) v += uu[i * 4 + y] * Sv[y * lda + j];
+        *bij = v;
+      } else if (i < a) {
+        *bij = -uS[i * 4 + (j - a)];
+      } else if (j < a) {
+        *bij = -Sv[(i - a) * lda + j];
+      } else {
+        *bij = s_Ai[(i - a) * 4 + (j - a)];
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < a2 * a2; e += blockDim.x) {
+      const int i = e / a2, j = e - i * a2;
+      const int blk = i & ~3, row = i & 3;
+      double dmr[4];
+      if (blk < a) {
+        const double *X = dXc + blk;
+        const double dMb[16] = {0, 0, X[0], X[1], 0, 0, X[2], X[3], -X[0], -X[2], 0, 0, -X[1], -X[3], 0, 0};
+        for (int z = 0; z < 4; ++z) dmr[z] = dMb[row * 4 + z];
+      } else {
+        for (int z = 0; z < 4; ++z) dmr[z] = s_dM[row * 4 + z];
+      }
+      double v = 0.0;
+      for (int z = 0; z < 4; ++z) v += dmr[z] * Binv[static_cast<size_t>(blk + z) * kDelayMax + j];
+      W[static_cast<size_t>(i) * a2 + j] = v;
+    }
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < 4; ++q) Ac[a + q] = U[q];
+      dXc[a + 0] = s_dM[2];
+      dXc[a + 1] = s_dM[3];
+      dXc[a + 2] = s_dM[6];
+      dXc[a + 3] = s_dM[7];
+      lc.dr[c] = a2;
     }
     return;
   }
-  if (!s_acc) return;
   // Woodbury with the stored rows and columns: G' = G - G[:,U] K G[U,:].
   // (Substituting -G[U,:]^T for G[:,U] would assume exact antisymmetry; rounding
   // breaks it and the symmetric part of the error then grows with every flip.)
+  const int u0 = U[0], u1 = U[1], u2 = U[2], u3 = U[3];
   T *PT = static_cast<T *>(lc.F) + ch.f_off;
   T *QT = PT + 4 * static_cast<size_t>(n);
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -346,6 +423,7 @@ __global__ void k_end_sweep(LaunchCtx lc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < lc.n_chains) lc.sweep[c] += 1u;
   if (c < 2) lc.acc_cnt[c] = 0;   // every sweep starts with both accepted counters cleared
+  if (c < 2 && lc.dcnt) lc.dcnt[c] = 0;
 }
 
 __global__ void k_hot_start(LaunchCtx lc, int max_links) {
@@ -582,16 +660,26 @@ static size_t pair_lds(int kmax) {
   return np > 0 ? static_cast<size_t>(np) * kPairLd * kPairLd * sizeof(double2) : 0;
 }
 
-void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int n_max) {
-  const size_t lds = pair_lds(kmax);
-  // (one wave per chain was measured slower on 8x8 float64: the pending-factor reads of an
-  // accepted flip need the full workgroup)
-  const int threads = 256;
-  (void)n_max;
+void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int wp) {
+  // pair workspaces, then for delayed updates G_IA (16 x 4F), G_AI (4F x 16) and 20 x 4F scratch
+  const size_t lds = pair_lds(kmax) + (lc.dly > 0 ? static_cast<size_t>(52) * 4 * lc.dly * sizeof(double) : 0);
+  // 9 pair workspaces (K = 4, 36 KB) with a 32-step window (53 KB) exceed the default
+  // 64 KB of dynamic LDS: raise the limit to what this launch needs (the launch reports
+  // an error if the device cannot provide it)
+  static size_t lds_set[2] = {64 * 1024, 64 * 1024};
+  const int ti = lc.precision == 64 ? 0 : 1;
+  if (lds > lds_set[ti]) {
+    const void *fn = lc.precision == 64 ? reinterpret_cast<const void *>(&k_ratio<double>)
+                                        : reinterpret_cast<const void *>(&k_ratio<float>);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) == hipSuccess)
+      lds_set[ti] = lds;
+    else
+      (void)hipGetLastError();
+  }
   if (lc.precision == 64)
-    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(threads), lds, lc.stream, lc, ell, parity, t);
+    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t, wp);
   else
-    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(threads), lds, lc.stream, lc, ell, parity, t);
+    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t, wp);
 }
 
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt) {
