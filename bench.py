@@ -105,9 +105,17 @@ def traffic_from(args):
                 if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
         return sum(vals) / len(vals), len(vals)
 
-    kernel = "k_flush" if args.delay > 0 else "k_update"
-    fetch, nf = per_kernel(args.traffic_from[0], "FETCH_SIZE", kernel)
-    write, nw = per_kernel(args.traffic_from[1], "WRITE_SIZE", kernel)
+    kernel = "k_window_flush" if args.delay > 0 else "k_update"
+    if args.delay > 0:
+        # the window flush is two dispatches per window: k_window_dt then k_block_gemm
+        fetch, write, nf, nw = 0.0, 0.0, 0, 0
+        for k in ("k_window_dt", "k_block_gemm"):
+            f_, n_ = per_kernel(args.traffic_from[0], "FETCH_SIZE", k)
+            w_, m_ = per_kernel(args.traffic_from[1], "WRITE_SIZE", k)
+            fetch, write, nf, nw = fetch + f_, write + w_, n_, m_
+    else:
+        fetch, nf = per_kernel(args.traffic_from[0], "FETCH_SIZE", kernel)
+        write, nw = per_kernel(args.traffic_from[1], "WRITE_SIZE", kernel)
     cfetch, _ = per_kernel(args.traffic_from[2], "FETCH_SIZE", "probe_copy")
     cwrite, _ = per_kernel(args.traffic_from[3], "WRITE_SIZE", "probe_copy")
     known_kib = args.copy_bytes / 1024.0
@@ -155,11 +163,15 @@ def block_traffic_from(args):
     out = {"source_digest": source_digest("ggf_block.inc"), "moves_per_launch": moves_per_launch,
            "fetch_scale": sf, "write_scale": sw}
     total = 0.0
-    for k in ("k_block_prep", "k_block_gemm"):
+    tname = "float" if rec["config"]["precision"] == 32 else "double"
+    # block moves only: the window flushes of the training sampler's delayed updates run
+    # k_block_gemm<T, true> and are left out
+    for k in (f"k_block_prep<{tname}>", f"k_block_gemm<{tname}, false>"):
         fv, wv = per_kernel(f_csv, "FETCH_SIZE", k), per_kernel(w_csv, "WRITE_SIZE", k)
         rd = sum(fv) / len(fv) * sf * 1024.0
         wr = sum(wv) / len(wv) * sw * 1024.0
-        out[k] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr, "dispatches": [len(fv), len(wv)]}
+        out[k.split("<")[0]] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+                                "dispatches": [len(fv), len(wv)]}
         total += rd + wr
     n = rec["config"]["n"]
     esz = 4 if rec["config"]["precision"] == 32 else 8
@@ -209,7 +221,7 @@ def copy_probe(nbytes: int):
     print(json.dumps(out))
 
 
-KERNEL_SOURCE = {"k_update": "ggf_sweep.hip", "k_flush": "ggf_block.inc"}
+KERNEL_SOURCE = {"k_update": "ggf_sweep.hip", "k_window_flush": "ggf_block.inc"}
 
 
 def traffic_key(args) -> str:
@@ -520,14 +532,15 @@ def main():
         bytes_per_flip = 2.0 * n * n * esz
     F = args.delay
     if F > 0:
-        # delayed updates: the dominant kernel is the window flush, one read and one write of
+        # delayed updates: the dominant kernel is the window flush (k_window_dt folding the window's
+        # capacitance into G[A,:], then the matrix-core k_block_gemm), one read and one write of
         # each chain's G per window in which the chain has a pending flip (at these acceptances,
-        # every window it has link steps in); the X, Y operand reads are not counted
+        # every window it has link steps in); the G[A,:] and operand reads are not counted
         nl_c = 2 * Lc.astype(np.int64) ** 2
         windows = -(-int(nl_c.max()) // F)
         share = np.minimum(-(-nl_c // F), windows) / windows
         bytes_per_launch = float((share * 2.0 * n_c.astype(np.float64) ** 2 * esz).sum())
-        kernel = "k_flush"
+        kernel = "k_window_flush"
     else:
         bytes_per_launch = upd_flips * bytes_per_flip / max(upd_launches, 1)
         kernel = "k_update"
