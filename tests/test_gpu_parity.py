@@ -194,6 +194,26 @@ def test_delayed_update_windows(delay):
         assert np.abs(G - oc.G).max() <= 1e-9 * np.abs(oc.G).max()
 
 
+@pytest.mark.parametrize("L,precision", [(8, 64), (6, 64), (2, 64), (8, 32)])
+def test_window_flush_antisymmetric(L, precision):
+    """G = M^-1 is antisymmetric (Sec. 3.2: M is); the window flush updates the 64 x 64 tiles on and above the
+    diagonal and writes each tile below as the negated transpose of its mirror.  After a sweep the stored
+    inverse is exactly antisymmetric with a zero diagonal, for full tiles (8x8: n = 512) and ragged ones
+    (6x6: n = 288; 2x2: n = 32, one partial tile), and matches the oracle's one-flip-at-a-time inverse."""
+    say(f"antisymmetric flush L={L} float{precision}")
+    spec = spec_for(L, 1, 2)
+    ctx = gpu_context([spec], [L] * 2, init=1, precision=precision, delay=16)
+    orc = [oracle_chain(spec, L, c, init=1)[1] for c in range(2)]
+    ctx.sweep(1)
+    for c, oc in enumerate(orc):
+        oc.sweep()
+        assert np.array_equal(ctx.get_state(c)[0], oc.k), f"chain {c}"
+        G = ctx.get_inverse(c)
+        assert np.array_equal(G, -G.T), f"chain {c}: max |G + G^T| = {np.abs(G + G.T).max()}"
+        tol = 1e-9 if precision == 64 else 1e-4
+        assert np.abs(G - oc.G).max() <= tol * np.abs(oc.G).max()
+
+
 def test_delay_window_changes_between_sweeps():
     """The window may change between sweeps (nothing is pending at a sweep's end)."""
     say("delay window changes")
