@@ -12,8 +12,9 @@ of the pending flips per window of 16 link steps) followed by the plaquette /
 
 Prints one JSON line: link-update proposals per second (value), effective
 samples per second of the lattice-mean plaquette, the HBM roofline of the
-dominant kernel (the window flush: one read and one write of every chain's G
-per window; time: HIP events around every flush launch on its stream; with
+dominant kernel (the window flush: per window, every chain's upper triangle of
+G read once and all of G written once, since G is antisymmetric; time: HIP
+events around every flush launch on its stream; with
 --delay 0 the rank-4 update, 2 n^2 * 8 bytes per accepted flip), the time of
 the ratio kernels, and the CPU oracle timed on a bounded sample of the same
 workload.
@@ -107,9 +108,9 @@ def traffic_from(args):
 
     kernel = "k_window_flush" if args.delay > 0 else "k_update"
     if args.delay > 0:
-        # the window flush is two dispatches per window: k_window_dt then k_block_gemm
+        # the window flush is two dispatches per window: k_window_snap then k_window_gemm
         fetch, write, nf, nw = 0.0, 0.0, 0, 0
-        for k in ("k_window_dt", "k_block_gemm"):
+        for k in ("k_window_snap", "k_window_gemm"):
             f_, n_ = per_kernel(args.traffic_from[0], "FETCH_SIZE", k)
             w_, m_ = per_kernel(args.traffic_from[1], "WRITE_SIZE", k)
             fetch, write, nf, nw = fetch + f_, write + w_, n_, m_
@@ -164,9 +165,8 @@ def block_traffic_from(args):
            "fetch_scale": sf, "write_scale": sw}
     total = 0.0
     tname = "float" if rec["config"]["precision"] == 32 else "double"
-    # block moves only: the window flushes of the training sampler's delayed updates run
-    # k_block_gemm<T, true> and are left out
-    for k in (f"k_block_prep<{tname}>", f"k_block_gemm<{tname}, false>"):
+    # block moves only (the training sampler's window flushes run k_window_snap / k_window_gemm)
+    for k in (f"k_block_prep<{tname}>", f"k_block_gemm<{tname}>"):
         fv, wv = per_kernel(f_csv, "FETCH_SIZE", k), per_kernel(w_csv, "WRITE_SIZE", k)
         rd = sum(fv) / len(fv) * sf * 1024.0
         wr = sum(wv) / len(wv) * sw * 1024.0
@@ -221,7 +221,7 @@ def copy_probe(nbytes: int):
     print(json.dumps(out))
 
 
-KERNEL_SOURCE = {"k_update": "ggf_sweep.hip", "k_window_flush": "ggf_block.inc"}
+KERNEL_SOURCE = {"k_update": ("ggf_sweep.hip",), "k_window_flush": ("ggf_block.inc", "ggf_window.inc")}
 
 
 def traffic_key(args) -> str:
@@ -229,11 +229,14 @@ def traffic_key(args) -> str:
     return key + (f"_flush{args.delay}" if args.delay > 0 else "")
 
 
-def source_digest(name: str = "ggf_sweep.hip") -> str:
-    """Digest of a kernel source file; traffic counters are only reported for the kernel they measured."""
+def source_digest(names=("ggf_sweep.hip",)) -> str:
+    """Digest of a kernel's source files; traffic counters are only reported for the kernel they measured."""
     import hashlib
-    with open(os.path.join(HERE, "paper_2412_01737_amd", "csrc", name), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ([names] if isinstance(names, str) else names):
+        with open(os.path.join(HERE, "paper_2412_01737_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(args, budget_s: float):
@@ -532,14 +535,16 @@ def main():
         bytes_per_flip = 2.0 * n * n * esz
     F = args.delay
     if F > 0:
-        # delayed updates: the dominant kernel is the window flush (k_window_dt folding the window's
-        # capacitance into G[A,:], then the matrix-core k_block_gemm), one read and one write of
-        # each chain's G per window in which the chain has a pending flip (at these acceptances,
-        # every window it has link steps in); the G[A,:] and operand reads are not counted
+        # delayed updates: the dominant kernel is the window flush (k_window_snap copying P = G[A,:],
+        # then the matrix-core k_window_gemm on the upper triangle, mirrored): per chain with a
+        # pending flip in the window (at these acceptances, every window it has link steps in) the
+        # upper triangle of G read once, n (n + 1) / 2 elements, and all of G written once, n^2;
+        # the snapshot and operand reads (2 r n elements) are not counted
         nl_c = 2 * Lc.astype(np.int64) ** 2
         windows = -(-int(nl_c.max()) // F)
         share = np.minimum(-(-nl_c // F), windows) / windows
-        bytes_per_launch = float((share * 2.0 * n_c.astype(np.float64) ** 2 * esz).sum())
+        nf_ = n_c.astype(np.float64)
+        bytes_per_launch = float((share * (nf_ * (nf_ + 1) / 2 + nf_ ** 2) * esz).sum())
         kernel = "k_window_flush"
     else:
         bytes_per_launch = upd_flips * bytes_per_flip / max(upd_launches, 1)

@@ -272,6 +272,7 @@ __global__ void k_nn_examples(int *__restrict__ ex_chain, int *__restrict__ ex_p
 // Block move: decision (forward pass, proposal, r x r Gauss-Jordan, K > 1 patch
 // Pfaffians, Metropolis-Hastings) and the rank-r Woodbury update.
 #include "ggf_block.inc"
+#include "ggf_window.inc"
 
 void ggf_nn_forward_launch(const NNArgs &a, const int *ex_chain, const int *ex_patch, int n_ex, float *logits,
                            hipStream_t s) {
