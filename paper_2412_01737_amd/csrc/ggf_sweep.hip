@@ -25,6 +25,8 @@
 // rows and columns (Schur complement S = 1 + G_cur,UU dM, whose determinant is
 // rho).  At the end of the window the block-update kernels apply the whole
 // window as one rank-|A| matrix-core update of G.
+#include <algorithm>
+
 #include "ggf_device.h"
 #include "ggf_launch.h"
 #include "ggf_nn.h"
@@ -34,11 +36,14 @@ namespace {
 
 constexpr int kDelayMax = GGF_BLOCK_RMAX;   // Majoranas pending in a window (4 per flip; the block-update rank limit)
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity, int t, int wp) {
+constexpr int kRatioThreads = 64;   // one wave per chain: the per-step work is small, residency is what counts
+
+// PAIRS: some chain of the context has K > 1 (patch Pfaffians; index sets up to 16 Majoranas).
+template <typename T, bool PAIRS>
+__global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, int parity, int t, int wp) {
   extern __shared__ double2 s_work[];   // pair workspaces, then (delayed) G_IA, G_AI and a scratch block
   __shared__ double s_K[16], s_Ai[16], s_dM[16];
-  __shared__ double s_GI[16 * 16];      // current inverse on the Majoranas I (U first)
+  __shared__ double s_GI[(PAIRS ? 16 : 4) * 16];   // current inverse on the Majoranas I (U first), row stride 16
   __shared__ int s_I[16];
   __shared__ int s_nI;
   __shared__ double s_rho, s_u;
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   int8_t *lk = lc.links + ch.link_off;
   int U[4];
   ggf_link_u(ell, ch.L, U);
-  const int K = ch.K;
+  const int K = PAIRS ? ch.K : 1;
   const int npairs = K * (K + 1) / 2 - 1;
   if (threadIdx.x == 0) {
     // index set: U first, then the Majoranas of every patch link of the superposition
@@ -83,17 +88,19 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   }
   __syncthreads();
   const int nI = s_nI;
-  // delayed-window work arrays after the pair workspaces: G_IA (16 x a), G_AI (a x 16), scratch (16 x a)
+  // delayed-window work arrays after the pair workspaces: G_IA (nIm x a), G_AI (a x nIm) and a
+  // scratch block (max(nIm, 8) x a), nIm the largest index set (4 Majoranas when K = 1)
+  const int nIm = PAIRS ? 16 : 4;
   const int lda = 4 * lc.dly;            // >= a + 4: pending Majoranas of a full window
   double *s_GIA = reinterpret_cast<double *>(s_work + (npairs > 0 ? npairs * kPairLd * kPairLd : 0));
-  double *s_GAI = s_GIA + 16 * lda;
-  double *s_T = s_GAI + 16 * lda;
+  double *s_GAI = s_GIA + nIm * lda;
+  double *s_T = s_GAI + nIm * lda;
   const int *A = delayed ? lc.dU + static_cast<size_t>(c) * kDelayMax : nullptr;
   if (a > 0) {
     for (int e = threadIdx.x; e < nI * a; e += blockDim.x) {
       const int i = e / a, p = e - i * a;
       s_GIA[i * lda + p] = static_cast<double>(G[static_cast<size_t>(s_I[i]) * n + A[p]]);
-      s_GAI[p * 16 + i] = static_cast<double>(G[static_cast<size_t>(A[p]) * n + s_I[i]]);
+      s_GAI[p * nIm + i] = static_cast<double>(G[static_cast<size_t>(A[p]) * n + s_I[i]]);
     }
     __syncthreads();
     const double *W = lc.dW + static_cast<size_t>(c) * kDelayMax * kDelayMax;   // a x a, leading dimension a
@@ -108,7 +115,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
   for (int e = threadIdx.x; e < nI * nI; e += blockDim.x) {
     const int i = e / nI, j = e - i * nI;
     double v = static_cast<double>(G[static_cast<size_t>(s_I[i]) * n + s_I[j]]);
-    for (int q = 0; q < a; ++q) v -= s_T[i * lda + q] * s_GAI[q * 16 + j];
+    for (int q = 0; q < a; ++q) v -= s_T[i * lda + q] * s_GAI[q * nIm + j];
     s_GI[i * 16 + j] = v;
   }
   __syncthreads();
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     s_u = ggf_u53(x.x, x.y);
   }
   __syncthreads();
-  if (K > 1) {
+  if (PAIRS && K > 1) {
     if (threadIdx.x < npairs) {
       int pa, pb;
       pair_of(threadIdx.x, K, pa, pb);
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     const double rho = s_rho;
     double2 snew = make_double2(1.0, 0.0);
     double sratio = 1.0;
-    if (K > 1) {
+    if (PAIRS && K > 1) {
       double sv = Tn.w[0][0].x;
       for (int p = 0; p < npairs; ++p) {
         int pa, pb;
@@ -212,14 +219,13 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
     int *Ac = lc.dU + static_cast<size_t>(c) * kDelayMax;
     double *b12 = s_T;                   // a x 4
     double *b21 = b12 + 4 * lda;         // 4 x a
-    double *uu = b21 + 4 * lda;          // a x 4: u
-    double *uS = uu + 4 * lda;           // a x 4: u S^-1
-    double *Sv = uS + 4 * lda;           // 4 x a: S^-1 v
+    double *uu = s_GIA;                  // a x 4: u (G_IA is dead once b21 is formed)
+    double *Sv = s_GAI;                  // 4 x a: S^-1 v (G_AI is dead once b12 is formed)
     if (a > 0) {
       for (int e = threadIdx.x; e < 4 * a; e += blockDim.x) {
         const int p = e >> 2, y = e & 3;
         double v = 0.0;
-        for (int x = 0; x < 4; ++x) v += s_GAI[p * 16 + x] * s_dM[x * 4 + y];
+        for (int x = 0; x < 4; ++x) v += s_GAI[p * nIm + x] * s_dM[x * 4 + y];
         b12[p * 4 + y] = v;
         const int xq = e / a, pp = e - xq * a;
         const int blk = pp & ~3, col = pp & 3;
@@ -239,13 +245,7 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
           for (int x = 0; x < 4; ++x) u4[x] += bij * b12[j * 4 + x];
         }
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          uu[i * 4 + y] = u4[y];
-          double v = 0.0;
-#pragma unroll
-          for (int x = 0; x < 4; ++x) v += u4[x] * s_Ai[x * 4 + y];
-          uS[i * 4 + y] = v;
-        }
+        for (int y = 0; y < 4; ++y) uu[i * 4 + y] = u4[y];
       }
       for (int j = threadIdx.x; j < a; j += blockDim.x) {
         double v4[4] = {0, 0, 0, 0};
@@ -274,7 +274,10 @@ __global__ __launch_bounds__(256) void k_ratio(LaunchCtx lc, int ell, int parity
         for (int y = 0; y < 4; ++y) v += uu[i * 4 + y] * Sv[y * lda + j];
         *bij = v;
       } else if (i < a) {
-        *bij = -uS[i * 4 + (j - a)];
+        double v = 0.0;   // -(u S^-1)[i][j - a]
+#pragma unroll
+        for (int x = 0; x < 4; ++x) v += uu[i * 4 + x] * s_Ai[x * 4 + (j - a)];
+        *bij = -v;
       } else if (j < a) {
         *bij = -Sv[(i - a) * lda + j];
       } else {
@@ -661,25 +664,43 @@ static size_t pair_lds(int kmax) {
 }
 
 void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int wp) {
-  // pair workspaces, then for delayed updates G_IA (16 x 4F), G_AI (4F x 16) and 20 x 4F scratch
-  const size_t lds = pair_lds(kmax) + (lc.dly > 0 ? static_cast<size_t>(52) * 4 * lc.dly * sizeof(double) : 0);
-  // 9 pair workspaces (K = 4, 36 KB) with a 32-step window (53 KB) exceed the default
-  // 64 KB of dynamic LDS: raise the limit to what this launch needs (the launch reports
-  // an error if the device cannot provide it)
-  static size_t lds_set[2] = {64 * 1024, 64 * 1024};
-  const int ti = lc.precision == 64 ? 0 : 1;
+  // pair workspaces, then for delayed updates G_IA (nIm x 4F), G_AI (4F x nIm) and max(nIm, 8) x 4F
+  // scratch, nIm = 16 with pairs, else 4
+  const bool pairs = kmax > 1;
+  const int nIm = pairs ? 16 : 4;
+  const size_t lds = pair_lds(kmax) +
+                     (lc.dly > 0 ? static_cast<size_t>(2 * nIm + std::max(nIm, 8)) * 4 * lc.dly * sizeof(double) : 0);
+  const void *fn = lc.precision == 64
+                       ? (pairs ? reinterpret_cast<const void *>(&k_ratio<double, true>)
+                                : reinterpret_cast<const void *>(&k_ratio<double, false>))
+                       : (pairs ? reinterpret_cast<const void *>(&k_ratio<float, true>)
+                                : reinterpret_cast<const void *>(&k_ratio<float, false>));
+  // 9 pair workspaces (K = 4, 36 KB) with a 32-step window exceed the default 64 KB of
+  // dynamic LDS: raise the limit to what this launch needs (the launch reports an error
+  // if the device cannot provide it)
+  static size_t lds_set[4] = {64 * 1024, 64 * 1024, 64 * 1024, 64 * 1024};
+  const int ti = (lc.precision == 64 ? 0 : 2) + (pairs ? 1 : 0);
   if (lds > lds_set[ti]) {
-    const void *fn = lc.precision == 64 ? reinterpret_cast<const void *>(&k_ratio<double>)
-                                        : reinterpret_cast<const void *>(&k_ratio<float>);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) == hipSuccess)
       lds_set[ti] = lds;
     else
       (void)hipGetLastError();
   }
-  if (lc.precision == 64)
-    hipLaunchKernelGGL(k_ratio<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t, wp);
-  else
-    hipLaunchKernelGGL(k_ratio<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, ell, parity, t, wp);
+  if (lc.precision == 64) {
+    if (pairs)
+      hipLaunchKernelGGL((k_ratio<double, true>), dim3(lc.n_chains), dim3(kRatioThreads), lds, lc.stream, lc, ell,
+                         parity, t, wp);
+    else
+      hipLaunchKernelGGL((k_ratio<double, false>), dim3(lc.n_chains), dim3(kRatioThreads), lds, lc.stream, lc, ell,
+                         parity, t, wp);
+  } else {
+    if (pairs)
+      hipLaunchKernelGGL((k_ratio<float, true>), dim3(lc.n_chains), dim3(kRatioThreads), lds, lc.stream, lc, ell,
+                         parity, t, wp);
+    else
+      hipLaunchKernelGGL((k_ratio<float, false>), dim3(lc.n_chains), dim3(kRatioThreads), lds, lc.stream, lc, ell,
+                         parity, t, wp);
+  }
 }
 
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt) {
