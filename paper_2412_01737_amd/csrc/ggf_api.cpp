@@ -234,7 +234,6 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.dr = ctx->blk_r;
   lc.dcnt = ctx->dly_cnt;
   lc.dBinv = ctx->blk_A;
-  lc.dW = ctx->blk_W;
   lc.dX = ctx->dly_dX;
   lc.key0 = static_cast<uint32_t>(ctx->seed & 0xFFFFFFFFu);
   lc.key1 = static_cast<uint32_t>(ctx->seed >> 32);

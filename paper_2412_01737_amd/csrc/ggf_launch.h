@@ -32,11 +32,11 @@ struct LaunchCtx {
   // the window are the Majoranas A (dU, 4 per flip, dr[c] of them) with their
   // link changes dX (2x2 per flip); the current inverse is
   // G - G[:,A] W G[A,:], W = dM_A Binv, Binv = (1 + G_AA dM_A)^-1 (float64,
-  // dBinv with leading dimension GGF_BLOCK_RMAX, dW with leading dimension dr[c]);
+  // dBinv with leading dimension GGF_BLOCK_RMAX; W is never formed);
   // chains with a flip pending are listed in acc_list, dcnt[window parity] of them
   int dly;
   int *dU, *dr, *dcnt;
-  double *dBinv, *dW, *dX;
+  double *dBinv, *dX;
   uint32_t key0, key1;
   int n_chains;
 };

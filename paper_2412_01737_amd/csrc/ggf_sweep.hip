@@ -25,8 +25,6 @@
 // rows and columns (Schur complement S = 1 + G_cur,UU dM, whose determinant is
 // rho).  At the end of the window the block-update kernels apply the whole
 // window as one rank-|A| matrix-core update of G.
-#include <algorithm>
-
 #include "ggf_device.h"
 #include "ggf_launch.h"
 #include "ggf_nn.h"
@@ -88,27 +86,43 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   }
   __syncthreads();
   const int nI = s_nI;
-  // delayed-window work arrays after the pair workspaces: G_IA (nIm x a), G_AI (a x nIm) and a
-  // scratch block (max(nIm, 8) x a), nIm the largest index set (4 Majoranas when K = 1)
+  // delayed-window work arrays after the pair workspaces, nIm the largest index set (4 Majoranas
+  // when K = 1): s_H (nIm x a) = G_IA, then H = G_IA dM_A in place; s_GAI (a x nIm) = G_AI;
+  // s_T ((nIm + 4) x a): T = H Binv in rows [0, nI), b12 in rows [nIm, nIm + 4)
   const int nIm = PAIRS ? 16 : 4;
   const int lda = 4 * lc.dly;            // >= a + 4: pending Majoranas of a full window
-  double *s_GIA = reinterpret_cast<double *>(s_work + (npairs > 0 ? npairs * kPairLd * kPairLd : 0));
-  double *s_GAI = s_GIA + nIm * lda;
+  double *s_H = reinterpret_cast<double *>(s_work + (npairs > 0 ? npairs * kPairLd * kPairLd : 0));
+  double *s_GAI = s_H + nIm * lda;
   double *s_T = s_GAI + nIm * lda;
   const int *A = delayed ? lc.dU + static_cast<size_t>(c) * kDelayMax : nullptr;
+  const double *dXc = delayed ? lc.dX + static_cast<size_t>(c) * kDelayMax : nullptr;   // X of each pending flip
+  const double *Binv = delayed ? lc.dBinv + static_cast<size_t>(c) * kDelayMax * kDelayMax : nullptr;
   if (a > 0) {
     for (int e = threadIdx.x; e < nI * a; e += blockDim.x) {
       const int i = e / a, p = e - i * a;
-      s_GIA[i * lda + p] = static_cast<double>(G[static_cast<size_t>(s_I[i]) * n + A[p]]);
+      s_H[i * lda + p] = static_cast<double>(G[static_cast<size_t>(s_I[i]) * n + A[p]]);
       s_GAI[p * nIm + i] = static_cast<double>(G[static_cast<size_t>(A[p]) * n + s_I[i]]);
     }
     __syncthreads();
-    const double *W = lc.dW + static_cast<size_t>(c) * kDelayMax * kDelayMax;   // a x a, leading dimension a
+    // H = G_IA dM_A, one 4-column block of one row per thread: dM_A is block diagonal with
+    // blocks [[0, X], [-X^T, 0]], X = (X0 X1; X2 X3) of the pending flip
+    for (int e = threadIdx.x; e < nI * (a / 4); e += blockDim.x) {
+      const int i = e / (a / 4), blk = 4 * (e - i * (a / 4));
+      double *h = s_H + i * lda + blk;
+      const double *X = dXc + blk;
+      const double g0 = h[0], g1 = h[1], g2 = h[2], g3 = h[3];
+      h[0] = -g2 * X[0] - g3 * X[1];
+      h[1] = -g2 * X[2] - g3 * X[3];
+      h[2] = g0 * X[0] + g1 * X[2];
+      h[3] = g0 * X[1] + g1 * X[3];
+    }
+    __syncthreads();
+    // T = H Binv = G_IA W, W = dM_A Binv
     for (int e = threadIdx.x; e < nI * a; e += blockDim.x) {
       const int i = e / a, q = e - i * a;
       double v = 0.0;
-      for (int p = 0; p < a; ++p) v += s_GIA[i * lda + p] * W[p * a + q];
-      s_T[i * lda + q] = v;                           // (G_IA W)[i][q]
+      for (int p = 0; p < a; ++p) v += s_H[i * lda + p] * Binv[static_cast<size_t>(p) * kDelayMax + q];
+      s_T[i * lda + q] = v;
     }
     __syncthreads();
   }
@@ -211,34 +225,25 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   if (delayed) {
     // border Binv (a x a, leading dimension kDelayMax) by the flip's rows and columns:
     //   B' = [[B, b12], [b21, S]],  b12 = G_AU dM,  b21 = G_UA dM_A,  S = 1 + G_cur,UU dM (S^-1 = s_Ai),
-    //   B'^-1 = [[Binv + u S^-1 v, -u S^-1], [-S^-1 v, S^-1]],  u = Binv b12,  v = b21 Binv,
-    // then W' = dM_A' B'^-1 with leading dimension a + 4.
-    double *Binv = lc.dBinv + static_cast<size_t>(c) * kDelayMax * kDelayMax;
-    double *W = lc.dW + static_cast<size_t>(c) * kDelayMax * kDelayMax;
-    double *dXc = lc.dX + static_cast<size_t>(c) * kDelayMax;   // 4 values (X of dM) per pending flip
+    //   B'^-1 = [[Binv + u S^-1 v, -u S^-1], [-S^-1 v, S^-1]],  u = Binv b12,  v = b21 Binv.
+    // b21 = H[U rows], so v = T[U rows] (rows 0 .. 3 of T, U being first in I).
+    double *BinvW = lc.dBinv + static_cast<size_t>(c) * kDelayMax * kDelayMax;
+    double *dXw = lc.dX + static_cast<size_t>(c) * kDelayMax;
     int *Ac = lc.dU + static_cast<size_t>(c) * kDelayMax;
-    double *b12 = s_T;                   // a x 4
-    double *b21 = b12 + 4 * lda;         // 4 x a
-    double *uu = s_GIA;                  // a x 4: u (G_IA is dead once b21 is formed)
-    double *Sv = s_GAI;                  // 4 x a: S^-1 v (G_AI is dead once b12 is formed)
+    double *b12 = s_T + nIm * lda;       // a x 4
+    double *uu = s_GAI;                  // a x 4: u (G_AI is dead once b12 is formed)
+    double *Sv = s_H;                    // 4 x a: S^-1 v (H is dead once T is formed)
     if (a > 0) {
       for (int e = threadIdx.x; e < 4 * a; e += blockDim.x) {
         const int p = e >> 2, y = e & 3;
         double v = 0.0;
         for (int x = 0; x < 4; ++x) v += s_GAI[p * nIm + x] * s_dM[x * 4 + y];
         b12[p * 4 + y] = v;
-        const int xq = e / a, pp = e - xq * a;
-        const int blk = pp & ~3, col = pp & 3;
-        const double *X = dXc + blk;
-        const double dMb[16] = {0, 0, X[0], X[1], 0, 0, X[2], X[3], -X[0], -X[2], 0, 0, -X[1], -X[3], 0, 0};
-        double w = 0.0;
-        for (int z = 0; z < 4; ++z) w += s_GIA[xq * lda + blk + z] * dMb[z * 4 + col];
-        b21[xq * lda + pp] = w;
       }
       __syncthreads();
       for (int i = threadIdx.x; i < a; i += blockDim.x) {
         double u4[4] = {0, 0, 0, 0};
-        const double *bi = Binv + static_cast<size_t>(i) * kDelayMax;
+        const double *bi = BinvW + static_cast<size_t>(i) * kDelayMax;
         for (int j = 0; j < a; ++j) {
           const double bij = bi[j];
 #pragma unroll
@@ -247,27 +252,19 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
 #pragma unroll
         for (int y = 0; y < 4; ++y) uu[i * 4 + y] = u4[y];
       }
-      for (int j = threadIdx.x; j < a; j += blockDim.x) {
-        double v4[4] = {0, 0, 0, 0};
-        for (int i = 0; i < a; ++i) {
-          const double bij = Binv[static_cast<size_t>(i) * kDelayMax + j];
+      for (int e = threadIdx.x; e < 4 * a; e += blockDim.x) {
+        const int x = e / a, j = e - x * a;
+        double v = 0.0;
 #pragma unroll
-          for (int y = 0; y < 4; ++y) v4[y] += b21[y * lda + i] * bij;
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          double v = 0.0;
-#pragma unroll
-          for (int y = 0; y < 4; ++y) v += s_Ai[x * 4 + y] * v4[y];
-          Sv[x * lda + j] = v;
-        }
+        for (int y = 0; y < 4; ++y) v += s_Ai[x * 4 + y] * s_T[y * lda + j];
+        Sv[x * lda + j] = v;
       }
       __syncthreads();
     }
     const int a2 = a + 4;
     for (int e = threadIdx.x; e < a2 * a2; e += blockDim.x) {
       const int i = e / a2, j = e - i * a2;
-      double *bij = Binv + static_cast<size_t>(i) * kDelayMax + j;
+      double *bij = BinvW + static_cast<size_t>(i) * kDelayMax + j;
       if (i < a && j < a) {
         double v = *bij;
 #pragma unroll
@@ -284,28 +281,12 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
         *bij = s_Ai[(i - a) * 4 + (j - a)];
       }
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < a2 * a2; e += blockDim.x) {
-      const int i = e / a2, j = e - i * a2;
-      const int blk = i & ~3, row = i & 3;
-      double dmr[4];
-      if (blk < a) {
-        const double *X = dXc + blk;
-        const double dMb[16] = {0, 0, X[0], X[1], 0, 0, X[2], X[3], -X[0], -X[2], 0, 0, -X[1], -X[3], 0, 0};
-        for (int z = 0; z < 4; ++z) dmr[z] = dMb[row * 4 + z];
-      } else {
-        for (int z = 0; z < 4; ++z) dmr[z] = s_dM[row * 4 + z];
-      }
-      double v = 0.0;
-      for (int z = 0; z < 4; ++z) v += dmr[z] * Binv[static_cast<size_t>(blk + z) * kDelayMax + j];
-      W[static_cast<size_t>(i) * a2 + j] = v;
-    }
     if (threadIdx.x == 0) {
       for (int q = 0; q < 4; ++q) Ac[a + q] = U[q];
-      dXc[a + 0] = s_dM[2];
-      dXc[a + 1] = s_dM[3];
-      dXc[a + 2] = s_dM[6];
-      dXc[a + 3] = s_dM[7];
+      dXw[a + 0] = s_dM[2];
+      dXw[a + 1] = s_dM[3];
+      dXw[a + 2] = s_dM[6];
+      dXw[a + 3] = s_dM[7];
       lc.dr[c] = a2;
     }
     return;
@@ -664,12 +645,11 @@ static size_t pair_lds(int kmax) {
 }
 
 void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int wp) {
-  // pair workspaces, then for delayed updates G_IA (nIm x 4F), G_AI (4F x nIm) and max(nIm, 8) x 4F
+  // pair workspaces, then for delayed updates H (nIm x 4F), G_AI (4F x nIm) and (nIm + 4) x 4F
   // scratch, nIm = 16 with pairs, else 4
   const bool pairs = kmax > 1;
   const int nIm = pairs ? 16 : 4;
-  const size_t lds = pair_lds(kmax) +
-                     (lc.dly > 0 ? static_cast<size_t>(2 * nIm + std::max(nIm, 8)) * 4 * lc.dly * sizeof(double) : 0);
+  const size_t lds = pair_lds(kmax) + (lc.dly > 0 ? static_cast<size_t>(3 * nIm + 4) * 4 * lc.dly * sizeof(double) : 0);
   const void *fn = lc.precision == 64
                        ? (pairs ? reinterpret_cast<const void *>(&k_ratio<double, true>)
                                 : reinterpret_cast<const void *>(&k_ratio<double, false>))
