@@ -117,12 +117,26 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
       h[3] = g0 * X[1] + g1 * X[3];
     }
     __syncthreads();
-    // T = H Binv = G_IA W, W = dM_A Binv
-    for (int e = threadIdx.x; e < nI * a; e += blockDim.x) {
-      const int i = e / a, q = e - i * a;
-      double v = 0.0;
-      for (int p = 0; p < a; ++p) v += s_H[i * lda + p] * Binv[static_cast<size_t>(p) * kDelayMax + q];
-      s_T[i * lda + q] = v;
+    // T = H Binv = G_IA W, W = dM_A Binv: one column q of Binv per thread, read once for all
+    // rows of T, 8 loads in flight
+    for (int q = threadIdx.x; q < a; q += blockDim.x) {
+      double v[PAIRS ? 16 : 4];
+#pragma unroll
+      for (int i = 0; i < nIm; ++i) v[i] = 0.0;
+      for (int p0 = 0; p0 < a; p0 += 8) {
+        double bq[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          bq[k] = p0 + k < a ? Binv[static_cast<size_t>(p0 + k) * kDelayMax + q] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+          for (int i = 0; i < nIm; ++i)
+            if (i < nI && p0 + k < a) v[i] += s_H[i * lda + p0 + k] * bq[k];
+      }
+#pragma unroll
+      for (int i = 0; i < nIm; ++i)
+        if (i < nI) s_T[i * lda + q] = v[i];
     }
     __syncthreads();
   }
@@ -262,23 +276,36 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
       __syncthreads();
     }
     const int a2 = a + 4;
-    for (int e = threadIdx.x; e < a2 * a2; e += blockDim.x) {
-      const int i = e / a2, j = e - i * a2;
-      double *bij = BinvW + static_cast<size_t>(i) * kDelayMax + j;
-      if (i < a && j < a) {
-        double v = *bij;
+    // one column j of Binv' per thread, rows in batches of 8: every element is read and written
+    // by its own thread only, so a batch's loads are all issued before its stores
+    for (int j = threadIdx.x; j < a2; j += blockDim.x) {
+      for (int i0 = 0; i0 < a2; i0 += 8) {
+        double old[8];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) v += uu[i * 4 + y] * Sv[y * lda + j];
-        *bij = v;
-      } else if (i < a) {
-        double v = 0.0;   // -(u S^-1)[i][j - a]
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k;
+          old[k] = (i < a && j < a) ? BinvW[static_cast<size_t>(i) * kDelayMax + j] : 0.0;
+        }
 #pragma unroll
-        for (int x = 0; x < 4; ++x) v += uu[i * 4 + x] * s_Ai[x * 4 + (j - a)];
-        *bij = -v;
-      } else if (j < a) {
-        *bij = -Sv[(i - a) * lda + j];
-      } else {
-        *bij = s_Ai[(i - a) * 4 + (j - a)];
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k;
+          if (i >= a2) break;
+          double v;
+          if (i < a && j < a) {
+            v = old[k];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) v += uu[i * 4 + y] * Sv[y * lda + j];
+          } else if (i < a) {
+            v = 0.0;   // -(u S^-1)[i][j - a]
+#pragma unroll
+            for (int x = 0; x < 4; ++x) v -= uu[i * 4 + x] * s_Ai[x * 4 + (j - a)];
+          } else if (j < a) {
+            v = -Sv[(i - a) * lda + j];
+          } else {
+            v = s_Ai[(i - a) * 4 + (j - a)];
+          }
+          BinvW[static_cast<size_t>(i) * kDelayMax + j] = v;
+        }
       }
     }
     if (threadIdx.x == 0) {
