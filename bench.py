@@ -142,7 +142,7 @@ def traffic_from(args):
 
 
 def block_traffic_from(args):
-    """HBM bytes per accepted block move of k_block_prep + k_block_gemm, from FETCH_SIZE / WRITE_SIZE.
+    """HBM bytes per accepted block move of k_window_snap + k_window_gemm, from FETCH_SIZE / WRITE_SIZE.
 
     Counters are scaled by the copy calibration as in traffic_from; the number of
     accepted moves per launch comes from the profiled run's own JSON line."""
@@ -164,12 +164,12 @@ def block_traffic_from(args):
             rec = json.loads(line)
     learned = rec["learned"]
     moves_per_launch = learned["accepted_moves"] / learned["update_launches"]
-    out = {"source_digest": source_digest("ggf_block.inc"), "moves_per_launch": moves_per_launch,
+    out = {"source_digest": source_digest(BLOCK_SOURCES), "moves_per_launch": moves_per_launch,
            "fetch_scale": sf, "write_scale": sw}
     total = 0.0
     tname = "float" if rec["config"]["precision"] == 32 else "double"
-    # block moves only (the training sampler's window flushes run k_window_snap / k_window_gemm)
-    for k in (f"k_block_prep<{tname}>", f"k_block_gemm<{tname}>"):
+    # block moves only: the <T, true> instances (the training sampler's window flushes run <T, false>)
+    for k in (f"k_window_snap<{tname}, true>", f"k_window_gemm<{tname}, 8, true>"):
         fv, wv = per_kernel(f_csv, "FETCH_SIZE", k), per_kernel(w_csv, "WRITE_SIZE", k)
         rd = sum(fv) / len(fv) * sf * 1024.0
         wr = sum(wv) / len(wv) * sw * 1024.0
@@ -179,7 +179,7 @@ def block_traffic_from(args):
     n = rec["config"]["n"]
     esz = 4 if rec["config"]["precision"] == 32 else 8
     out["bytes_per_accepted_move"] = total / moves_per_launch
-    out["algorithmic_bytes_per_accepted_move"] = 2.0 * n * n * esz
+    out["algorithmic_bytes_per_accepted_move"] = (n * (n + 1) / 2 + n * n) * esz
     key = f"L{rec['config']['L']}_K{rec['config']['K']}_Z{rec['config']['group']}_p{rec['config']['precision']}"
     path = os.path.join(HERE, "profiles", "k_block_traffic.json")
     try:
@@ -225,6 +225,7 @@ def copy_probe(nbytes: int):
 
 
 KERNEL_SOURCE = {"k_update": ("ggf_sweep.hip",), "k_window_flush": ("ggf_block.inc", "ggf_window.inc")}
+BLOCK_SOURCES = ("ggf_block.inc", "ggf_window.inc")   # block moves: decision in the first, update in the second
 
 
 def traffic_key(args) -> str:
@@ -414,20 +415,20 @@ def run_c5(args):
 
     learned = sampler(args.chains, args.precision, args.refresh, True, args.steps, args.warmup)
     plain = sampler(args.plain_chains, 64, 1024, False, args.plain_steps, 1) if args.plain_steps > 0 else None
-    # block update G -= G[:,U] W G[U,:] per accepted move of m changed links (rank r = 4 m):
-    # algorithmic bytes = one read and one write of G (2 n^2 * 4), flops = 2 n^2 r; at r ~ 64 the
-    # arithmetic intensity (~16 flop/B) is below the float32 matrix-core ridge (157.3 / 8 ~ 19.7)
+    # block update G -= G[:,U] W G[U,:] per accepted move of m changed links (rank r = 4 m), on the
+    # upper triangle of the antisymmetric G and mirrored: algorithmic bytes = the upper triangle read
+    # and all of G written ((n (n + 1) / 2 + n^2) * 4), flops = n^2 r
     esz = 4 if args.precision == 32 else 8
     upd_s = learned["update_ms_total"] * 1e-3
-    bytes_moved = 2.0 * n * n * esz * learned["accepted_moves"]
-    flops = 2.0 * n * n * 4.0 * learned["links_changed"]
+    bytes_moved = (n * (n + 1) / 2 + n * n) * esz * learned["accepted_moves"]
+    flops = n * n * 4.0 * learned["links_changed"]
     achieved = bytes_moved / upd_s / 1e9 if upd_s > 0 else 0.0
     tflops = flops / upd_s / 1e12 if upd_s > 0 else 0.0
     traffic = None
     try:
         with open(os.path.join(HERE, "profiles", "k_block_traffic.json")) as f:
             tj = json.load(f).get(f"L{L}_K{K}_Z{group}_p{args.precision}")
-        if tj and tj["source_digest"] == source_digest("ggf_block.inc"):
+        if tj and tj["source_digest"] == source_digest(BLOCK_SOURCES):
             # measured bytes per accepted move x accepted moves per launch of this run
             traffic = tj["bytes_per_accepted_move"] * learned["accepted_moves"] / learned["update_launches"]
     except (OSError, ValueError, KeyError):
@@ -458,11 +459,12 @@ def run_c5(args):
         "training": {"chains": args.train_chains, "sweeps": args.train_sweeps, "adam_steps_per_sweep": args.train_steps,
                      "loss_nats_per_patch": losses, "seconds": t_train},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_block_prep + k_block_gemm",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_window_snap + k_window_gemm (block moves)",
                      "algorithmic_bytes_per_launch": bytes_moved / max(learned["update_launches"], 1),
-                     "bytes_per_accepted_move": 2.0 * n * n * esz,
+                     "bytes_per_accepted_move": (n * (n + 1) / 2 + n * n) * esz,
                      "tflops": tflops, "mfma_peak_tflops": MFMA_PEAK_F32_TFLOPS,
-                     "flops_per_changed_link": 8.0 * n * n},
+                     "flops_per_changed_link": 4.0 * n * n},
         "cpu_baseline": None,
     }
     print(json.dumps(out))

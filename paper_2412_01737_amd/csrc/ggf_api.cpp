@@ -75,7 +75,7 @@ struct ggf_ctx {
   std::vector<void *> nn_allocs;
   // block-move buffers (tied to the chains)
   double *blk_A = nullptr, *blk_W = nullptr;
-  void *blk_C = nullptr, *blk_D = nullptr;
+  void *blk_D = nullptr;
   size_t *blk_doff = nullptr;
   int *blk_U = nullptr, *blk_r = nullptr;
   unsigned long long *blk_prop = nullptr, *blk_acc = nullptr;
@@ -192,7 +192,7 @@ void free_chains(ggf_ctx *ctx) {
   for (void *p : ctx->allocs) hipFree(p);
   ctx->allocs.clear();
   ctx->blk_A = ctx->blk_W = nullptr;
-  ctx->blk_C = ctx->blk_D = nullptr;
+  ctx->blk_D = nullptr;
   ctx->dly_dX = nullptr;
   ctx->dly_cnt = nullptr;
   ctx->blk_doff = nullptr;
@@ -439,7 +439,7 @@ ggf_status block_buffers(ggf_ctx *ctx) {
   ctx->blk_r = dalloc<int>(ctx, ctx->n_chains, e);
   ctx->blk_prop = dalloc<unsigned long long>(ctx, 3 * static_cast<size_t>(ctx->n_chains), e);   // proposed, accepted, links
   ctx->blk_acc = ctx->blk_prop;
-  for (void **dst : {&ctx->blk_C, &ctx->blk_D}) {
+  for (void **dst : {&ctx->blk_D}) {
     if (e != hipSuccess) break;
     void *p = nullptr;
     e = hipMalloc(&p, tot * esz);
@@ -1113,7 +1113,6 @@ ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   bl.nn = nn_args(ctx);
   bl.A = ctx->blk_A;
   bl.Wf = ctx->blk_W;
-  bl.C = ctx->blk_C;
   bl.D = ctx->blk_D;
   bl.d_off = ctx->blk_doff;
   bl.U = ctx->blk_U;

@@ -21,7 +21,7 @@ struct BlockLaunch {
   LaunchCtx lc;
   NNArgs nn;
   double *A, *Wf;
-  void *C, *D;
+  void *D;
   const size_t *d_off;
   int *U, *rcnt;
   unsigned long long *bprop, *bacc;
