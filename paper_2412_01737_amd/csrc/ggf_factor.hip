@@ -318,19 +318,29 @@ __global__ __launch_bounds__(256, 2) void k_gj_gemm(const int *__restrict__ list
     }
     __syncthreads();
   }
-  // epilogue: X (zero on the pivot rows) + Z Y, columns of the panel untouched
+  // epilogue: X (zero on the pivot rows) + Z Y, columns of the panel untouched; per 16-row
+  // block all loads are issued before the stores (each element is read and written by its own
+  // lane only, but the compiler cannot tell the stores from the next loads)
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a) {
+    double xv[CB][4];
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = r0 + wr + 16 * a + g + 4 * e, col = c0 + wc + 16 * c + li;
-        if (r < n && col < hi && !(col >= pj && col < pj + pwe)) {
-          double *x = A + static_cast<size_t>(r) * n + col;
-          *x = (r >= pj && r < pj + pwe) ? acc[a][c][e] : *x + acc[a][c][e];
-        }
+        const bool upd = r < n && col < hi && !(col >= pj && col < pj + pwe) && !(r >= pj && r < pj + pwe);
+        xv[c][e] = upd ? A[static_cast<size_t>(r) * n + col] : 0.0;
       }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + wr + 16 * a + g + 4 * e, col = c0 + wc + 16 * c + li;
+        if (r < n && col < hi && !(col >= pj && col < pj + pwe))
+          A[static_cast<size_t>(r) * n + col] = xv[c][e] + acc[a][c][e];
+      }
+  }
 }
 
 // Column permutation that undoes the row pivoting: result column q = panel-ordered column arr[q].
