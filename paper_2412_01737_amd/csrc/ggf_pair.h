@@ -112,6 +112,108 @@ __device__ inline double2 pair_ratio(double2 *W, int s) {
   return pf;
 }
 
+// Lane-parallel forms for one wave (64 lanes) evaluating up to 8 pairs at once,
+// 8 lanes per pair; lane gl of a group owns rows gl, gl + 8 of the pair matrix.
+// They perform per element the same operations as build_pair_matrix and
+// ggf_cpfaffian (bit-identical results, the same pivots).
+constexpr int kPairLanes = 8;
+
+// Rows of the pair matrix of (a, b) with G' = G_II + G_IU K G_UI read from the
+// current inverse on the index set I (gI: nI x nI, row stride 16, U first in I).
+__device__ inline void build_pair_rows(const TensorDev &Tn, int a, int b, int group, const double *gI,
+                                       const int *I, int nI, const int8_t *lk, const double *Kw, int ell_prop,
+                                       int k_prop, const PatchSet &ps, double2 *W, int gl) {
+  const int s = ps.s, m = 2 * s;
+  int pos[8];
+  for (int i = 0; i < s; ++i) {
+    pos[i] = 0;
+    for (int q = 0; q < nI; ++q)
+      if (I[q] == ps.idx[i]) pos[i] = q;
+  }
+  for (int i = gl; i < m; i += kPairLanes) {
+    if (i < s) {
+      double t[4];
+      for (int q2 = 0; q2 < 4; ++q2) {
+        double v = 0.0;
+        for (int q = 0; q < 4; ++q) v += gI[pos[i] * 16 + q] * Kw[q * 4 + q2];
+        t[q2] = v;
+      }
+      for (int j = 0; j < s; ++j) {
+        double v = 0.0;
+        for (int q2 = 0; q2 < 4; ++q2) v += t[q2] * gI[pos[j] * 16 + q2];
+        W[i * kPairLd + j] = make_double2(gI[pos[i] * 16 + pos[j]] + v, 0.0);
+      }
+      for (int j = s; j < m; ++j) W[i * kPairLd + j] = make_double2(j == i + s ? 1.0 : 0.0, 0.0);
+    } else {
+      for (int j = 0; j < s; ++j) W[i * kPairLd + j] = make_double2(j == i - s ? -1.0 : 0.0, 0.0);
+      const int l = (i - s) >> 2, ii = (i - s) & 3;
+      const int link = Tn.lk[a][b][l];
+      const int kv = (link == ell_prop) ? k_prop : lk[link];
+      double2 blk[16];
+      ggf_rotate_dg(Tn.dg[a][b][l], kv, group, blk);
+      for (int j = s; j < m; ++j)
+        W[i * kPairLd + j] = ((j - s) >> 2) == l ? blk[ii * 4 + ((j - s) & 3)] : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Pfaffian of the m x m (m <= 16) skew matrix A (leading dimension kPairLd) by the
+// group's 8 lanes; tv: 32 complex of group scratch.  Every lane of the wave must
+// call it (it synchronises the workgroup, one wave); lanes of an idle group pass m = 0.
+__device__ inline double2 pfaffian_lanes(double2 *A, int m, double2 *tv, int gl) {
+  constexpr int ld = kPairLd;
+  double2 pf = make_double2(1.0, 0.0);
+  bool zero = false;
+  for (int k = 0; k < 16; k += 2) {
+    const bool live = !zero && k + 1 < m;
+    double best = -1.0;
+    int kp = k + 1;
+    if (live)
+      for (int i = k + 1 + gl; i < m; i += kPairLanes) {
+        const double v = cabs2(A[i * ld + k]);
+        if (v > best) { best = v; kp = i; }
+      }
+    for (int off = kPairLanes / 2; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, kPairLanes);
+      const int oi = __shfl_xor(kp, off, kPairLanes);
+      if (ob > best || (ob == best && oi < kp)) { best = ob; kp = oi; }
+    }
+    const bool sw = live && kp != k + 1;
+    __syncthreads();
+    if (sw)
+      for (int j = gl; j < m; j += kPairLanes) {
+        const double2 t = A[(k + 1) * ld + j]; A[(k + 1) * ld + j] = A[kp * ld + j]; A[kp * ld + j] = t;
+      }
+    __syncthreads();
+    if (sw)
+      for (int i = gl; i < m; i += kPairLanes) {
+        const double2 t = A[i * ld + k + 1]; A[i * ld + k + 1] = A[i * ld + kp]; A[i * ld + kp] = t;
+      }
+    __syncthreads();
+    double2 piv = make_double2(1.0, 0.0);
+    if (live) {
+      if (sw) pf = cscale(pf, -1.0);
+      piv = A[k * ld + k + 1];
+      if (piv.x == 0.0 && piv.y == 0.0) zero = true;
+      else pf = cmul(pf, piv);
+    }
+    if (live && !zero)
+      for (int x = k + 2 + gl; x < m; x += kPairLanes) {
+        tv[x] = cdiv(A[k * ld + x], piv);
+        tv[16 + x] = A[x * ld + k + 1];
+      }
+    __syncthreads();
+    if (live && !zero)
+      for (int i = k + 2 + gl; i < m; i += kPairLanes) {
+        const double2 ti = tv[i], vi = tv[16 + i];
+        for (int j = k + 2; j < m; ++j)
+          A[i * ld + j] = cadd(A[i * ld + j], csub(cmul(ti, tv[16 + j]), cmul(vi, tv[j])));
+      }
+    __syncthreads();
+  }
+  return zero ? make_double2(0.0, 0.0) : pf;
+}
+
 __device__ inline void pair_of(int p, int K, int &a, int &b) {
   // enumerate a <= b, skipping (0, 0): p = 0 .. K(K+1)/2 - 2
   int q = p + 1;

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   __shared__ double s_rho, s_u;
   __shared__ int s_kn, s_acc;
   __shared__ double2 s_r[16];
+  __shared__ double2 s_tv[PAIRS ? kRatioThreads / kPairLanes : 1][32];   // pair elimination scratch
   const int c = blockIdx.x;
   const bool delayed = lc.dly > 0;
   if (c == 0 && threadIdx.x == 0) {
@@ -182,19 +183,28 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   }
   __syncthreads();
   if (PAIRS && K > 1) {
-    if (threadIdx.x < npairs) {
-      int pa, pb;
-      pair_of(threadIdx.x, K, pa, pb);
+    // pairs 8 at a time, 8 lanes each (K = 1 .. 4: at most 9 pairs); K is uniform in the workgroup
+    const int grp = threadIdx.x / kPairLanes, gl = threadIdx.x % kPairLanes;
+    for (int p0 = 0; p0 < npairs; p0 += kRatioThreads / kPairLanes) {
+      const int p = p0 + grp;
+      const bool act = p < npairs;
       PatchSet ps;
-      double2 *Wp = s_work + threadIdx.x * kPairLd * kPairLd;
-      GView<T> gv{G, n};
-      gv.cache = s_GI;
-      gv.cidx = s_I;
-      gv.nc = nI;
-      build_pair_matrix(Tn, pa, pb, ch.L, ch.group, gv, lk, U, s_K, ell, s_kn, Wp, ps);
-      s_r[threadIdx.x] = pair_ratio(Wp, ps.s);
+      ps.s = 0;
+      int pa = 0, pb = 0;
+      double2 *Wp = s_work + (act ? p : 0) * kPairLd * kPairLd;
+      if (act) {
+        pair_of(p, K, pa, pb);
+        pair_set(Tn, pa, pb, ch.L, ps);
+        build_pair_rows(Tn, pa, pb, ch.group, s_GI, s_I, nI, lk, s_K, ell, s_kn, ps, Wp, gl);
+      }
+      __syncthreads();
+      double2 pf = pfaffian_lanes(Wp, act ? 2 * ps.s : 0, s_tv[grp], gl);
+      if (act && gl == 0) {
+        if ((ps.s / 2) & 1) pf = cscale(pf, -1.0);   // r = (-1)^(s/2) Pf, as pair_ratio
+        s_r[p] = pf;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     const double rho = s_rho;
