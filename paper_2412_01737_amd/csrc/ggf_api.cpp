@@ -36,6 +36,7 @@ struct ggf_ctx {
 
   // chains
   int n_chains = 0, precision = 64, refresh_every = 0, kmax = 1, max_links = 0, n_max = 0;
+  int nidx = 4;   // largest index set of a link step (Majoranas)
   uint64_t seed = 0;
   std::vector<ChainDev> chains;
   std::vector<unsigned long long> recoveries;
@@ -230,6 +231,7 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.acc_cnt = ctx->acc_cnt;
   lc.scratch = ctx->scratch;
   lc.dly = 0;                      // set by record_sweep when the window is delayed
+  lc.nidx = ctx->nidx;
   lc.dU = ctx->blk_U;
   lc.dr = ctx->blk_r;
   lc.dcnt = ctx->dly_cnt;
@@ -557,7 +559,7 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
   if (refresh_every < 0) return fail(ctx, GGF_EINVAL, "refresh_every must be >= 0");
   std::vector<ChainDev> ch(n_chains);
   size_t goff = 0, foff = 0, loff = 0;
-  int kmax = 1, max_links = 0, n_max = 0;
+  int kmax = 1, max_links = 0, n_max = 0, nidx = 4;
   size_t max_need = 0, tot_need = 0;
   for (int c = 0; c < n_chains; ++c) {
     const int l = L[c];
@@ -585,6 +587,16 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
     foff += 8 * static_cast<size_t>(d.n);
     loff += (d.nlinks + 63) & ~63;
     kmax = std::max(kmax, t.K);
+    {
+      // index set of a link step: U plus the Majoranas of every distinct patch link of the pairs
+      std::vector<int> pl;
+      for (int a = 0; a < t.K; ++a)
+        for (int b = a; b < t.K; ++b)
+          if (a + b > 0)
+            for (int l = 0; l < t.nl[a][b]; ++l)
+              if (std::find(pl.begin(), pl.end(), t.lk[a][b][l]) == pl.end()) pl.push_back(t.lk[a][b][l]);
+      nidx = std::max(nidx, std::min(16, 4 + 4 * static_cast<int>(pl.size())));
+    }
     max_links = std::max(max_links, d.nlinks);
     n_max = std::max(n_max, d.n);
     max_need = std::max(max_need, nn);
@@ -637,6 +649,7 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
   ctx->precision = precision;
   ctx->refresh_every = refresh_every;
   ctx->kmax = kmax;
+  ctx->nidx = nidx;
   ctx->max_links = max_links;
   ctx->n_max = n_max;
   ctx->seed = seed;

@@ -35,6 +35,7 @@ struct LaunchCtx {
   // dBinv with leading dimension GGF_BLOCK_RMAX; W is never formed);
   // chains with a flip pending are listed in acc_list, dcnt[window parity] of them
   int dly;
+  int nidx;                      // largest index set of a link step (4 .. 16 Majoranas)
   int *dU, *dr, *dcnt;
   double *dBinv, *dX;
   uint32_t key0, key1;

@@ -118,6 +118,27 @@ __device__ inline double2 pair_ratio(double2 *W, int s) {
 // ggf_cpfaffian (bit-identical results, the same pivots).
 constexpr int kPairLanes = 8;
 
+// Row ii of ggf_rotate_dg's O dg O^T, by the same operations in the same order.
+__device__ inline void rotate_dg_row(const double2 dg[16], int k, int group, int ii, double2 out[4]) {
+  double c = 1.0, s = 0.0;
+  if (k != 0) {
+    if (group == 2) { c = -1.0; s = 0.0; }
+    else { sincospi(2.0 * k / group, &s, &c); }
+  }
+  const double o[16] = {c, s, 0, 0, -s, c, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+  double2 t[4];
+  for (int j = 0; j < 4; ++j) {
+    double2 v = make_double2(0, 0);
+    for (int q = 0; q < 4; ++q) v = cadd(v, cscale(dg[q * 4 + j], o[ii * 4 + q]));
+    t[j] = v;
+  }
+  for (int j = 0; j < 4; ++j) {
+    double2 v = make_double2(0, 0);
+    for (int q = 0; q < 4; ++q) v = cadd(v, cscale(t[q], o[j * 4 + q]));
+    out[j] = v;
+  }
+}
+
 // Rows of the pair matrix of (a, b) with G' = G_II + G_IU K G_UI read from the
 // current inverse on the index set I (gI: nI x nI, row stride 16, U first in I).
 __device__ inline void build_pair_rows(const TensorDev &Tn, int a, int b, int group, const double *gI,
@@ -149,10 +170,10 @@ __device__ inline void build_pair_rows(const TensorDev &Tn, int a, int b, int gr
       const int l = (i - s) >> 2, ii = (i - s) & 3;
       const int link = Tn.lk[a][b][l];
       const int kv = (link == ell_prop) ? k_prop : lk[link];
-      double2 blk[16];
-      ggf_rotate_dg(Tn.dg[a][b][l], kv, group, blk);
+      double2 brow[4];
+      rotate_dg_row(Tn.dg[a][b][l], kv, group, ii, brow);
       for (int j = s; j < m; ++j)
-        W[i * kPairLd + j] = ((j - s) >> 2) == l ? blk[ii * 4 + ((j - s) & 3)] : make_double2(0.0, 0.0);
+        W[i * kPairLd + j] = ((j - s) >> 2) == l ? brow[(j - s) & 3] : make_double2(0.0, 0.0);
     }
   }
 }

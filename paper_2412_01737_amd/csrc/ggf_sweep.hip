@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   // delayed-window work arrays after the pair workspaces, nIm the largest index set (4 Majoranas
   // when K = 1): s_H (nIm x a) = G_IA, then H = G_IA dM_A in place; s_GAI (a x nIm) = G_AI;
   // s_T ((nIm + 4) x a): T = H Binv in rows [0, nI), b12 in rows [nIm, nIm + 4)
-  const int nIm = PAIRS ? 16 : 4;
+  const int nIm = PAIRS ? lc.nidx : 4;
   const int lda = 4 * lc.dly;            // >= a + 4: pending Majoranas of a full window
   double *s_H = reinterpret_cast<double *>(s_work + (npairs > 0 ? npairs * kPairLd * kPairLd : 0));
   double *s_GAI = s_H + nIm * lda;
@@ -120,10 +120,11 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
     __syncthreads();
     // T = H Binv = G_IA W, W = dM_A Binv: one column q of Binv per thread, read once for all
     // rows of T, 8 loads in flight
+    constexpr int kNI = PAIRS ? 16 : 4;   // register bound of the index set
     for (int q = threadIdx.x; q < a; q += blockDim.x) {
-      double v[PAIRS ? 16 : 4];
+      double v[kNI];
 #pragma unroll
-      for (int i = 0; i < nIm; ++i) v[i] = 0.0;
+      for (int i = 0; i < kNI; ++i) v[i] = 0.0;
       for (int p0 = 0; p0 < a; p0 += 8) {
         double bq[8];
 #pragma unroll
@@ -132,11 +133,11 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
-          for (int i = 0; i < nIm; ++i)
+          for (int i = 0; i < kNI; ++i)
             if (i < nI && p0 + k < a) v[i] += s_H[i * lda + p0 + k] * bq[k];
       }
 #pragma unroll
-      for (int i = 0; i < nIm; ++i)
+      for (int i = 0; i < kNI; ++i)
         if (i < nI) s_T[i * lda + q] = v[i];
     }
     __syncthreads();
@@ -683,9 +684,9 @@ static size_t pair_lds(int kmax) {
 
 void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int wp) {
   // pair workspaces, then for delayed updates H (nIm x 4F), G_AI (4F x nIm) and (nIm + 4) x 4F
-  // scratch, nIm = 16 with pairs, else 4
+  // scratch, nIm the largest index set of the context (4 without pairs)
   const bool pairs = kmax > 1;
-  const int nIm = pairs ? 16 : 4;
+  const int nIm = pairs ? lc.nidx : 4;
   const size_t lds = pair_lds(kmax) + (lc.dly > 0 ? static_cast<size_t>(3 * nIm + 4) * 4 * lc.dly * sizeof(double) : 0);
   const void *fn = lc.precision == 64
                        ? (pairs ? reinterpret_cast<const void *>(&k_ratio<double, true>)
