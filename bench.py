@@ -243,6 +243,22 @@ def source_digest(names=("ggf_sweep.hip",)) -> str:
     return h.hexdigest()[:16]
 
 
+def refresh_rates(st0, st1, steps: int, refresh: int):
+    """Mean refactorisations per chain over `steps` sweeps: (at the true rate, counted).
+
+    st0, st1: per-chain state dicts ("accepts", "refreshes") before and after the
+    sweeps.  A chain is refactorised at the first sweep end after `refresh`
+    accepted flips, i.e. every ceil(refresh / accepted flips per sweep) sweeps."""
+    import math
+    expected, actual = [], []
+    for a, b in zip(st0, st1):
+        fps = (b["accepts"] - a["accepts"]) / steps
+        period = math.ceil(refresh / fps) if refresh > 0 and fps > 0 else 0
+        expected.append(steps / period if period > 0 else 0.0)
+        actual.append(b["refreshes"] - a["refreshes"])
+    return float(np.mean(expected)), float(np.mean(actual))
+
+
 def refresh_correction(ctx, args, st0, stream):
     """Float64 refactorisations charged at their true rate.
 
@@ -251,16 +267,9 @@ def refresh_correction(ctx, args, st0, stream):
     sweeps contain however many refactorisations their alignment gives; the
     difference to the true rate is charged (or credited) at the measured cost
     of refactorising all chains, timed here after the timed region."""
-    import math
     import torch
     st1 = [ctx.get_state(c)[1] for c in range(args.chains)]
-    expected, actual = [], []
-    for a, b in zip(st0, st1):
-        fps = (b["accepts"] - a["accepts"]) / args.steps
-        period = math.ceil(args.refresh / fps) if args.refresh > 0 and fps > 0 else 0
-        expected.append(args.steps / period if period > 0 else 0.0)
-        actual.append(b["refreshes"] - a["refreshes"])
-    exp_mean, act_mean = float(np.mean(expected)), float(np.mean(actual))
+    exp_mean, act_mean = refresh_rates(st0, st1, args.steps, args.refresh)
     torch.cuda.synchronize()
     t = time.perf_counter()
     ctx.refresh_all(stream=stream)

@@ -1,0 +1,30 @@
+"""Host-side accounting of bench.py (no GPU): refactorisations charged at their true rate."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def _st(accepts, refreshes):
+    return {"accepts": accepts, "refreshes": refreshes}
+
+
+def test_refresh_rate_cadence():
+    # 126 accepted flips per sweep, refresh every 1024: period ceil(1024/126) = 9 sweeps
+    st0 = [_st(1000, 1), _st(0, 0)]
+    st1 = [_st(1000 + 20 * 126, 3), _st(20 * 63, 0)]   # second chain: 63 per sweep -> period 17
+    exp, act = bench.refresh_rates(st0, st1, 20, 1024)
+    assert exp == pytest.approx((20 / 9 + 20 / 17) / 2)
+    assert act == pytest.approx(1.0)
+
+
+def test_refresh_rate_every_sweep_and_off():
+    # more accepted flips per sweep than the interval: once per sweep (checked at the sweep end)
+    exp, act = bench.refresh_rates([_st(0, 0)], [_st(3 * 126, 3)], 3, 64)
+    assert exp == pytest.approx(1.0 * 3) and act == 3
+    # refresh off, or a chain with no accepted flip: no refactorisation due
+    assert bench.refresh_rates([_st(0, 0)], [_st(500, 0)], 4, 0) == (0.0, 0.0)
+    assert bench.refresh_rates([_st(7, 2)], [_st(7, 2)], 4, 64) == (0.0, 0.0)
