@@ -40,7 +40,7 @@ constexpr int kRatioThreads = 64;   // one wave per chain: the per-step work is 
 template <typename T, bool PAIRS>
 __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, int parity, int t, int wp) {
   extern __shared__ double2 s_work[];   // pair workspaces, then (delayed) G_IA, G_AI and a scratch block
-  __shared__ double s_K[16], s_Ai[16], s_dM[16];
+  __shared__ double s_K[16], s_Ai[16], s_dM[16], s_Am[16];
   __shared__ double s_GI[(PAIRS ? 16 : 4) * 16];   // current inverse on the Majoranas I (U first), row stride 16
   __shared__ int s_I[16];
   __shared__ int s_nI;
@@ -159,25 +159,23 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
     ggf_bond_block(Tn.x0, kn, ch.group, yn);
     const double X0 = yn[0] - yo[0], X1 = yn[1] - yo[1], X2 = yn[2] - yo[2], X3 = yn[3] - yo[3];
     const double dM[16] = {0, 0, X0, X1, 0, 0, X2, X3, -X0, -X2, 0, 0, -X1, -X3, 0, 0};
-    double Am[16], Ai[16];
+    // the 4x4 system lives in LDS (s_Am, s_Ai): its pivoting on registers would set the
+    // register budget of the whole kernel
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
         double v = (i == j) ? 1.0 : 0.0;
         for (int q = 0; q < 4; ++q) v += s_GI[i * 16 + q] * dM[q * 4 + j];
-        Am[i * 4 + j] = v;
-        Ai[i * 4 + j] = (i == j) ? 1.0 : 0.0;
+        s_Am[i * 4 + j] = v;
+        s_Ai[i * 4 + j] = (i == j) ? 1.0 : 0.0;
       }
-    const double rho = ggf_solve4(Am, Ai);      // Ai <- (1 + G_UU dM)^-1
+    const double rho = ggf_solve4(s_Am, s_Ai);      // s_Ai <- (1 + G_UU dM)^-1
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
         double v = 0.0;
-        for (int q = 0; q < 4; ++q) v += dM[i * 4 + q] * Ai[q * 4 + j];
+        for (int q = 0; q < 4; ++q) v += dM[i * 4 + q] * s_Ai[q * 4 + j];
         s_K[i * 4 + j] = v;
       }
-    for (int q = 0; q < 16; ++q) {
-      s_Ai[q] = Ai[q];
-      s_dM[q] = dM[q];
-    }
+    for (int q = 0; q < 16; ++q) s_dM[q] = dM[q];
     s_rho = rho;
     s_kn = kn;
     s_u = ggf_u53(x.x, x.y);
