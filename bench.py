@@ -111,9 +111,9 @@ def traffic_from(args):
 
     kernel = "k_window_flush" if args.delay > 0 else "k_update"
     if args.delay > 0:
-        # the window flush is two dispatches per window: k_window_snap then k_window_gemm
+        # the window flush is one dispatch per window (k_window_gemm; the link steps copy P = G[A,:])
         fetch, write, nf, nw = 0.0, 0.0, 0, 0
-        for k in ("k_window_snap", "k_window_gemm"):
+        for k in ("k_window_gemm",):
             f_, n_ = per_kernel(args.traffic_from[0], "FETCH_SIZE", k)
             w_, m_ = per_kernel(args.traffic_from[1], "WRITE_SIZE", k)
             fetch, write, nf, nw = fetch + f_, write + w_, n_, m_
@@ -168,8 +168,9 @@ def block_traffic_from(args):
            "fetch_scale": sf, "write_scale": sw}
     total = 0.0
     tname = "float" if rec["config"]["precision"] == 32 else "double"
-    # block moves only: the <T, true> instances (the training sampler's window flushes run <T, false>)
-    for k in (f"k_window_snap<{tname}, true>", f"k_window_gemm<{tname}, 8, true>"):
+    # block moves only: k_window_snap and the <T, 8, true> instance of k_window_gemm (the training
+    # sampler's window flushes run <T, 4, false>)
+    for k in (f"k_window_snap<{tname}>", f"k_window_gemm<{tname}, 8, true>"):
         fv, wv = per_kernel(f_csv, "FETCH_SIZE", k), per_kernel(w_csv, "WRITE_SIZE", k)
         rd = sum(fv) / len(fv) * sf * 1024.0
         wr = sum(wv) / len(wv) * sw * 1024.0
@@ -581,11 +582,11 @@ def main():
         bytes_per_flip = 2.0 * n * n * esz
     F = args.delay
     if F > 0:
-        # delayed updates: the dominant kernel is the window flush (k_window_snap copying P = G[A,:],
-        # then the matrix-core k_window_gemm on the upper triangle, mirrored): per chain with a
-        # pending flip in the window (at these acceptances, every window it has link steps in) the
-        # upper triangle of G read once, n (n + 1) / 2 elements, and all of G written once, n^2;
-        # the snapshot and operand reads (2 r n elements) are not counted
+        # delayed updates: the dominant kernel is the window flush (the matrix-core k_window_gemm
+        # on the upper triangle, mirrored): per chain with a pending flip in the window (at these
+        # acceptances, every window it has link steps in) the upper triangle of G read once,
+        # n (n + 1) / 2 elements, and all of G written once, n^2; the reads of P = G[A,:] (r n
+        # elements, copied by the link steps) are not counted
         nl_c = 2 * Lc.astype(np.int64) ** 2
         windows = -(-int(nl_c.max()) // F)
         share = np.minimum(-(-nl_c // F), windows) / windows

@@ -237,6 +237,8 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.dcnt = ctx->dly_cnt;
   lc.dBinv = ctx->blk_A;
   lc.dX = ctx->dly_dX;
+  lc.dP = ctx->blk_D;
+  lc.dP_off = ctx->blk_doff;
   lc.key0 = static_cast<uint32_t>(ctx->seed & 0xFFFFFFFFu);
   lc.key1 = static_cast<uint32_t>(ctx->seed >> 32);
   lc.n_chains = ctx->n_chains;
@@ -343,7 +345,7 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell + 1], s));
     if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
-    if (F > 0) ggf_launch_window_flush(lc, wp, ctx->blk_D, ctx->blk_doff, 1024);
+    if (F > 0) ggf_launch_window_flush(lc, wp, 1024);
     else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
     ++k;

@@ -25,6 +25,8 @@
 // rows and columns (Schur complement S = 1 + G_cur,UU dM, whose determinant is
 // rho).  At the end of the window the block-update kernels apply the whole
 // window as one rank-|A| matrix-core update of G.
+#include <type_traits>
+
 #include "ggf_device.h"
 #include "ggf_launch.h"
 #include "ggf_nn.h"
@@ -64,6 +66,21 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   int8_t *lk = lc.links + ch.link_off;
   int U[4];
   ggf_link_u(ell, ch.L, U);
+  if (delayed && a + 4 <= kDelayMax) {
+    // rows U of the stored G (unchanged within the window) become rows a .. a + 3 of the
+    // window's P = G[A,:], read by the flush if this flip is accepted; a rejected step's
+    // rows are overwritten by the next accepted one
+    typedef typename std::conditional<sizeof(T) == 8, d2v, f4v>::type V;
+    constexpr int VW = 16 / sizeof(T);
+    T *P = static_cast<T *>(lc.dP) + lc.dP_off[c] + static_cast<size_t>(a) * n;
+    const int nv = n / VW;
+#pragma unroll 8
+    for (int e = threadIdx.x; e < 4 * nv; e += blockDim.x) {
+      const int q = e / nv, v = e - q * nv;
+      reinterpret_cast<V *>(P + static_cast<size_t>(q) * n)[v] =
+          reinterpret_cast<const V *>(G + static_cast<size_t>(U[q]) * n)[v];
+    }
+  }
   const int K = PAIRS ? ch.K : 1;
   const int npairs = K * (K + 1) / 2 - 1;
   if (threadIdx.x == 0) {
