@@ -438,8 +438,9 @@ void gj_apply(const GJRun &g, int pj, int pw, int c_lo, int c_hi) {
 // Factor the panel columns [j, j+w): recursively, left half, its transform on the right half,
 // right half, its transform on the left half; base panels of 8 columns held in registers.
 void gj_panel(const GJRun &g, int j, int w) {
-  // base panels in registers: <= 4 rows x 8 columns per thread up to n = 4096, 8 x 4 above
-  const int T = g.n_max <= 1024 ? 256 : 1024;
+  // base panels in registers: <= 4 rows x 8 columns per thread up to n = 4096, 8 x 4 above;
+  // the fewest threads that cover the rows (each pivot search is a workgroup reduction)
+  const int T = g.n_max <= 1024 ? 256 : (g.n_max <= 2048 ? 512 : 1024);
   const int bw = g.n_max <= 4096 ? 8 : 4;
   if (w <= bw) {
     if (g.n_max <= 4096)
