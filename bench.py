@@ -111,9 +111,11 @@ def traffic_from(args):
 
     kernel = "k_window_flush" if args.delay > 0 else "k_update"
     if args.delay > 0:
-        # the window flush is one dispatch per window (k_window_gemm; the link steps copy P = G[A,:])
+        # the window flush: k_window_gemm, after k_window_snap when the context has K > 1
+        # (with K = 1 the link steps copy P = G[A,:])
         fetch, write, nf, nw = 0.0, 0.0, 0, 0
-        for k in ("k_window_gemm",):
+        pairs = args.K > 1 or args.workload == "c4"
+        for k in ("k_window_snap", "k_window_gemm") if pairs else ("k_window_gemm",):
             f_, n_ = per_kernel(args.traffic_from[0], "FETCH_SIZE", k)
             w_, m_ = per_kernel(args.traffic_from[1], "WRITE_SIZE", k)
             fetch, write, nf, nw = fetch + f_, write + w_, n_, m_

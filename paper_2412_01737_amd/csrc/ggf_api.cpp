@@ -345,7 +345,7 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell + 1], s));
     if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
-    if (F > 0) ggf_launch_window_flush(lc, wp, 1024);
+    if (F > 0) ggf_launch_window_flush(lc, wp, 1024, ctx->kmax > 1);
     else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
     ++k;

@@ -39,7 +39,7 @@ struct LaunchCtx {
   int *dU, *dr, *dcnt;
   double *dBinv, *dX;
   // rows of the stored G of the pending Majoranas, P = G[A,:] (128 x n per chain, type
-  // of G, at dP_off[c]): copied by the link steps, read by the flush
+  // of G, at dP_off[c]): copied by the link steps (K = 1) or the flush, read by the flush
   void *dP;
   const size_t *dP_off;
   uint32_t key0, key1;
@@ -57,8 +57,9 @@ void ggf_launch_post(const LaunchCtx &lc, const int *list, int count, int is_ref
 // (or, with delayed updates, the factors of window slot t).
 void ggf_launch_ratio(const LaunchCtx &lc, int ell, int parity, int kmax, int t, int wp);
 // Delayed updates, end of a window of parity wp: G -= G[:,A] W G[A,:] for every
-// listed chain, evaluated on the upper triangle and mirrored (P = G[A,:] in lc.dP).
-void ggf_launch_window_flush(const LaunchCtx &lc, int wp, int grid);
+// listed chain, evaluated on the upper triangle and mirrored (P = G[A,:] in lc.dP,
+// copied by the link steps, or by the flush itself when snapshot is set).
+void ggf_launch_window_flush(const LaunchCtx &lc, int wp, int grid, bool snapshot);
 void ggf_launch_update(const LaunchCtx &lc, int parity, int grid, int tiles, int nt);
 void ggf_launch_end_sweep(const LaunchCtx &lc);
 void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);

@@ -66,10 +66,11 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   int8_t *lk = lc.links + ch.link_off;
   int U[4];
   ggf_link_u(ell, ch.L, U);
-  if (delayed && a + 4 <= kDelayMax) {
+  if (!PAIRS && delayed && a + 4 <= kDelayMax) {
     // rows U of the stored G (unchanged within the window) become rows a .. a + 3 of the
     // window's P = G[A,:], read by the flush if this flip is accepted; a rejected step's
-    // rows are overwritten by the next accepted one
+    // rows are overwritten by the next accepted one (with pairs the workgroups are fewer per
+    // CU, the copy does not hide, and the flush copies the rows itself)
     typedef typename std::conditional<sizeof(T) == 8, d2v, f4v>::type V;
     constexpr int VW = 16 / sizeof(T);
     T *P = static_cast<T *>(lc.dP) + lc.dP_off[c] + static_cast<size_t>(a) * n;
