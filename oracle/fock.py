@@ -169,3 +169,26 @@ class FockPEPS:
         c = np.ones(1) if c is None else np.asarray(c)
         psi = sum(c[k] * ph[k] for k in range(self.K))
         return np.vdot(psi, op @ psi) / np.vdot(psi, psi)
+
+    def electric(self, links_k, ell: int, spectrum, c=None) -> complex:
+        """f_E(G) on link ell (Sec. 5.3) from dense states: J^2 is built in the group basis as
+        F diag(e) F^+ with the irrep columns F[g, j] = N^-1/2 w^(j g), and every overlap
+        <psi_n(G)|psi_m(g'; G)> is an inner product of contracted vectors."""
+        N = self.group
+        w = np.exp(2j * np.pi / N)
+        F = np.array([[w ** (j * g) for j in range(N)] for g in range(N)]) / np.sqrt(N)
+        J2 = F @ np.diag(np.asarray(spectrum, complex)) @ F.conj().T
+        c = np.ones(1) if c is None else np.asarray(c)
+        k = np.asarray(links_k).copy()
+        g = int(k[ell]) % N
+        ph = self.states(k)
+        psi = sum(c[n] * ph[n] for n in range(self.K))
+        num = 0.0 + 0j
+        for gp in range(N):
+            k2 = k.copy()
+            k2[ell] = gp
+            ph2 = self.states(k2)
+            psi2 = sum(c[m] * ph2[m] for m in range(self.K))
+            num += J2[g, gp] * np.vdot(psi, psi2)
+        return num / np.vdot(psi, psi)
+

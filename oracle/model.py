@@ -23,6 +23,17 @@ bonds gives the virtual matrix
   two-point functions by Wick's theorem, <c_a c_b> = -i Gamma_out_ab (Sec. 3.2;
   the printed exponent of (-i) is read as w/2), combined over cross terms as
   in Sec. 5.2.
+* electric field (Sec. 2.2, the H_E term; Sec. 5.3):
+    f_E(G) = sum_g' <g|J^2|g'> sum_nm c_n^* c_m <psi_n(G)|psi_m(g'; G)> / N(G),
+  g = g_ell, with psi_m(g'; G) the state of G with link ell set to g'.  For Z_N the
+  Casimir is read as diagonal on the irreps j (eigenvalue e_j), irrep basis
+  |j> = N^-1/2 sum_g w^(j g) |g>, w = exp(2 pi i / N).  The overlaps are Gaussian
+  traces with the bond operator of link ell taken between U(g)^+ b_n and
+  U(g')^+ b_m.  For Z2 with a maximally entangled bond that bond overlap is zero
+  and the transition covariance does not exist, so the overlaps are evaluated
+  through exp(i theta n_out) = 1 + (e^(i theta) - 1) n_out (n_out^2 = n_out): an
+  overlap is affine in e^(i theta), and its slope is read at the regular angle
+  THETA_REGULAR.
 """
 from __future__ import annotations
 
@@ -31,9 +42,11 @@ import numpy as np
 from . import gaussian
 from .lattice import Lattice
 
-NOBS = 20           # observable slots: plaq, wilson2x2, density, logN, meson r=1..16
+NOBS = 21           # observable slots: plaq, wilson2x2, density, logN, meson r=1..16, electric
 OBS_PLAQ, OBS_WILSON, OBS_DENSITY, OBS_LOGN, OBS_MESON0 = 0, 1, 2, 3, 4
+OBS_ELECTRIC = 20
 MAX_MESON = 16
+THETA_REGULAR = np.pi / 2   # phase angle at which the mixed occupation is read off (Sec. 5.3)
 
 
 def rotation(theta: float) -> np.ndarray:
@@ -91,9 +104,14 @@ class Ansatz:
             self._trans_cache[key] = self._link_transition(*key)
         return self._trans_cache[key]
 
-    def _link_transition(self, ell: int, n: int, m: int):
+    def bond_vectors(self, ell: int, n: int, m: int):
+        """(ket, bra): two-mode bond states of link ell in the transition |B_n><B_m|."""
         ket = self.bstate[n] if (n > 0 and self.patch_link[n] == ell) else self.bstate[0]
         bra = self.bstate[m] if (m > 0 and self.patch_link[m] == ell) else self.bstate[0]
+        return ket, bra
+
+    def _link_transition(self, ell: int, n: int, m: int):
+        ket, bra = self.bond_vectors(ell, n, m)
         ov = np.vdot(bra, ket)
         if ket is bra:
             cov = gaussian.covariance_of_state(ket, 2, self._cs2)
@@ -200,6 +218,98 @@ class Ansatz:
     def s_factor_patch(self, G_SS, links_k) -> complex:
         return np.conj(self.c) @ (self.bond_overlaps() * self.cross_ratio_patch(G_SS, links_k)) @ self.c
 
+    # ----- electric field (Sec. 2.2 electric term, Sec. 5.3) -----
+    def casimir_kernel(self, spectrum) -> np.ndarray:
+        """kappa[D] = <g|J^2|g'> for g - g' = D (mod N): (1/N) sum_j e_j w^(j D)."""
+        N = self.group
+        e = np.asarray(spectrum, complex)
+        return np.array([sum(e[j] * np.exp(2j * np.pi * j * D / N) for j in range(N)) / N
+                         for D in range(N)])
+
+    @staticmethod
+    def out_phase(theta: float) -> np.ndarray:
+        """exp(i theta n_out) on a link's two-mode space (mode 0 = out, the high bit)."""
+        e = np.exp(1j * theta)
+        return np.diag([1.0, 1.0, e, e])
+
+    def shifted_transition(self, links_k, ell: int, theta: float, n: int, m: int):
+        """(covariance, overlap <bra|ket>) of link ell's bond operator in
+        <psi_n(G)|psi_m(G; theta)>, psi_m(G; theta) = <B_m|U(G) exp(i theta n_out)|A>:
+        ket U(g)^+ b_n, bra U(g)^+ exp(-i theta n_out) b_m."""
+        ket, bra = self.bond_vectors(ell, n, m)
+        u = self.out_phase(2 * np.pi * (int(links_k[ell]) % self.group) / self.group).conj()
+        ket = u @ ket
+        bra = u @ self.out_phase(-theta) @ bra
+        cov = gaussian.transition_covariance(bra, ket, 2, self._cs2)
+        return cov, np.vdot(bra, ket)
+
+    def shifted_overlap_def(self, links_k, ell: int, theta: float, n: int, m: int) -> complex:
+        """<psi_n(G)|psi_m(G; theta)> by full Pfaffians (theta = 2 pi d / N: link ell set to g + d)."""
+        M = self.assemble_M(links_k, n, m).astype(complex)
+        u = self.lat.link_majoranas(ell)
+        cov, ov = self.shifted_transition(links_k, ell, theta, n, m)
+        M[np.ix_(u, u)] = self.D[np.ix_(u, u)] + cov
+        for l2 in set(int(self.patch_link[k]) for k in (n, m) if k > 0):
+            if l2 != ell:
+                ov *= self.link_transition(l2, n, m)[1]
+        pf0 = gaussian.pfaffian(self.assemble_M(links_k))
+        return self.weight(links_k) * ov * gaussian.pfaffian(M) / pf0
+
+    def electric_def(self, links_k, ell: int, spectrum) -> complex:
+        """f_E(G) on link ell from its definition: the sum over g' of <g|J^2|g'> times the
+        superposed overlaps, divided by N(G)."""
+        N, g = self.group, int(links_k[ell]) % self.group
+        kap = self.casimir_kernel(spectrum)
+        e0 = np.exp(1j * THETA_REGULAR) - 1.0
+        num = den = 0.0 + 0j
+        for n in range(self.K):
+            for m in range(self.K):
+                w = np.conj(self.c[n]) * self.c[m]
+                o0 = self.shifted_overlap_def(links_k, ell, 0.0, n, m)
+                slope = (self.shifted_overlap_def(links_k, ell, THETA_REGULAR, n, m) - o0) / e0
+                for gp in range(N):
+                    ov = o0 + (np.exp(2j * np.pi * (gp - g) / N) - 1.0) * slope
+                    num += w * kap[(g - gp) % N] * ov
+                den += w * o0
+        return num / den
+
+    def mixed_occupation_patch(self, ginv_uu: np.ndarray, links_k, ell: int, n: int, m: int) -> complex:
+        """X_nm = <psi_n(G)|psi_m(G; theta)> slope / <psi_n|psi_m>, from the 4x4 block of
+        M_nm^-1 on link ell: the patch lemma gives the ratio of the theta overlap to the
+        theta = 0 one as [ov(theta)/ov(0)] Pf([[G_UU, 1], [-1, Delta]]), Delta the change of
+        the link block."""
+        c0, o0 = self.shifted_transition(links_k, ell, 0.0, n, m)
+        ct, ot = self.shifted_transition(links_k, ell, THETA_REGULAR, n, m)
+        blk = np.zeros((8, 8), complex)
+        blk[:4, :4] = ginv_uu
+        blk[:4, 4:] = np.eye(4)
+        blk[4:, :4] = -np.eye(4)
+        blk[4:, 4:] = ct - c0
+        ratio = (ot / o0) * gaussian.pfaffian(blk)
+        return (ratio - 1.0) / (np.exp(1j * THETA_REGULAR) - 1.0)
+
+    def electric_patch(self, links_k, ell: int, spectrum, ginv, wts) -> complex:
+        """f_E(G) on link ell from M_nm^-1 (ginv[n][m], full n x n) and the cross weights
+        wts[n, m] = c_n^* c_m <B_m|B_n> r_nm (K = 1: [[1]])."""
+        N, g = self.group, int(links_k[ell]) % self.group
+        kap = self.casimir_kernel(spectrum)
+        u = self.lat.link_majoranas(ell)
+        num = 0.0 + 0j
+        for n in range(self.K):
+            for m in range(self.K):
+                x = self.mixed_occupation_patch(ginv[n][m][np.ix_(u, u)], links_k, ell, n, m)
+                for gp in range(N):
+                    num += wts[n, m] * kap[(g - gp) % N] * (1.0 + (np.exp(2j * np.pi * (gp - g) / N) - 1.0) * x)
+        return num / np.sum(wts)
+
+    def electric_mean(self, links_k, ginv, wts) -> float:
+        """Lattice mean over links of Re f_E with e_0 = 0 and e_j = 1 otherwise (the flux
+        carried by the link in units of the Casimir of the non-trivial irreps)."""
+        spec = np.ones(self.group)
+        spec[0] = 0.0
+        tot = sum(self.electric_patch(links_k, ell, spec, ginv, wts).real for ell in range(self.lat.n_links))
+        return tot / self.lat.n_links
+
     # ----- observables -----
     def plaquette(self, links_k) -> float:
         lat, N = self.lat, self.group
@@ -267,7 +377,7 @@ class Ansatz:
         return out
 
     def observables(self, links_k, Ginv=None) -> np.ndarray:
-        """All observable slots for one configuration (Sec. 5.1, 5.2), real parts."""
+        """All observable slots for one configuration (Sec. 5.1, 5.2, 5.3), real parts."""
         if Ginv is None:
             Ginv = np.linalg.inv(self.assemble_M(links_k))
         out = np.zeros(NOBS)
@@ -277,18 +387,21 @@ class Ansatz:
         if self.K == 1:
             f = self.fermion_obs(self.gamma_out(Ginv), links_k)
             out[OBS_LOGN] = lw
+            out[OBS_ELECTRIC] = self.electric_mean(links_k, [[Ginv]], np.ones((1, 1)))
         else:
             ov = self.bond_overlaps()
             r = self.cross_ratio_def(links_k)
             wts = np.conj(self.c)[:, None] * self.c[None, :] * ov * r
             S = wts.sum()
             f = np.zeros(NOBS, complex)
+            ginv = [[None] * self.K for _ in range(self.K)]
             for n in range(self.K):
                 for m in range(self.K):
-                    Mnm = self.assemble_M(links_k, n, m)
-                    gnm = self.A + self.B @ np.linalg.inv(Mnm) @ self.B.T
+                    ginv[n][m] = np.linalg.inv(self.assemble_M(links_k, n, m))
+                    gnm = self.A + self.B @ ginv[n][m] @ self.B.T
                     f += wts[n, m] / S * self.fermion_obs(gnm, links_k)
             out[OBS_LOGN] = lw + np.log(S.real)
+            out[OBS_ELECTRIC] = self.electric_mean(links_k, ginv, wts)
         keep = [OBS_DENSITY] + [OBS_MESON0 + i for i in range(MAX_MESON)]
         out[keep] = f[keep].real
         return out
