@@ -482,6 +482,34 @@ def run_c5(args):
     print(json.dumps(out))
 
 
+def electric_measurement(ctx, args, Lc, stream, reps=20):
+    """Electric-field observable f_E (Sec. 5.3) of every chain's final configuration: the
+    electric-only measurement kernel (k_electric, one workgroup per chain) timed with HIP events
+    on its launch stream, after the timed sweeps.  Algorithmic bytes per link: the six distinct
+    entries of the antisymmetric 4x4 block of G on the link's Majoranas (for K > 1 each pair
+    of the superposition also reads G on the link rows and the pair's patch columns, not
+    counted)."""
+    import torch
+    from paper_2412_01737_amd.ggf import OBS_ELECTRIC, GGF_NOBS
+    out = torch.zeros((args.chains, GGF_NOBS), dtype=torch.float64, device=stream.device)
+    ctx.measure(OBS_ELECTRIC, out, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.measure(OBS_ELECTRIC, out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    links = int((2 * Lc.astype(np.int64) ** 2).sum())
+    esz = 8 if args.precision == 64 else 4
+    nbytes = links * 6 * esz
+    achieved = nbytes / (us * 1e-6) / 1e9
+    return {"kernel": "k_electric", "us_per_launch": us, "links_per_s": links / (us * 1e-6),
+            "algorithmic_bytes_per_launch": nbytes, "achieved_GBs": achieved, "peak_GBs": HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS, "mean_final": float(out[:, 20].mean().item())}
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -564,6 +592,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     refresh = refresh_correction(ctx, args, st0, stream)
+    electric = electric_measurement(ctx, args, Lc, stream)
     timed_s = elapsed
     elapsed = elapsed + refresh["correction_ms"] * 1e-3
     proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
@@ -648,6 +677,7 @@ def main():
         "kernels_ms_per_step": {kernel: upd_ms / args.steps, "k_ratio": rat_ms / args.steps},
         "timed_s": timed_s,
         "refresh": refresh,
+        "electric": electric,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

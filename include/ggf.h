@@ -52,7 +52,7 @@ typedef enum {
 } ggf_status;
 
 #define GGF_KMAX 4       /* largest number of Gaussians in a superposition */
-#define GGF_NOBS 20      /* observable slots per chain, see ggf_measure */
+#define GGF_NOBS 21      /* observable slots per chain, see ggf_measure */
 
 /* Variational data of one ansatz (Sec. 5: lambda_n, Gamma_A, Gamma_{B_n}).
  * All host pointers, row-major float64; the library copies them and the caller
@@ -114,7 +114,8 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
 ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
 
 /* Observables of every chain's current configuration (Sec. 2.3 plaquette,
- * Sec. 5.1 Wilson loops, Sec. 5.2 fermionic two-point functions), written to
+ * Sec. 5.1 Wilson loops, Sec. 5.2 fermionic two-point functions, Sec. 5.3
+ * electric field), written to
  * out[n_chains][GGF_NOBS] (float64; device pointer when out_is_device != 0,
  * else host pointer, which makes the call synchronous).  Slots:
  *   0 mean plaquette Re[U U U* U*]       (obs_mask bit 0)
@@ -122,6 +123,10 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
  *   2 mean density <psi_p^+ psi_p>       (bit 1)
  *   3 log N(G) = log W + log S            (bit 1)
  *   4+r-1 meson string M_r, r = 1..min(L/2, 16), along e1 (bit 2)
+ *   20 electric field: lattice mean over links of Re f_E(G) (Sec. 5.3), the
+ *      mixed estimator of <J^2_l> with the Z_N Casimir read as 0 on the trivial
+ *      irrep and 1 on the others (bit 3); for eigenvalues e_0, e_1 = e_{N-1}
+ *      the estimator is e_0 + (e_1 - e_0) x slot 20
  * Slots not requested are written as 0. */
 ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out_is_device,
                        void *stream);

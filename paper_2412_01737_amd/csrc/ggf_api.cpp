@@ -16,6 +16,9 @@
 #include "ggf_launch.h"
 #include "ggf_nn.h"
 
+static_assert(GGF_NOBS == GGF_NOBS_DEV, "observable slot counts of the ABI and the kernels differ");
+static_assert(GGF_KMAX == GGF_KMAX_DEV, "superposition sizes of the ABI and the kernels differ");
+
 typedef std::complex<double> cplx;
 
 namespace {
@@ -142,6 +145,37 @@ void transition_cov(const Even2 &bra, const Even2 &ket, cplx out[16]) {
       out[p * 4 + q] = g;
       out[q * 4 + p] = -g;
     }
+}
+
+// Response of a link's bond operator |ket><bra| to a phase exp(i theta n_out) on the
+// outgoing mode of the bra side (Sec. 5.3, overlaps of configurations that differ on
+// one link).  The overlap and the Gaussian trace are affine in e^(i theta); their
+// slope at theta = 0, divided by i and by the overlap, is
+//   nbar = <bra|n_out|ket> / <bra|ket>,
+//   Q_pq = i <bra|n_out c_p c_q|ket> / <bra|ket> - Gamma_pq nbar   (p != q),
+// the derivative of the transition covariance Gamma.  n_out is |11><11| in the even basis.
+void occupation_response(const Even2 &bra, const Even2 &ket, cplx &nbar, cplx q_out[16]) {
+  const cplx ov = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
+  nbar = std::conj(bra.b) * ket.b / ov;
+  cplx g[16];
+  transition_cov(bra, ket, g);
+  for (int i = 0; i < 16; ++i) q_out[i] = 0.0;
+  for (int p = 0; p < 4; ++p)
+    for (int q = p + 1; q < 4; ++q) {
+      cplx m[2][2];
+      bilinear(p, q, m);
+      const cplx e = std::conj(bra.b) * (m[1][0] * ket.a + m[1][1] * ket.b);
+      const cplx v = cplx(0, 1) * e / ov - g[p * 4 + q] * nbar;
+      q_out[p * 4 + q] = v;
+      q_out[q * 4 + p] = -v;
+    }
+}
+
+void store_response(const Even2 &bra, const Even2 &ket, double2 &en, double2 eq[16]) {
+  cplx nb, q[16];
+  occupation_response(bra, ket, nb, q);
+  en = make_double2(nb.real(), nb.imag());
+  for (int i = 0; i < 16; ++i) eq[i] = make_double2(q[i].real(), q[i].imag());
 }
 
 bool even_state(const double *g, Even2 &st, std::string &why) {
@@ -519,6 +553,7 @@ ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tenso
   if (K > 1)
     for (int k = 0; k < K; ++k) cc[k] = cplx(d->c_re[k], d->c_im[k]);
   const double *g0 = d->gamma_bond;
+  store_response(b0, b0, t.en0, t.eq0);
   for (int n = 0; n < K; ++n)
     for (int m = 0; m < K; ++m) {
       int links[2], cnt = 0;
@@ -536,6 +571,7 @@ ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tenso
         transition_cov(bra, ket, g);
         t.lk[n][m][l] = links[l];
         for (int q = 0; q < 16; ++q) t.dg[n][m][l][q] = make_double2((g[q] - g0[q]).real(), (g[q] - g0[q]).imag());
+        store_response(bra, ket, t.en[n][m][l], t.eq[n][m][l]);
       }
       const cplx w = std::conj(cc[n]) * cc[m] * ovl;
       t.w[n][m] = make_double2(w.real(), w.imag());

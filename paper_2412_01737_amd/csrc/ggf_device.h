@@ -14,7 +14,7 @@
 #include <stdint.h>
 
 #define GGF_KMAX_DEV 4
-#define GGF_NOBS_DEV 20
+#define GGF_NOBS_DEV 21
 #define GGF_MAX_MESON 16
 
 // Per-ansatz constants.  Pair (n, m) of the superposition involves at most
@@ -31,6 +31,13 @@ struct TensorDev {
   int nl[GGF_KMAX_DEV][GGF_KMAX_DEV];                 // involved patch links of pair (n,m): 0..2
   int lk[GGF_KMAX_DEV][GGF_KMAX_DEV][2];              // their lattice link indices
   double2 dg[GGF_KMAX_DEV][GGF_KMAX_DEV][2][16];      // 4x4 complex per involved link
+  // electric field (Sec. 5.3): mixed occupation of a link's outgoing mode in the
+  // transition |ket><bra| of its bond, X = en + (1/2) tr(G_UU O eq O^T), O the link's
+  // rotation; reference bond on both sides (en0, eq0), or per involved patch link
+  double2 en0;
+  double2 eq0[16];
+  double2 en[GGF_KMAX_DEV][GGF_KMAX_DEV][2];
+  double2 eq[GGF_KMAX_DEV][GGF_KMAX_DEV][2][16];
 };
 
 struct ChainDev {

@@ -369,6 +369,10 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { typedef d2v type; static constexpr int n = 2; };
 template <> struct Vec16<float> { typedef f4v type; static constexpr int n = 4; };
+// Two adjacent elements of G (8-byte aligned for float, 16-byte for double at even offsets).
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double2 type; };
+template <> struct Vec2<float> { typedef float2 type; };
 
 template <typename V, typename S>
 __device__ __forceinline__ void upd(V &g, S q0, S q1, S q2, S q3, const V &p0, const V &p1, const V &p2,
@@ -534,12 +538,12 @@ __device__ inline double block_sum(double v, double *red) {
   return t;
 }
 
-// Observables of one chain per workgroup (Sec. 2.3, 5.1, 5.2).  Fermionic
+// Observables of one chain per workgroup (Sec. 2.3, 5.1, 5.2, 5.3).  Fermionic
 // two-point functions: Gamma_out = A + B M^-1 B^T (per pair (a, b) of the
 // superposition with M_ab^-1 = G - G_S Y_ab G_S^T, Y_ab = Delta (1 + G_SS Delta)^-1),
 // <c_p c_q> = -i Gamma_out, weights lambda_a^* lambda_b <B_b|B_a> r_ab / S.
-template <typename T>
-__global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, double *out) {
+template <typename T, bool EL_ONLY>
+__device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask, double *out) {
   __shared__ double2 s_Y[16][64];
   __shared__ double2 s_om[16];
   __shared__ int s_S[16][8];
@@ -594,7 +598,7 @@ __global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, do
   double acc[GGF_NOBS_DEV];
   for (int q = 0; q < GGF_NOBS_DEV; ++q) acc[q] = 0.0;
   const int nmes = min(L / 2, GGF_MAX_MESON);
-  for (int x = threadIdx.x; x < V; x += blockDim.x) {
+  for (int x = threadIdx.x; !EL_ONLY && x < V; x += blockDim.x) {
     if (mask & 1u) {
       const int x1 = ggf_shift(x, L, 1, 0), x2 = ggf_shift(x, L, 0, 1);
       double2 z = cmul(link_phase(lk[2 * x], group), link_phase(lk[2 * x1 + 1], group));
@@ -683,12 +687,77 @@ __global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, do
       }
     }
   }
+  if (EL_ONLY || (mask & 8u)) {
+    // Electric field per link (Sec. 5.3), lattice mean of Re f_E with e_0 = 0, e_j = 1:
+    // f_E = sum_ab om_ab X_ab / S, X_ab = en + (1/2) tr(M_ab^-1[U,U] O eq O^T) the mixed
+    // occupation of the link's outgoing mode, M_ab^-1[U,U] = G_UU + G_US Y_ab G_US^T.
+    // The six entries of the antisymmetric G_UU: (u0,u1) and (u2,u3) on the sites' diagonal
+    // blocks, (u0|u1, u2..u3) as two aligned pairs (u2 is even).
+    using V2 = typename Vec2<T>::type;
+    for (int ell = threadIdx.x; ell < 2 * V; ell += blockDim.x) {
+      int u[4];
+      ggf_link_u(ell, L, u);
+      const V2 r0 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[0]) * n + u[2]);
+      const V2 r1 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[1]) * n + u[2]);
+      const double g01 = static_cast<double>(G[static_cast<size_t>(u[0]) * n + u[1]]);
+      const double g23 = static_cast<double>(G[static_cast<size_t>(u[2]) * n + u[3]]);
+      const double gu[16] = {0.0, g01, static_cast<double>(r0.x), static_cast<double>(r0.y),
+                             -g01, 0.0, static_cast<double>(r1.x), static_cast<double>(r1.y),
+                             -static_cast<double>(r0.x), -static_cast<double>(r1.x), 0.0, g23,
+                             -static_cast<double>(r0.y), -static_cast<double>(r1.y), -g23, 0.0};
+      const int kv = lk[ell];
+      double2 tot = make_double2(0.0, 0.0);
+      for (int pr = 0; pr < npairs; ++pr) {
+        const int a = pr / K, b = pr % K;
+        double2 gm[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gm[q] = make_double2(gu[q], 0.0);
+        const int s = s_s[pr];
+        if (s > 0) {
+          double vs[4][8];
+          for (int i = 0; i < 4; ++i)
+            for (int q = 0; q < s; ++q) vs[i][q] = static_cast<double>(G[static_cast<size_t>(u[i]) * n + s_S[pr][q]]);
+          for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+              double2 v = make_double2(0.0, 0.0);
+              for (int p = 0; p < s; ++p)
+                for (int q = 0; q < s; ++q) v = cadd(v, cscale(s_Y[pr][p * 8 + q], vs[i][p] * vs[j][q]));
+              gm[i * 4 + j] = cadd(gm[i * 4 + j], v);
+            }
+        }
+        const double2 *eq = Tn.eq0;
+        double2 x = Tn.en0;
+        for (int l = 0; l < Tn.nl[a][b]; ++l)
+          if (Tn.lk[a][b][l] == ell) { eq = Tn.eq[a][b][l]; x = Tn.en[a][b][l]; }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          double2 row[4];
+          rotate_dg_row(eq, kv, group, jj, row);     // row jj of O eq O^T
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x = cadd(x, cscale(cmul(gm[i * 4 + jj], row[i]), 0.5));
+        }
+        tot = cadd(tot, cmul(s_om[pr], x));
+      }
+      acc[GGF_NOBS_DEV - 1] += 0.5 * tot.x * invS;   // two links per site
+    }
+  }
   for (int q = 0; q < GGF_NOBS_DEV; ++q) {
     const double t = block_sum(acc[q], red);
     if (threadIdx.x == 0) out[static_cast<size_t>(c) * GGF_NOBS_DEV + q] = t / V;
   }
   if (threadIdx.x == 0) out[static_cast<size_t>(c) * GGF_NOBS_DEV + 3] =
-      (mask & 2u) ? lc.logw[c] + (K > 1 ? log(Sv) : 0.0) : 0.0;
+      (!EL_ONLY && (mask & 2u)) ? lc.logw[c] + (K > 1 ? log(Sv) : 0.0) : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, double *out) {
+  measure_chain<T, false>(lc, mask, out);
+}
+
+// Electric-field slot only (the other slots written as 0).
+template <typename T>
+__global__ __launch_bounds__(128) void k_electric(LaunchCtx lc, double *out) {
+  measure_chain<T, true>(lc, 8u, out);
 }
 
 }  // namespace
@@ -767,6 +836,13 @@ void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax) 
 
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax) {
   const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
+  if (mask == 8u) {
+    if (lc.precision == 64)
+      hipLaunchKernelGGL(k_electric<double>, dim3(lc.n_chains), dim3(128), lds, lc.stream, lc, out);
+    else
+      hipLaunchKernelGGL(k_electric<float>, dim3(lc.n_chains), dim3(128), lds, lc.stream, lc, out);
+    return;
+  }
   if (lc.precision == 64)
     hipLaunchKernelGGL(k_measure<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, mask, out);
   else

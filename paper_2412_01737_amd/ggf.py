@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libggf.so")
 
 GGF_OK, GGF_EINVAL, GGF_ENOMEM, GGF_ESINGULAR, GGF_ENONFINITE, GGF_EDEVICE, GGF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 GGF_KMAX = 4
-GGF_NOBS = 20
-OBS_LINK, OBS_DENSITY, OBS_MESON = 1, 2, 4
-OBS_ALL = 7
+GGF_NOBS = 21
+OBS_LINK, OBS_DENSITY, OBS_MESON, OBS_ELECTRIC = 1, 2, 4, 8
+OBS_ALL = 15
 _STATUS = {0: "GGF_OK", -1: "GGF_EINVAL", -2: "GGF_ENOMEM", -3: "GGF_ESINGULAR",
            -4: "GGF_ENONFINITE", -5: "GGF_EDEVICE", -6: "GGF_ESTATE"}
 

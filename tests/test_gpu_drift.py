@@ -24,11 +24,12 @@ import numpy as np
 import pytest
 
 from gpu_common import ansatz_for, gpu_context, say, spec_for
-from oracle.model import NOBS, OBS_DENSITY, OBS_LOGN, OBS_MESON0
+from oracle.model import NOBS, OBS_DENSITY, OBS_ELECTRIC, OBS_LOGN, OBS_MESON0
 
 pytestmark = pytest.mark.gpu
 
-SLOT_NAMES = {0: "plaquette", 1: "wilson2x2", OBS_DENSITY: "density", OBS_LOGN: "logN"}
+SLOT_NAMES = {0: "plaquette", 1: "wilson2x2", OBS_DENSITY: "density", OBS_LOGN: "logN",
+              OBS_ELECTRIC: "electric"}
 
 
 def _slot_name(s):
