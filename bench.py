@@ -83,6 +83,10 @@ def parse():
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "BENCH_JSON"),
                     help="derive the block update's HBM bytes per accepted move from rocprofv3 --pmc CSVs of a "
                          "--workload c5 run and that run's JSON line, write profiles/k_block_traffic.json and exit")
+    ap.add_argument("--electric-traffic-from", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="derive the electric measurement kernel's HBM bytes per launch from rocprofv3 --pmc "
+                         "CSVs, write profiles/k_electric_traffic.json and exit (no GPU needed)")
     args = ap.parse_args()
     presets = {
         "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384, delay=16),
@@ -141,6 +145,45 @@ def traffic_from(args):
     with open(args.traffic_json, "w") as f:
         json.dump(tj, f, indent=1)
     print(json.dumps({key: rec}))
+
+
+ELECTRIC_TRAFFIC_JSON = os.path.join(HERE, "profiles", "k_electric_traffic.json")
+
+
+def electric_kernel(args) -> str:
+    return "k_electric1" if (args.workload != "c4" and args.K == 1) else "k_electric"
+
+
+def electric_traffic_from(args):
+    """HBM bytes per electric measurement launch from FETCH_SIZE / WRITE_SIZE, scaled by the
+    plain-copy calibration as for the update kernels."""
+    import csv
+    kernel = electric_kernel(args)
+
+    def per_kernel(path, counter, match):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Counter_Name"] == counter and match + "<" in r["Kernel_Name"]]
+        return sum(vals) / len(vals), len(vals)
+
+    fetch, nf = per_kernel(args.electric_traffic_from[0], "FETCH_SIZE", kernel)
+    write, nw = per_kernel(args.electric_traffic_from[1], "WRITE_SIZE", kernel)
+    cfetch, _ = per_kernel(args.electric_traffic_from[2], "FETCH_SIZE", "probe_copy")
+    cwrite, _ = per_kernel(args.electric_traffic_from[3], "WRITE_SIZE", "probe_copy")
+    known_kib = args.copy_bytes / 1024.0
+    sf, sw = known_kib / cfetch, known_kib / cwrite
+    rec = {"bytes_per_launch": (fetch * sf + write * sw) * 1024.0,
+           "read_bytes_per_launch": fetch * sf * 1024.0, "write_bytes_per_launch": write * sw * 1024.0,
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+           "fetch_scale": sf, "write_scale": sw, "kernel": kernel, "source_digest": source_digest()}
+    try:
+        with open(ELECTRIC_TRAFFIC_JSON) as f:
+            tj = json.load(f)
+    except (OSError, ValueError):
+        tj = {}
+    tj[traffic_key(args)] = rec
+    with open(ELECTRIC_TRAFFIC_JSON, "w") as f:
+        json.dump(tj, f, indent=1)
+    print(json.dumps({traffic_key(args): rec}))
 
 
 def block_traffic_from(args):
@@ -484,7 +527,8 @@ def run_c5(args):
 
 def electric_measurement(ctx, args, Lc, stream, reps=20):
     """Electric-field observable f_E (Sec. 5.3) of every chain's final configuration: the
-    electric-only measurement kernel (k_electric, one workgroup per chain) timed with HIP events
+    electric-only measurement kernel (k_electric1 when every chain has K = 1, else k_electric;
+    one workgroup per chain) timed with HIP events
     on its launch stream, after the timed sweeps.  Algorithmic bytes per link: the six distinct
     entries of the antisymmetric 4x4 block of G on the link's Majoranas (for K > 1 each pair
     of the superposition also reads G on the link rows and the pair's patch columns, not
@@ -505,15 +549,27 @@ def electric_measurement(ctx, args, Lc, stream, reps=20):
     esz = 8 if args.precision == 64 else 4
     nbytes = links * 6 * esz
     achieved = nbytes / (us * 1e-6) / 1e9
-    return {"kernel": "k_electric", "us_per_launch": us, "links_per_s": links / (us * 1e-6),
-            "algorithmic_bytes_per_launch": nbytes, "achieved_GBs": achieved, "peak_GBs": HBM_PEAK_GBS,
-            "frac": achieved / HBM_PEAK_GBS, "mean_final": float(out[:, 20].mean().item())}
+    kernel = electric_kernel(args)
+    traffic = None
+    try:
+        with open(ELECTRIC_TRAFFIC_JSON) as f:
+            rec = json.load(f).get(traffic_key(args))
+        if rec and rec.get("kernel") == kernel and rec.get("source_digest") == source_digest():
+            traffic = rec["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return {"kernel": kernel, "bound": "hbm", "us_per_launch": us, "links_per_s": links / (us * 1e-6),
+            "algorithmic_bytes_per_launch": nbytes, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "mean_final": float(out[:, 20].mean().item())}
 
 
 def main():
     args = parse()
     if args.traffic_from:
         traffic_from(args)
+        return
+    if args.electric_traffic_from:
+        electric_traffic_from(args)
         return
     if args.block_traffic_from:
         block_traffic_from(args)

@@ -16,6 +16,7 @@
 #define GGF_KMAX_DEV 4
 #define GGF_NOBS_DEV 21
 #define GGF_MAX_MESON 16
+#define GGF_ZN_MAX 3       // largest gauge group Z_N
 
 // Per-ansatz constants.  Pair (n, m) of the superposition involves at most
 // two patch links (those where B_n or B_m differ from B_0); for each of them

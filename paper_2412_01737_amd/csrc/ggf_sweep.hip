@@ -741,6 +741,13 @@ __device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask
       acc[GGF_NOBS_DEV - 1] += 0.5 * tot.x * invS;   // two links per site
     }
   }
+  if (EL_ONLY) {
+    const double t = block_sum(acc[GGF_NOBS_DEV - 1], red);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < GGF_NOBS_DEV; ++q)
+        out[static_cast<size_t>(c) * GGF_NOBS_DEV + q] = (q == GGF_NOBS_DEV - 1) ? t / V : 0.0;
+    return;
+  }
   for (int q = 0; q < GGF_NOBS_DEV; ++q) {
     const double t = block_sum(acc[q], red);
     if (threadIdx.x == 0) out[static_cast<size_t>(c) * GGF_NOBS_DEV + q] = t / V;
@@ -758,6 +765,66 @@ __global__ __launch_bounds__(256) void k_measure(LaunchCtx lc, uint32_t mask, do
 template <typename T>
 __global__ __launch_bounds__(128) void k_electric(LaunchCtx lc, double *out) {
   measure_chain<T, true>(lc, 8u, out);
+}
+
+// Electric-field slot only when every chain has K = 1: f_E = Re X with
+// X = en0 + (1/2) tr(G_UU R_k) = en0 + sum_{i<j} G_UU[i][j] R_k[j][i] (G_UU and R_k
+// antisymmetric), R_k = O_k eq0 O_k^T for link value k, one table per workgroup.
+template <typename T>
+__global__ __launch_bounds__(128) void k_electric1(LaunchCtx lc, double *out) {
+  __shared__ double s_R[GGF_ZN_MAX][16];
+  __shared__ double red[2];
+  using V2 = typename Vec2<T>::type;
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  if (threadIdx.x < 16 * group) {
+    // entry e of Re(O_k eq0 O_k^T), unrolled with constant indices (no private-array scratch)
+    const int k = threadIdx.x >> 4, e = threadIdx.x & 15;
+    double co = 1.0, si = 0.0;
+    if (k != 0) {
+      if (group == 2) co = -1.0;
+      else sincospi(2.0 * k / group, &si, &co);
+    }
+    const double o[4][4] = {{co, si, 0.0, 0.0}, {-si, co, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}, {0.0, 0.0, 0.0, 1.0}};
+    double q[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) q[i] = Tn.eq0[i].x;
+    double val = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) v += o[i][a] * q[a * 4 + b] * o[j][b];
+        if (i * 4 + j == e) val = v;
+      }
+    s_R[k][e] = val;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int ell = threadIdx.x; ell < 2 * V; ell += blockDim.x) {
+    int u[4];
+    ggf_link_u(ell, L, u);
+    const V2 r0 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[0]) * n + u[2]);
+    const V2 r1 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[1]) * n + u[2]);
+    const double g01 = static_cast<double>(G[static_cast<size_t>(u[0]) * n + u[1]]);
+    const double g23 = static_cast<double>(G[static_cast<size_t>(u[2]) * n + u[3]]);
+    const double *R = s_R[lk[ell]];
+    acc += Tn.en0.x + g01 * R[1 * 4 + 0] + static_cast<double>(r0.x) * R[2 * 4 + 0] +
+           static_cast<double>(r0.y) * R[3 * 4 + 0] + static_cast<double>(r1.x) * R[2 * 4 + 1] +
+           static_cast<double>(r1.y) * R[3 * 4 + 1] + g23 * R[3 * 4 + 2];
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < GGF_NOBS_DEV; ++q)
+      out[static_cast<size_t>(c) * GGF_NOBS_DEV + q] = (q == GGF_NOBS_DEV - 1) ? 0.5 * t / V : 0.0;
 }
 
 }  // namespace
@@ -837,10 +904,14 @@ void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax) 
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax) {
   const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
   if (mask == 8u) {
-    if (lc.precision == 64)
-      hipLaunchKernelGGL(k_electric<double>, dim3(lc.n_chains), dim3(128), lds, lc.stream, lc, out);
-    else
-      hipLaunchKernelGGL(k_electric<float>, dim3(lc.n_chains), dim3(128), lds, lc.stream, lc, out);
+    const dim3 grid(lc.n_chains), block(128);
+    if (lc.precision == 64) {
+      if (kmax > 1) hipLaunchKernelGGL(k_electric<double>, grid, block, lds, lc.stream, lc, out);
+      else hipLaunchKernelGGL(k_electric1<double>, grid, block, 0, lc.stream, lc, out);
+    } else {
+      if (kmax > 1) hipLaunchKernelGGL(k_electric<float>, grid, block, lds, lc.stream, lc, out);
+      else hipLaunchKernelGGL(k_electric1<float>, grid, block, 0, lc.stream, lc, out);
+    }
     return;
   }
   if (lc.precision == 64)

@@ -1,6 +1,8 @@
 """Electric-field observable on the GPU (Sec. 5.3) against the oracle.
 
-The kernel evaluates, per link and pair (n, m) of the superposition, the mixed
+Contexts whose chains all have K = 1 run the lean kernel (one 4x4 block of G per
+link, rotated response table in LDS); any K > 1 chain selects the general one.
+The general kernel evaluates, per link and pair (n, m) of the superposition, the mixed
 occupation of the link's outgoing mode from the 4x4 block of M_nm^-1 (Woodbury
 form for K > 1) and the bond's response matrix computed by the C ABI.  The
 oracle reads the same quantity off a Pfaffian of the link's 8x8 patch matrix
@@ -61,5 +63,21 @@ def test_electric_full_size_sampled():
     for c in (0, 1723, chains - 1):
         links, _ = ctx.get_state(c)
         ref = an.observables(links)[OBS_ELECTRIC]
+        assert abs(got[c, OBS_ELECTRIC] - ref) < 1e-10, (c, got[c, OBS_ELECTRIC], ref)
+    ctx.close()
+
+
+def test_electric_mixed_batch():
+    """One context with K = 1 and K = 3 chains of different L (general kernel for all of them)."""
+    from paper_2412_01737_amd.ggf import OBS_ELECTRIC as BIT
+    say("electric mixed batch")
+    specs = [spec_for(2, 1, 2), spec_for(2, 3, 2)]
+    Ls, tids = [4, 2, 6, 4], [0, 1, 0, 1]
+    ctx = gpu_context(specs, Ls, tensor_ids=tids, init=1)
+    ctx.sweep(1)
+    got = ctx.measure(BIT)
+    for c, (L, t) in enumerate(zip(Ls, tids)):
+        links, _ = ctx.get_state(c)
+        ref = ansatz_for(specs[t], L).observables(links)[OBS_ELECTRIC]
         assert abs(got[c, OBS_ELECTRIC] - ref) < 1e-10, (c, got[c, OBS_ELECTRIC], ref)
     ctx.close()
