@@ -192,3 +192,90 @@ class FockPEPS:
             num += J2[g, gp] * np.vdot(psi, psi2)
         return num / np.vdot(psi, psi)
 
+
+
+# ----- Hamiltonian (Sec. 2, 2.2, 2.3) on dense vectors -----
+def annihilators(n_modes: int) -> list[np.ndarray]:
+    """psi_j = (prod_{k<j} Z_k) |0><1|_j, mode 0 the highest bit (the basis of ``gaussian``)."""
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    lower = np.array([[0.0, 1.0], [0.0, 0.0]], complex)
+    I2 = np.eye(2, dtype=complex)
+    ops = []
+    for j in range(n_modes):
+        m = np.eye(1, dtype=complex)
+        for k in range(n_modes):
+            m = np.kron(m, Z if k < j else (lower if k == j else I2))
+        ops.append(m)
+    return ops
+
+
+def fermion_hamiltonian(lat: Lattice, links_k, group: int, cp, eta, ann) -> np.ndarray:
+    """<G|H|G> on the physical modes: hopping with D(g) = w^g and the pi-flux phases eta,
+    chemical and staggered mass terms, and the plaquette term times the identity."""
+    V = lat.V
+    w = np.exp(2j * np.pi / group)
+    H = np.zeros((2 ** V, 2 ** V), complex)
+    for x in range(V):
+        nx = ann[x].conj().T @ ann[x]
+        x1, x2 = lat.coords(x)
+        H += cp.mu * nx + cp.m * (-1) ** (x1 + x2) * nx
+        for mu in range(2):
+            y = lat.shift(x, 1, 0) if mu == 0 else lat.shift(x, 0, 1)
+            T = 1j * eta(lat, x, mu) * w ** int(links_k[lat.link(x, mu)]) * (ann[x].conj().T @ ann[y])
+            H += cp.t * (T + T.conj().T)
+        l1, l2, l3, l4 = lat.plaquette_links(x)
+        z = w ** int(links_k[l1] + links_k[l2] - links_k[l3] - links_k[l4])
+        H += cp.kb * (z + np.conj(z)) * np.eye(2 ** V)
+    return H
+
+
+def _unit_casimir(group: int) -> np.ndarray:
+    """J^2 on one link in the group basis: 0 on the trivial irrep, 1 on the others."""
+    w = np.exp(2j * np.pi / group)
+    F = np.array([[w ** (j * g) for j in range(group)] for g in range(group)]) / np.sqrt(group)
+    e = np.ones(group)
+    e[0] = 0.0
+    return F @ np.diag(e) @ F.conj().T
+
+
+def fock_local_energy(fk: "FockPEPS", links_k, cp, eta, c) -> complex:
+    """E_loc(G) = [<psi(G)|H(G)|psi(G)> + ke sum_l sum_g' <g|J^2|g'> <psi(G)|psi(g'; G)>] / <psi|psi>."""
+    k = np.asarray(links_k)
+    ph = fk.states(k)
+    psi = sum(c[n] * ph[n] for n in range(fk.K))
+    Hf = fermion_hamiltonian(fk.lat, k, fk.group, cp, eta, annihilators(fk.lat.V))
+    den = np.vdot(psi, psi)
+    num = np.vdot(psi, Hf @ psi)
+    if cp.ke != 0.0:
+        spec = np.ones(fk.group)
+        spec[0] = 0.0
+        for ell in range(fk.lat.n_links):
+            num += cp.ke * fk.electric(k, ell, spec, c) * den
+    return num / den
+
+
+def subspace_matrices(fk: "FockPEPS", cp, eta):
+    """<Psi_n|H|Psi_m> and <Psi_n|Psi_m> for Psi_n = sum_G |G> (x) psi_n(G) on the full
+    gauge (x) fermion space; the electric term acts as J^2 on each link's axis."""
+    import itertools
+    lat, N, V, K = fk.lat, fk.group, fk.lat.V, fk.K
+    nl = lat.n_links
+    shape = [N] * nl + [2 ** V]
+    Psi = [np.zeros(shape, complex) for _ in range(K)]
+    HPsi = [np.zeros(shape, complex) for _ in range(K)]
+    ann = annihilators(V)
+    for G in itertools.product(range(N), repeat=nl):
+        k = np.array(G)
+        ph = fk.states(k)
+        Hf = fermion_hamiltonian(lat, k, N, cp, eta, ann)
+        for n in range(K):
+            Psi[n][G] = ph[n]
+            HPsi[n][G] = Hf @ ph[n]
+    if cp.ke != 0.0:
+        J2 = _unit_casimir(N)
+        for n in range(K):
+            for ell in range(nl):
+                HPsi[n] += cp.ke * np.moveaxis(np.tensordot(J2, Psi[n], axes=([1], [ell])), 0, ell)
+    Hm = np.array([[np.vdot(Psi[a], HPsi[b]) for b in range(K)] for a in range(K)])
+    Nm = np.array([[np.vdot(Psi[a], Psi[b]) for b in range(K)] for a in range(K)])
+    return Hm, Nm
