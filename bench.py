@@ -563,6 +563,29 @@ def electric_measurement(ctx, args, Lc, stream, reps=20):
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "mean_final": float(out[:, 20].mean().item())}
 
 
+BENCH_COUPLINGS = dict(t=1.0, mu=0.0, m=0.5, kb=-1.0, ke=1.0)
+
+
+def energy_measurement(ctx, args, stream, reps=5):
+    """Local energy of the gauged Hamiltonian (Sec. 2, 2.3; estimators of Sec. 5.2, 5.3) and the
+    pair matrices of the linear step for lambda, for every chain's final configuration: k_energy
+    (one workgroup per chain) timed with HIP events on its launch stream after the timed sweeps."""
+    import torch
+    from paper_2412_01737_amd.ggf import GGF_ENERGY_STRIDE
+    out = torch.zeros((args.chains, GGF_ENERGY_STRIDE), dtype=torch.float64, device=stream.device)
+    ctx.measure_energy(BENCH_COUPLINGS, out, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.measure_energy(BENCH_COUPLINGS, out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"kernel": "k_energy", "bound": "latency", "us_per_launch": us, "couplings": BENCH_COUPLINGS,
+            "mean_local_energy": float(out[:, 0].mean().item())}
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -649,6 +672,7 @@ def main():
     elapsed = time.perf_counter() - t0
     refresh = refresh_correction(ctx, args, st0, stream)
     electric = electric_measurement(ctx, args, Lc, stream)
+    energy = energy_measurement(ctx, args, stream)
     timed_s = elapsed
     elapsed = elapsed + refresh["correction_ms"] * 1e-3
     proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
@@ -734,6 +758,7 @@ def main():
         "timed_s": timed_s,
         "refresh": refresh,
         "electric": electric,
+        "energy": energy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -131,6 +131,46 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
 ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out_is_device,
                        void *stream);
 
+/* Couplings of the gauged Hamiltonian (Sec. 2 staggered fermions, Sec. 2.2
+ * gauging, Sec. 2.3 plaquette and electric terms), one fermion mode per site:
+ *   H = t  sum_{x,mu} [ i eta_mu(x) psi_x^+ D(g_{x,mu}) psi_{x+mu} + h.c. ]
+ *     + mu sum_x psi_x^+ psi_x + m sum_x (-1)^(x1+x2) psi_x^+ psi_x
+ *     + kb sum_x [ U_sq(x) + U_sq(x)^* ] + ke sum_l J^2_l
+ * with D(g) = exp(2 pi i g / N), eta = -1 on the horizontal links of odd rows
+ * (pi flux through every plaquette) and +1 elsewhere, and J^2 = 0 on the
+ * trivial irrep of Z_N and 1 on the others.  All couplings are free and signed. */
+typedef struct {
+  double t, mu, m, kb, ke;
+} ggf_couplings;
+
+#define GGF_ENERGY_STRIDE (1 + 4 * GGF_KMAX * GGF_KMAX)   /* doubles per chain, ggf_measure_energy */
+
+/* Local energy of every chain's current configuration (Sec. 5.2 and 5.3 applied
+ * to H): per pair (a, b) of the superposition h_ab is the transition expectation
+ * of H, rho_ab = <B_b|B_a> Pf(M_ab)/Pf(M_00), S = sum lambda_a^* lambda_b rho_ab.
+ * Row c of out[n_chains][GGF_ENERGY_STRIDE] (float64; device pointer when
+ * out_is_device != 0, else host pointer and synchronous):
+ *   [0]            Re E_loc(G) = Re sum_ab lambda_a^* lambda_b rho_ab h_ab / S
+ *   [1 + 4p + 0,1] rho_p / S          (complex, p = a K + b < K^2)
+ *   [1 + 4p + 2,3] rho_p h_p / S      (complex)
+ * remaining entries 0.  <H> is the mean of [0] over samples of p(G). */
+ggf_status ggf_measure_energy(ggf_ctx *ctx, const ggf_couplings *couplings, double *out, int32_t out_is_device,
+                              void *stream);
+
+/* Linear variational step for lambda (the optimisation of the variational
+ * parameters that the outlook of Sec. 6.3 asks for, restricted to lambda_n):
+ * rows[n_rows][GGF_ENERGY_STRIDE] (host) are ggf_measure_energy rows of chains
+ * with K Gaussians, sampled from p(G) of one lambda.  With Hb, Nb the means of
+ * rho h / S and rho / S (Hermitian parts), <H>(lambda') =
+ * lambda'^+ Hb lambda' / lambda'^+ Nb lambda' for every lambda' (reweighting);
+ * writes the lowest generalised eigenvalue to *energy and its eigenvector,
+ * normalised to lambda^+ Nb lambda = 1 with lambda_0 real and >= 0, to
+ * lambda_re/lambda_im [K].  Host only; ctx may be NULL (it only receives the
+ * error message).  GGF_ESINGULAR if Nb is not positive definite, GGF_ENONFINITE
+ * for a non-finite row. */
+ggf_status ggf_lambda_step(ggf_ctx *ctx, int32_t K, const double *rows, int64_t n_rows, double *energy,
+                           double *lambda_re, double *lambda_im);
+
 /* Synchronous read-back of one chain: link values (int8, 2V entries),
  * counters and scalars.  Any argument may be NULL. */
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info);

@@ -18,6 +18,7 @@
 
 static_assert(GGF_NOBS == GGF_NOBS_DEV, "observable slot counts of the ABI and the kernels differ");
 static_assert(GGF_KMAX == GGF_KMAX_DEV, "superposition sizes of the ABI and the kernels differ");
+static_assert(GGF_ENERGY_STRIDE == GGF_ENERGY_STRIDE_DEV, "energy row lengths of the ABI and the kernels differ");
 
 typedef std::complex<double> cplx;
 
@@ -575,6 +576,7 @@ ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tenso
       }
       const cplx w = std::conj(cc[n]) * cc[m] * ovl;
       t.w[n][m] = make_double2(w.real(), w.imag());
+      t.ov[n][m] = make_double2(ovl.real(), ovl.imag());
     }
   ctx->tensors.push_back(t);
   if (ctx->tensors.size() > ctx->tensors_cap) {
@@ -802,6 +804,161 @@ ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(tmp);
   if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+ggf_status ggf_measure_energy(ggf_ctx *ctx, const ggf_couplings *cp, double *out, int32_t out_is_device,
+                              void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (!out || !cp) return fail(ctx, GGF_EINVAL, "out and couplings are required");
+  const double cv[5] = {cp->t, cp->mu, cp->m, cp->kb, cp->ke};
+  for (double v : cv)
+    if (!std::isfinite(v)) return fail(ctx, GGF_EINVAL, "couplings must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LaunchCtx lc = launch_ctx(ctx, s);
+  const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};
+  const size_t bytes = static_cast<size_t>(ctx->n_chains) * GGF_ENERGY_STRIDE * sizeof(double);
+  if (out_is_device) {
+    ggf_launch_energy(lc, ec, out, ctx->kmax);
+    HIP_TRY(ctx, hipGetLastError());
+    return GGF_OK;
+  }
+  double *tmp = nullptr;
+  HIP_TRY(ctx, hipMalloc(&tmp, bytes));
+  ggf_launch_energy(lc, ec, tmp, ctx->kmax);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure_energy: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+namespace {
+
+// Eigenpairs of a real symmetric matrix (order <= 2 GGF_KMAX) by cyclic Jacobi rotations;
+// a is destroyed, v receives the eigenvectors as columns, w the eigenvalues.
+void jacobi_eigen(int m, double *a, double *v, double *w) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) v[i * m + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) off += a[i * m + j] * a[i * m + j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = a[p * m + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (a[q * m + q] - a[p * m + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < m; ++k) {   // columns p, q
+          const double akp = a[k * m + p], akq = a[k * m + q];
+          a[k * m + p] = c * akp - s * akq;
+          a[k * m + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < m; ++k) {   // rows p, q
+          const double apk = a[p * m + k], aqk = a[q * m + k];
+          a[p * m + k] = c * apk - s * aqk;
+          a[q * m + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double vkp = v[k * m + p], vkq = v[k * m + q];
+          v[k * m + p] = c * vkp - s * vkq;
+          v[k * m + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < m; ++i) w[i] = a[i * m + i];
+}
+
+}  // namespace
+
+ggf_status ggf_lambda_step(ggf_ctx *ctx, int32_t K, const double *rows, int64_t n_rows, double *energy,
+                           double *lambda_re, double *lambda_im) {
+  if (K < 1 || K > GGF_KMAX) return fail(ctx, GGF_EINVAL, "K must be in 1..GGF_KMAX");
+  if (!rows || n_rows <= 0 || !energy || !lambda_re || !lambda_im)
+    return fail(ctx, GGF_EINVAL, "rows, n_rows > 0, energy and lambda are required");
+  // Hb = mean of rho h / S, Nb = mean of rho / S (Hermitian parts)
+  std::vector<cplx> Hb(K * K, 0.0), Nb(K * K, 0.0);
+  for (int64_t r = 0; r < n_rows; ++r) {
+    const double *row = rows + r * GGF_ENERGY_STRIDE;
+    for (int p = 0; p < K * K; ++p) {
+      const cplx rho(row[1 + 4 * p], row[2 + 4 * p]), rh(row[3 + 4 * p], row[4 + 4 * p]);
+      if (!std::isfinite(rho.real()) || !std::isfinite(rho.imag()) || !std::isfinite(rh.real()) ||
+          !std::isfinite(rh.imag()))
+        return fail(ctx, GGF_ENONFINITE, "non-finite pair matrices in row " + std::to_string(r));
+      Nb[p] += rho;
+      Hb[p] += rh;
+    }
+  }
+  std::vector<cplx> H(K * K), S(K * K);
+  for (int i = 0; i < K; ++i)
+    for (int j = 0; j < K; ++j) {
+      H[i * K + j] = 0.5 * (Hb[i * K + j] + std::conj(Hb[j * K + i])) / static_cast<double>(n_rows);
+      S[i * K + j] = 0.5 * (Nb[i * K + j] + std::conj(Nb[j * K + i])) / static_cast<double>(n_rows);
+    }
+  // Cholesky S = C C^+ (lower C)
+  std::vector<cplx> C(K * K, 0.0);
+  for (int j = 0; j < K; ++j) {
+    double d = S[j * K + j].real();
+    for (int k = 0; k < j; ++k) d -= std::norm(C[j * K + k]);
+    if (!(d > 0.0)) return fail(ctx, GGF_ESINGULAR, "overlap matrix of the superposition is not positive definite");
+    C[j * K + j] = std::sqrt(d);
+    for (int i = j + 1; i < K; ++i) {
+      cplx v = S[i * K + j];
+      for (int k = 0; k < j; ++k) v -= C[i * K + k] * std::conj(C[j * K + k]);
+      C[i * K + j] = v / C[j * K + j];
+    }
+  }
+  // Ci = C^-1 (lower triangular), A = Ci H Ci^+
+  std::vector<cplx> Ci(K * K, 0.0);
+  for (int j = 0; j < K; ++j) {
+    Ci[j * K + j] = 1.0 / C[j * K + j];
+    for (int i = j + 1; i < K; ++i) {
+      cplx v = 0.0;
+      for (int k = j; k < i; ++k) v -= C[i * K + k] * Ci[k * K + j];
+      Ci[i * K + j] = v / C[i * K + i];
+    }
+  }
+  std::vector<cplx> T(K * K, 0.0), A(K * K, 0.0);
+  for (int i = 0; i < K; ++i)
+    for (int j = 0; j < K; ++j)
+      for (int k = 0; k < K; ++k) T[i * K + j] += Ci[i * K + k] * H[k * K + j];
+  for (int i = 0; i < K; ++i)
+    for (int j = 0; j < K; ++j)
+      for (int k = 0; k < K; ++k) A[i * K + j] += T[i * K + k] * std::conj(Ci[j * K + k]);
+  // Hermitian A as the real symmetric [[Re, -Im], [Im, Re]] (each eigenvalue twice)
+  const int m = 2 * K;
+  std::vector<double> R(m * m), Vv(m * m), w(m);
+  for (int i = 0; i < K; ++i)
+    for (int j = 0; j < K; ++j) {
+      const cplx z = A[i * K + j];
+      R[i * m + j] = z.real();
+      R[i * m + K + j] = -z.imag();
+      R[(K + i) * m + j] = z.imag();
+      R[(K + i) * m + K + j] = z.real();
+    }
+  jacobi_eigen(m, R.data(), Vv.data(), w.data());
+  int lo = 0;
+  for (int i = 1; i < m; ++i)
+    if (w[i] < w[lo]) lo = i;
+  std::vector<cplx> y(K), lam(K, 0.0);
+  for (int i = 0; i < K; ++i) y[i] = cplx(Vv[i * m + lo], Vv[(K + i) * m + lo]);
+  double ny = 0.0;
+  for (int i = 0; i < K; ++i) ny += std::norm(y[i]);
+  for (int i = 0; i < K; ++i) y[i] /= std::sqrt(ny);
+  // lambda = Ci^+ y, so lambda^+ S lambda = 1; phase with lambda_0 real and positive
+  for (int i = 0; i < K; ++i)
+    for (int k = 0; k < K; ++k) lam[i] += std::conj(Ci[k * K + i]) * y[k];
+  const cplx ph = std::abs(lam[0]) > 0 ? std::conj(lam[0]) / std::abs(lam[0]) : cplx(1.0, 0.0);
+  for (int i = 0; i < K; ++i) {
+    lambda_re[i] = (lam[i] * ph).real();
+    lambda_im[i] = (lam[i] * ph).imag();
+  }
+  *energy = w[lo];
   return GGF_OK;
 }
 

@@ -17,6 +17,7 @@
 #define GGF_NOBS_DEV 21
 #define GGF_MAX_MESON 16
 #define GGF_ZN_MAX 3       // largest gauge group Z_N
+#define GGF_ENERGY_STRIDE_DEV (1 + 4 * GGF_KMAX_DEV * GGF_KMAX_DEV)
 
 // Per-ansatz constants.  Pair (n, m) of the superposition involves at most
 // two patch links (those where B_n or B_m differ from B_0); for each of them
@@ -29,6 +30,7 @@ struct TensorDev {
   double d[64];         // virtual block (8x8)
   double x0[4];         // out-in block of the reference bond (2x2)
   double2 w[GGF_KMAX_DEV][GGF_KMAX_DEV];              // lambda_n^* lambda_m <B_m|B_n>
+  double2 ov[GGF_KMAX_DEV][GGF_KMAX_DEV];             // <B_m|B_n>
   int nl[GGF_KMAX_DEV][GGF_KMAX_DEV];                 // involved patch links of pair (n,m): 0..2
   int lk[GGF_KMAX_DEV][GGF_KMAX_DEV][2];              // their lattice link indices
   double2 dg[GGF_KMAX_DEV][GGF_KMAX_DEV][2][16];      // 4x4 complex per involved link

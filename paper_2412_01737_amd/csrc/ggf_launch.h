@@ -65,4 +65,9 @@ void ggf_launch_end_sweep(const LaunchCtx &lc);
 void ggf_launch_hot_start(const LaunchCtx &lc, int max_links);
 void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax);
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax);
+// Couplings of the gauged Hamiltonian (hopping, chemical, staggered mass, plaquette, electric).
+struct EnergyCp {
+  double t, mu, m, kb, ke;
+};
+void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax);
 int ggf_launch_probe(int mode, void *a, void *b, size_t bytes, int grid, hipStream_t s);

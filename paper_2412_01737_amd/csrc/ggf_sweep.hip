@@ -542,20 +542,14 @@ __device__ inline double block_sum(double v, double *red) {
 // two-point functions: Gamma_out = A + B M^-1 B^T (per pair (a, b) of the
 // superposition with M_ab^-1 = G - G_S Y_ab G_S^T, Y_ab = Delta (1 + G_SS Delta)^-1),
 // <c_p c_q> = -i Gamma_out, weights lambda_a^* lambda_b <B_b|B_a> r_ab / S.
-template <typename T, bool EL_ONLY>
-__device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask, double *out) {
-  __shared__ double2 s_Y[16][64];
-  __shared__ double2 s_om[16];
-  __shared__ int s_S[16][8];
-  __shared__ int s_s[16];
-  __shared__ double red[8];
-  extern __shared__ double2 s_work[];
-  const int c = blockIdx.x;
-  const ChainDev ch = lc.chains[c];
-  const TensorDev &Tn = lc.tensors[ch.tensor];
-  const int n = ch.n, L = ch.L, V = L * L, K = ch.K, group = ch.group;
-  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
-  const int8_t *lk = lc.links + ch.link_off;
+// Per ordered pair (a, b) of the chain's superposition: om = lambda_a^* lambda_b <B_b|B_a> r_ab,
+// rho = <B_b|B_a> r_ab (when s_rho is given), the patch set S and Y_ab = Delta (1 + G_SS Delta)^-1,
+// so that M_ab^-1 = G + G_S Y_ab G_S^T on the rows and columns used (G antisymmetric).
+template <typename T>
+__device__ inline void pair_setup(const LaunchCtx &lc, int c, const ChainDev &ch, const TensorDev &Tn, const T *G,
+                                  const int8_t *lk, double2 (*s_Y)[64], double2 *s_om, double2 *s_rho,
+                                  int (*s_S)[8], int *s_s, double2 *s_work) {
+  const int n = ch.n, L = ch.L, K = ch.K, group = ch.group;
   const int npairs = K * K;
   // per ordered pair: r_ab and Y_ab = Delta (1 + G_SS Delta)^-1, four pairs at a time
   for (int p0 = 0; p0 < npairs; p0 += 4) {
@@ -589,8 +583,151 @@ __device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask
       }
       s_s[pr] = s;
       s_om[pr] = cmul(Tn.w[a][b], r);
+      if (s_rho) s_rho[pr] = cmul(Tn.ov[a][b], r);
     }
   }
+  __syncthreads();
+}
+
+// b G_xy b^T on the 2x2 physical block of sites (x, y), plus the on-site block a when x == y.
+template <typename T>
+__device__ inline void out_base(const T *G, int n, const TensorDev &Tn, int x, int y, double base[4]) {
+  base[0] = base[1] = base[2] = base[3] = 0.0;
+  for (int i = 0; i < 8; ++i) {
+    const T *grow = G + static_cast<size_t>(8 * x + i) * n + 8 * y;
+    double t0 = 0.0, t1 = 0.0;
+    for (int j = 0; j < 8; ++j) {
+      const double g = static_cast<double>(grow[j]);
+      t0 += g * Tn.b[0 * 8 + j];
+      t1 += g * Tn.b[1 * 8 + j];
+    }
+    base[0] += Tn.b[0 * 8 + i] * t0;
+    base[1] += Tn.b[0 * 8 + i] * t1;
+    base[2] += Tn.b[1 * 8 + i] * t0;
+    base[3] += Tn.b[1 * 8 + i] * t1;
+  }
+  if (x == y) {
+    base[0] += Tn.a[0]; base[1] += Tn.a[1]; base[2] += Tn.a[2]; base[3] += Tn.a[3];
+  }
+}
+
+// Gamma_out of one pair on the block (x, y): base + v_x Y v_y^T, v_x[p][q] = b_p . G[x-block, S_q]
+// (G_Sy = -G_yS^T turns -G_xS Y G_Sy into + v_x Y v_y^T).
+template <typename T>
+__device__ inline void out_pair(const T *G, int n, const TensorDev &Tn, int x, int y, int s, const int *S,
+                                const double2 *Y, const double base[4], double2 gm[4]) {
+  for (int q = 0; q < 4; ++q) gm[q] = make_double2(base[q], 0.0);
+  if (s == 0) return;
+  double vx[2][8], vy[2][8];
+  for (int q = 0; q < s; ++q) {
+    const int col = S[q];
+    double ax0 = 0, ax1 = 0, ay0 = 0, ay1 = 0;
+    for (int i = 0; i < 8; ++i) {
+      const double gx = static_cast<double>(G[static_cast<size_t>(8 * x + i) * n + col]);
+      const double gy = static_cast<double>(G[static_cast<size_t>(8 * y + i) * n + col]);
+      ax0 += Tn.b[i] * gx; ax1 += Tn.b[8 + i] * gx;
+      ay0 += Tn.b[i] * gy; ay1 += Tn.b[8 + i] * gy;
+    }
+    vx[0][q] = ax0; vx[1][q] = ax1; vy[0][q] = ay0; vy[1][q] = ay1;
+  }
+  for (int pp = 0; pp < 2; ++pp)
+    for (int qq = 0; qq < 2; ++qq) {
+      double2 v = make_double2(0, 0);
+      for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) v = cadd(v, cscale(Y[i * 8 + j], vx[pp][i] * vy[qq][j]));
+      gm[pp * 2 + qq] = cadd(gm[pp * 2 + qq], v);
+    }
+}
+
+// <phi_x^+ phi_y> (x != y) from Gamma_out on the block (x, y): phi = (c_0 + i c_1)/2,
+// <c_p c_q> = -i Gamma_pq, so 1/4 [<c0c0> + i<c0c1> - i<c1c0> + <c1c1>].
+__device__ inline double2 hop_xy(const double2 gm[4]) {
+  const double2 m00 = make_double2(gm[0].y, -gm[0].x), m01 = make_double2(gm[1].y, -gm[1].x);
+  const double2 m10 = make_double2(gm[2].y, -gm[2].x), m11 = make_double2(gm[3].y, -gm[3].x);
+  double2 bil = cadd(m00, m11);
+  bil = cadd(bil, make_double2(-m01.y, m01.x));
+  bil = csub(bil, make_double2(-m10.y, m10.x));
+  return cscale(bil, 0.25);
+}
+
+// <phi_y^+ phi_x> from the same block: <c_{y b} c_{x a}> = -i Gamma[y b][x a] = +i Gamma[x a][y b].
+__device__ inline double2 hop_yx(const double2 gm[4]) {
+  // 1/4 [<cy0 cx0> + i<cy0 cx1> - i<cy1 cx0> + <cy1 cx1>]
+  const double2 m00 = make_double2(-gm[0].y, gm[0].x), m10 = make_double2(-gm[2].y, gm[2].x);
+  const double2 m01 = make_double2(-gm[1].y, gm[1].x), m11 = make_double2(-gm[3].y, gm[3].x);
+  double2 bil = cadd(m00, m11);
+  bil = cadd(bil, make_double2(-m10.y, m10.x));      // + i <cy0 cx1> = + i m10 (Gamma[x1][y0])
+  bil = csub(bil, make_double2(-m01.y, m01.x));      // - i <cy1 cx0> = - i m01 (Gamma[x0][y1])
+  return cscale(bil, 0.25);
+}
+
+// G on the 4 Majoranas of link ell (antisymmetric 4x4 from six entries).
+template <typename T>
+__device__ inline void link_block(const T *G, int n, const int u[4], double gu[16]) {
+  using V2 = typename Vec2<T>::type;
+  const V2 r0 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[0]) * n + u[2]);
+  const V2 r1 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[1]) * n + u[2]);
+  const double g01 = static_cast<double>(G[static_cast<size_t>(u[0]) * n + u[1]]);
+  const double g23 = static_cast<double>(G[static_cast<size_t>(u[2]) * n + u[3]]);
+  const double v[16] = {0.0, g01, static_cast<double>(r0.x), static_cast<double>(r0.y),
+                        -g01, 0.0, static_cast<double>(r1.x), static_cast<double>(r1.y),
+                        -static_cast<double>(r0.x), -static_cast<double>(r1.x), 0.0, g23,
+                        -static_cast<double>(r0.y), -static_cast<double>(r1.y), -g23, 0.0};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) gu[q] = v[q];
+}
+
+// Mixed occupation X_ab of link ell's outgoing mode (Sec. 5.3):
+// X = en + (1/2) tr(M_ab^-1[U,U] O eq O^T), M_ab^-1[U,U] = G_UU + G_US Y G_US^T.
+template <typename T>
+__device__ inline double2 mixed_occupation(const T *G, int n, const TensorDev &Tn, int a, int b, int ell, int kv,
+                                           int group, const int u[4], const double gu[16], int s, const int *S,
+                                           const double2 *Y) {
+  double2 gm[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) gm[q] = make_double2(gu[q], 0.0);
+  if (s > 0) {
+    double vs[4][8];
+    for (int i = 0; i < 4; ++i)
+      for (int q = 0; q < s; ++q) vs[i][q] = static_cast<double>(G[static_cast<size_t>(u[i]) * n + S[q]]);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double2 v = make_double2(0.0, 0.0);
+        for (int p = 0; p < s; ++p)
+          for (int q = 0; q < s; ++q) v = cadd(v, cscale(Y[p * 8 + q], vs[i][p] * vs[j][q]));
+        gm[i * 4 + j] = cadd(gm[i * 4 + j], v);
+      }
+  }
+  const double2 *eq = Tn.eq0;
+  double2 x = Tn.en0;
+  for (int l = 0; l < Tn.nl[a][b]; ++l)
+    if (Tn.lk[a][b][l] == ell) { eq = Tn.eq[a][b][l]; x = Tn.en[a][b][l]; }
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    double2 row[4];
+    rotate_dg_row(eq, kv, group, jj, row);     // row jj of O eq O^T
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x = cadd(x, cscale(cmul(gm[i * 4 + jj], row[i]), 0.5));
+  }
+  return x;
+}
+
+template <typename T, bool EL_ONLY>
+__device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask, double *out) {
+  __shared__ double2 s_Y[16][64];
+  __shared__ double2 s_om[16];
+  __shared__ int s_S[16][8];
+  __shared__ int s_s[16];
+  __shared__ double red[8];
+  extern __shared__ double2 s_work[];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, K = ch.K, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int npairs = K * K;
+  pair_setup<T>(lc, c, ch, Tn, G, lk, s_Y, s_om, nullptr, s_S, s_s, s_work);
   __syncthreads();
   double Sv = 0.0;
   for (int p = 0; p < npairs; ++p) Sv += s_om[p].x;
@@ -618,62 +755,15 @@ __device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask
       for (int r = 0; r <= ((mask & 4u) ? nmes : 0); ++r) {
         if (r == 0 && !(mask & 2u)) continue;
         const int y = (r == 0) ? x : ggf_shift(x, L, r, 0);
-        double base[4] = {0, 0, 0, 0};   // (b G_xy b^T)[p][q]
-        for (int i = 0; i < 8; ++i) {
-          const T *grow = G + static_cast<size_t>(8 * x + i) * n + 8 * y;
-          double t0 = 0.0, t1 = 0.0;
-          for (int j = 0; j < 8; ++j) {
-            const double g = static_cast<double>(grow[j]);
-            t0 += g * Tn.b[0 * 8 + j];
-            t1 += g * Tn.b[1 * 8 + j];
-          }
-          base[0] += Tn.b[0 * 8 + i] * t0;
-          base[1] += Tn.b[0 * 8 + i] * t1;
-          base[2] += Tn.b[1 * 8 + i] * t0;
-          base[3] += Tn.b[1 * 8 + i] * t1;
-        }
-        if (r == 0) {
-          base[0] += Tn.a[0]; base[1] += Tn.a[1]; base[2] += Tn.a[2]; base[3] += Tn.a[3];
-        }
+        double base[4];   // (b G_xy b^T)[p][q] (+ a on site)
+        out_base(G, n, Tn, x, y, base);
         double2 tot = make_double2(0.0, 0.0);
         for (int pr = 0; pr < npairs; ++pr) {
-          double2 gm[4] = {make_double2(base[0], 0), make_double2(base[1], 0), make_double2(base[2], 0),
-                           make_double2(base[3], 0)};
-          const int s = s_s[pr];
-          if (s > 0) {
-            double vx[2][8], vy[2][8];
-            for (int q = 0; q < s; ++q) {
-              const int col = s_S[pr][q];
-              double ax0 = 0, ax1 = 0, ay0 = 0, ay1 = 0;
-              for (int i = 0; i < 8; ++i) {
-                const double gx = static_cast<double>(G[static_cast<size_t>(8 * x + i) * n + col]);
-                const double gy = static_cast<double>(G[static_cast<size_t>(8 * y + i) * n + col]);
-                ax0 += Tn.b[i] * gx; ax1 += Tn.b[8 + i] * gx;
-                ay0 += Tn.b[i] * gy; ay1 += Tn.b[8 + i] * gy;
-              }
-              vx[0][q] = ax0; vx[1][q] = ax1; vy[0][q] = ay0; vy[1][q] = ay1;
-            }
-            // + v_x Y v_y^T   (G_Sy = -G_yS^T makes -G_xS Y G_Sy = + v_x Y v_y^T)
-            for (int pp = 0; pp < 2; ++pp)
-              for (int qq = 0; qq < 2; ++qq) {
-                double2 v = make_double2(0, 0);
-                for (int i = 0; i < s; ++i)
-                  for (int j = 0; j < s; ++j) v = cadd(v, cscale(s_Y[pr][i * 8 + j], vx[pp][i] * vy[qq][j]));
-                gm[pp * 2 + qq] = cadd(gm[pp * 2 + qq], v);
-              }
-          }
+          double2 gm[4];
+          out_pair(G, n, Tn, x, y, s_s[pr], s_S[pr], s_Y[pr], base, gm);
           double2 f;
-          if (r == 0) {
-            f = cscale(cadd(make_double2(1.0, 0.0), gm[1]), 0.5);    // (1 + Gamma_out[x0,x1]) / 2
-          } else {
-            // <phi_x^+ phi_y> = 1/4 [<c0c0> + i<c0c1> - i<c1c0> + <c1c1>], <c_p c_q> = -i Gamma
-            const double2 m00 = make_double2(gm[0].y, -gm[0].x), m01 = make_double2(gm[1].y, -gm[1].x);
-            const double2 m10 = make_double2(gm[2].y, -gm[2].x), m11 = make_double2(gm[3].y, -gm[3].x);
-            double2 bil = cadd(m00, m11);
-            bil = cadd(bil, make_double2(-m01.y, m01.x));
-            bil = csub(bil, make_double2(-m10.y, m10.x));
-            f = cscale(bil, 0.5);                                       // 2 * (1/4) * bilinear
-          }
+          if (r == 0) f = cscale(cadd(make_double2(1.0, 0.0), gm[1]), 0.5);    // (1 + Gamma_out[x0,x1]) / 2
+          else f = cscale(hop_xy(gm), 2.0);                                      // 2 <phi_x^+ phi_y>
           tot = cadd(tot, cmul(s_om[pr], f));
         }
         if (r == 0) {
@@ -693,51 +783,16 @@ __device__ __forceinline__ void measure_chain(const LaunchCtx &lc, uint32_t mask
     // occupation of the link's outgoing mode, M_ab^-1[U,U] = G_UU + G_US Y_ab G_US^T.
     // The six entries of the antisymmetric G_UU: (u0,u1) and (u2,u3) on the sites' diagonal
     // blocks, (u0|u1, u2..u3) as two aligned pairs (u2 is even).
-    using V2 = typename Vec2<T>::type;
     for (int ell = threadIdx.x; ell < 2 * V; ell += blockDim.x) {
       int u[4];
       ggf_link_u(ell, L, u);
-      const V2 r0 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[0]) * n + u[2]);
-      const V2 r1 = *reinterpret_cast<const V2 *>(G + static_cast<size_t>(u[1]) * n + u[2]);
-      const double g01 = static_cast<double>(G[static_cast<size_t>(u[0]) * n + u[1]]);
-      const double g23 = static_cast<double>(G[static_cast<size_t>(u[2]) * n + u[3]]);
-      const double gu[16] = {0.0, g01, static_cast<double>(r0.x), static_cast<double>(r0.y),
-                             -g01, 0.0, static_cast<double>(r1.x), static_cast<double>(r1.y),
-                             -static_cast<double>(r0.x), -static_cast<double>(r1.x), 0.0, g23,
-                             -static_cast<double>(r0.y), -static_cast<double>(r1.y), -g23, 0.0};
+      double gu[16];
+      link_block(G, n, u, gu);
       const int kv = lk[ell];
       double2 tot = make_double2(0.0, 0.0);
-      for (int pr = 0; pr < npairs; ++pr) {
-        const int a = pr / K, b = pr % K;
-        double2 gm[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) gm[q] = make_double2(gu[q], 0.0);
-        const int s = s_s[pr];
-        if (s > 0) {
-          double vs[4][8];
-          for (int i = 0; i < 4; ++i)
-            for (int q = 0; q < s; ++q) vs[i][q] = static_cast<double>(G[static_cast<size_t>(u[i]) * n + s_S[pr][q]]);
-          for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) {
-              double2 v = make_double2(0.0, 0.0);
-              for (int p = 0; p < s; ++p)
-                for (int q = 0; q < s; ++q) v = cadd(v, cscale(s_Y[pr][p * 8 + q], vs[i][p] * vs[j][q]));
-              gm[i * 4 + j] = cadd(gm[i * 4 + j], v);
-            }
-        }
-        const double2 *eq = Tn.eq0;
-        double2 x = Tn.en0;
-        for (int l = 0; l < Tn.nl[a][b]; ++l)
-          if (Tn.lk[a][b][l] == ell) { eq = Tn.eq[a][b][l]; x = Tn.en[a][b][l]; }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          double2 row[4];
-          rotate_dg_row(eq, kv, group, jj, row);     // row jj of O eq O^T
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x = cadd(x, cscale(cmul(gm[i * 4 + jj], row[i]), 0.5));
-        }
-        tot = cadd(tot, cmul(s_om[pr], x));
-      }
+      for (int pr = 0; pr < npairs; ++pr)
+        tot = cadd(tot, cmul(s_om[pr], mixed_occupation(G, n, Tn, pr / K, pr % K, ell, kv, group, u, gu, s_s[pr],
+                                                        s_S[pr], s_Y[pr])));
       acc[GGF_NOBS_DEV - 1] += 0.5 * tot.x * invS;   // two links per site
     }
   }
@@ -827,6 +882,98 @@ __global__ __launch_bounds__(128) void k_electric1(LaunchCtx lc, double *out) {
       out[static_cast<size_t>(c) * GGF_NOBS_DEV + q] = (q == GGF_NOBS_DEV - 1) ? 0.5 * t / V : 0.0;
 }
 
+
+// Local energy of the gauged Hamiltonian (Sec. 2 hopping with the link phase D(g) and the
+// pi-flux signs, chemical and staggered mass terms; Sec. 2.3 plaquette; Sec. 5.3 electric
+// term) per chain, with the pair matrices of the linear variational step for lambda:
+//   h_ab = transition expectation of H in the pair (a, b) (Sec. 5.2, 5.3),
+//   out[0] = Re sum_ab om_ab h_ab / S, out[1 + 4 p ..] = rho_p / S and rho_p h_p / S
+//   (complex, p = a K + b), rho_ab = <B_b|B_a> r_ab; the other entries 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy(LaunchCtx lc, EnergyCp cp, double *out) {
+  __shared__ double2 s_Y[16][64];
+  __shared__ double2 s_om[16], s_rho[16], s_h[16];
+  __shared__ int s_S[16][8];
+  __shared__ int s_s[16];
+  __shared__ double red[8];
+  extern __shared__ double2 s_work[];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, K = ch.K, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int npairs = K * K;
+  pair_setup<T>(lc, c, ch, Tn, G, lk, s_Y, s_om, s_rho, s_S, s_s, s_work);
+  for (int pr = 0; pr < npairs; ++pr) {
+    const int a = pr / K, b = pr % K, s = s_s[pr];
+    double hr = 0.0, hi = 0.0;
+    for (int x = threadIdx.x; x < V; x += blockDim.x) {
+      const int x2 = x / L;
+      double2 h = make_double2(0.0, 0.0);
+      double base[4];
+      double2 gm[4];
+      // chemical + staggered mass: <phi_x^+ phi_x> = (1 + Gamma_out[x0,x1]) / 2
+      out_base(G, n, Tn, x, x, base);
+      out_pair(G, n, Tn, x, x, s, s_S[pr], s_Y[pr], base, gm);
+      const double sgn = (((x % L) + x2) & 1) ? -1.0 : 1.0;
+      h = cadd(h, cscale(cscale(cadd(make_double2(1.0, 0.0), gm[1]), 0.5), cp.mu + sgn * cp.m));
+      for (int mu = 0; mu < 2; ++mu) {
+        const int ell = 2 * x + mu;
+        const int y = mu == 0 ? ggf_shift(x, L, 1, 0) : ggf_shift(x, L, 0, 1);
+        // hopping: i eta D <phi_x^+ phi_y> - i eta D^* <phi_y^+ phi_x>, eta = -1 on horizontal
+        // links of odd rows
+        out_base(G, n, Tn, x, y, base);
+        out_pair(G, n, Tn, x, y, s, s_S[pr], s_Y[pr], base, gm);
+        const double2 D = link_phase(lk[ell], group);
+        const double te = (mu == 0 && (x2 & 1)) ? -cp.t : cp.t;
+        const double2 f = cmul(D, hop_xy(gm));
+        const double2 g = cmul(cconj(D), hop_yx(gm));
+        h = cadd(h, cscale(make_double2(g.y - f.y, f.x - g.x), te));   // i (f - g)
+        if (cp.ke != 0.0) {
+          int u[4];
+          ggf_link_u(ell, L, u);
+          double gu[16];
+          link_block(G, n, u, gu);
+          h = cadd(h, cscale(mixed_occupation(G, n, Tn, a, b, ell, lk[ell], group, u, gu, s, s_S[pr], s_Y[pr]),
+                             cp.ke));
+        }
+      }
+      if (cp.kb != 0.0) {
+        const int x1n = ggf_shift(x, L, 1, 0), x2n = ggf_shift(x, L, 0, 1);
+        double2 z = cmul(link_phase(lk[2 * x], group), link_phase(lk[2 * x1n + 1], group));
+        z = cmul(z, cconj(link_phase(lk[2 * x2n], group)));
+        z = cmul(z, cconj(link_phase(lk[2 * x + 1], group)));
+        h.x += 2.0 * cp.kb * z.x;                                     // kb (U + U^*)
+      }
+      hr += h.x;
+      hi += h.y;
+    }
+    const double tr = block_sum(hr, red);
+    const double ti = block_sum(hi, red);
+    if (threadIdx.x == 0) s_h[pr] = make_double2(tr, ti);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double Sv = 0.0, e = 0.0;
+    for (int p = 0; p < npairs; ++p) {
+      Sv += s_om[p].x;
+      e += cmul(s_om[p], s_h[p]).x;
+    }
+    const double invS = 1.0 / Sv;
+    double *o = out + static_cast<size_t>(c) * GGF_ENERGY_STRIDE_DEV;
+    for (int q = 0; q < GGF_ENERGY_STRIDE_DEV; ++q) o[q] = 0.0;
+    for (int p = 0; p < npairs; ++p) {
+      const double2 rh = cmul(s_rho[p], s_h[p]);
+      o[1 + 4 * p] = s_rho[p].x * invS;
+      o[2 + 4 * p] = s_rho[p].y * invS;
+      o[3 + 4 * p] = rh.x * invS;
+      o[4 + 4 * p] = rh.y * invS;
+    }
+    o[0] = e * invS;
+    if (!isfinite(o[0])) lc.flags[c] |= GGF_FLAG_NONFINITE;
+  }
+}
 }  // namespace
 
 static size_t pair_lds(int kmax) {
@@ -899,6 +1046,14 @@ void ggf_launch_sfac(const LaunchCtx &lc, const int *list, int count, int kmax) 
     hipLaunchKernelGGL(k_sfac<double>, dim3(count), dim3(64), lds, lc.stream, lc, list, count);
   else
     hipLaunchKernelGGL(k_sfac<float>, dim3(count), dim3(64), lds, lc.stream, lc, list, count);
+}
+
+void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax) {
+  const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_energy<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
+  else
+    hipLaunchKernelGGL(k_energy<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
 }
 
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax) {

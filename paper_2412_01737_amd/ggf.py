@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libggf.so")
 GGF_OK, GGF_EINVAL, GGF_ENOMEM, GGF_ESINGULAR, GGF_ENONFINITE, GGF_EDEVICE, GGF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 GGF_KMAX = 4
 GGF_NOBS = 21
+GGF_ENERGY_STRIDE = 1 + 4 * GGF_KMAX * GGF_KMAX
 OBS_LINK, OBS_DENSITY, OBS_MESON, OBS_ELECTRIC = 1, 2, 4, 8
 OBS_ALL = 15
 _STATUS = {0: "GGF_OK", -1: "GGF_EINVAL", -2: "GGF_ENOMEM", -3: "GGF_ESINGULAR",
@@ -43,6 +44,12 @@ class ChainInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Couplings(ctypes.Structure):
+    """ggf_couplings: H = t hopping + mu density + m staggered density + kb plaquettes + ke J^2."""
+    _fields_ = [("t", ctypes.c_double), ("mu", ctypes.c_double), ("m", ctypes.c_double), ("kb", ctypes.c_double),
+                ("ke", ctypes.c_double)]
+
+
 EXPORTS = {
     "ggf_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
     "ggf_set_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(TensorDesc), ctypes.POINTER(ctypes.c_int32)]),
@@ -50,6 +57,9 @@ EXPORTS = {
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "ggf_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "ggf_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_measure_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Couplings), ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p]),
+    "ggf_lambda_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_int64, _dp, _dp, _dp]),
     "ggf_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ChainInfo)]),
     "ggf_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64]),
     "ggf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
@@ -202,6 +212,20 @@ class Context:
         self._check(self._lib.ggf_measure(self.h, int(mask), ctypes.c_void_p(ptr), 1, _stream_ptr(stream)))
         return out
 
+    def measure_energy(self, couplings, out=None, stream=None):
+        """Local-energy rows [n_chains, GGF_ENERGY_STRIDE] (ggf_measure_energy); couplings is a
+        Couplings or a mapping with keys t, mu, m, kb, ke."""
+        cp = couplings if isinstance(couplings, Couplings) else Couplings(**dict(couplings))
+        if out is None:
+            host = np.zeros((self.n_chains, GGF_ENERGY_STRIDE))
+            self._check(self._lib.ggf_measure_energy(self.h, ctypes.byref(cp), host.ctypes.data_as(ctypes.c_void_p),
+                                                     0, _stream_ptr(stream)))
+            return host
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        self._check(self._lib.ggf_measure_energy(self.h, ctypes.byref(cp), ctypes.c_void_p(ptr), 1,
+                                                 _stream_ptr(stream)))
+        return out
+
     def get_state(self, chain: int):
         info = ChainInfo()
         self._check(self._lib.ggf_get_state(self.h, int(chain), None, ctypes.byref(info)))
@@ -315,3 +339,18 @@ def autocorr_time(series, c: float = 5.0):
     if st != GGF_OK:
         raise GGFError(st, "ggf_autocorr_time: bad arguments")
     return tau.value, err.value, w.value
+
+
+def lambda_step(K: int, rows):
+    """ggf_lambda_step on host rows [n, GGF_ENERGY_STRIDE]: (energy, lambda as a complex array)."""
+    lib = load()
+    r = np.ascontiguousarray(np.asarray(rows, np.float64).reshape(-1, GGF_ENERGY_STRIDE))
+    e = ctypes.c_double()
+    lr = np.zeros(K)
+    li = np.zeros(K)
+    st = lib.ggf_lambda_step(None, int(K), r.ctypes.data_as(_dp), r.shape[0], ctypes.byref(e),
+                             lr.ctypes.data_as(_dp), li.ctypes.data_as(_dp))
+    if st != GGF_OK:
+        raise GGFError(st, f"ggf_lambda_step failed ({_STATUS.get(st, st)})")
+    return e.value, lr + 1j * li
+
