@@ -83,6 +83,10 @@ def parse():
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "BENCH_JSON"),
                     help="derive the block update's HBM bytes per accepted move from rocprofv3 --pmc CSVs of a "
                          "--workload c5 run and that run's JSON line, write profiles/k_block_traffic.json and exit")
+    ap.add_argument("--lambda-iters", type=int, default=0,
+                    help="after the timed sweeps, rounds of the variational optimisation of lambda (K > 1 "
+                         "workloads; --lambda-sweeps sweeps per round), reported under 'lambda_opt'")
+    ap.add_argument("--lambda-sweeps", type=int, default=2)
     ap.add_argument("--electric-traffic-from", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="derive the electric measurement kernel's HBM bytes per launch from rocprofv3 --pmc "
@@ -673,6 +677,17 @@ def main():
     refresh = refresh_correction(ctx, args, st0, stream)
     electric = electric_measurement(ctx, args, Lc, stream)
     energy = energy_measurement(ctx, args, stream)
+    lambda_opt = None
+    if args.lambda_iters > 0 and args.workload != "c4" and args.K > 1:
+        torch.cuda.synchronize()
+        t_opt = time.perf_counter()
+        en_, eo_, lam_ = ctx.optimise_lambda(int(tids), BENCH_COUPLINGS, args.lambda_iters, args.lambda_sweeps,
+                                             args.K, stream=stream)
+        t_opt = time.perf_counter() - t_opt
+        lambda_opt = {"rounds": args.lambda_iters, "sweeps_per_round": args.lambda_sweeps,
+                      "s_per_round": t_opt / args.lambda_iters, "energy_per_round": en_.tolist(),
+                      "optimum_per_round": eo_.tolist(), "lambda_re": lam_.real.tolist(),
+                      "lambda_im": lam_.imag.tolist(), "couplings": BENCH_COUPLINGS}
     timed_s = elapsed
     elapsed = elapsed + refresh["correction_ms"] * 1e-3
     proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
@@ -759,6 +774,7 @@ def main():
         "refresh": refresh,
         "electric": electric,
         "energy": energy,
+        "lambda_opt": lambda_opt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -171,6 +171,25 @@ ggf_status ggf_measure_energy(ggf_ctx *ctx, const ggf_couplings *couplings, doub
 ggf_status ggf_lambda_step(ggf_ctx *ctx, int32_t K, const double *rows, int64_t n_rows, double *energy,
                            double *lambda_re, double *lambda_im);
 
+/* Replace the amplitudes lambda_n of tensor tensor_id (c_re, c_im [K], host;
+ * the linear variational parameters of Sec. 5) and recompute S(G) = N(G)/W(G)
+ * of every chain that uses the tensor, so that the next sweep samples p(G) of
+ * the new lambda.  Call between sweeps; synchronous.  K = 1 tensors are left
+ * unchanged (lambda only scales the state). */
+ggf_status ggf_set_lambda(ggf_ctx *ctx, int32_t tensor_id, const double *c_re, const double *c_im, void *stream);
+
+/* Variational optimisation of lambda_n for H (the outlook of Sec. 6.3, restricted
+ * to the linear parameters): n_iters rounds of [n_sweeps sweeps, each followed by
+ * ggf_measure_energy; ggf_lambda_step over the rows of the chains that use
+ * tensor_id; ggf_set_lambda with the result].  energies[n_iters] receives <H>
+ * estimated in each round (mean of Re E_loc over those rows, with that round's
+ * lambda), e_opt[n_iters] the step's optimum over the same rows, lambda_re/im [K]
+ * the last lambda.  Synchronous; allocates n_sweeps x n_chains x GGF_ENERGY_STRIDE
+ * doubles of device memory for the call. */
+ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_couplings *couplings, int32_t n_iters,
+                               int32_t n_sweeps, double *energies, double *e_opt, double *lambda_re,
+                               double *lambda_im, void *stream);
+
 /* Synchronous read-back of one chain: link values (int8, 2V entries),
  * counters and scalars.  Any argument may be NULL. */
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info);

@@ -807,6 +807,41 @@ ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out
   return GGF_OK;
 }
 
+ggf_status ggf_set_lambda(ggf_ctx *ctx, int32_t tensor_id, const double *c_re, const double *c_im, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(ctx->tensors.size()))
+    return fail(ctx, GGF_EINVAL, "bad tensor id");
+  if (!c_re || !c_im) return fail(ctx, GGF_EINVAL, "c_re and c_im are required");
+  TensorDev &t = ctx->tensors[tensor_id];
+  const int K = t.K;
+  if (K == 1) return GGF_OK;   // a single Gaussian: lambda only scales the state
+  double nrm = 0.0;
+  for (int k = 0; k < K; ++k) {
+    if (!std::isfinite(c_re[k]) || !std::isfinite(c_im[k])) return fail(ctx, GGF_EINVAL, "lambda must be finite");
+    nrm += c_re[k] * c_re[k] + c_im[k] * c_im[k];
+  }
+  if (!(nrm > 0.0)) return fail(ctx, GGF_EINVAL, "lambda must not vanish");
+  for (int n = 0; n < K; ++n)
+    for (int m = 0; m < K; ++m) {
+      const cplx w = std::conj(cplx(c_re[n], c_im[n])) * cplx(c_re[m], c_im[m]) *
+                     cplx(t.ov[n][m].x, t.ov[n][m].y);
+      t.w[n][m] = make_double2(w.real(), w.imag());
+    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->tensors_dev + tensor_id, &t, sizeof(TensorDev), hipMemcpyHostToDevice, s));
+  std::vector<int> which;
+  for (int c = 0; c < ctx->n_chains; ++c)
+    if (ctx->chains[c].tensor == tensor_id) which.push_back(c);
+  if (!which.empty()) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->list_dev, which.data(), which.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const LaunchCtx lc = launch_ctx(ctx, s);
+    ggf_launch_sfac(lc, ctx->list_dev, static_cast<int>(which.size()), ctx->kmax);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return GGF_OK;
+}
+
 ggf_status ggf_measure_energy(ggf_ctx *ctx, const ggf_couplings *cp, double *out, int32_t out_is_device,
                               void *stream) {
   if (!ctx) return GGF_EINVAL;
@@ -960,6 +995,58 @@ ggf_status ggf_lambda_step(ggf_ctx *ctx, int32_t K, const double *rows, int64_t 
   }
   *energy = w[lo];
   return GGF_OK;
+}
+
+ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_couplings *cp, int32_t n_iters,
+                               int32_t n_sweeps, double *energies, double *e_opt, double *lambda_re,
+                               double *lambda_im, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(ctx->tensors.size()))
+    return fail(ctx, GGF_EINVAL, "bad tensor id");
+  if (!cp || n_iters < 1 || n_sweeps < 1 || !energies || !e_opt || !lambda_re || !lambda_im)
+    return fail(ctx, GGF_EINVAL, "couplings, n_iters >= 1, n_sweeps >= 1 and the outputs are required");
+  const int K = ctx->tensors[tensor_id].K;
+  std::vector<int> which;
+  for (int c = 0; c < ctx->n_chains; ++c)
+    if (ctx->chains[c].tensor == tensor_id) which.push_back(c);
+  if (which.empty()) return fail(ctx, GGF_EINVAL, "no chain uses this tensor");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t row_bytes = static_cast<size_t>(ctx->n_chains) * GGF_ENERGY_STRIDE * sizeof(double);
+  double *dev = nullptr;
+  HIP_TRY(ctx, hipMalloc(&dev, row_bytes * n_sweeps));
+  std::vector<double> host(static_cast<size_t>(ctx->n_chains) * GGF_ENERGY_STRIDE * n_sweeps);
+  std::vector<double> rows(which.size() * GGF_ENERGY_STRIDE * n_sweeps);
+  ggf_status st = GGF_OK;
+  for (int it = 0; it < n_iters && st == GGF_OK; ++it) {
+    for (int sw = 0; sw < n_sweeps && st == GGF_OK; ++sw) {
+      st = ggf_sweep(ctx, 1, stream);
+      if (st == GGF_OK)
+        st = ggf_measure_energy(ctx, cp, dev + static_cast<size_t>(sw) * ctx->n_chains * GGF_ENERGY_STRIDE, 1,
+                                stream);
+    }
+    if (st != GGF_OK) break;
+    hipError_t e = hipMemcpyAsync(host.data(), dev, row_bytes * n_sweeps, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      st = fail(ctx, GGF_EDEVICE, std::string("optimise_lambda: ") + hipGetErrorString(e));
+      break;
+    }
+    double esum = 0.0;
+    size_t r = 0;
+    for (int sw = 0; sw < n_sweeps; ++sw)
+      for (int c : which) {
+        const double *src = host.data() + (static_cast<size_t>(sw) * ctx->n_chains + c) * GGF_ENERGY_STRIDE;
+        std::copy(src, src + GGF_ENERGY_STRIDE, rows.data() + r * GGF_ENERGY_STRIDE);
+        esum += src[0];
+        ++r;
+      }
+    energies[it] = esum / static_cast<double>(r);
+    st = ggf_lambda_step(ctx, K, rows.data(), static_cast<int64_t>(r), &e_opt[it], lambda_re, lambda_im);
+    if (st == GGF_OK) st = ggf_set_lambda(ctx, tensor_id, lambda_re, lambda_im, stream);
+  }
+  hipFree(dev);
+  return st;
 }
 
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info) {

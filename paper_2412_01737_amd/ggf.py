@@ -59,6 +59,9 @@ EXPORTS = {
     "ggf_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "ggf_measure_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Couplings), ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p]),
+    "ggf_optimise_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Couplings), ctypes.c_int32,
+                                           ctypes.c_int32, _dp, _dp, _dp, _dp, ctypes.c_void_p]),
+    "ggf_set_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, ctypes.c_void_p]),
     "ggf_lambda_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_int64, _dp, _dp, _dp]),
     "ggf_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ChainInfo)]),
     "ggf_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64]),
@@ -225,6 +228,27 @@ class Context:
         self._check(self._lib.ggf_measure_energy(self.h, ctypes.byref(cp), ctypes.c_void_p(ptr), 1,
                                                  _stream_ptr(stream)))
         return out
+
+    def set_lambda(self, tensor_id: int, c, stream=None):
+        """ggf_set_lambda: new amplitudes lambda_n (complex [K]) for a tensor; S(G) recomputed."""
+        c = np.asarray(c, complex)
+        re = np.ascontiguousarray(c.real, np.float64)
+        im = np.ascontiguousarray(c.imag, np.float64)
+        self._check(self._lib.ggf_set_lambda(self.h, int(tensor_id), re.ctypes.data_as(_dp), im.ctypes.data_as(_dp),
+                                             _stream_ptr(stream)))
+
+    def optimise_lambda(self, tensor_id: int, couplings, n_iters: int, n_sweeps: int, K: int, stream=None):
+        """ggf_optimise_lambda: (energies [n_iters], e_opt [n_iters], final lambda complex [K])."""
+        cp = couplings if isinstance(couplings, Couplings) else Couplings(**dict(couplings))
+        en = np.zeros(n_iters)
+        eo = np.zeros(n_iters)
+        lr = np.zeros(K)
+        li = np.zeros(K)
+        self._check(self._lib.ggf_optimise_lambda(self.h, int(tensor_id), ctypes.byref(cp), int(n_iters),
+                                                  int(n_sweeps), en.ctypes.data_as(_dp), eo.ctypes.data_as(_dp),
+                                                  lr.ctypes.data_as(_dp), li.ctypes.data_as(_dp),
+                                                  _stream_ptr(stream)))
+        return en, eo, lr + 1j * li
 
     def get_state(self, chain: int):
         info = ChainInfo()

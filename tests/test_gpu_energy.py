@@ -97,3 +97,42 @@ def test_lambda_step_end_to_end():
     cur = np.concatenate(rows)[:, 0].mean()
     assert e <= cur + 1e-9
     ctx.close()
+
+
+def test_set_lambda_recomputes_superposition():
+    """After ggf_set_lambda, S(G) of every chain and its energy rows follow the new lambda."""
+    import dataclasses
+    say("set lambda K=3 Z3")
+    L, K = 4, 3
+    spec = spec_for(L, K, 3)
+    ctx = gpu_context([spec], [L] * 3, init=1)
+    ctx.sweep(1)
+    c_new = np.array([0.8, -0.3 + 0.5j, 0.2 - 0.7j])
+    ctx.set_lambda(0, c_new)
+    an = ansatz_for(dataclasses.replace(spec, c=c_new), L)
+    rows = ctx.measure_energy(CP)
+    for c in range(3):
+        links, info = ctx.get_state(c)
+        S = an.s_factor_def(links)
+        assert abs(info["s_re"] - S.real) <= 1e-10 * abs(S.real)
+        _check(rows[c], an, links, 1e-10)
+    ctx.close()
+
+
+def test_optimise_lambda_rounds():
+    """Three rounds of two sweeps on K = 3 Z3 chains: each round's optimum over its samples is not
+    above the estimate with that round's lambda, and the chains end on the last lambda."""
+    import dataclasses
+    say("optimise lambda K=3 Z3")
+    L, K, chains = 4, 3, 16
+    spec = spec_for(L, K, 3)
+    ctx = gpu_context([spec], [L] * chains, init=1)
+    energies, e_opt, lam = ctx.optimise_lambda(0, CP, 3, 2, K)
+    assert np.all(np.isfinite(energies)) and np.all(np.isfinite(e_opt))
+    assert np.all(e_opt <= energies + 1e-9), (energies, e_opt)
+    an = ansatz_for(dataclasses.replace(spec, c=lam), L)
+    for c in range(0, chains, 5):
+        links, info = ctx.get_state(c)
+        S = an.s_factor_def(links)
+        assert abs(info["s_re"] - S.real) <= 1e-10 * abs(S.real)
+    ctx.close()
