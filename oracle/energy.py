@@ -29,6 +29,13 @@ give <H>(lambda') = lambda'^+ Hb lambda' / lambda'^+ Nb lambda' for every
 lambda' (reweighting), so the best lambda' is the lowest generalised eigenvector
 of (Hb, Nb).  This is the optimisation of the lambda_n among the variational
 parameters (the outlook of Sec. 6.3 asks for gradient descent on all of them).
+
+Gradient with respect to Gamma_A (K = 1): Gamma_A(theta) = exp(theta E) Gamma_A
+exp(-theta E) for antisymmetric generators E keeps the on-site state pure and
+even.  With Delta = [E, Gamma_A],
+    d<H> = E_p[d e] + E_p[(e - <H>) d log N],
+where d e(G) = tr(Delta S_e(G)) and d log N(G) = tr(Delta S_N(G)) for 10 x 10
+sensitivity matrices of the configuration.
 """
 from __future__ import annotations
 
@@ -126,3 +133,118 @@ def linear_method(Hb: np.ndarray, Nb: np.ndarray):
     lam = Li.conj().T @ v[:, 0]
     lam = lam * (abs(lam[0]) / lam[0]) if abs(lam[0]) > 0 else lam
     return float(w[0]), lam
+
+
+# ----- gradient with respect to Gamma_A (K = 1) -----
+def rotated_gamma_loc(gamma_loc: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """exp(X) Gamma_A exp(-X) for a real antisymmetric 10 x 10 generator X (stays pure and even)."""
+    from scipy.linalg import expm
+    R = expm(X)
+    return R @ gamma_loc @ R.T
+
+
+def generator(k: int, l: int) -> np.ndarray:
+    E = np.zeros((10, 10))
+    E[k, l] = 1.0
+    E[l, k] = -1.0
+    return E
+
+
+def sensitivities(an: Ansatz, links_k, cp: Couplings):
+    """(e, S_e, S_N) of one configuration, K = 1: for every antisymmetric generator E,
+    d e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N) with Delta = [E, Gamma_A] the
+    change of the on-site covariance (the same on every site).
+
+    e(G) is the local energy.  Gamma_out = A + B G B^T gives
+    d Gamma_out = dA + dB G B^T + B G dB^T + P dM P^T, with P = B G (G antisymmetric),
+    and the electric term X = en + (1/2) tr(G_UU R) gives dX = -(1/2) tr((G dM G)_UU R).
+    With N(G) = W(G) = 2^-4V sqrt(det M), d log N = (1/2) tr(G dM), dM = (+)_x Delta_d."""
+    assert an.K == 1
+    lat, N = an.lat, an.group
+    V, n = lat.V, lat.n
+    M = an.assemble_M(links_k)
+    G = np.linalg.inv(M)
+    gout = an.A + an.B @ G @ an.B.T
+    # energy as sum_pq C[p, q] (delta_pq - i Gamma_out[p, q]) / 4-type terms: collect the
+    # coefficient of Gamma_out[p, q] in e(G) (dE/dGamma_out) by linearity
+    C = np.zeros((2 * V, 2 * V), complex)
+
+    def add_bilinear(coef, x, y):
+        # coef * <phi_x^+ phi_y>, <phi_x^+ phi_y> = 1/4 [cc(x0,y0) + i cc(x0,y1) - i cc(x1,y0) + cc(x1,y1)],
+        # cc(a, b) = delta_ab - i Gamma[a, b]
+        for (a, b, w) in ((0, 0, 1.0), (0, 1, 1j), (1, 0, -1j), (1, 1, 1.0)):
+            C[2 * x + a, 2 * y + b] += coef * 0.25 * w * (-1j)
+
+    for x in range(V):
+        x1, x2 = lat.coords(x)
+        add_bilinear(cp.mu + cp.m * (-1) ** (x1 + x2), x, x)
+        for mu in range(2):
+            y = lat.shift(x, 1, 0) if mu == 0 else lat.shift(x, 0, 1)
+            D = link_phase(links_k[lat.link(x, mu)], N)
+            e_ = eta(lat, x, mu)
+            add_bilinear(cp.t * 1j * e_ * D, x, y)
+            add_bilinear(-cp.t * 1j * e_ * np.conj(D), y, x)
+    e = local_energy(an, links_k, cp)
+    # sensitivity: d e = sum_pq C[p, q] d Gamma_out[p, q] + ke sum_l dX_l
+    Sa = np.zeros((2, 2), complex)
+    Sb = np.zeros((2, 8), complex)
+    Sd = np.zeros((8, 8), complex)
+    GBt = G @ an.B.T                       # n x 2V
+    P = an.B @ G                           # 2V x n
+    for x in range(V):
+        rows = slice(2 * x, 2 * x + 2)
+        cols8 = slice(8 * x, 8 * x + 8)
+        # dA: Gamma_out[2x+a, 2x+b] += Delta_a[a, b]
+        Sa += C[rows, rows].T
+        # dB G B^T: Gamma_out[2x+a, q] += sum_i Delta_b[a, i] (G B^T)[8x+i, q]
+        Sb += (GBt[cols8, :] @ C[rows, :].T).T
+        # B G dB^T: Gamma_out[p, 2x+b] += sum_i (B G)[p, 8x+i] Delta_b[b, i]
+        Sb += (P[:, cols8].T @ C[:, rows]).T
+    # P dM P^T: sum_pq C[p,q] (P dM P^T)[p,q] = sum_z tr(Delta_d (P^T C P)[z, z]) with the
+    # trace convention tr(Delta S) = sum_ij Delta[i, j] S[j, i]
+    Q = P.T @ C @ P
+    for z in range(V):
+        blk = slice(8 * z, 8 * z + 8)
+        Sd += Q[blk, blk].T
+    if cp.ke != 0.0:
+        # X_l is affine in the antisymmetric G_UU: its slope along e_ij - e_ji (i < j) is read
+        # off the oracle's own X at unit steps (exact for an affine function), and
+        # d G_UU = -(G dM G)_UU with (G dM G)[a, b] = sum_z tr(Delta_d outer(G[z-block, b], G[a, z-block]))
+        for ell in range(lat.n_links):
+            u = lat.link_majoranas(ell)
+            g_uu = G[np.ix_(u, u)]
+            x0 = an.mixed_occupation_patch(g_uu, links_k, ell, 0, 0)
+            for i in range(4):
+                for j in range(i + 1, 4):
+                    step = np.zeros((4, 4))
+                    step[i, j], step[j, i] = 1.0, -1.0
+                    slope = an.mixed_occupation_patch(g_uu + step, links_k, ell, 0, 0) - x0
+                    for z in range(V):
+                        blk = slice(8 * z, 8 * z + 8)
+                        Sd += -cp.ke * slope * np.outer(G[blk, u[j]], G[u[i], blk])
+    S_e = np.zeros((10, 10), complex)
+    S_e[0:2, 0:2] = Sa
+    S_e[2:10, 0:2] = Sb.T
+    S_e[2:10, 2:10] = Sd
+    S_N = np.zeros((10, 10))
+    for x in range(V):
+        blk = slice(8 * x, 8 * x + 8)
+        S_N[2:10, 2:10] += 0.5 * G[blk, blk]
+    return e, S_e, S_N
+
+
+def gradient_from_samples(gamma_loc: np.ndarray, es, S_es, S_Ns, weights=None):
+    """d<H>/d theta_kl for the generators E_kl (k < l) from per-configuration (e, S_e, S_N)
+    drawn from p(G) (or weighted by p(G) when weights are given):
+    mean[tr(Delta S_e)] + mean[(e - mean e) tr(Delta S_N)], real part, from
+    <H> = sum_G N(G) e(G) / sum_G N(G).  Returned as the antisymmetric 10 x 10 matrix g with
+    g[k, l] = d<H>/d theta_kl."""
+    es = np.asarray(es)
+    w = np.full(len(es), 1.0 / len(es)) if weights is None else np.asarray(weights) / np.sum(weights)
+    ebar = np.sum(w * es)
+    Sbar = (np.tensordot(w, np.asarray(S_es), axes=1)
+            + np.tensordot(w * (es - ebar), np.asarray(S_Ns), axes=1))
+    # tr([E, Gamma] S) = tr(E (Gamma S - S Gamma)); for E_kl: Y[l, k] - Y[k, l]
+    Y = gamma_loc @ Sbar - Sbar @ gamma_loc
+    g = (Y.T - Y).real
+    return g

@@ -10,7 +10,11 @@
 * the linear method on the reweighted matrices gives the lowest generalised
   eigenvalue of the dense K-dimensional subspace (<Psi_n|H|Psi_m>, <Psi_n|Psi_m>),
   whatever lambda the configurations were weighted with;
-* E_loc is gauge invariant (Z2, flipping the links of a site).
+* E_loc is gauge invariant (Z2, flipping the links of a site);
+* K = 1 gradient with respect to the on-site covariance Gamma_A (rotations
+  exp(theta E) Gamma_A exp(-theta E)): the per-configuration sensitivities of e(G)
+  and log N(G) against central differences, and the p(G)-weighted gradient over
+  every configuration against central differences of the exactly enumerated <H>.
 """
 import itertools
 
@@ -128,3 +132,61 @@ def test_gauge_invariance_z2():
         for ell in lat.site_links(int(rng.integers(lat.V))):
             k2[ell] ^= 1
         assert abs(en.local_energy(an, k, CP) - en.local_energy(an, k2, CP)) < 1e-12
+
+
+# ----- gradient with respect to Gamma_A (K = 1) -----
+def _exact_energy(lat, gamma_loc, gamma_bond, group):
+    an = Ansatz(lat, gamma_loc, gamma_bond, group)
+    num = den = 0.0
+    for G in itertools.product(range(group), repeat=lat.n_links):
+        k = np.array(G)
+        Nk = an.weight(k)
+        num += Nk * en.local_energy(an, k, CP)
+        den += Nk
+    return (num / den).real
+
+
+@pytest.mark.parametrize("group", [2, 3])
+def test_sensitivities_against_finite_differences(group):
+    """d e(G) and d log N(G) along generators of the on-site rotation, per configuration."""
+    lat = Lattice(2, 2)
+    spec = synth.make_tensor(2, K=1, group=group)
+    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, group)
+    k = np.random.default_rng(1).integers(0, group, lat.n_links)
+    e, Se, SN = en.sensitivities(an, k, CP)
+    assert abs(e - en.local_energy(an, k, CP)) < 1e-13
+    h = 1e-5
+    for (a, b) in [(0, 1), (0, 5), (2, 7), (3, 9), (1, 4), (6, 8)]:
+        E = en.generator(a, b)
+        D = E @ spec.gamma_loc - spec.gamma_loc @ E
+        ap = Ansatz(lat, en.rotated_gamma_loc(spec.gamma_loc, h * E), spec.gamma_bond, group)
+        am = Ansatz(lat, en.rotated_gamma_loc(spec.gamma_loc, -h * E), spec.gamma_bond, group)
+        de = (en.local_energy(ap, k, CP) - en.local_energy(am, k, CP)) / (2 * h)
+        dn = (ap.log_weight(k) - am.log_weight(k)) / (2 * h)
+        assert abs(np.sum(D * Se.T) - de) <= 1e-7 * max(1.0, abs(de))
+        assert abs(np.sum(D * SN.T) - dn) <= 1e-7 * max(1.0, abs(dn))
+
+
+@pytest.mark.parametrize("group", [2, 3])
+def test_gradient_against_exact_energy(group):
+    """d<H>/d theta from per-configuration sensitivities weighted by p(G) over every configuration
+    of a 2x1 lattice equals central differences of the exactly enumerated <H>(theta)."""
+    lat = Lattice(2, 1)
+    spec = synth.make_tensor(2, K=1, group=group)
+    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, group)
+    es, Ses, SNs, ws = [], [], [], []
+    for G in itertools.product(range(group), repeat=lat.n_links):
+        k = np.array(G)
+        e, Se, SN = en.sensitivities(an, k, CP)
+        es.append(e)
+        Ses.append(Se)
+        SNs.append(SN)
+        ws.append(an.weight(k))
+    g = en.gradient_from_samples(spec.gamma_loc, es, Ses, SNs, weights=ws)
+    assert np.abs(g + g.T).max() < 1e-14
+    h = 1e-5
+    for (a, b) in [(0, 1), (0, 6), (2, 9), (4, 5)]:
+        E = en.generator(a, b)
+        fd = (_exact_energy(lat, en.rotated_gamma_loc(spec.gamma_loc, h * E), spec.gamma_bond, group)
+              - _exact_energy(lat, en.rotated_gamma_loc(spec.gamma_loc, -h * E), spec.gamma_bond, group)) / (2 * h)
+        assert abs(g[a, b] - fd) <= 1e-7 * max(1.0, abs(fd)), (a, b, g[a, b], fd)
