@@ -586,8 +586,28 @@ def energy_measurement(ctx, args, stream, reps=5):
     e1.record(stream)
     e1.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / reps
-    return {"kernel": "k_energy", "bound": "latency", "us_per_launch": us, "couplings": BENCH_COUPLINGS,
-            "mean_local_energy": float(out[:, 0].mean().item())}
+    res = {"kernel": "k_energy", "bound": "latency", "us_per_launch": us, "couplings": BENCH_COUPLINGS,
+           "mean_local_energy": float(out[:, 0].mean().item())}
+    if args.workload != "c4" and args.K == 1 and args.L <= 16:
+        # sensitivities to the on-site covariance (gradient of <H> with respect to Gamma_A)
+        from paper_2412_01737_amd.ggf import GGF_SENS_STRIDE, gamma_gradient
+        sens = torch.zeros((args.chains, GGF_SENS_STRIDE), dtype=torch.float64, device=stream.device)
+        ctx.measure_sensitivity(BENCH_COUPLINGS, sens, stream=stream)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.measure_sensitivity(BENCH_COUPLINGS, sens, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        g = gamma_gradient(synth_gamma_loc(args), out.cpu().numpy(), sens.cpu().numpy())
+        res["sensitivity"] = {"kernel": "k_sens", "bound": "latency",
+                              "us_per_launch": e0.elapsed_time(e1) * 1e3 / reps,
+                              "gradient_norm": float(np.abs(g).max())}
+    return res
+
+
+def synth_gamma_loc(args):
+    import synth
+    return synth.make_tensor(args.L, K=args.K, group=args.group).gamma_loc
 
 
 def main():

@@ -190,6 +190,34 @@ ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_coupli
                                int32_t n_sweeps, double *energies, double *e_opt, double *lambda_re,
                                double *lambda_im, void *stream);
 
+#define GGF_SENS_STRIDE 200   /* doubles per chain, ggf_measure_sensitivity */
+
+/* Sensitivities of every chain's local energy and log N(G) to the on-site
+ * covariance Gamma_A (gradient descent on Gamma_A, the outlook of Sec. 6.3;
+ * K = 1 chains with L <= 16, else GGF_EINVAL).  For a rotation
+ * Gamma_A -> exp(theta E) Gamma_A exp(-theta E) (E real antisymmetric 10 x 10,
+ * Delta = [E, Gamma_A]): d Re E_loc(G)/d theta = tr(Delta S_e) and
+ * d log N(G)/d theta = tr(Delta S_N), tr(Delta S) = sum_ij Delta_ij S_ji.
+ * Row c of out[n_chains][GGF_SENS_STRIDE]: [0..99] S_e, [100..199] S_N,
+ * row-major 10 x 10 (device pointer when out_is_device != 0, else host and
+ * synchronous). */
+ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *couplings, double *out,
+                                   int32_t out_is_device, void *stream);
+
+/* Gradient of <H> with respect to the rotation generators of Gamma_A from
+ * n_rows samples of p(G) (host rows of ggf_measure_energy and
+ * ggf_measure_sensitivity of the same chains and configurations):
+ * d<H>/d theta_kl = mean tr(Delta_kl S_e) + mean (e - mean e) tr(Delta_kl S_N),
+ * written as the antisymmetric grad[10][10] (grad[k][l] for E_kl = e_kl - e_lk);
+ * gamma_loc is the current on-site covariance.  Host only; ctx may be NULL. */
+ggf_status ggf_gamma_gradient(ggf_ctx *ctx, const double *gamma_loc, const double *energy_rows,
+                              const double *sens_rows, int64_t n_rows, double *grad);
+
+/* Replace the on-site covariance of tensor tensor_id (10 x 10, checked as in
+ * ggf_set_tensor) and refactorise every chain that uses it from its link field
+ * (float64), so that G, log W and S follow the new tensor.  Synchronous. */
+ggf_status ggf_set_gamma_loc(ggf_ctx *ctx, int32_t tensor_id, const double *gamma_loc, void *stream);
+
 /* Synchronous read-back of one chain: link values (int8, 2V entries),
  * counters and scalars.  Any argument may be NULL. */
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info);

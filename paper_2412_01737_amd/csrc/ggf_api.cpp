@@ -19,6 +19,7 @@
 static_assert(GGF_NOBS == GGF_NOBS_DEV, "observable slot counts of the ABI and the kernels differ");
 static_assert(GGF_KMAX == GGF_KMAX_DEV, "superposition sizes of the ABI and the kernels differ");
 static_assert(GGF_ENERGY_STRIDE == GGF_ENERGY_STRIDE_DEV, "energy row lengths of the ABI and the kernels differ");
+static_assert(GGF_SENS_STRIDE == GGF_SENS_STRIDE_DEV, "sensitivity row lengths of the ABI and the kernels differ");
 
 typedef std::complex<double> cplx;
 
@@ -1047,6 +1048,102 @@ ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_coupli
   }
   hipFree(dev);
   return st;
+}
+
+ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double *out, int32_t out_is_device,
+                                   void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (!out || !cp) return fail(ctx, GGF_EINVAL, "out and couplings are required");
+  const double cv[5] = {cp->t, cp->mu, cp->m, cp->kb, cp->ke};
+  for (double v : cv)
+    if (!std::isfinite(v)) return fail(ctx, GGF_EINVAL, "couplings must be finite");
+  int max_sites = 0;
+  for (const ChainDev &ch : ctx->chains) {
+    if (ch.K != 1) return fail(ctx, GGF_EINVAL, "sensitivities need K = 1 chains");
+    if (ch.L > 16) return fail(ctx, GGF_EINVAL, "sensitivities need L <= 16");
+    max_sites = std::max(max_sites, ch.L * ch.L);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LaunchCtx lc = launch_ctx(ctx, s);
+  const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};
+  const size_t bytes = static_cast<size_t>(ctx->n_chains) * GGF_SENS_STRIDE * sizeof(double);
+  if (out_is_device) {
+    ggf_launch_sens(lc, ec, out, max_sites);
+    HIP_TRY(ctx, hipGetLastError());
+    return GGF_OK;
+  }
+  double *tmp = nullptr;
+  HIP_TRY(ctx, hipMalloc(&tmp, bytes));
+  ggf_launch_sens(lc, ec, tmp, max_sites);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure_sensitivity: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+ggf_status ggf_gamma_gradient(ggf_ctx *ctx, const double *gamma_loc, const double *energy_rows,
+                              const double *sens_rows, int64_t n_rows, double *grad) {
+  if (!gamma_loc || !energy_rows || !sens_rows || n_rows <= 0 || !grad)
+    return fail(ctx, GGF_EINVAL, "gamma_loc, rows, n_rows > 0 and grad are required");
+  double ebar = 0.0;
+  for (int64_t r = 0; r < n_rows; ++r) {
+    const double e = energy_rows[r * GGF_ENERGY_STRIDE];
+    if (!std::isfinite(e)) return fail(ctx, GGF_ENONFINITE, "non-finite energy in row " + std::to_string(r));
+    ebar += e;
+  }
+  ebar /= static_cast<double>(n_rows);
+  // Sbar = mean S_e + mean (e - ebar) S_N
+  double S[100] = {0.0};
+  for (int64_t r = 0; r < n_rows; ++r) {
+    const double de = energy_rows[r * GGF_ENERGY_STRIDE] - ebar;
+    const double *row = sens_rows + r * GGF_SENS_STRIDE;
+    for (int q = 0; q < 100; ++q) {
+      if (!std::isfinite(row[q]) || !std::isfinite(row[100 + q]))
+        return fail(ctx, GGF_ENONFINITE, "non-finite sensitivity in row " + std::to_string(r));
+      S[q] += row[q] + de * row[100 + q];
+    }
+  }
+  for (double &v : S) v /= static_cast<double>(n_rows);
+  // d<H>/d theta_kl = tr([E_kl, Gamma] S) = Y[l][k] - Y[k][l], Y = Gamma S - S Gamma
+  double Y[100];
+  for (int i = 0; i < 10; ++i)
+    for (int j = 0; j < 10; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 10; ++k) v += gamma_loc[i * 10 + k] * S[k * 10 + j] - S[i * 10 + k] * gamma_loc[k * 10 + j];
+      Y[i * 10 + j] = v;
+    }
+  for (int k = 0; k < 10; ++k)
+    for (int l = 0; l < 10; ++l) grad[k * 10 + l] = Y[l * 10 + k] - Y[k * 10 + l];
+  return GGF_OK;
+}
+
+ggf_status ggf_set_gamma_loc(ggf_ctx *ctx, int32_t tensor_id, const double *gamma_loc, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(ctx->tensors.size()))
+    return fail(ctx, GGF_EINVAL, "bad tensor id");
+  if (!gamma_loc) return fail(ctx, GGF_EINVAL, "gamma_loc is required");
+  std::string why;
+  if (!check_local(gamma_loc, why)) return fail(ctx, GGF_EINVAL, why);
+  TensorDev &t = ctx->tensors[tensor_id];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) t.a[i * 2 + j] = gamma_loc[i * 10 + j];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 8; ++j) t.b[i * 8 + j] = gamma_loc[i * 10 + 2 + j];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) t.d[i * 8 + j] = gamma_loc[(2 + i) * 10 + 2 + j];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->tensors_dev + tensor_id, &t, sizeof(TensorDev), hipMemcpyHostToDevice, s));
+  std::vector<int> which;
+  for (int c = 0; c < ctx->n_chains; ++c)
+    if (ctx->chains[c].tensor == tensor_id) which.push_back(c);
+  if (which.empty()) {
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return GGF_OK;
+  }
+  return factorize(ctx, which, 0, s);
 }
 
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info) {

@@ -18,6 +18,7 @@
 #define GGF_MAX_MESON 16
 #define GGF_ZN_MAX 3       // largest gauge group Z_N
 #define GGF_ENERGY_STRIDE_DEV (1 + 4 * GGF_KMAX_DEV * GGF_KMAX_DEV)
+#define GGF_SENS_STRIDE_DEV 200
 
 // Per-ansatz constants.  Pair (n, m) of the superposition involves at most
 // two patch links (those where B_n or B_m differ from B_0); for each of them

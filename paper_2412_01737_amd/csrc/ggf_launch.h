@@ -70,4 +70,6 @@ struct EnergyCp {
   double t, mu, m, kb, ke;
 };
 void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax);
+// Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 16).
+void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites);
 int ggf_launch_probe(int mode, void *a, void *b, size_t bytes, int grid, hipStream_t s);

@@ -974,6 +974,214 @@ __global__ __launch_bounds__(256) void k_energy(LaunchCtx lc, EnergyCp cp, doubl
     if (!isfinite(o[0])) lc.flags[c] |= GGF_FLAG_NONFINITE;
   }
 }
+
+// Real part of Re(coef * Wc), Wc = (1/4) [[-i, 1], [-1, -i]]: the coefficient block of
+// Gamma_out[2x + a][2y + b] in coef <phi_x^+ phi_y> (with <c_p c_q> = -i Gamma_pq).
+__device__ inline void coef_block(double2 coef, double o[4]) {
+  o[0] = 0.25 * coef.y;
+  o[1] = 0.25 * coef.x;
+  o[2] = -0.25 * coef.x;
+  o[3] = 0.25 * coef.y;
+}
+
+// The five bilinear blocks of H that involve site x: term 0 on-site (x, x), terms 1 + 2 mu
+// the hop (x, x + mu), terms 2 + 2 mu the reverse (x + mu, x); (row site, column site, block).
+__device__ inline void h_term(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
+                              int &y, double o[4]) {
+  if (term == 0) {
+    const int sgn = (((x % L) + x / L) & 1) ? -1 : 1;
+    w = y = x;
+    coef_block(make_double2(cp.mu + sgn * cp.m, 0.0), o);
+    return;
+  }
+  const int mu = (term - 1) >> 1;
+  const int xn = mu == 0 ? ggf_shift(x, L, 1, 0) : ggf_shift(x, L, 0, 1);
+  const double2 D = link_phase(lk[2 * x + mu], group);
+  const double te = (mu == 0 && ((x / L) & 1)) ? -cp.t : cp.t;
+  if ((term & 1) == 1) {           // t i eta D <phi_x^+ phi_xn>
+    w = x;
+    y = xn;
+    coef_block(make_double2(-te * D.y, te * D.x), o);
+  } else {                         // -t i eta D^* <phi_xn^+ phi_x>
+    w = xn;
+    y = x;
+    coef_block(make_double2(-te * D.y, -te * D.x), o);
+  }
+}
+
+// Sensitivities of one K = 1 chain to its on-site covariance Gamma_A: for Delta = [E, Gamma_A]
+// (E antisymmetric), Re d e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N), with the
+// transposed-trace convention tr(Delta S) = sum_ij Delta_ij S_ji.  With P = B G, C the
+// coefficients of Gamma_out in the local energy and R_k the rotated electric response,
+//   S_e[a-block]  = sum_x C[x, x]^T,
+//   S_e[b^T-block] from dB G B^T + B G dB^T (rows of G on the 5 neighbouring blocks),
+//   S_e[d-block]  = sum_z (P^T C P)[z, z]^T + ke sum_l sum_{i<j} R_k[j][i] G[z, u_j] (x) G[z, u_i],
+//   S_N[d-block]  = (1/2) sum_x G[x, x]  (log N = (1/2) log det M + const).
+// out[c][0..99] = Re S_e, out[c][100..199] = S_N (row-major 10 x 10).  L <= 16.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double *out) {
+  extern __shared__ double s_U[];            // U_z[i][2w + a] = sum_j G[8z+i][8w+j] b[a][j], 8 x 2V
+  __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
+  __shared__ double s_R[GGF_ZN_MAX][16];
+  __shared__ double s_red[4][64];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int tid = threadIdx.x;
+  if (tid < 4) s_Sa[tid] = 0.0;
+  if (tid < 16) s_Sb[tid] = 0.0;
+  if (tid < 64) s_SN[tid] = 0.0;
+  if (tid < 16 * group) {
+    const int k = tid >> 4, e = tid & 15;
+    double co = 1.0, si = 0.0;
+    if (k != 0) {
+      if (group == 2) co = -1.0;
+      else sincospi(2.0 * k / group, &si, &co);
+    }
+    const double o[4][4] = {{co, si, 0.0, 0.0}, {-si, co, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}, {0.0, 0.0, 0.0, 1.0}};
+    double q[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) q[i] = Tn.eq0[i].x;
+    double val = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) v += o[i][a] * q[a * 4 + b] * o[j][b];
+        if (i * 4 + j == e) val = v;
+      }
+    s_R[k][e] = val;
+  }
+  __syncthreads();
+  // (1) per site: a-block, b-block and S_N
+  for (int x = tid; x < V; x += blockDim.x) {
+    double sb[16];
+    for (int q = 0; q < 16; ++q) sb[q] = 0.0;
+    for (int term = 0; term < 5; ++term) {
+      int w, y;
+      double o[4];
+      h_term(cp, lk, L, group, x, term, w, y, o);
+      if (term == 0) {
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) atomicAdd(&s_Sa[b * 2 + a], o[a * 2 + b]);
+      }
+    }
+    // blocks with row site x: (x, y) for y = x, x + mu (hop) and x - mu (reverse of the hop into x)
+    // blocks with column site x: (w, x) for w = x, x - mu (hop) and x + mu (reverse)
+    for (int nb = 0; nb < 5; ++nb) {
+      // neighbour y of x and the blocks (x, y) and (y, x) among the terms of x and of x - mu
+      int y = x;
+      if (nb == 1) y = ggf_shift(x, L, 1, 0);
+      if (nb == 2) y = ggf_shift(x, L, 0, 1);
+      if (nb == 3) y = ggf_shift(x, L, -1, 0);
+      if (nb == 4) y = ggf_shift(x, L, 0, -1);
+      // L = 2: x - mu is x + mu, whose blocks nb = 1, 2 already collected (from both owners)
+      if ((nb == 3 && y == ggf_shift(x, L, 1, 0)) || (nb == 4 && y == ggf_shift(x, L, 0, 1))) continue;
+      double orow[4] = {0, 0, 0, 0}, ocol[4] = {0, 0, 0, 0};   // blocks (x, y) and (y, x)
+      const int owners[2] = {x, y};
+      for (int oi = 0; oi < (nb == 0 ? 1 : 2); ++oi)
+        for (int term = 0; term < 5; ++term) {
+          int w2, y2;
+          double o[4];
+          h_term(cp, lk, L, group, owners[oi], term, w2, y2, o);
+          if (nb == 0 && term != 0) continue;
+          if (nb != 0 && term == 0) continue;
+          if (w2 == x && y2 == y)
+            for (int q = 0; q < 4; ++q) orow[q] += o[q];
+          if (w2 == y && y2 == x)
+            for (int q = 0; q < 4; ++q) ocol[q] += o[q];
+        }
+      if (nb == 0) {
+        for (int q = 0; q < 4; ++q) ocol[q] = orow[q];
+      }
+      for (int i = 0; i < 8; ++i) {
+        const T *grow = G + static_cast<size_t>(8 * x + i) * n + 8 * y;
+        double t0 = 0.0, t1 = 0.0;   // T[i][y][beta] = sum_j G[8x+i][8y+j] b[beta][j]
+        for (int j = 0; j < 8; ++j) {
+          const double g = static_cast<double>(grow[j]);
+          t0 += g * Tn.b[j];
+          t1 += g * Tn.b[8 + j];
+        }
+        for (int a = 0; a < 2; ++a) {
+          // dB G B^T: Sb[a][i] += sum_beta C[x a][y beta] T[i][y][beta]
+          sb[a * 8 + i] += orow[a * 2 + 0] * t0 + orow[a * 2 + 1] * t1;
+          // B G dB^T: Sb[b][i] -= sum_alpha C[y alpha][x b] T[i][y][alpha]
+          sb[a * 8 + i] -= ocol[0 * 2 + a] * t0 + ocol[1 * 2 + a] * t1;
+        }
+      }
+    }
+    for (int q = 0; q < 16; ++q) atomicAdd(&s_Sb[q], sb[q]);
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j)
+        atomicAdd(&s_SN[i * 8 + j], 0.5 * static_cast<double>(G[static_cast<size_t>(8 * x + i) * n + 8 * x + j]));
+  }
+  // (2) d-block: per row stripe z
+  const int ij = tid & 63, part = tid >> 6;
+  const int pi = ij >> 3, pj = ij & 7;
+  double sd = 0.0;
+  for (int z = 0; z < V; ++z) {
+    __syncthreads();
+    for (int e = tid; e < 16 * V; e += blockDim.x) {
+      const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, a = col & 1;
+      const T *grow = G + static_cast<size_t>(8 * z + i) * n + 8 * w;
+      double v = 0.0;
+      for (int j = 0; j < 8; ++j) v += static_cast<double>(grow[j]) * Tn.b[a * 8 + j];
+      s_U[i * 2 * V + col] = v;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int x = part; x < V; x += 4)
+      for (int term = 0; term < 5; ++term) {
+        int w, y;
+        double o[4];
+        h_term(cp, lk, L, group, x, term, w, y, o);
+        const double ui0 = s_U[pi * 2 * V + 2 * w], ui1 = s_U[pi * 2 * V + 2 * w + 1];
+        const double uj0 = s_U[pj * 2 * V + 2 * y], uj1 = s_U[pj * 2 * V + 2 * y + 1];
+        acc += ui0 * (o[0] * uj0 + o[1] * uj1) + ui1 * (o[2] * uj0 + o[3] * uj1);
+      }
+    if (cp.ke != 0.0)
+      for (int ell = part; ell < 2 * V; ell += 4) {
+        int u[4];
+        ggf_link_u(ell, L, u);
+        const double *R = s_R[lk[ell]];
+        const T *gp = G + static_cast<size_t>(8 * z + pj) * n;   // G[8z + p][.], p = the column index of S
+        const T *gq = G + static_cast<size_t>(8 * z + pi) * n;   // G[8z + q][.]
+        for (int i = 0; i < 4; ++i)
+          for (int j = i + 1; j < 4; ++j)
+            acc += cp.ke * R[j * 4 + i] * static_cast<double>(gp[u[j]]) * static_cast<double>(gq[u[i]]);
+      }
+    sd += acc;   // (P^T C P)[z][pi][pj] + electric part; S_d[pj][pi] collects it
+  }
+  s_red[part][ij] = sd;
+  __syncthreads();
+  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
+  if (tid < 64) {
+    const double v = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+    // thread (pi, pj) summed (P^T C P)[pi][pj] for the d-block's transpose: S_d[pj][pi]
+    o[(2 + pj) * 10 + 2 + pi] = v;
+    o[100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7)] = s_SN[tid];
+  }
+  if (tid < 16) {
+    const int a = tid >> 3, i = tid & 7;
+    o[(2 + i) * 10 + a] = s_Sb[tid];          // S_e[2 + i][a] = Sb[a][i]
+  }
+  if (tid < 4) o[(tid >> 1) * 10 + (tid & 1)] = s_Sa[tid];
+  if (tid < 20) {
+    const int a = tid / 10, j = tid % 10;
+    if (j >= 2) o[a * 10 + j] = 0.0;           // S_e[0:2][2:10] = 0
+  }
+  if (tid < 100) {
+    const int i = tid / 10, j = tid % 10;
+    if (i < 2 || j < 2) o[100 + tid] = 0.0;    // S_N outside the d-block
+  }
+}
 }  // namespace
 
 static size_t pair_lds(int kmax) {
@@ -1054,6 +1262,14 @@ void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int
     hipLaunchKernelGGL(k_energy<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
   else
     hipLaunchKernelGGL(k_energy<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
+}
+
+void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites) {
+  const size_t lds = static_cast<size_t>(16) * max_sites * sizeof(double);
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_sens<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
+  else
+    hipLaunchKernelGGL(k_sens<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
 }
 
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax) {

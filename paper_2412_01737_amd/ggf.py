@@ -19,6 +19,7 @@ GGF_OK, GGF_EINVAL, GGF_ENOMEM, GGF_ESINGULAR, GGF_ENONFINITE, GGF_EDEVICE, GGF_
 GGF_KMAX = 4
 GGF_NOBS = 21
 GGF_ENERGY_STRIDE = 1 + 4 * GGF_KMAX * GGF_KMAX
+GGF_SENS_STRIDE = 200
 OBS_LINK, OBS_DENSITY, OBS_MESON, OBS_ELECTRIC = 1, 2, 4, 8
 OBS_ALL = 15
 _STATUS = {0: "GGF_OK", -1: "GGF_EINVAL", -2: "GGF_ENOMEM", -3: "GGF_ESINGULAR",
@@ -61,6 +62,10 @@ EXPORTS = {
                                           ctypes.c_void_p]),
     "ggf_optimise_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Couplings), ctypes.c_int32,
                                            ctypes.c_int32, _dp, _dp, _dp, _dp, ctypes.c_void_p]),
+    "ggf_measure_sensitivity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Couplings), ctypes.c_void_p,
+                                               ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_gamma_gradient": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int64, _dp]),
+    "ggf_set_gamma_loc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_void_p]),
     "ggf_set_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, ctypes.c_void_p]),
     "ggf_lambda_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_int64, _dp, _dp, _dp]),
     "ggf_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ChainInfo)]),
@@ -229,6 +234,25 @@ class Context:
                                                  _stream_ptr(stream)))
         return out
 
+    def measure_sensitivity(self, couplings, out=None, stream=None):
+        """Sensitivity rows [n_chains, GGF_SENS_STRIDE] (ggf_measure_sensitivity)."""
+        cp = couplings if isinstance(couplings, Couplings) else Couplings(**dict(couplings))
+        if out is None:
+            host = np.zeros((self.n_chains, GGF_SENS_STRIDE))
+            self._check(self._lib.ggf_measure_sensitivity(self.h, ctypes.byref(cp),
+                                                          host.ctypes.data_as(ctypes.c_void_p), 0,
+                                                          _stream_ptr(stream)))
+            return host
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        self._check(self._lib.ggf_measure_sensitivity(self.h, ctypes.byref(cp), ctypes.c_void_p(ptr), 1,
+                                                      _stream_ptr(stream)))
+        return out
+
+    def set_gamma_loc(self, tensor_id: int, gamma_loc, stream=None):
+        """ggf_set_gamma_loc: new on-site covariance for a tensor; its chains are refactorised."""
+        g = np.ascontiguousarray(np.asarray(gamma_loc, np.float64).reshape(10, 10))
+        self._check(self._lib.ggf_set_gamma_loc(self.h, int(tensor_id), g.ctypes.data_as(_dp), _stream_ptr(stream)))
+
     def set_lambda(self, tensor_id: int, c, stream=None):
         """ggf_set_lambda: new amplitudes lambda_n (complex [K]) for a tensor; S(G) recomputed."""
         c = np.asarray(c, complex)
@@ -377,4 +401,20 @@ def lambda_step(K: int, rows):
     if st != GGF_OK:
         raise GGFError(st, f"ggf_lambda_step failed ({_STATUS.get(st, st)})")
     return e.value, lr + 1j * li
+
+
+def gamma_gradient(gamma_loc, energy_rows, sens_rows):
+    """ggf_gamma_gradient on host rows: the antisymmetric 10 x 10 gradient of <H>."""
+    lib = load()
+    g = np.ascontiguousarray(np.asarray(gamma_loc, np.float64).reshape(10, 10))
+    er = np.ascontiguousarray(np.asarray(energy_rows, np.float64).reshape(-1, GGF_ENERGY_STRIDE))
+    sr = np.ascontiguousarray(np.asarray(sens_rows, np.float64).reshape(-1, GGF_SENS_STRIDE))
+    if er.shape[0] != sr.shape[0]:
+        raise ValueError("energy and sensitivity rows must describe the same samples")
+    out = np.zeros((10, 10))
+    st = lib.ggf_gamma_gradient(None, g.ctypes.data_as(_dp), er.ctypes.data_as(_dp), sr.ctypes.data_as(_dp),
+                                er.shape[0], out.ctypes.data_as(_dp))
+    if st != GGF_OK:
+        raise GGFError(st, f"ggf_gamma_gradient failed ({_STATUS.get(st, st)})")
+    return out
 

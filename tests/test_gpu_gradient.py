@@ -1,0 +1,95 @@
+"""Gradient of <H> with respect to the on-site covariance on the GPU (K = 1) against the oracle.
+
+ggf_measure_sensitivity returns per chain S_e (real part) and S_N with
+d Re e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N) for Delta = [E, Gamma_A].
+The oracle builds them with dense NumPy products of a fresh float64 inverse and
+reads the electric slopes off its own mixed occupation; its sensitivities are
+pinned against finite differences and its gradient against the exactly
+enumerated <H> (tests/test_oracle_energy.py).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import ansatz_for, gpu_context, say, spec_for
+from oracle import energy as en
+
+pytestmark = pytest.mark.gpu
+
+CP = dict(t=0.7, mu=0.3, m=0.45, kb=-0.8, ke=1.3)
+
+
+def _check_sens(row, an, links, tol):
+    _, Se, SN = en.sensitivities(an, links, en.Couplings(**CP))
+    got_e = row[:100].reshape(10, 10)
+    got_n = row[100:].reshape(10, 10)
+    scale = max(1.0, np.abs(Se.real).max())
+    assert np.abs(got_e - Se.real).max() <= tol * scale, np.abs(got_e - Se.real).max()
+    assert np.abs(got_n - SN).max() <= tol * max(1.0, np.abs(SN).max())
+
+
+@pytest.mark.parametrize("L,group,precision", [(2, 2, 64), (4, 3, 64), (6, 2, 64), (4, 2, 32)])
+def test_sensitivity_rows(L, group, precision):
+    say(f"sensitivities L={L} Z{group} float{precision}")
+    spec = spec_for(L, 1, group)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * 2, init=1, precision=precision, refresh_every=16 if precision == 32 else 0)
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    tol = 1e-10 if precision == 64 else 2e-5
+    for c in range(2):
+        _check_sens(rows[c], an, ctx.get_state(c)[0], tol)
+    ctx.close()
+
+
+def test_sensitivity_full_size_sampled():
+    """4096 chains of 8x8 Z2 (float64) in one launch; two chains checked, every row finite."""
+    L, chains = 8, 4096
+    say(f"sensitivities full size L={L} chains={chains}")
+    spec = spec_for(L, 1, 2)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * chains, init=1)
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    assert np.all(np.isfinite(rows))
+    for c in (0, chains - 1):
+        _check_sens(rows[c], an, ctx.get_state(c)[0], 1e-10)
+    ctx.close()
+
+
+def test_gradient_end_to_end_and_update():
+    """GPU rows -> library gradient = oracle gradient from oracle sensitivities of the same link
+    fields; then a step exp(-eta g) on Gamma_A through ggf_set_gamma_loc refactorises the chains
+    to the oracle's log W of the new tensor."""
+    from paper_2412_01737_amd.ggf import gamma_gradient
+    say("gradient end to end L=4 Z2")
+    L, chains = 4, 6
+    spec = spec_for(L, 1, 2)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * chains, init=1)
+    ctx.sweep(2)
+    er = ctx.measure_energy(CP)
+    sr = ctx.measure_sensitivity(CP)
+    g = gamma_gradient(spec.gamma_loc, er, sr)
+    es, Ses, SNs = [], [], []
+    for c in range(chains):
+        e, Se, SN = en.sensitivities(an, ctx.get_state(c)[0], en.Couplings(**CP))
+        es.append(e.real)
+        Ses.append(Se.real)
+        SNs.append(SN)
+    ref = en.gradient_from_samples(spec.gamma_loc, es, Ses, SNs)
+    assert np.abs(g - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+    new = en.rotated_gamma_loc(spec.gamma_loc, -0.05 * g / max(1e-12, np.abs(g).max()))
+    ctx.set_gamma_loc(0, new)
+    an2 = ansatz_for(dataclasses.replace(spec, gamma_loc=new), L)
+    for c in range(chains):
+        links, info = ctx.get_state(c)
+        lw = an2.log_weight(links)
+        assert abs(info["logw"] - lw) <= 1e-10 * abs(lw)
+    rows = ctx.measure_energy(CP)
+    for c in range(chains):
+        e = en.local_energy(an2, ctx.get_state(c)[0], en.Couplings(**CP))
+        assert abs(rows[c, 0] - e.real) <= 1e-10 * max(1.0, abs(e))
+    ctx.close()

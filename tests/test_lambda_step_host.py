@@ -51,3 +51,20 @@ def test_lambda_step_rejects_bad_input():
     rows[:, 1] = np.nan
     with pytest.raises(GGFError):
         lambda_step(1, rows)
+
+
+def test_gamma_gradient_matches_oracle():
+    """ggf_gamma_gradient (host) against the oracle's combination of per-sample sensitivities."""
+    import synth
+    from oracle.energy import gradient_from_samples
+    from paper_2412_01737_amd.ggf import GGF_ENERGY_STRIDE, GGF_SENS_STRIDE, gamma_gradient
+    rng = np.random.default_rng(90)
+    n = 23
+    g = synth.local_gamma()
+    er = np.zeros((n, GGF_ENERGY_STRIDE))
+    er[:, 0] = rng.standard_normal(n)
+    sr = rng.standard_normal((n, GGF_SENS_STRIDE))
+    out = gamma_gradient(g, er, sr)
+    ref = gradient_from_samples(g, er[:, 0], sr[:, :100].reshape(n, 10, 10), sr[:, 100:].reshape(n, 10, 10))
+    assert np.abs(out - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.abs(out + out.T).max() < 1e-14
