@@ -1018,9 +1018,12 @@ __device__ inline void h_term(const EnergyCp &cp, const int8_t *lk, int L, int g
 //   S_e[d-block]  = sum_z (P^T C P)[z, z]^T + ke sum_l sum_{i<j} R_k[j][i] G[z, u_j] (x) G[z, u_i],
 //   S_N[d-block]  = (1/2) sum_x G[x, x]  (log N = (1/2) log det M + const).
 // out[c][0..99] = Re S_e, out[c][100..199] = S_N (row-major 10 x 10).  L <= 16.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double *out) {
-  extern __shared__ double s_U[];            // U_z[i][2w + a] = sum_j G[8z+i][8w+j] b[a][j], 8 x 2V
+// STAGE: the 8 rows of stripe z are staged in LDS (8 n float64 after U_z's 16 max_sites).
+template <typename T, bool STAGE>
+__global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double *out, int max_sites) {
+  extern __shared__ double s_dyn[];
+  double *s_U = s_dyn;                       // U_z[i][2w + a] = sum_j G[8z+i][8w+j] b[a][j], 8 x 2V
+  double *s_G = s_dyn + 16 * max_sites;      // stripe z, 8 x n (STAGE)
   __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
   __shared__ double s_R[GGF_ZN_MAX][16];
   __shared__ double s_red[4][64];
@@ -1128,11 +1131,21 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
   double sd = 0.0;
   for (int z = 0; z < V; ++z) {
     __syncthreads();
+    if (STAGE) {
+      for (int e = tid; e < 8 * n; e += blockDim.x)
+        s_G[e] = static_cast<double>(G[static_cast<size_t>(8 * z) * n + e]);
+      __syncthreads();
+    }
     for (int e = tid; e < 16 * V; e += blockDim.x) {
       const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, a = col & 1;
-      const T *grow = G + static_cast<size_t>(8 * z + i) * n + 8 * w;
       double v = 0.0;
-      for (int j = 0; j < 8; ++j) v += static_cast<double>(grow[j]) * Tn.b[a * 8 + j];
+      if (STAGE) {
+        const double *grow = s_G + i * n + 8 * w;
+        for (int j = 0; j < 8; ++j) v += grow[j] * Tn.b[a * 8 + j];
+      } else {
+        const T *grow = G + static_cast<size_t>(8 * z + i) * n + 8 * w;
+        for (int j = 0; j < 8; ++j) v += static_cast<double>(grow[j]) * Tn.b[a * 8 + j];
+      }
       s_U[i * 2 * V + col] = v;
     }
     __syncthreads();
@@ -1151,11 +1164,18 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
         int u[4];
         ggf_link_u(ell, L, u);
         const double *R = s_R[lk[ell]];
-        const T *gp = G + static_cast<size_t>(8 * z + pj) * n;   // G[8z + p][.], p = the column index of S
-        const T *gq = G + static_cast<size_t>(8 * z + pi) * n;   // G[8z + q][.]
+        double vp[4], vq[4];   // G[8z + pj][u], G[8z + pi][u] (S_d[pj][pi] collects the sum)
+        for (int i = 0; i < 4; ++i) {
+          if (STAGE) {
+            vp[i] = s_G[pj * n + u[i]];
+            vq[i] = s_G[pi * n + u[i]];
+          } else {
+            vp[i] = static_cast<double>(G[static_cast<size_t>(8 * z + pj) * n + u[i]]);
+            vq[i] = static_cast<double>(G[static_cast<size_t>(8 * z + pi) * n + u[i]]);
+          }
+        }
         for (int i = 0; i < 4; ++i)
-          for (int j = i + 1; j < 4; ++j)
-            acc += cp.ke * R[j * 4 + i] * static_cast<double>(gp[u[j]]) * static_cast<double>(gq[u[i]]);
+          for (int j = i + 1; j < 4; ++j) acc += cp.ke * R[j * 4 + i] * vp[j] * vq[i];
       }
     sd += acc;   // (P^T C P)[z][pi][pj] + electric part; S_d[pj][pi] collects it
   }
@@ -1265,11 +1285,18 @@ void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int
 }
 
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites) {
-  const size_t lds = static_cast<size_t>(16) * max_sites * sizeof(double);
-  if (lc.precision == 64)
-    hipLaunchKernelGGL(k_sens<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
-  else
-    hipLaunchKernelGGL(k_sens<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
+  // stage each row stripe (8 n = 64 V float64) in LDS while it and U_z fit in 64 KB (V <= 102)
+  const size_t lds_u = static_cast<size_t>(16) * max_sites * sizeof(double);
+  const size_t lds_g = static_cast<size_t>(64) * max_sites * sizeof(double);
+  const bool stage = lds_u + lds_g <= 65536;
+  const dim3 grid(lc.n_chains), block(256);
+  if (lc.precision == 64) {
+    if (stage) hipLaunchKernelGGL((k_sens<double, true>), grid, block, lds_u + lds_g, lc.stream, lc, cp, out, max_sites);
+    else hipLaunchKernelGGL((k_sens<double, false>), grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
+  } else {
+    if (stage) hipLaunchKernelGGL((k_sens<float, true>), grid, block, lds_u + lds_g, lc.stream, lc, cp, out, max_sites);
+    else hipLaunchKernelGGL((k_sens<float, false>), grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
+  }
 }
 
 void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kmax) {
