@@ -136,3 +136,46 @@ def test_optimise_lambda_rounds():
         S = an.s_factor_def(links)
         assert abs(info["s_re"] - S.real) <= 1e-10 * abs(S.real)
     ctx.close()
+
+
+def test_energy_entry_points_reject_bad_input():
+    """The variational entry points validate their arguments before any launch."""
+    from paper_2412_01737_amd.ggf import Context, GGFError, GGF_EINVAL, GGF_ESTATE
+    say("energy entry points: invalid input")
+    ctx = Context(0)
+    spec1, spec3 = spec_for(4, 1, 2), spec_for(2, 3, 2)
+    t1 = ctx.set_tensor_spec(spec1)
+    t3 = ctx.set_tensor_spec(spec3)
+    with pytest.raises(GGFError) as e:
+        ctx.measure_energy(CP)
+    assert e.value.status == GGF_ESTATE
+    ctx.init_chains([4, 2], [t1, t3], 1, init=1)
+    with pytest.raises(GGFError) as e:
+        ctx.measure_energy(dict(CP, t=float("nan")))
+    assert e.value.status == GGF_EINVAL
+    with pytest.raises(GGFError) as e:            # a K = 3 chain in the context
+        ctx.measure_sensitivity(CP)
+    assert e.value.status == GGF_EINVAL
+    with pytest.raises(GGFError):
+        ctx.set_lambda(t3 + 5, [1.0, 0.0, 0.0])
+    with pytest.raises(GGFError):
+        ctx.set_lambda(t3, [0.0, 0.0, 0.0])
+    with pytest.raises(GGFError):
+        ctx.set_lambda(t3, [1.0, float("inf"), 0.0])
+    bad = spec1.gamma_loc.copy()
+    bad[0, 1] += 0.1
+    with pytest.raises(GGFError):
+        ctx.set_gamma_loc(t1, bad)
+    with pytest.raises(GGFError):
+        ctx.optimise_lambda(t3, CP, 0, 1, 3)
+    ctx.set_lambda(t1, [2.0])                    # K = 1: lambda only scales the state; no change
+    rows = ctx.measure_energy(CP)
+    assert np.all(np.isfinite(rows[:, 0]))
+    ctx.close()
+    big = Context(0)
+    tb = big.set_tensor_spec(spec_for(18, 1, 2))
+    big.init_chains([18], [tb], 1)
+    with pytest.raises(GGFError) as e:            # sensitivities need L <= 16
+        big.measure_sensitivity(CP)
+    assert e.value.status == GGF_EINVAL
+    big.close()

@@ -190,3 +190,27 @@ def test_gradient_against_exact_energy(group):
         fd = (_exact_energy(lat, en.rotated_gamma_loc(spec.gamma_loc, h * E), spec.gamma_bond, group)
               - _exact_energy(lat, en.rotated_gamma_loc(spec.gamma_loc, -h * E), spec.gamma_bond, group)) / (2 * h)
         assert abs(g[a, b] - fd) <= 1e-7 * max(1.0, abs(fd)), (a, b, g[a, b], fd)
+
+
+@pytest.mark.parametrize("group", [2, 3])
+def test_bond_phase_is_an_on_site_rotation(group):
+    """The one free parameter of an out-in coupled pure bond, the phase of its out mode, is
+    absorbed by Gamma_A: rotating the bond's out pair by phi equals rotating the right and up
+    virtual pairs of Gamma_A by -phi (same W(G) and E_loc(G) for every G).  So
+    d<H>/d phi = -(g[r0, r1] + g[u0, u1]) in terms of the Gamma_A gradient."""
+    from oracle.lattice import VSLOT_R, VSLOT_U
+    from oracle.model import rotation
+    lat = Lattice(2, 2)
+    spec = synth.make_tensor(2, K=1, group=group)
+    phi = 0.37
+    o = np.eye(4)
+    o[0:2, 0:2] = rotation(phi)
+    a1 = Ansatz(lat, spec.gamma_loc, o @ spec.gamma_bond @ o.T, group)
+    X = np.zeros((10, 10))
+    for slot in (VSLOT_R, VSLOT_U):
+        X -= phi * en.generator(2 + 2 * slot, 3 + 2 * slot)
+    a2 = Ansatz(lat, en.rotated_gamma_loc(spec.gamma_loc, X), spec.gamma_bond, group)
+    for G in itertools.islice(itertools.product(range(group), repeat=lat.n_links), 0, None, 7):
+        k = np.array(G)
+        assert abs(a1.log_weight(k) - a2.log_weight(k)) < 1e-12
+        assert abs(en.local_energy(a1, k, CP) - en.local_energy(a2, k, CP)) < 1e-11
