@@ -1067,14 +1067,13 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
   for (int x = tid; x < V; x += blockDim.x) {
     double sb[16];
     for (int q = 0; q < 16; ++q) sb[q] = 0.0;
-    for (int term = 0; term < 5; ++term) {
+    {
+      // a-block: the on-site term's block, transposed
       int w, y;
       double o[4];
-      h_term(cp, lk, L, group, x, term, w, y, o);
-      if (term == 0) {
-        for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b) atomicAdd(&s_Sa[b * 2 + a], o[a * 2 + b]);
-      }
+      h_term(cp, lk, L, group, x, 0, w, y, o);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) atomicAdd(&s_Sa[b * 2 + a], o[a * 2 + b]);
     }
     // blocks with row site x: (x, y) for y = x, x + mu (hop) and x - mu (reverse of the hop into x)
     // blocks with column site x: (w, x) for w = x, x - mu (hop) and x + mu (reverse)
