@@ -58,7 +58,7 @@ typedef enum {
  * All host pointers, row-major float64; the library copies them and the caller
  * keeps ownership. */
 typedef struct {
-  int32_t group;              /* 2 = Z2, 3 = Z3 */
+  int32_t group;              /* N of the gauge group Z_N, 2 <= N <= 64 (2 = Z2, 3 = Z3) */
   const double *gamma_loc;    /* 10x10 on-site covariance, Majorana order (p,l,u,r,d) x (0,1);
                                  real antisymmetric with Gamma^2 = -1 */
   const double *gamma_bond;   /* 4x4 reference bond b_0 on every link, order (out0,out1,in0,in1);

@@ -2,8 +2,8 @@
 p(G) = N(G)/N, sampled without a sign problem).
 
 The paper names no sampler; the reading used here is single-link Metropolis:
-a sweep visits links 0 .. 2V-1 in order; Z2 proposes k -> 1-k, Z3 proposes
-k -> (k + 1 + (x2 & 1)) mod 3; the proposal is accepted iff u < N(G')/N(G)
+a sweep visits links 0 .. 2V-1 in order; Z_N proposes k -> (k + 1 + (x2 mod (N-1))) mod N
+(Z2: k -> 1-k; Z3: k -> (k + 1 + (x2 & 1)) mod 3); the proposal is accepted iff u < N(G')/N(G)
 (strict), with (u, x2) from Philox at counter (chain, sweep, link, 0).
 A cold start has every k = 0; a hot start takes k = x0 mod N from Philox at
 counter (chain, 0xffffffff, link, 1).
@@ -35,7 +35,7 @@ def hot_links(seed: int, chain: int, n_links: int, group: int) -> np.ndarray:
 
 
 def propose(k: int, step: int, group: int) -> int:
-    return (k + (1 if group == 2 else step)) % group
+    return (k + step) % group
 
 
 def delta_uu(an: Ansatz, k_old: int, k_new: int) -> np.ndarray:
@@ -68,7 +68,7 @@ class DefinitionChain:
     def sweep(self):
         an = self.an
         for ell in range(an.lat.n_links):
-            u, step = philox.draw(self.seed, self.chain, self.sweep_idx, ell)
+            u, step = philox.draw(self.seed, self.chain, self.sweep_idx, ell, an.group)
             knew = self.k.copy()
             knew[ell] = propose(int(self.k[ell]), int(step), an.group)
             ln_new = self._logn(knew)
@@ -141,7 +141,7 @@ class WoodburyChain:
     def sweep(self):
         an = self.an
         for ell in range(an.lat.n_links):
-            u, step = philox.draw(self.seed, self.chain, self.sweep_idx, ell)
+            u, step = philox.draw(self.seed, self.chain, self.sweep_idx, ell, an.group)
             k_new = propose(int(self.k[ell]), int(step), an.group)
             R, rho, s_new, dm = self.ratio(ell, k_new)
             self.proposals += 1

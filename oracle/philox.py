@@ -9,9 +9,9 @@ rounds.  Ten rounds are applied.
 
 The Metropolis sampler draws one Philox block per (chain, sweep, link):
 key = (seed & 0xffffffff, seed >> 32), counter = (chain, sweep, link, 0).
-The uniform is u = (((x1 << 32) | x0) >> 11) * 2^-53 in [0, 1), and the Z3
-proposal step is 1 + (x2 & 1).  This is the sampler reading for Sec. 5.1 (the
-paper does not name a sampler).
+The uniform is u = (((x1 << 32) | x0) >> 11) * 2^-53 in [0, 1), and the Z_N
+proposal step is 1 + (x2 mod (N - 1)) (1 for Z2, 1 + (x2 & 1) for Z3).  This is
+the sampler reading for Sec. 5.1 (the paper does not name a sampler).
 """
 from __future__ import annotations
 
@@ -68,9 +68,10 @@ def uniform_from_words(x0, x1):
     return bits.astype(np.float64) * (2.0 ** -53)
 
 
-def draw(seed: int, chain, sweep, link):
-    """(u, z3_step) for the proposal at (chain, sweep, link); arrays broadcast."""
+def draw(seed: int, chain, sweep, link, group: int = 3):
+    """(u, step) for the Z_N proposal at (chain, sweep, link); arrays broadcast.  The step
+    1 + (x2 mod (N - 1)) is uniform over the N - 1 other elements (symmetric proposal)."""
     x0, x1, x2, _ = philox_vec(chain, sweep, link, 0, seed & MASK, (seed >> 32) & MASK)
     u = uniform_from_words(x0, x1)
-    step = 1 + (x2 & np.uint64(1)).astype(np.int64)
+    step = 1 + (x2 % np.uint64(group - 1)).astype(np.int64)
     return u, step

@@ -513,7 +513,7 @@ ggf_status ggf_create(ggf_ctx **out, int device) {
 ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tensor_id_out) {
   if (!ctx) return GGF_EINVAL;
   if (!d || !tensor_id_out || !d->gamma_loc || !d->gamma_bond) return fail(ctx, GGF_EINVAL, "null descriptor field");
-  if (d->group < 2 || d->group > GGF_ZN_MAX) return fail(ctx, GGF_EINVAL, "group must be 2 or 3");
+  if (d->group < 2 || d->group > GGF_ZN_MAX) return fail(ctx, GGF_EINVAL, "group must be in 2..64");
   if (d->K < 1 || d->K > GGF_KMAX) return fail(ctx, GGF_EINVAL, "K must be in 1..GGF_KMAX");
   if (d->K > 1 && (!d->patch_link || !d->gamma_bond_k || !d->c_re || !d->c_im))
     return fail(ctx, GGF_EINVAL, "K > 1 needs patch_link, gamma_bond_k, c_re, c_im");

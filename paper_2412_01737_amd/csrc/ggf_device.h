@@ -16,7 +16,7 @@
 #define GGF_KMAX_DEV 4
 #define GGF_NOBS_DEV 21
 #define GGF_MAX_MESON 16
-#define GGF_ZN_MAX 3       // largest gauge group Z_N
+#define GGF_ZN_MAX 64      // largest gauge group Z_N (link values are int8)
 #define GGF_ENERGY_STRIDE_DEV (1 + 4 * GGF_KMAX_DEV * GGF_KMAX_DEV)
 #define GGF_SENS_STRIDE_DEV 200
 

@@ -171,7 +171,8 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
     const int kold = lk[ell];
     const uint4 x = ggf_philox(make_uint4(static_cast<uint32_t>(c), lc.sweep[c], static_cast<uint32_t>(ell), 0u),
                                lc.key0, lc.key1);
-    const int kn = (ch.group == 2) ? (1 - kold) : (kold + 1 + static_cast<int>(x.z & 1u)) % 3;
+    // Z_N proposal: a step of 1 + (x.z mod (N - 1)), uniform over the other N - 1 elements
+    const int kn = (kold + 1 + static_cast<int>(x.z % static_cast<uint32_t>(ch.group - 1))) % ch.group;
     double yo[4], yn[4];
     ggf_bond_block(Tn.x0, kold, ch.group, yo);
     ggf_bond_block(Tn.x0, kn, ch.group, yn);
@@ -836,9 +837,9 @@ __global__ __launch_bounds__(128) void k_electric1(LaunchCtx lc, double *out) {
   const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
   const T *G = static_cast<const T *>(lc.G) + ch.g_off;
   const int8_t *lk = lc.links + ch.link_off;
-  if (threadIdx.x < 16 * group) {
+  for (int te = threadIdx.x; te < 16 * group; te += blockDim.x) {
     // entry e of Re(O_k eq0 O_k^T), unrolled with constant indices (no private-array scratch)
-    const int k = threadIdx.x >> 4, e = threadIdx.x & 15;
+    const int k = te >> 4, e = te & 15;
     double co = 1.0, si = 0.0;
     if (k != 0) {
       if (group == 2) co = -1.0;
@@ -1037,8 +1038,8 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
   if (tid < 4) s_Sa[tid] = 0.0;
   if (tid < 16) s_Sb[tid] = 0.0;
   if (tid < 64) s_SN[tid] = 0.0;
-  if (tid < 16 * group) {
-    const int k = tid >> 4, e = tid & 15;
+  for (int te = tid; te < 16 * group; te += blockDim.x) {
+    const int k = te >> 4, e = te & 15;
     double co = 1.0, si = 0.0;
     if (k != 0) {
       if (group == 2) co = -1.0;

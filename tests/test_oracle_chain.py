@@ -112,11 +112,19 @@ def test_synthetic_inputs():
 
 
 def test_proposal_rule_table():
-    """Z2 flips; Z3 moves k -> k + step (mod 3) with step = 1 + (x2 & 1) from the chain's Philox block."""
+    """Z_N moves k -> k + step (mod N) with step = 1 + (x2 mod (N - 1)) from the chain's Philox
+    block: Z2 flips, Z3 steps by 1 + (x2 & 1), and the step is uniform over the N - 1 other
+    elements (a symmetric proposal)."""
     from oracle.chain import propose
     from oracle import philox
-    assert [propose(k, s, 2) for k in (0, 1) for s in (1, 2)] == [1, 1, 0, 0]
+    assert [propose(k, 1, 2) for k in (0, 1)] == [1, 0]
     assert [propose(k, s, 3) for k in (0, 1, 2) for s in (1, 2)] == [1, 2, 2, 0, 0, 1]
     x = philox.philox4x32_10((2, 5, 11, 0), (synth.SEED_CHAIN, 0))
     _, step = philox.draw(synth.SEED_CHAIN, 2, 5, 11)
     assert int(step) == 1 + (x[2] & 1)
+    _, step2 = philox.draw(synth.SEED_CHAIN, 2, 5, 11, 2)
+    assert int(step2) == 1
+    _, s5 = philox.draw(synth.SEED_CHAIN, np.arange(8000), 3, 7, 5)
+    counts = np.bincount(s5, minlength=6)
+    assert counts[0] == 0 and counts[5] == 0
+    assert np.all(np.abs(counts[1:5] - 2000) < 200)
