@@ -691,13 +691,19 @@ __device__ inline double2 mixed_occupation(const T *G, int n, const TensorDev &T
     double vs[4][8];
     for (int i = 0; i < 4; ++i)
       for (int q = 0; q < s; ++q) vs[i][q] = static_cast<double>(G[static_cast<size_t>(u[i]) * n + S[q]]);
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      double2 vy[8];   // (G_US Y)[i][q]
+      for (int q = 0; q < s; ++q) {
+        double2 v = make_double2(0.0, 0.0);
+        for (int p = 0; p < s; ++p) v = cadd(v, cscale(Y[p * 8 + q], vs[i][p]));
+        vy[q] = v;
+      }
       for (int j = 0; j < 4; ++j) {
         double2 v = make_double2(0.0, 0.0);
-        for (int p = 0; p < s; ++p)
-          for (int q = 0; q < s; ++q) v = cadd(v, cscale(Y[p * 8 + q], vs[i][p] * vs[j][q]));
+        for (int q = 0; q < s; ++q) v = cadd(v, cscale(vy[q], vs[j][q]));
         gm[i * 4 + j] = cadd(gm[i * 4 + j], v);
       }
+    }
   }
   const double2 *eq = Tn.eq0;
   double2 x = Tn.en0;
