@@ -87,6 +87,10 @@ def parse():
                     help="after the timed sweeps, rounds of the variational optimisation of lambda (K > 1 "
                          "workloads; --lambda-sweeps sweeps per round), reported under 'lambda_opt'")
     ap.add_argument("--lambda-sweeps", type=int, default=2)
+    ap.add_argument("--gamma-iters", type=int, default=0,
+                    help="after the timed sweeps, rounds of gradient descent on Gamma_A (K = 1 workloads, "
+                         "L <= 16; --lambda-sweeps sweeps per round, --gamma-step), reported under 'gamma_opt'")
+    ap.add_argument("--gamma-step", type=float, default=0.01)
     ap.add_argument("--electric-traffic-from", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="derive the electric measurement kernel's HBM bytes per launch from rocprofv3 --pmc "
@@ -708,6 +712,16 @@ def main():
                       "s_per_round": t_opt / args.lambda_iters, "energy_per_round": en_.tolist(),
                       "optimum_per_round": eo_.tolist(), "lambda_re": lam_.real.tolist(),
                       "lambda_im": lam_.imag.tolist(), "couplings": BENCH_COUPLINGS}
+    gamma_opt = None
+    if args.gamma_iters > 0 and args.workload != "c4" and args.K == 1 and args.L <= 16:
+        torch.cuda.synchronize()
+        t_opt = time.perf_counter()
+        en_, gn_, _ = ctx.optimise_gamma(int(tids), BENCH_COUPLINGS, args.gamma_iters, args.lambda_sweeps,
+                                         args.gamma_step, stream=stream)
+        t_opt = time.perf_counter() - t_opt
+        gamma_opt = {"rounds": args.gamma_iters, "sweeps_per_round": args.lambda_sweeps, "step": args.gamma_step,
+                     "s_per_round": t_opt / args.gamma_iters, "energy_per_round": en_.tolist(),
+                     "grad_norm_per_round": gn_.tolist(), "couplings": BENCH_COUPLINGS}
     timed_s = elapsed
     elapsed = elapsed + refresh["correction_ms"] * 1e-3
     proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
@@ -795,6 +809,7 @@ def main():
         "electric": electric,
         "energy": energy,
         "lambda_opt": lambda_opt,
+        "gamma_opt": gamma_opt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

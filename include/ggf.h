@@ -218,6 +218,19 @@ ggf_status ggf_gamma_gradient(ggf_ctx *ctx, const double *gamma_loc, const doubl
  * (float64), so that G, log W and S follow the new tensor.  Synchronous. */
 ggf_status ggf_set_gamma_loc(ggf_ctx *ctx, int32_t tensor_id, const double *gamma_loc, void *stream);
 
+/* Gradient descent on the on-site covariance Gamma_A (the outlook of Sec. 6.3;
+ * K = 1 chains, L <= 16): n_iters rounds of [n_sweeps sweeps, each followed by
+ * ggf_measure_energy and ggf_measure_sensitivity; ggf_gamma_gradient over the
+ * rows of the chains that use tensor_id; Gamma_A <- exp(X) Gamma_A exp(-X) with
+ * X = -step grad; ggf_set_gamma_loc].  energies[n_iters]: <H> estimated in each
+ * round with that round's Gamma_A; grad_norms[n_iters]: max |grad|;
+ * gamma_loc_out[10][10]: the last Gamma_A.  Synchronous; allocates
+ * n_sweeps x n_chains x (GGF_ENERGY_STRIDE + GGF_SENS_STRIDE) doubles of device
+ * memory for the call. */
+ggf_status ggf_optimise_gamma(ggf_ctx *ctx, int32_t tensor_id, const ggf_couplings *couplings, int32_t n_iters,
+                              int32_t n_sweeps, double step, double *energies, double *grad_norms,
+                              double *gamma_loc_out, void *stream);
+
 /* Synchronous read-back of one chain: link values (int8, 2V entries),
  * counters and scalars.  Any argument may be NULL. */
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info);

@@ -1146,6 +1146,129 @@ ggf_status ggf_set_gamma_loc(ggf_ctx *ctx, int32_t tensor_id, const double *gamm
   return factorize(ctx, which, 0, s);
 }
 
+namespace {
+
+// exp(X) of a real 10 x 10 matrix by scaling and squaring with a degree-16 Taylor polynomial
+// (X antisymmetric here, so the result is a rotation to rounding).
+void expm10(const double *X, double *R) {
+  double nrm = 0.0;
+  for (int i = 0; i < 100; ++i) nrm = std::max(nrm, std::fabs(X[i]));
+  int sq = 0;
+  while (nrm * 10.0 > 0.25 && sq < 60) { nrm *= 0.5; ++sq; }
+  const double scale = std::ldexp(1.0, -sq);
+  double A[100], T[100], U[100];
+  for (int i = 0; i < 100; ++i) { A[i] = X[i] * scale; R[i] = (i % 11 == 0) ? 1.0 : 0.0; T[i] = R[i]; }
+  for (int k = 1; k <= 16; ++k) {
+    for (int i = 0; i < 10; ++i)
+      for (int j = 0; j < 10; ++j) {
+        double v = 0.0;
+        for (int q = 0; q < 10; ++q) v += T[i * 10 + q] * A[q * 10 + j];
+        U[i * 10 + j] = v / k;
+      }
+    for (int i = 0; i < 100; ++i) { T[i] = U[i]; R[i] += U[i]; }
+  }
+  for (int s2 = 0; s2 < sq; ++s2) {
+    for (int i = 0; i < 10; ++i)
+      for (int j = 0; j < 10; ++j) {
+        double v = 0.0;
+        for (int q = 0; q < 10; ++q) v += R[i * 10 + q] * R[q * 10 + j];
+        U[i * 10 + j] = v;
+      }
+    for (int i = 0; i < 100; ++i) R[i] = U[i];
+  }
+}
+
+}  // namespace
+
+ggf_status ggf_optimise_gamma(ggf_ctx *ctx, int32_t tensor_id, const ggf_couplings *cp, int32_t n_iters,
+                              int32_t n_sweeps, double step, double *energies, double *grad_norms,
+                              double *gamma_loc_out, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(ctx->tensors.size()))
+    return fail(ctx, GGF_EINVAL, "bad tensor id");
+  if (!cp || n_iters < 1 || n_sweeps < 1 || !(std::isfinite(step) && step > 0.0) || !energies || !grad_norms ||
+      !gamma_loc_out)
+    return fail(ctx, GGF_EINVAL, "couplings, n_iters >= 1, n_sweeps >= 1, step > 0 and the outputs are required");
+  std::vector<int> which;
+  for (int c = 0; c < ctx->n_chains; ++c)
+    if (ctx->chains[c].tensor == tensor_id) which.push_back(c);
+  if (which.empty()) return fail(ctx, GGF_EINVAL, "no chain uses this tensor");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nc = static_cast<size_t>(ctx->n_chains);
+  double *dev_e = nullptr, *dev_s = nullptr;
+  HIP_TRY(ctx, hipMalloc(&dev_e, nc * GGF_ENERGY_STRIDE * sizeof(double) * n_sweeps));
+  hipError_t ea = hipMalloc(&dev_s, nc * GGF_SENS_STRIDE * sizeof(double) * n_sweeps);
+  if (ea != hipSuccess) {
+    hipFree(dev_e);
+    return fail(ctx, GGF_EDEVICE, std::string("optimise_gamma: ") + hipGetErrorString(ea));
+  }
+  std::vector<double> he(nc * GGF_ENERGY_STRIDE * n_sweeps), hs(nc * GGF_SENS_STRIDE * n_sweeps);
+  std::vector<double> re(which.size() * GGF_ENERGY_STRIDE * n_sweeps), rs(which.size() * GGF_SENS_STRIDE * n_sweeps);
+  ggf_status st = GGF_OK;
+  for (int it = 0; it < n_iters && st == GGF_OK; ++it) {
+    for (int sw = 0; sw < n_sweeps && st == GGF_OK; ++sw) {
+      st = ggf_sweep(ctx, 1, stream);
+      if (st == GGF_OK) st = ggf_measure_energy(ctx, cp, dev_e + sw * nc * GGF_ENERGY_STRIDE, 1, stream);
+      if (st == GGF_OK) st = ggf_measure_sensitivity(ctx, cp, dev_s + sw * nc * GGF_SENS_STRIDE, 1, stream);
+    }
+    if (st != GGF_OK) break;
+    hipError_t e = hipMemcpyAsync(he.data(), dev_e, he.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), dev_s, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      st = fail(ctx, GGF_EDEVICE, std::string("optimise_gamma: ") + hipGetErrorString(e));
+      break;
+    }
+    size_t r = 0;
+    double esum = 0.0;
+    for (int sw = 0; sw < n_sweeps; ++sw)
+      for (int c : which) {
+        const double *se = he.data() + (sw * nc + c) * GGF_ENERGY_STRIDE;
+        const double *ss = hs.data() + (sw * nc + c) * GGF_SENS_STRIDE;
+        std::copy(se, se + GGF_ENERGY_STRIDE, re.data() + r * GGF_ENERGY_STRIDE);
+        std::copy(ss, ss + GGF_SENS_STRIDE, rs.data() + r * GGF_SENS_STRIDE);
+        esum += se[0];
+        ++r;
+      }
+    energies[it] = esum / static_cast<double>(r);
+    // current Gamma_A of the tensor
+    const TensorDev &t = ctx->tensors[tensor_id];
+    double gam[100], grad[100], X[100], R[100], nxt[100];
+    for (int i = 0; i < 100; ++i) gam[i] = 0.0;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) gam[i * 10 + j] = t.a[i * 2 + j];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 8; ++j) {
+        gam[i * 10 + 2 + j] = t.b[i * 8 + j];
+        gam[(2 + j) * 10 + i] = -t.b[i * 8 + j];
+      }
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) gam[(2 + i) * 10 + 2 + j] = t.d[i * 8 + j];
+    st = ggf_gamma_gradient(ctx, gam, re.data(), rs.data(), static_cast<int64_t>(r), grad);
+    if (st != GGF_OK) break;
+    double gn = 0.0;
+    for (int i = 0; i < 100; ++i) gn = std::max(gn, std::fabs(grad[i]));
+    grad_norms[it] = gn;
+    // descent step: theta_kl = -step g_kl, Gamma <- exp(X) Gamma exp(-X), X = -step g
+    for (int i = 0; i < 100; ++i) X[i] = -step * grad[i];
+    expm10(X, R);
+    for (int i = 0; i < 10; ++i)
+      for (int j = 0; j < 10; ++j) {
+        double v = 0.0;
+        for (int p = 0; p < 10; ++p)
+          for (int q = 0; q < 10; ++q) v += R[i * 10 + p] * gam[p * 10 + q] * R[j * 10 + q];
+        nxt[i * 10 + j] = v;
+      }
+    for (int i = 0; i < 10; ++i)   // exact antisymmetry (the purity check allows 1e-8)
+      for (int j = 0; j < 10; ++j) gamma_loc_out[i * 10 + j] = 0.5 * (nxt[i * 10 + j] - nxt[j * 10 + i]);
+    st = ggf_set_gamma_loc(ctx, tensor_id, gamma_loc_out, stream);
+  }
+  hipFree(dev_e);
+  hipFree(dev_s);
+  return st;
+}
+
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info) {
   if (!ctx) return GGF_EINVAL;
   if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");

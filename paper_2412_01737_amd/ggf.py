@@ -66,6 +66,8 @@ EXPORTS = {
                                                ctypes.c_int32, ctypes.c_void_p]),
     "ggf_gamma_gradient": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int64, _dp]),
     "ggf_set_gamma_loc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_void_p]),
+    "ggf_optimise_gamma": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Couplings), ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp, ctypes.c_void_p]),
     "ggf_set_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, ctypes.c_void_p]),
     "ggf_lambda_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_int64, _dp, _dp, _dp]),
     "ggf_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ChainInfo)]),
@@ -252,6 +254,17 @@ class Context:
         """ggf_set_gamma_loc: new on-site covariance for a tensor; its chains are refactorised."""
         g = np.ascontiguousarray(np.asarray(gamma_loc, np.float64).reshape(10, 10))
         self._check(self._lib.ggf_set_gamma_loc(self.h, int(tensor_id), g.ctypes.data_as(_dp), _stream_ptr(stream)))
+
+    def optimise_gamma(self, tensor_id: int, couplings, n_iters: int, n_sweeps: int, step: float, stream=None):
+        """ggf_optimise_gamma: (energies [n_iters], grad_norms [n_iters], final Gamma_A 10 x 10)."""
+        cp = couplings if isinstance(couplings, Couplings) else Couplings(**dict(couplings))
+        en = np.zeros(n_iters)
+        gn = np.zeros(n_iters)
+        g = np.zeros((10, 10))
+        self._check(self._lib.ggf_optimise_gamma(self.h, int(tensor_id), ctypes.byref(cp), int(n_iters), int(n_sweeps),
+                                                 float(step), en.ctypes.data_as(_dp), gn.ctypes.data_as(_dp),
+                                                 g.ctypes.data_as(_dp), _stream_ptr(stream)))
+        return en, gn, g
 
     def set_lambda(self, tensor_id: int, c, stream=None):
         """ggf_set_lambda: new amplitudes lambda_n (complex [K]) for a tensor; S(G) recomputed."""

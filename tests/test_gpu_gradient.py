@@ -93,3 +93,35 @@ def test_gradient_end_to_end_and_update():
         e = en.local_energy(an2, ctx.get_state(c)[0], en.Couplings(**CP))
         assert abs(rows[c, 0] - e.real) <= 1e-10 * max(1.0, abs(e))
     ctx.close()
+
+
+def test_optimise_gamma_round():
+    """One round of ggf_optimise_gamma (one sweep): the returned Gamma_A is the oracle's
+    exp(-eta g) Gamma_A exp(eta g) for the gradient the oracle computes on the same link fields,
+    and the chains are refactorised to it.  Then a second call runs two more rounds."""
+    say("optimise gamma L=4 Z2")
+    L, chains, eta = 4, 8, 0.02
+    spec = spec_for(L, 1, 2)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * chains, init=1)
+    energies, gnorm, g_new = ctx.optimise_gamma(0, CP, 1, 1, eta)
+    es, Ses, SNs = [], [], []
+    for c in range(chains):
+        e, Se, SN = en.sensitivities(an, ctx.get_state(c)[0], en.Couplings(**CP))
+        es.append(e.real)
+        Ses.append(Se.real)
+        SNs.append(SN)
+    g = en.gradient_from_samples(spec.gamma_loc, es, Ses, SNs)
+    assert abs(energies[0] - np.mean(es)) <= 1e-10 * max(1.0, abs(np.mean(es)))
+    assert abs(gnorm[0] - np.abs(g).max()) <= 1e-9 * max(1.0, np.abs(g).max())
+    expect = en.rotated_gamma_loc(spec.gamma_loc, -eta * g)
+    assert np.abs(g_new - expect).max() < 1e-10
+    assert np.abs(g_new @ g_new + np.eye(10)).max() < 1e-10
+    an2 = ansatz_for(dataclasses.replace(spec, gamma_loc=g_new), L)
+    for c in range(chains):
+        links, info = ctx.get_state(c)
+        lw = an2.log_weight(links)
+        assert abs(info["logw"] - lw) <= 1e-10 * abs(lw)
+    energies2, gnorm2, _ = ctx.optimise_gamma(0, CP, 2, 1, eta)
+    assert np.all(np.isfinite(energies2)) and np.all(np.isfinite(gnorm2))
+    ctx.close()
