@@ -275,8 +275,9 @@ def test_invalid_inputs_rejected():
     with pytest.raises(GGFError) as e:
         ctx.set_tensor(2, bad, spec.gamma_bond)
     assert e.value.status == GGF_EINVAL
-    with pytest.raises(GGFError):
-        ctx.set_tensor(5, spec.gamma_loc, spec.gamma_bond)
+    for bad_group in (1, 65):                   # Z_N with 2 <= N <= 64
+        with pytest.raises(GGFError):
+            ctx.set_tensor(bad_group, spec.gamma_loc, spec.gamma_bond)
     tid = ctx.set_tensor_spec(spec)
     for L in (3, 0, 34):
         with pytest.raises(GGFError):
