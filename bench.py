@@ -629,8 +629,9 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent; "
-              "sharding them across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent and "
+              "would shard by contiguous ranges of chains with one reduction of the observables, but that "
+              "path is not built)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "c5":
         run_c5(args)
