@@ -179,3 +179,41 @@ def test_energy_entry_points_reject_bad_input():
         big.measure_sensitivity(CP)
     assert e.value.status == GGF_EINVAL
     big.close()
+
+
+def test_k3_full_size_sampled():
+    """2048 chains of 16x16 Z2 K=3 in float32 with a float64 refresh every 64 flips (the shape
+    of the K = 3 benchmark): electric slot and energy rows in one launch each, every chain
+    finite, one chain checked against the oracle (float32 tolerance)."""
+    from paper_2412_01737_amd.ggf import OBS_ELECTRIC as BIT
+    from oracle.model import OBS_ELECTRIC
+    L, K, chains = 16, 3, 2048
+    say(f"electric + energy full size L={L} K={K} chains={chains}")
+    spec = spec_for(L, K, 2)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * chains, init=1, precision=32, refresh_every=64)
+    ctx.sweep(1)
+    obs = ctx.measure(BIT)
+    rows = ctx.measure_energy(CP)
+    assert np.all(np.isfinite(obs[:, OBS_ELECTRIC])) and np.all(np.isfinite(rows[:, 0]))
+    c = chains - 1
+    links, _ = ctx.get_state(c)
+    # reference with the oracle's patch-lemma cross ratios (pinned against full Pfaffians) and a
+    # float64 inverse of every M_nm
+    G = np.linalg.inv(an.assemble_M(links))
+    rho = an.bond_overlaps() * an.cross_ratio_patch(G[np.ix_(an.S, an.S)], links)
+    ginv = [[np.linalg.inv(an.assemble_M(links, n, m)) for m in range(K)] for n in range(K)]
+    wts = np.conj(an.c)[:, None] * an.c[None, :] * rho
+    ref = an.electric_mean(links, ginv, wts)
+    assert abs(obs[c, OBS_ELECTRIC] - ref) < 1e-5, (obs[c, OBS_ELECTRIC], ref)
+    cp = en.Couplings(**CP)
+    rh = np.array([[rho[n, m] * en.pair_energy(an, links, ginv[n][m], n, m, cp) for m in range(K)]
+                   for n in range(K)])
+    S = np.conj(an.c) @ rho @ an.c
+    e = (np.conj(an.c) @ rh @ an.c) / S
+    assert abs(rows[c, 0] - e.real) <= 2e-5 * max(1.0, abs(e))
+    for p in range(K * K):
+        i, j = divmod(p, K)
+        assert abs(rows[c, 1 + 4 * p] + 1j * rows[c, 2 + 4 * p] - rho[i, j] / S) <= 2e-5 * max(1.0, abs(rho[i, j] / S))
+        assert abs(rows[c, 3 + 4 * p] + 1j * rows[c, 4 + 4 * p] - rh[i, j] / S) <= 2e-5 * max(1.0, abs(rh[i, j] / S))
+    ctx.close()
