@@ -30,7 +30,7 @@ lambda' (reweighting), so the best lambda' is the lowest generalised eigenvector
 of (Hb, Nb).  This is the optimisation of the lambda_n among the variational
 parameters (the outlook of Sec. 6.3 asks for gradient descent on all of them).
 
-Gradient with respect to Gamma_A (K = 1): Gamma_A(theta) = exp(theta E) Gamma_A
+Gradient with respect to Gamma_A (any K): Gamma_A(theta) = exp(theta E) Gamma_A
 exp(-theta E) for antisymmetric generators E keeps the on-site state pure and
 even.  With Delta = [E, Gamma_A],
     d<H> = E_p[d e] + E_p[(e - <H>) d log N],
@@ -135,7 +135,7 @@ def linear_method(Hb: np.ndarray, Nb: np.ndarray):
     return float(w[0]), lam
 
 
-# ----- gradient with respect to Gamma_A (K = 1) -----
+# ----- gradient with respect to Gamma_A -----
 def rotated_gamma_loc(gamma_loc: np.ndarray, X: np.ndarray) -> np.ndarray:
     """exp(X) Gamma_A exp(-X) for a real antisymmetric 10 x 10 generator X (stays pure and even)."""
     from scipy.linalg import expm
@@ -150,28 +150,14 @@ def generator(k: int, l: int) -> np.ndarray:
     return E
 
 
-def sensitivities(an: Ansatz, links_k, cp: Couplings):
-    """(e, S_e, S_N) of one configuration, K = 1: for every antisymmetric generator E,
-    d e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N) with Delta = [E, Gamma_A] the
-    change of the on-site covariance (the same on every site).
-
-    e(G) is the local energy.  Gamma_out = A + B G B^T gives
-    d Gamma_out = dA + dB G B^T + B G dB^T + P dM P^T, with P = B G (G antisymmetric),
-    and the electric term X = en + (1/2) tr(G_UU R) gives dX = -(1/2) tr((G dM G)_UU R).
-    With N(G) = W(G) = 2^-4V sqrt(det M), d log N = (1/2) tr(G dM), dM = (+)_x Delta_d."""
-    assert an.K == 1
-    lat, N = an.lat, an.group
-    V, n = lat.V, lat.n
-    M = an.assemble_M(links_k)
-    G = np.linalg.inv(M)
-    gout = an.A + an.B @ G @ an.B.T
-    # energy as sum_pq C[p, q] (delta_pq - i Gamma_out[p, q]) / 4-type terms: collect the
-    # coefficient of Gamma_out[p, q] in e(G) (dE/dGamma_out) by linearity
+def energy_coefficients(an: Ansatz, links_k, cp: Couplings) -> np.ndarray:
+    """C[p, q]: the coefficient of Gamma_out[p, q] in the fermion part of the local energy
+    (by linearity; <phi_x^+ phi_y> = 1/4 [cc(x0,y0) + i cc(x0,y1) - i cc(x1,y0) + cc(x1,y1)],
+    cc(a, b) = delta_ab - i Gamma_out[a, b])."""
+    lat, N, V = an.lat, an.group, an.lat.V
     C = np.zeros((2 * V, 2 * V), complex)
 
     def add_bilinear(coef, x, y):
-        # coef * <phi_x^+ phi_y>, <phi_x^+ phi_y> = 1/4 [cc(x0,y0) + i cc(x0,y1) - i cc(x1,y0) + cc(x1,y1)],
-        # cc(a, b) = delta_ab - i Gamma[a, b]
         for (a, b, w) in ((0, 0, 1.0), (0, 1, 1j), (1, 0, -1j), (1, 1, 1.0)):
             C[2 * x + a, 2 * y + b] += coef * 0.25 * w * (-1j)
 
@@ -184,8 +170,18 @@ def sensitivities(an: Ansatz, links_k, cp: Couplings):
             e_ = eta(lat, x, mu)
             add_bilinear(cp.t * 1j * e_ * D, x, y)
             add_bilinear(-cp.t * 1j * e_ * np.conj(D), y, x)
-    e = local_energy(an, links_k, cp)
-    # sensitivity: d e = sum_pq C[p, q] d Gamma_out[p, q] + ke sum_l dX_l
+    return C
+
+
+def pair_sensitivities(an: Ansatz, links_k, cp: Couplings, G: np.ndarray, n: int = 0, m: int = 0):
+    """(S_e, S_N) of the pair (n, m) from G = M_nm^-1: d h_nm = tr(Delta S_e) and
+    (1/2) tr(G dM) = tr(Delta S_N) for Delta = [E, Gamma_A], tr(Delta S) = sum_ij Delta_ij S_ji.
+
+    Gamma_out = A + B G B^T gives d Gamma_out = dA + dB G B^T + B G dB^T + P dM P^T with
+    P = B G (G antisymmetric, dG = -G dM G); the electric term X = en + (1/2) tr(G_UU R) of
+    the pair gives dX = -(1/2) tr((G dM G)_UU R); dM = (+)_x Delta_d on every site."""
+    lat, V = an.lat, an.lat.V
+    C = energy_coefficients(an, links_k, cp)
     Sa = np.zeros((2, 2), complex)
     Sb = np.zeros((2, 8), complex)
     Sd = np.zeros((8, 8), complex)
@@ -200,8 +196,7 @@ def sensitivities(an: Ansatz, links_k, cp: Couplings):
         Sb += (GBt[cols8, :] @ C[rows, :].T).T
         # B G dB^T: Gamma_out[p, 2x+b] += sum_i (B G)[p, 8x+i] Delta_b[b, i]
         Sb += (P[:, cols8].T @ C[:, rows]).T
-    # P dM P^T: sum_pq C[p,q] (P dM P^T)[p,q] = sum_z tr(Delta_d (P^T C P)[z, z]) with the
-    # trace convention tr(Delta S) = sum_ij Delta[i, j] S[j, i]
+    # P dM P^T: sum_pq C[p,q] (P dM P^T)[p,q] = sum_z tr(Delta_d (P^T C P)[z, z])
     Q = P.T @ C @ P
     for z in range(V):
         blk = slice(8 * z, 8 * z + 8)
@@ -213,12 +208,12 @@ def sensitivities(an: Ansatz, links_k, cp: Couplings):
         for ell in range(lat.n_links):
             u = lat.link_majoranas(ell)
             g_uu = G[np.ix_(u, u)]
-            x0 = an.mixed_occupation_patch(g_uu, links_k, ell, 0, 0)
+            x0 = an.mixed_occupation_patch(g_uu, links_k, ell, n, m)
             for i in range(4):
                 for j in range(i + 1, 4):
                     step = np.zeros((4, 4))
                     step[i, j], step[j, i] = 1.0, -1.0
-                    slope = an.mixed_occupation_patch(g_uu + step, links_k, ell, 0, 0) - x0
+                    slope = an.mixed_occupation_patch(g_uu + step, links_k, ell, n, m) - x0
                     for z in range(V):
                         blk = slice(8 * z, 8 * z + 8)
                         Sd += -cp.ke * slope * np.outer(G[blk, u[j]], G[u[i], blk])
@@ -226,11 +221,44 @@ def sensitivities(an: Ansatz, links_k, cp: Couplings):
     S_e[0:2, 0:2] = Sa
     S_e[2:10, 0:2] = Sb.T
     S_e[2:10, 2:10] = Sd
-    S_N = np.zeros((10, 10))
+    S_N = np.zeros((10, 10), complex)
     for x in range(V):
         blk = slice(8 * x, 8 * x + 8)
         S_N[2:10, 2:10] += 0.5 * G[blk, blk]
-    return e, S_e, S_N
+    return S_e, S_N
+
+
+def sensitivities(an: Ansatz, links_k, cp: Couplings):
+    """(e, S_e, S_N) of one configuration: for every antisymmetric generator E,
+    d e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N) with Delta = [E, Gamma_A] the
+    change of the on-site covariance (the same on every site); e(G) is the local energy.
+
+    K = 1: N(G) = W(G) = 2^-4V sqrt(det M), d log N = (1/2) tr(G dM).  K > 1: with
+    om_ab = lambda_a^* lambda_b rho_ab, S = sum om, E = sum om h / S and
+    d log r_ab = (1/2) tr(M_ab^-1 dM) - (1/2) tr(G dM) (the cross terms' Delta_ab do not depend on
+    Gamma_A),
+        d log N = sum_ab (om_ab / S) (1/2) tr(M_ab^-1 dM),
+        d E     = sum_ab (om_ab / S) [d h_ab + (h_ab - E) (1/2) tr(M_ab^-1 dM)]
+    (the (1/2) tr(G dM) terms cancel since sum om / S = 1)."""
+    K = an.K
+    if K == 1:
+        G = np.linalg.inv(an.assemble_M(links_k))
+        S_e, S_N = pair_sensitivities(an, links_k, cp, G)
+        return local_energy(an, links_k, cp), S_e, S_N.real
+    rho, rh = pair_matrices(an, links_k, cp)
+    om = np.conj(an.c)[:, None] * an.c[None, :] * rho
+    S = om.sum()
+    h = rh / rho
+    E = (om * h).sum() / S
+    S_e = np.zeros((10, 10), complex)
+    S_N = np.zeros((10, 10), complex)
+    for a in range(K):
+        for b in range(K):
+            Gab = np.linalg.inv(an.assemble_M(links_k, a, b))
+            se, sn = pair_sensitivities(an, links_k, cp, Gab, a, b)
+            S_e += om[a, b] / S * (se + (h[a, b] - E) * sn)
+            S_N += om[a, b] / S * sn
+    return E, S_e, S_N
 
 
 def gradient_from_samples(gamma_loc: np.ndarray, es, S_es, S_Ns, weights=None):

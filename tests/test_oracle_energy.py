@@ -11,10 +11,11 @@
   eigenvalue of the dense K-dimensional subspace (<Psi_n|H|Psi_m>, <Psi_n|Psi_m>),
   whatever lambda the configurations were weighted with;
 * E_loc is gauge invariant (Z2, flipping the links of a site);
-* K = 1 gradient with respect to the on-site covariance Gamma_A (rotations
-  exp(theta E) Gamma_A exp(-theta E)): the per-configuration sensitivities of e(G)
-  and log N(G) against central differences, and the p(G)-weighted gradient over
-  every configuration against central differences of the exactly enumerated <H>.
+* gradient with respect to the on-site covariance Gamma_A (rotations
+  exp(theta E) Gamma_A exp(-theta E), K = 1..3): the per-configuration
+  sensitivities of e(G) and log N(G) against central differences, and the
+  p(G)-weighted gradient over every configuration against central differences of
+  the exactly enumerated <H>.
 """
 import itertools
 
@@ -135,45 +136,58 @@ def test_gauge_invariance_z2():
 
 
 # ----- gradient with respect to Gamma_A (K = 1) -----
-def _exact_energy(lat, gamma_loc, gamma_bond, group):
-    an = Ansatz(lat, gamma_loc, gamma_bond, group)
-    num = den = 0.0
-    for G in itertools.product(range(group), repeat=lat.n_links):
-        k = np.array(G)
-        Nk = an.weight(k)
-        num += Nk * en.local_energy(an, k, CP)
-        den += Nk
-    return (num / den).real
-
-
-@pytest.mark.parametrize("group", [2, 3])
-def test_sensitivities_against_finite_differences(group):
-    """d e(G) and d log N(G) along generators of the on-site rotation, per configuration."""
+@pytest.mark.parametrize("K,group", [(1, 2), (1, 3), (2, 2), (3, 3)])
+def test_sensitivities_against_finite_differences(K, group):
+    """d e(G) and d log N(G) along generators of the on-site rotation, per configuration
+    (K > 1: through every pair's M_nm^-1 and the cross-term weights)."""
     lat = Lattice(2, 2)
-    spec = synth.make_tensor(2, K=1, group=group)
-    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, group)
+    spec = synth.make_tensor(2, K=K, group=group)
+    if K > 1:
+        links, gk = synth.patch_bonds(lat.n_links, K)
+        spec.patch_link, spec.gamma_bond_k = links, gk
+
+    def mk(g):
+        return Ansatz(lat, g, spec.gamma_bond, group, spec.patch_link, spec.gamma_bond_k, spec.c)
+
+    an = mk(spec.gamma_loc)
     k = np.random.default_rng(1).integers(0, group, lat.n_links)
     e, Se, SN = en.sensitivities(an, k, CP)
-    assert abs(e - en.local_energy(an, k, CP)) < 1e-13
+    assert abs(e - en.local_energy(an, k, CP)) < 1e-12
     h = 1e-5
     for (a, b) in [(0, 1), (0, 5), (2, 7), (3, 9), (1, 4), (6, 8)]:
         E = en.generator(a, b)
         D = E @ spec.gamma_loc - spec.gamma_loc @ E
-        ap = Ansatz(lat, en.rotated_gamma_loc(spec.gamma_loc, h * E), spec.gamma_bond, group)
-        am = Ansatz(lat, en.rotated_gamma_loc(spec.gamma_loc, -h * E), spec.gamma_bond, group)
+        ap, am = mk(en.rotated_gamma_loc(spec.gamma_loc, h * E)), mk(en.rotated_gamma_loc(spec.gamma_loc, -h * E))
         de = (en.local_energy(ap, k, CP) - en.local_energy(am, k, CP)) / (2 * h)
-        dn = (ap.log_weight(k) - am.log_weight(k)) / (2 * h)
+        dn = (np.log(ap.norm(k)) - np.log(am.norm(k))) / (2 * h)
         assert abs(np.sum(D * Se.T) - de) <= 1e-7 * max(1.0, abs(de))
-        assert abs(np.sum(D * SN.T) - dn) <= 1e-7 * max(1.0, abs(dn))
+        assert abs(np.sum(D * SN.T).real - dn) <= 1e-7 * max(1.0, abs(dn))
 
 
-@pytest.mark.parametrize("group", [2, 3])
-def test_gradient_against_exact_energy(group):
+@pytest.mark.parametrize("K,group", [(1, 2), (1, 3), (2, 2)])
+def test_gradient_against_exact_energy(K, group):
     """d<H>/d theta from per-configuration sensitivities weighted by p(G) over every configuration
     of a 2x1 lattice equals central differences of the exactly enumerated <H>(theta)."""
     lat = Lattice(2, 1)
-    spec = synth.make_tensor(2, K=1, group=group)
-    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, group)
+    spec = synth.make_tensor(2, K=K, group=group)
+    if K > 1:
+        links, gk = synth.patch_bonds(lat.n_links, K)
+        spec.patch_link, spec.gamma_bond_k = links, gk
+
+    def mk(g):
+        return Ansatz(lat, g, spec.gamma_bond, group, spec.patch_link, spec.gamma_bond_k, spec.c)
+
+    def exact(g):
+        a = mk(g)
+        num = den = 0.0
+        for G in itertools.product(range(group), repeat=lat.n_links):
+            k = np.array(G)
+            Nk = a.norm(k)
+            num += Nk * en.local_energy(a, k, CP)
+            den += Nk
+        return (num / den).real
+
+    an = mk(spec.gamma_loc)
     es, Ses, SNs, ws = [], [], [], []
     for G in itertools.product(range(group), repeat=lat.n_links):
         k = np.array(G)
@@ -181,14 +195,14 @@ def test_gradient_against_exact_energy(group):
         es.append(e)
         Ses.append(Se)
         SNs.append(SN)
-        ws.append(an.weight(k))
+        ws.append(an.norm(k))
     g = en.gradient_from_samples(spec.gamma_loc, es, Ses, SNs, weights=ws)
     assert np.abs(g + g.T).max() < 1e-14
     h = 1e-5
     for (a, b) in [(0, 1), (0, 6), (2, 9), (4, 5)]:
         E = en.generator(a, b)
-        fd = (_exact_energy(lat, en.rotated_gamma_loc(spec.gamma_loc, h * E), spec.gamma_bond, group)
-              - _exact_energy(lat, en.rotated_gamma_loc(spec.gamma_loc, -h * E), spec.gamma_bond, group)) / (2 * h)
+        fd = (exact(en.rotated_gamma_loc(spec.gamma_loc, h * E))
+              - exact(en.rotated_gamma_loc(spec.gamma_loc, -h * E))) / (2 * h)
         assert abs(g[a, b] - fd) <= 1e-7 * max(1.0, abs(fd)), (a, b, g[a, b], fd)
 
 
