@@ -194,13 +194,20 @@ ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_coupli
 
 /* Sensitivities of every chain's local energy and log N(G) to the on-site
  * covariance Gamma_A (gradient descent on Gamma_A, the outlook of Sec. 6.3;
- * K = 1 chains with L <= 16, else GGF_EINVAL).  For a rotation
+ * L <= 16 when every chain has K = 1, L <= 8 when any chain has K > 1, else
+ * GGF_EINVAL).  For a rotation
  * Gamma_A -> exp(theta E) Gamma_A exp(-theta E) (E real antisymmetric 10 x 10,
  * Delta = [E, Gamma_A]): d Re E_loc(G)/d theta = tr(Delta S_e) and
  * d log N(G)/d theta = tr(Delta S_N), tr(Delta S) = sum_ij Delta_ij S_ji.
  * Row c of out[n_chains][GGF_SENS_STRIDE]: [0..99] S_e, [100..199] S_N,
  * row-major 10 x 10 (device pointer when out_is_device != 0, else host and
- * synchronous). */
+ * synchronous).  K > 1 (superposition of Sec. 4 with the patch cross terms):
+ * with om_ab = lambda_a^* lambda_b <B_b|B_a> r_ab, S = sum om, h_ab the pair's
+ * transition energy and E the local energy, d log N = sum (om_ab / S) (1/2)
+ * tr(M_ab^-1 dM) and d E = sum (om_ab / S) [d h_ab + (h_ab - E) (1/2)
+ * tr(M_ab^-1 dM)], real parts.  Such a call is synchronous and allocates
+ * n_chains x (GGF_ENERGY_STRIDE doubles + n^2 complex doubles) of device memory
+ * for its duration (4 MiB per 8 x 8 chain). */
 ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *couplings, double *out,
                                    int32_t out_is_device, void *stream);
 
@@ -219,7 +226,7 @@ ggf_status ggf_gamma_gradient(ggf_ctx *ctx, const double *gamma_loc, const doubl
 ggf_status ggf_set_gamma_loc(ggf_ctx *ctx, int32_t tensor_id, const double *gamma_loc, void *stream);
 
 /* Gradient descent on the on-site covariance Gamma_A (the outlook of Sec. 6.3;
- * K = 1 chains, L <= 16): n_iters rounds of [n_sweeps sweeps, each followed by
+ * the chains as in ggf_measure_sensitivity): n_iters rounds of [n_sweeps sweeps, each followed by
  * ggf_measure_energy and ggf_measure_sensitivity; ggf_gamma_gradient over the
  * rows of the chains that use tensor_id; Gamma_A <- exp(X) Gamma_A exp(-X) with
  * X = -step grad; ggf_set_gamma_loc].  energies[n_iters]: <H> estimated in each

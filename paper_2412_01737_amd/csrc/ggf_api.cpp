@@ -1058,28 +1058,48 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
   const double cv[5] = {cp->t, cp->mu, cp->m, cp->kb, cp->ke};
   for (double v : cv)
     if (!std::isfinite(v)) return fail(ctx, GGF_EINVAL, "couplings must be finite");
-  int max_sites = 0;
+  int max_sites = 0, max_n = 0;
+  bool pairs = false;
   for (const ChainDev &ch : ctx->chains) {
-    if (ch.K != 1) return fail(ctx, GGF_EINVAL, "sensitivities need K = 1 chains");
-    if (ch.L > 16) return fail(ctx, GGF_EINVAL, "sensitivities need L <= 16");
+    if (ch.K > 1) pairs = true;
     max_sites = std::max(max_sites, ch.L * ch.L);
+    max_n = std::max(max_n, ch.n);
   }
+  for (const ChainDev &ch : ctx->chains)
+    if (ch.L > (pairs ? 8 : 16))
+      return fail(ctx, GGF_EINVAL, pairs ? "sensitivities of K > 1 chains need L <= 8" : "sensitivities need L <= 16");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const LaunchCtx lc = launch_ctx(ctx, s);
   const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};
   const size_t bytes = static_cast<size_t>(ctx->n_chains) * GGF_SENS_STRIDE * sizeof(double);
-  if (out_is_device) {
+  if (!pairs && out_is_device) {
     ggf_launch_sens(lc, ec, out, max_sites);
     HIP_TRY(ctx, hipGetLastError());
     return GGF_OK;
   }
-  double *tmp = nullptr;
-  HIP_TRY(ctx, hipMalloc(&tmp, bytes));
-  ggf_launch_sens(lc, ec, tmp, max_sites);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(tmp);
+  // K > 1: the chains' energy rows (pair weights, h_ab and E) and one complex n x n M_ab^-1 per chain
+  double *tmp = nullptr, *erows = nullptr;
+  double2 *gab = nullptr;
+  hipError_t e = out_is_device ? hipSuccess : hipMalloc(&tmp, bytes);
+  if (e == hipSuccess && pairs)
+    e = hipMalloc(&erows, static_cast<size_t>(ctx->n_chains) * GGF_ENERGY_STRIDE * sizeof(double));
+  if (e == hipSuccess && pairs)
+    e = hipMalloc(&gab, static_cast<size_t>(ctx->n_chains) * max_n * max_n * sizeof(double2));
+  double *dst = out_is_device ? out : tmp;
+  if (e == hipSuccess) {
+    if (pairs) {
+      ggf_launch_energy(lc, ec, erows, ctx->kmax);
+      ggf_launch_sens_pairs(lc, ec, gab, max_n, erows, dst, ctx->kmax);
+    } else {
+      ggf_launch_sens(lc, ec, dst, max_sites);
+    }
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && !out_is_device) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && (pairs || !out_is_device)) e = hipStreamSynchronize(s);
+  if (tmp) hipFree(tmp);
+  if (erows) hipFree(erows);
+  if (gab) hipFree(gab);
   if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure_sensitivity: ") + hipGetErrorString(e));
   return GGF_OK;
 }

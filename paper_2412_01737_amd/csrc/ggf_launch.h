@@ -72,4 +72,8 @@ struct EnergyCp {
 void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax);
 // Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 16).
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites);
+// K > 1 (L <= 8): per pair, M_ab^-1 formed into gab (n_chains x nmax^2 complex) and its weighted
+// contribution accumulated into out, using the chains' energy rows erows.
+void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,
+                           double *out, int kmax);
 int ggf_launch_probe(int mode, void *a, void *b, size_t bytes, int grid, hipStream_t s);

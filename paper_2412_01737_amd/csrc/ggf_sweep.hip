@@ -1208,6 +1208,259 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
     if (i < 2 || j < 2) o[100 + tid] = 0.0;    // S_N outside the d-block
   }
 }
+
+// ---- Gamma_A sensitivities with K > 1 (L <= 8): per pair (a, b), with M_ab^-1 formed explicitly ----
+
+// M_ab^-1 = G + G_S Y_ab G_S^T of every chain for one ordered pair pr (complex, n x n at
+// c * nmax^2 of Gab); chains with K^2 <= pr get G.  s_A: G[:, S] staged per chain.
+template <typename T>
+__global__ __launch_bounds__(256) void k_form_pair(LaunchCtx lc, int pr, double2 *Gab, int nmax) {
+  __shared__ double2 s_Y[16][64];
+  __shared__ double2 s_om[16];
+  __shared__ int s_S[16][8];
+  __shared__ int s_s[16];
+  __shared__ double s_A[512 * 8];
+  extern __shared__ double2 s_work[];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  pair_setup<T>(lc, c, ch, Tn, G, lk, s_Y, s_om, nullptr, s_S, s_s, s_work);
+  const bool has = pr < ch.K * ch.K;
+  const int s = has ? s_s[pr] : 0;
+  for (int e = threadIdx.x; e < n * s; e += blockDim.x) {
+    const int r = e / s, q = e - r * s;
+    s_A[r * 8 + q] = static_cast<double>(G[static_cast<size_t>(r) * n + s_S[pr][q]]);
+  }
+  __syncthreads();
+  double2 *out = Gab + static_cast<size_t>(c) * nmax * nmax;
+  for (int r = threadIdx.x >> 5; r < n; r += blockDim.x >> 5) {
+    double2 ay[8];   // (G_S Y)[r][q]
+    for (int q = 0; q < s; ++q) {
+      double2 v = make_double2(0.0, 0.0);
+      for (int p = 0; p < s; ++p) v = cadd(v, cscale(s_Y[pr][p * 8 + q], s_A[r * 8 + p]));
+      ay[q] = v;
+    }
+    for (int col = threadIdx.x & 31; col < n; col += 32) {
+      double2 v = make_double2(static_cast<double>(G[static_cast<size_t>(r) * n + col]), 0.0);
+      for (int q = 0; q < s; ++q) v = cadd(v, cscale(ay[q], s_A[col * 8 + q]));
+      out[static_cast<size_t>(r) * n + col] = v;
+    }
+  }
+}
+
+// coef * Wc, Wc = (1/4) [[-i, 1], [-1, -i]]: the complex coefficient block of Gamma_out[2x+a][2y+b]
+__device__ inline void coef_block_c(double2 coef, double2 o[4]) {
+  o[0] = make_double2(0.25 * coef.y, -0.25 * coef.x);
+  o[1] = cscale(coef, 0.25);
+  o[2] = cscale(coef, -0.25);
+  o[3] = o[0];
+}
+
+__device__ inline void h_term_c(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
+                                int &y, double2 o[4]) {
+  if (term == 0) {
+    const int sgn = (((x % L) + x / L) & 1) ? -1 : 1;
+    w = y = x;
+    coef_block_c(make_double2(cp.mu + sgn * cp.m, 0.0), o);
+    return;
+  }
+  const int mu = (term - 1) >> 1;
+  const int xn = mu == 0 ? ggf_shift(x, L, 1, 0) : ggf_shift(x, L, 0, 1);
+  const double2 D = link_phase(lk[2 * x + mu], group);
+  const double te = (mu == 0 && ((x / L) & 1)) ? -cp.t : cp.t;
+  if ((term & 1) == 1) {
+    w = x;
+    y = xn;
+    coef_block_c(make_double2(-te * D.y, te * D.x), o);
+  } else {
+    w = xn;
+    y = x;
+    coef_block_c(make_double2(-te * D.y, -te * D.x), o);
+  }
+}
+
+// One pair's contribution to the K > 1 sensitivities of a chain (the K = 1 computation of
+// k_sens with the complex M_ab^-1 of Gab and the pair's electric slopes), weighted by the
+// pair's om / S and combined with h_ab and E from the chain's energy row:
+//   S_e += Re (om/S) [S_e^ab + (h_ab - E) S_N^ab],   S_N += Re (om/S) S_N^ab.
+// pr == 0 writes the row, later pairs add to it.  L <= 8.
+__global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, int pr, const double2 *Gab, int nmax,
+                                                   const double *erows, double *out) {
+  __shared__ double2 s_U[16 * 64];        // U_z[i][2w + a], 8 x 2V
+  __shared__ double2 s_sl[128][6];        // electric slopes of the pair per link
+  __shared__ double2 s_Sa[4], s_Sb[16], s_SN[64];
+  __shared__ double2 s_red[4][64];
+  __shared__ double2 s_wt[2];             // om/S, om/S (h - E)
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group, K = ch.K;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int tid = threadIdx.x;
+  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
+  if (pr >= K * K) return;
+  const int a = pr / K, b = pr % K;
+  const double2 *Gc = Gab + static_cast<size_t>(c) * nmax * nmax;
+  if (tid == 0) {
+    // om/S = lambda_a^* lambda_b rho/S, lambda_a^* lambda_b = w / ov; E = sum_p lambda^* lambda (rho h / S)_p
+    const double *row = erows + static_cast<size_t>(c) * GGF_ENERGY_STRIDE_DEV;
+    double2 E = make_double2(0.0, 0.0);
+    for (int p = 0; p < K * K; ++p) {
+      const int pa = p / K, pb = p % K;
+      const double2 ll = cdiv(Tn.w[pa][pb], Tn.ov[pa][pb]);
+      E = cadd(E, cmul(ll, make_double2(row[3 + 4 * p], row[4 + 4 * p])));
+    }
+    const double2 rho = make_double2(row[1 + 4 * pr], row[2 + 4 * pr]);
+    const double2 rh = make_double2(row[3 + 4 * pr], row[4 + 4 * pr]);
+    const double2 om = cmul(cdiv(Tn.w[a][b], Tn.ov[a][b]), rho);
+    s_wt[0] = om;
+    s_wt[1] = cmul(om, csub(cdiv(rh, rho), E));
+  }
+  if (tid < 4) s_Sa[tid] = make_double2(0.0, 0.0);
+  if (tid < 16) s_Sb[tid] = make_double2(0.0, 0.0);
+  if (tid < 64) s_SN[tid] = make_double2(0.0, 0.0);
+  for (int ell = tid; ell < 2 * V; ell += blockDim.x) {
+    // slope of the pair's X along e_ij - e_ji: R[j][i], R = O eq_ab O^T of this link
+    const double2 *eq = Tn.eq0;
+    for (int l = 0; l < Tn.nl[a][b]; ++l)
+      if (Tn.lk[a][b][l] == ell) eq = Tn.eq[a][b][l];
+    int k = 0;
+    for (int i = 0; i < 4; ++i) {
+      for (int j = i + 1; j < 4; ++j) {
+        double2 row[4];
+        rotate_dg_row(eq, lk[ell], group, j, row);   // row j of O eq O^T
+        s_sl[ell][k++] = row[i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < V; x += blockDim.x) {
+    double2 o4[4];
+    int w, y;
+    h_term_c(cp, lk, L, group, x, 0, w, y, o4);
+    for (int aa = 0; aa < 2; ++aa)
+      for (int bb = 0; bb < 2; ++bb) {
+        atomicAdd(&s_Sa[bb * 2 + aa].x, o4[aa * 2 + bb].x);
+        atomicAdd(&s_Sa[bb * 2 + aa].y, o4[aa * 2 + bb].y);
+      }
+    double2 sb[16];
+    for (int q = 0; q < 16; ++q) sb[q] = make_double2(0.0, 0.0);
+    for (int nb = 0; nb < 5; ++nb) {
+      int yy = x;
+      if (nb == 1) yy = ggf_shift(x, L, 1, 0);
+      if (nb == 2) yy = ggf_shift(x, L, 0, 1);
+      if (nb == 3) yy = ggf_shift(x, L, -1, 0);
+      if (nb == 4) yy = ggf_shift(x, L, 0, -1);
+      if ((nb == 3 && yy == ggf_shift(x, L, 1, 0)) || (nb == 4 && yy == ggf_shift(x, L, 0, 1))) continue;
+      double2 orow[4], ocol[4];
+      for (int q = 0; q < 4; ++q) orow[q] = ocol[q] = make_double2(0.0, 0.0);
+      const int owners[2] = {x, yy};
+      for (int oi = 0; oi < (nb == 0 ? 1 : 2); ++oi)
+        for (int term = 0; term < 5; ++term) {
+          if ((nb == 0) != (term == 0)) continue;
+          int w2, y2;
+          double2 ot[4];
+          h_term_c(cp, lk, L, group, owners[oi], term, w2, y2, ot);
+          if (w2 == x && y2 == yy)
+            for (int q = 0; q < 4; ++q) orow[q] = cadd(orow[q], ot[q]);
+          if (w2 == yy && y2 == x)
+            for (int q = 0; q < 4; ++q) ocol[q] = cadd(ocol[q], ot[q]);
+        }
+      if (nb == 0)
+        for (int q = 0; q < 4; ++q) ocol[q] = orow[q];
+      for (int i = 0; i < 8; ++i) {
+        const double2 *grow = Gc + static_cast<size_t>(8 * x + i) * n + 8 * yy;
+        double2 t0 = make_double2(0.0, 0.0), t1 = make_double2(0.0, 0.0);
+        for (int j = 0; j < 8; ++j) {
+          t0 = cadd(t0, cscale(grow[j], Tn.b[j]));
+          t1 = cadd(t1, cscale(grow[j], Tn.b[8 + j]));
+        }
+        for (int aa = 0; aa < 2; ++aa) {
+          sb[aa * 8 + i] = cadd(sb[aa * 8 + i], cadd(cmul(orow[aa * 2 + 0], t0), cmul(orow[aa * 2 + 1], t1)));
+          sb[aa * 8 + i] = csub(sb[aa * 8 + i], cadd(cmul(ocol[0 * 2 + aa], t0), cmul(ocol[1 * 2 + aa], t1)));
+        }
+      }
+    }
+    for (int q = 0; q < 16; ++q) {
+      atomicAdd(&s_Sb[q].x, sb[q].x);
+      atomicAdd(&s_Sb[q].y, sb[q].y);
+    }
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        const double2 g = Gc[static_cast<size_t>(8 * x + i) * n + 8 * x + j];
+        atomicAdd(&s_SN[i * 8 + j].x, 0.5 * g.x);
+        atomicAdd(&s_SN[i * 8 + j].y, 0.5 * g.y);
+      }
+  }
+  const int ij = tid & 63, part = tid >> 6;
+  const int pi = ij >> 3, pj = ij & 7;
+  double2 sd = make_double2(0.0, 0.0);
+  for (int z = 0; z < V; ++z) {
+    __syncthreads();
+    for (int e = tid; e < 16 * V; e += blockDim.x) {
+      const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, al = col & 1;
+      const double2 *grow = Gc + static_cast<size_t>(8 * z + i) * n + 8 * w;
+      double2 v = make_double2(0.0, 0.0);
+      for (int j = 0; j < 8; ++j) v = cadd(v, cscale(grow[j], Tn.b[al * 8 + j]));
+      s_U[i * 2 * V + col] = v;
+    }
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    for (int x = part; x < V; x += 4)
+      for (int term = 0; term < 5; ++term) {
+        int w, y;
+        double2 o4[4];
+        h_term_c(cp, lk, L, group, x, term, w, y, o4);
+        const double2 ui0 = s_U[pi * 2 * V + 2 * w], ui1 = s_U[pi * 2 * V + 2 * w + 1];
+        const double2 uj0 = s_U[pj * 2 * V + 2 * y], uj1 = s_U[pj * 2 * V + 2 * y + 1];
+        acc = cadd(acc, cmul(ui0, cadd(cmul(o4[0], uj0), cmul(o4[1], uj1))));
+        acc = cadd(acc, cmul(ui1, cadd(cmul(o4[2], uj0), cmul(o4[3], uj1))));
+      }
+    if (cp.ke != 0.0)
+      for (int ell = part; ell < 2 * V; ell += 4) {
+        int u[4];
+        ggf_link_u(ell, L, u);
+        double2 vp[4], vq[4];
+        for (int i = 0; i < 4; ++i) {
+          vp[i] = Gc[static_cast<size_t>(8 * z + pj) * n + u[i]];
+          vq[i] = Gc[static_cast<size_t>(8 * z + pi) * n + u[i]];
+        }
+        int k = 0;
+        for (int i = 0; i < 4; ++i)
+          for (int j = i + 1; j < 4; ++j) acc = cadd(acc, cscale(cmul(s_sl[ell][k++], cmul(vp[j], vq[i])), cp.ke));
+      }
+    sd = cadd(sd, acc);
+  }
+  s_red[part][ij] = sd;
+  __syncthreads();
+  // combine: S_e^ab entries e and S_N^ab entries n: row += Re(om/S e + om/S (h - E) n), S_N += Re(om/S n)
+  const double2 w0 = s_wt[0], w1 = s_wt[1];
+  const bool first = pr == 0;
+  auto put = [&](int idx, double v) { o[idx] = first ? v : o[idx] + v; };
+  if (tid < 64) {
+    const double2 v = cadd(cadd(s_red[0][tid], s_red[1][tid]), cadd(s_red[2][tid], s_red[3][tid]));
+    const double2 sn = s_SN[pj * 8 + pi];   // S_N^ab[2+pj][2+pi]
+    put((2 + pj) * 10 + 2 + pi, cmul(w0, v).x + cmul(w1, sn).x);
+    const double2 sn2 = s_SN[tid];
+    put(100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7), cmul(w0, sn2).x);
+  }
+  if (tid < 16) {
+    const int al = tid >> 3, i = tid & 7;
+    put((2 + i) * 10 + al, cmul(w0, s_Sb[tid]).x);
+  }
+  if (tid < 4) put((tid >> 1) * 10 + (tid & 1), cmul(w0, s_Sa[tid]).x);
+  if (tid < 20) {
+    const int al = tid / 10, j = tid % 10;
+    if (j >= 2) put(al * 10 + j, 0.0);
+  }
+  if (tid < 100) {
+    const int i = tid / 10, j = tid % 10;
+    if (i < 2 || j < 2) put(100 + tid, 0.0);
+  }
+}
 }  // namespace
 
 static size_t pair_lds(int kmax) {
@@ -1302,6 +1555,18 @@ void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int m
   } else {
     if (stage) hipLaunchKernelGGL((k_sens<float, true>), grid, block, lds_u + lds_g, lc.stream, lc, cp, out, max_sites);
     else hipLaunchKernelGGL((k_sens<float, false>), grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
+  }
+}
+
+void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,
+                           double *out, int kmax) {
+  const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
+  for (int pr = 0; pr < kmax * kmax; ++pr) {
+    if (lc.precision == 64)
+      hipLaunchKernelGGL(k_form_pair<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
+    else
+      hipLaunchKernelGGL(k_form_pair<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
+    hipLaunchKernelGGL(k_sens_pair, dim3(lc.n_chains), dim3(256), 0, lc.stream, lc, cp, pr, gab, nmax, erows, out);
   }
 }
 

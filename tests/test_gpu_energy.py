@@ -153,9 +153,6 @@ def test_energy_entry_points_reject_bad_input():
     with pytest.raises(GGFError) as e:
         ctx.measure_energy(dict(CP, t=float("nan")))
     assert e.value.status == GGF_EINVAL
-    with pytest.raises(GGFError) as e:            # a K = 3 chain in the context
-        ctx.measure_sensitivity(CP)
-    assert e.value.status == GGF_EINVAL
     with pytest.raises(GGFError):
         ctx.set_lambda(t3 + 5, [1.0, 0.0, 0.0])
     with pytest.raises(GGFError):
@@ -179,6 +176,13 @@ def test_energy_entry_points_reject_bad_input():
         big.measure_sensitivity(CP)
     assert e.value.status == GGF_EINVAL
     big.close()
+    pairs = Context(0)
+    tp = pairs.set_tensor_spec(spec_for(10, 2, 2))
+    pairs.init_chains([10], [tp], 1)
+    with pytest.raises(GGFError) as e:            # K > 1 sensitivities need L <= 8
+        pairs.measure_sensitivity(CP)
+    assert e.value.status == GGF_EINVAL
+    pairs.close()
 
 
 def test_k3_full_size_sampled():

@@ -1,11 +1,13 @@
-"""Gradient of <H> with respect to the on-site covariance on the GPU (K = 1) against the oracle.
+"""Gradient of <H> with respect to the on-site covariance on the GPU against the oracle.
 
 ggf_measure_sensitivity returns per chain S_e (real part) and S_N with
 d Re e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N) for Delta = [E, Gamma_A].
 The oracle builds them with dense NumPy products of a fresh float64 inverse and
 reads the electric slopes off its own mixed occupation; its sensitivities are
 pinned against finite differences and its gradient against the exactly
-enumerated <H> (tests/test_oracle_energy.py).
+enumerated <H> (tests/test_oracle_energy.py).  For K > 1 the library forms each
+pair's M_ab^-1 explicitly and combines the pair terms with the weights and
+h_ab of the chain's energy row; the oracle inverts M_ab densely per pair.
 """
 import dataclasses
 
@@ -27,7 +29,8 @@ def _check_sens(row, an, links, tol):
     got_n = row[100:].reshape(10, 10)
     scale = max(1.0, np.abs(Se.real).max())
     assert np.abs(got_e - Se.real).max() <= tol * scale, np.abs(got_e - Se.real).max()
-    assert np.abs(got_n - SN).max() <= tol * max(1.0, np.abs(SN).max())
+    assert np.abs(got_n - SN.real).max() <= tol * max(1.0, np.abs(SN).max())
+    assert np.abs(np.imag(SN)).max() <= 1e-9 * max(1.0, np.abs(SN).max())   # d log N is real
 
 
 @pytest.mark.parametrize("L,group,precision", [(2, 2, 64), (4, 3, 64), (6, 2, 64), (4, 2, 32)])
@@ -124,4 +127,58 @@ def test_optimise_gamma_round():
         assert abs(info["logw"] - lw) <= 1e-10 * abs(lw)
     energies2, gnorm2, _ = ctx.optimise_gamma(0, CP, 2, 1, eta)
     assert np.all(np.isfinite(energies2)) and np.all(np.isfinite(gnorm2))
+    ctx.close()
+
+
+@pytest.mark.parametrize("L,K,group,precision", [(4, 2, 2, 64), (4, 3, 3, 64), (2, 2, 2, 64), (6, 2, 2, 64),
+                                                 (4, 2, 2, 32)])
+def test_sensitivity_rows_pairs(L, K, group, precision):
+    """K > 1: per pair (a, b) the K = 1 sensitivities with the complex M_ab^-1 and the pair's
+    electric slopes, weighted by om_ab / S with (h_ab - E) on the log-norm part."""
+    say(f"sensitivities K={K} L={L} Z{group} float{precision}")
+    spec = spec_for(L, K, group)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * 3, init=1, precision=precision, refresh_every=16 if precision == 32 else 0)
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    tol = 1e-10 if precision == 64 else 2e-5
+    for c in range(3):
+        _check_sens(rows[c], an, ctx.get_state(c)[0], tol)
+    ctx.close()
+
+
+def test_sensitivity_rows_mixed_k():
+    """K = 1 and K = 2 chains in one context: both go through the pair path, each to its oracle."""
+    say("sensitivities mixed K=1 / K=2 L=4 Z2")
+    specs = [spec_for(4, 1, 2), spec_for(4, 2, 2)]
+    ctx = gpu_context(specs, [4, 4, 4], init=1, tensor_ids=[0, 1, 1])
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    for c, t in enumerate([0, 1, 1]):
+        _check_sens(rows[c], ansatz_for(specs[t], 4), ctx.get_state(c)[0], 1e-10)
+    ctx.close()
+
+
+def test_gradient_pairs_end_to_end():
+    """K = 2: GPU energy and sensitivity rows -> library gradient = oracle gradient from the oracle's
+    K > 1 sensitivities of the same link fields."""
+    from paper_2412_01737_amd.ggf import gamma_gradient
+    say("gradient end to end K=2 L=4 Z2")
+    L, chains = 4, 6
+    spec = spec_for(L, 2, 2)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * chains, init=1)
+    ctx.sweep(2)
+    er = ctx.measure_energy(CP)
+    sr = ctx.measure_sensitivity(CP)
+    g = gamma_gradient(spec.gamma_loc, er, sr)
+    es, Ses, SNs = [], [], []
+    for c in range(chains):
+        e, Se, SN = en.sensitivities(an, ctx.get_state(c)[0], en.Couplings(**CP))
+        assert abs(er[c, 0] - e.real) <= 1e-10 * max(1.0, abs(e))
+        es.append(e.real)
+        Ses.append(Se.real)
+        SNs.append(SN.real)
+    ref = en.gradient_from_samples(spec.gamma_loc, es, Ses, SNs)
+    assert np.abs(g - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
     ctx.close()
