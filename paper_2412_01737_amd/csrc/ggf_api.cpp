@@ -1058,12 +1058,13 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
   const double cv[5] = {cp->t, cp->mu, cp->m, cp->kb, cp->ke};
   for (double v : cv)
     if (!std::isfinite(v)) return fail(ctx, GGF_EINVAL, "couplings must be finite");
-  int max_sites = 0, max_n = 0;
+  int max_sites = 0, max_n = 0, max_group = 0;
   bool pairs = false;
   for (const ChainDev &ch : ctx->chains) {
     if (ch.K > 1) pairs = true;
     max_sites = std::max(max_sites, ch.L * ch.L);
     max_n = std::max(max_n, ch.n);
+    max_group = std::max(max_group, ch.group);
   }
   for (const ChainDev &ch : ctx->chains)
     if (ch.L > (pairs ? 8 : 16))
@@ -1073,7 +1074,7 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
   const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};
   const size_t bytes = static_cast<size_t>(ctx->n_chains) * GGF_SENS_STRIDE * sizeof(double);
   if (!pairs && out_is_device) {
-    ggf_launch_sens(lc, ec, out, max_sites);
+    ggf_launch_sens(lc, ec, out, max_sites, max_group);
     HIP_TRY(ctx, hipGetLastError());
     return GGF_OK;
   }
@@ -1091,7 +1092,7 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
       ggf_launch_energy(lc, ec, erows, ctx->kmax);
       ggf_launch_sens_pairs(lc, ec, gab, max_n, erows, dst, ctx->kmax);
     } else {
-      ggf_launch_sens(lc, ec, dst, max_sites);
+      ggf_launch_sens(lc, ec, dst, max_sites, max_group);
     }
     e = hipGetLastError();
   }

@@ -70,8 +70,9 @@ struct EnergyCp {
   double t, mu, m, kb, ke;
 };
 void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax);
-// Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 16).
-void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites);
+// Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 16);
+// max_group: the largest link group among the chains.
+void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group);
 // K > 1 (L <= 8): per pair, M_ab^-1 formed into gab (n_chains x nmax^2 complex) and its weighted
 // contribution accumulated into out, using the chains' energy rows erows.
 void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,

@@ -1016,34 +1016,9 @@ __device__ inline void h_term(const EnergyCp &cp, const int8_t *lk, int L, int g
   }
 }
 
-// Sensitivities of one K = 1 chain to its on-site covariance Gamma_A: for Delta = [E, Gamma_A]
-// (E antisymmetric), Re d e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N), with the
-// transposed-trace convention tr(Delta S) = sum_ij Delta_ij S_ji.  With P = B G, C the
-// coefficients of Gamma_out in the local energy and R_k the rotated electric response,
-//   S_e[a-block]  = sum_x C[x, x]^T,
-//   S_e[b^T-block] from dB G B^T + B G dB^T (rows of G on the 5 neighbouring blocks),
-//   S_e[d-block]  = sum_z (P^T C P)[z, z]^T + ke sum_l sum_{i<j} R_k[j][i] G[z, u_j] (x) G[z, u_i],
-//   S_N[d-block]  = (1/2) sum_x G[x, x]  (log N = (1/2) log det M + const).
-// out[c][0..99] = Re S_e, out[c][100..199] = S_N (row-major 10 x 10).  L <= 16.
-// STAGE: the 8 rows of stripe z are staged in LDS (8 n float64 after U_z's 16 max_sites).
-template <typename T, bool STAGE>
-__global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double *out, int max_sites) {
-  extern __shared__ double s_dyn[];
-  double *s_U = s_dyn;                       // U_z[i][2w + a] = sum_j G[8z+i][8w+j] b[a][j], 8 x 2V
-  double *s_G = s_dyn + 16 * max_sites;      // stripe z, 8 x n (STAGE)
-  __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
-  __shared__ double s_R[GGF_ZN_MAX][16];
-  __shared__ double s_red[4][64];
-  const int c = blockIdx.x;
-  const ChainDev ch = lc.chains[c];
-  const TensorDev &Tn = lc.tensors[ch.tensor];
-  const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
-  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
-  const int8_t *lk = lc.links + ch.link_off;
+// Rotated electric response R_k = O_k eq0 O_k^T (real part) for every link value k, 16 doubles each.
+__device__ inline void sens_r_table(const TensorDev &Tn, int group, double *s_R) {
   const int tid = threadIdx.x;
-  if (tid < 4) s_Sa[tid] = 0.0;
-  if (tid < 16) s_Sb[tid] = 0.0;
-  if (tid < 64) s_SN[tid] = 0.0;
   for (int te = tid; te < 16 * group; te += blockDim.x) {
     const int k = te >> 4, e = te & 15;
     double co = 1.0, si = 0.0;
@@ -1067,10 +1042,16 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
           for (int b = 0; b < 4; ++b) v += o[i][a] * q[a * 4 + b] * o[j][b];
         if (i * 4 + j == e) val = v;
       }
-    s_R[k][e] = val;
+    s_R[k * 16 + e] = val;
   }
-  __syncthreads();
-  // (1) per site: a-block, b-block and S_N
+}
+
+// a-block, b-block and S_N of the K = 1 sensitivities: per site the rows of G on the 5
+// neighbouring blocks (accumulated into s_Sa, s_Sb, s_SN by LDS atomics).
+template <typename T>
+__device__ inline void sens_sites(const EnergyCp &cp, const int8_t *lk, int L, int group, const T *G, int n,
+                                  const TensorDev &Tn, double *s_Sa, double *s_Sb, double *s_SN) {
+  const int V = L * L, tid = threadIdx.x;
   for (int x = tid; x < V; x += blockDim.x) {
     double sb[16];
     for (int q = 0; q < 16; ++q) sb[q] = 0.0;
@@ -1131,6 +1112,59 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
       for (int j = 0; j < 8; ++j)
         atomicAdd(&s_SN[i * 8 + j], 0.5 * static_cast<double>(G[static_cast<size_t>(8 * x + i) * n + 8 * x + j]));
   }
+}
+
+// Every entry of the sensitivity row but the S_e d-block (thread tid < 100 writes its share).
+__device__ inline void sens_write_rest(double *o, const double *s_Sa, const double *s_Sb, const double *s_SN) {
+  const int tid = threadIdx.x;
+  if (tid < 64) o[100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7)] = s_SN[tid];
+  if (tid < 16) {
+    const int a = tid >> 3, i = tid & 7;
+    o[(2 + i) * 10 + a] = s_Sb[tid];          // S_e[2 + i][a] = Sb[a][i]
+  }
+  if (tid < 4) o[(tid >> 1) * 10 + (tid & 1)] = s_Sa[tid];
+  if (tid < 20) {
+    const int a = tid / 10, j = tid % 10;
+    if (j >= 2) o[a * 10 + j] = 0.0;           // S_e[0:2][2:10] = 0
+  }
+  if (tid < 100) {
+    const int i = tid / 10, j = tid % 10;
+    if (i < 2 || j < 2) o[100 + tid] = 0.0;    // S_N outside the d-block
+  }
+}
+
+// Sensitivities of one K = 1 chain to its on-site covariance Gamma_A: for Delta = [E, Gamma_A]
+// (E antisymmetric), Re d e(G) = tr(Delta S_e) and d log N(G) = tr(Delta S_N), with the
+// transposed-trace convention tr(Delta S) = sum_ij Delta_ij S_ji.  With P = B G, C the
+// coefficients of Gamma_out in the local energy and R_k the rotated electric response,
+//   S_e[a-block]  = sum_x C[x, x]^T,
+//   S_e[b^T-block] from dB G B^T + B G dB^T (rows of G on the 5 neighbouring blocks),
+//   S_e[d-block]  = sum_z (P^T C P)[z, z]^T + ke sum_l sum_{i<j} R_k[j][i] G[z, u_j] (x) G[z, u_i],
+//   S_N[d-block]  = (1/2) sum_x G[x, x]  (log N = (1/2) log det M + const).
+// out[c][0..99] = Re S_e, out[c][100..199] = S_N (row-major 10 x 10).  L <= 16.
+// STAGE: the 8 rows of stripe z are staged in LDS (8 n float64 after U_z's 16 max_sites).
+template <typename T, bool STAGE>
+__global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double *out, int max_sites) {
+  extern __shared__ double s_dyn[];
+  double *s_U = s_dyn;                       // U_z[i][2w + a] = sum_j G[8z+i][8w+j] b[a][j], 8 x 2V
+  double *s_G = s_dyn + 16 * max_sites;      // stripe z, 8 x n (STAGE)
+  __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
+  __shared__ double s_R[GGF_ZN_MAX][16];
+  __shared__ double s_red[4][64];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int tid = threadIdx.x;
+  if (tid < 4) s_Sa[tid] = 0.0;
+  if (tid < 16) s_Sb[tid] = 0.0;
+  if (tid < 64) s_SN[tid] = 0.0;
+  sens_r_table(Tn, group, &s_R[0][0]);
+  __syncthreads();
+  // (1) per site: a-block, b-block and S_N
+  sens_sites<T>(cp, lk, L, group, G, n, Tn, s_Sa, s_Sb, s_SN);
   // (2) d-block: per row stripe z
   const int ij = tid & 63, part = tid >> 6;
   const int pi = ij >> 3, pj = ij & 7;
@@ -1192,21 +1226,142 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
     const double v = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
     // thread (pi, pj) summed (P^T C P)[pi][pj] for the d-block's transpose: S_d[pj][pi]
     o[(2 + pj) * 10 + 2 + pi] = v;
-    o[100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7)] = s_SN[tid];
   }
-  if (tid < 16) {
-    const int a = tid >> 3, i = tid & 7;
-    o[(2 + i) * 10 + a] = s_Sb[tid];          // S_e[2 + i][a] = Sb[a][i]
+  sens_write_rest(o, s_Sa, s_Sb, s_SN);
+}
+
+// The d-block of k_sens as two contractions per row stripe z (V <= 100, stripe staged):
+//   CU[2w + a][p] = sum over the 5 bilinear blocks (w, y) with row site w of C[w a][y b] U_z[p][2y + b],
+//   T_z[m][p]     = sum_a b[a][m mod 8] CU[2 (m / 8) + a][p] + ke sum_{j > i} R_l[j][i] G[8z + p][u_j]
+//                   (m = u_i of link l; every virtual Majorana belongs to one link),
+//   S_d[q][p]    += sum_m G[8z + p][m] T_z[m][q],
+// so the Hamiltonian's blocks are evaluated once per (site, row) rather than once per (site, row, column).
+// Dynamic LDS (float64): stripe 8 n, T_z n x 8 (U_z 8 x 2V at its start), CU 2V x 8, R group x 16.
+// Launched with 256 threads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, double *out, int max_sites) {
+  extern __shared__ double s_dyn[];
+  double *s_G = s_dyn;                       // stripe z, 8 x n
+  double *s_T = s_G + 64 * max_sites;        // T_z[m][p]
+  double *s_U = s_T;                         // U_z[i][2w + a], dead once CU is formed
+  double *s_CU = s_T + 64 * max_sites;       // CU[2w + a][p]
+  double *s_R = s_CU + 16 * max_sites;       // R_k, 16 per link value
+  __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int tid = threadIdx.x;
+  if (tid < 4) s_Sa[tid] = 0.0;
+  if (tid < 16) s_Sb[tid] = 0.0;
+  if (tid < 64) s_SN[tid] = 0.0;
+  sens_r_table(Tn, group, s_R);
+  __syncthreads();
+  sens_sites<T>(cp, lk, L, group, G, n, Tn, s_Sa, s_Sb, s_SN);
+  // final contraction: thread = (2 x 2 block of (p, q), one of 16 strided parts of m)
+  const int part = tid & 15, blk = tid >> 4;
+  const int p0 = 2 * (blk >> 2), q0 = 2 * (blk & 3);
+  double sd00 = 0.0, sd01 = 0.0, sd10 = 0.0, sd11 = 0.0;
+  // stripe z + 1 is loaded into registers while stripe z is contracted (8 n <= 25 x 256 for V <= 100)
+  constexpr int kStripeRegs = 25;
+  double pf[kStripeRegs];
+  auto load_stripe = [&](int z) {
+    const T *src = G + static_cast<size_t>(8 * z) * n;
+#pragma unroll
+    for (int k = 0; k < kStripeRegs; ++k) {
+      const int e = tid + 256 * k;
+      pf[k] = e < 8 * n ? static_cast<double>(src[e]) : 0.0;
+    }
+  };
+  load_stripe(0);
+  for (int z = 0; z < V; ++z) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kStripeRegs; ++k) {
+      const int e = tid + 256 * k;
+      if (e < 8 * n) s_G[e] = pf[k];
+    }
+    if (z + 1 < V) load_stripe(z + 1);
+    __syncthreads();
+    for (int e = tid; e < 16 * V; e += blockDim.x) {
+      const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, a = col & 1;
+      const double *grow = s_G + i * n + 8 * w;
+      double v = 0.0;
+      for (int j = 0; j < 8; ++j) v += grow[j] * Tn.b[a * 8 + j];
+      s_U[i * 2 * V + col] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < 8 * V; e += blockDim.x) {
+      const int w = e >> 3, p = e & 7;
+      double c0 = 0.0, c1 = 0.0;
+      for (int t = 0; t < 5; ++t) {
+        // the five blocks with row site w: on site, the hops to w + e1 and w + e2 (terms 1, 3 of w),
+        // the reverse hops from w - e1 and w - e2 (terms 2, 4 of those sites)
+        int owner = w, term = t;
+        if (t == 2) term = 3;
+        else if (t == 3) { owner = ggf_shift(w, L, -1, 0); term = 2; }
+        else if (t == 4) { owner = ggf_shift(w, L, 0, -1); term = 4; }
+        int wr, y;
+        double o[4];
+        h_term(cp, lk, L, group, owner, term, wr, y, o);
+        const double u0 = s_U[p * 2 * V + 2 * y], u1 = s_U[p * 2 * V + 2 * y + 1];
+        c0 += o[0] * u0 + o[1] * u1;
+        c1 += o[2] * u0 + o[3] * u1;
+      }
+      s_CU[(2 * w) * 8 + p] = c0;
+      s_CU[(2 * w + 1) * 8 + p] = c1;
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * V; e += blockDim.x) {
+      const int ell = e >> 3, p = e & 7;
+      int u[4];
+      ggf_link_u(ell, L, u);
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+      if (cp.ke != 0.0) {
+        const double *R = s_R + 16 * lk[ell];
+        const double g1 = s_G[p * n + u[1]], g2 = s_G[p * n + u[2]], g3 = s_G[p * n + u[3]];
+        q0 = cp.ke * (R[4] * g1 + R[8] * g2 + R[12] * g3);
+        q1 = cp.ke * (R[9] * g2 + R[13] * g3);
+        q2 = cp.ke * (R[14] * g3);
+      }
+      s_T[u[0] * 8 + p] = q0;
+      s_T[u[1] * 8 + p] = q1;
+      s_T[u[2] * 8 + p] = q2;
+      s_T[u[3] * 8 + p] = 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 8 * n; e += blockDim.x) {
+      const int m = e >> 3, p = e & 7, w = m >> 3, j = m & 7;
+      s_T[e] += Tn.b[j] * s_CU[(2 * w) * 8 + p] + Tn.b[8 + j] * s_CU[(2 * w + 1) * 8 + p];
+    }
+    __syncthreads();
+    for (int m = part; m < n; m += 16) {
+      const double g0 = s_G[p0 * n + m], g1 = s_G[(p0 + 1) * n + m];
+      const double2 t = *reinterpret_cast<const double2 *>(s_T + m * 8 + q0);
+      sd00 += g0 * t.x;
+      sd01 += g0 * t.y;
+      sd10 += g1 * t.x;
+      sd11 += g1 * t.y;
+    }
   }
-  if (tid < 4) o[(tid >> 1) * 10 + (tid & 1)] = s_Sa[tid];
-  if (tid < 20) {
-    const int a = tid / 10, j = tid % 10;
-    if (j >= 2) o[a * 10 + j] = 0.0;           // S_e[0:2][2:10] = 0
+  for (int off = 8; off > 0; off >>= 1) {
+    sd00 += __shfl_xor(sd00, off, 64);
+    sd01 += __shfl_xor(sd01, off, 64);
+    sd10 += __shfl_xor(sd10, off, 64);
+    sd11 += __shfl_xor(sd11, off, 64);
   }
-  if (tid < 100) {
-    const int i = tid / 10, j = tid % 10;
-    if (i < 2 || j < 2) o[100 + tid] = 0.0;    // S_N outside the d-block
+  __syncthreads();
+  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
+  if (part == 0) {
+    // sum_z (G_z T_z)[p][q] is S_d[q][p]
+    o[(2 + q0) * 10 + 2 + p0] = sd00;
+    o[(2 + q0 + 1) * 10 + 2 + p0] = sd01;
+    o[(2 + q0) * 10 + 2 + p0 + 1] = sd10;
+    o[(2 + q0 + 1) * 10 + 2 + p0 + 1] = sd11;
   }
+  sens_write_rest(o, s_Sa, s_Sb, s_SN);
 }
 
 // ---- Gamma_A sensitivities with K > 1 (L <= 8): per pair (a, b), with M_ab^-1 formed explicitly ----
@@ -1543,12 +1698,19 @@ void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int
     hipLaunchKernelGGL(k_energy<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
 }
 
-void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites) {
+void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group) {
+  const dim3 grid(lc.n_chains), block(256);
+  if (max_sites <= 100) {
+    // two-stage stripe contraction: stripe, T_z (U_z inside), CU and the R table in LDS
+    const size_t lds = (static_cast<size_t>(144) * max_sites + 16 * max_group) * sizeof(double);
+    if (lc.precision == 64) hipLaunchKernelGGL(k_sens_t<double>, grid, block, lds, lc.stream, lc, cp, out, max_sites);
+    else hipLaunchKernelGGL(k_sens_t<float>, grid, block, lds, lc.stream, lc, cp, out, max_sites);
+    return;
+  }
   // stage each row stripe (8 n = 64 V float64) in LDS while it and U_z fit in 64 KB (V <= 102)
   const size_t lds_u = static_cast<size_t>(16) * max_sites * sizeof(double);
   const size_t lds_g = static_cast<size_t>(64) * max_sites * sizeof(double);
   const bool stage = lds_u + lds_g <= 65536;
-  const dim3 grid(lc.n_chains), block(256);
   if (lc.precision == 64) {
     if (stage) hipLaunchKernelGGL((k_sens<double, true>), grid, block, lds_u + lds_g, lc.stream, lc, cp, out, max_sites);
     else hipLaunchKernelGGL((k_sens<double, false>), grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
