@@ -1252,8 +1252,11 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
   const TensorDev &Tn = lc.tensors[ch.tensor];
   const int n = ch.n, L = ch.L, V = L * L, group = ch.group;
   const T *G = static_cast<const T *>(lc.G) + ch.g_off;
-  const int8_t *lk = lc.links + ch.link_off;
+  const int8_t *lk_g = lc.links + ch.link_off;
+  __shared__ int8_t s_lk[200];               // the chain's link values (2V <= 200), read by every stage
+  const int8_t *lk = s_lk;
   const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * V; e += blockDim.x) s_lk[e] = lk_g[e];
   if (tid < 4) s_Sa[tid] = 0.0;
   if (tid < 16) s_Sb[tid] = 0.0;
   if (tid < 64) s_SN[tid] = 0.0;
