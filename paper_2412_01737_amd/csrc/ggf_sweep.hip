@@ -991,15 +991,15 @@ __device__ inline void coef_block(double2 coef, double o[4]) {
   o[3] = 0.25 * coef.y;
 }
 
-// The five bilinear blocks of H that involve site x: term 0 on-site (x, x), terms 1 + 2 mu
-// the hop (x, x + mu), terms 2 + 2 mu the reverse (x + mu, x); (row site, column site, block).
-__device__ inline void h_term(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
-                              int &y, double o[4]) {
+// The five bilinear terms of H that involve site x: term 0 on-site (x, x), terms 1 + 2 mu
+// the hop (x, x + mu), terms 2 + 2 mu the reverse (x + mu, x); (row site, column site, complex
+// coefficient of <phi_w^+ phi_y>).
+__device__ inline double2 h_coef(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
+                                 int &y) {
   if (term == 0) {
     const int sgn = (((x % L) + x / L) & 1) ? -1 : 1;
     w = y = x;
-    coef_block(make_double2(cp.mu + sgn * cp.m, 0.0), o);
-    return;
+    return make_double2(cp.mu + sgn * cp.m, 0.0);
   }
   const int mu = (term - 1) >> 1;
   const int xn = mu == 0 ? ggf_shift(x, L, 1, 0) : ggf_shift(x, L, 0, 1);
@@ -1008,12 +1008,17 @@ __device__ inline void h_term(const EnergyCp &cp, const int8_t *lk, int L, int g
   if ((term & 1) == 1) {           // t i eta D <phi_x^+ phi_xn>
     w = x;
     y = xn;
-    coef_block(make_double2(-te * D.y, te * D.x), o);
-  } else {                         // -t i eta D^* <phi_xn^+ phi_x>
-    w = xn;
-    y = x;
-    coef_block(make_double2(-te * D.y, -te * D.x), o);
+    return make_double2(-te * D.y, te * D.x);
   }
+  w = xn;                          // -t i eta D^* <phi_xn^+ phi_x>
+  y = x;
+  return make_double2(-te * D.y, -te * D.x);
+}
+
+// The same terms as coefficient blocks of Gamma_out[2w + a][2y + b].
+__device__ inline void h_term(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
+                              int &y, double o[4]) {
+  coef_block(h_coef(cp, lk, L, group, x, term, w, y), o);
 }
 
 // Rotated electric response R_k = O_k eq0 O_k^T (real part) for every link value k, 16 doubles each.
@@ -1236,16 +1241,20 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
 //                   (m = u_i of link l; every virtual Majorana belongs to one link),
 //   S_d[q][p]    += sum_m G[8z + p][m] T_z[m][q],
 // so the Hamiltonian's blocks are evaluated once per (site, row) rather than once per (site, row, column).
-// Dynamic LDS (float64): stripe 8 n, T_z n x 8 (U_z 8 x 2V at its start), CU 2V x 8, R group x 16.
+// Dynamic LDS: stripe 8 (n + 2), T_z n x 8 (U_z 2V x 8 at its start), CU 2V x 8, R max_group x 16 (float64);
+// the 5 V block coefficients (complex), their column sites and the links' Majoranas (int16).
 // Launched with 256 threads.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, double *out, int max_sites) {
+__global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, double *out, int max_sites, int max_group) {
   extern __shared__ double s_dyn[];
-  double *s_G = s_dyn;                       // stripe z, 8 x n
-  double *s_T = s_G + 64 * max_sites;        // T_z[m][p]
-  double *s_U = s_T;                         // U_z[i][2w + a], dead once CU is formed
+  double *s_G = s_dyn;                       // stripe z, 8 rows of pitch n + 2 (rows on distinct banks)
+  double *s_T = s_G + 64 * max_sites + 16;   // T_z[m][p]
+  double *s_U = s_T;                         // U_z[2w + a][i], dead once CU is formed
   double *s_CU = s_T + 64 * max_sites;       // CU[2w + a][p]
   double *s_R = s_CU + 16 * max_sites;       // R_k, 16 per link value
+  double2 *s_cc = reinterpret_cast<double2 *>(s_R + 16 * max_group);   // coefficients of the 5 blocks of row site w
+  int16_t *s_cy = reinterpret_cast<int16_t *>(s_cc + 5 * max_sites);  // their column sites
+  int16_t *s_lu = s_cy + 5 * max_sites;                              // the 4 Majoranas of each link
   __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
   const int c = blockIdx.x;
   const ChainDev ch = lc.chains[c];
@@ -1261,70 +1270,88 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
   if (tid < 16) s_Sb[tid] = 0.0;
   if (tid < 64) s_SN[tid] = 0.0;
   sens_r_table(Tn, group, s_R);
+  __syncthreads();   // s_lk complete before the tables read it
+  for (int e = tid; e < 5 * V; e += blockDim.x) {
+    // row site w: on site, the hops to w + e1 and w + e2 (terms 1, 3 of w), the reverse hops from
+    // w - e1 and w - e2 (terms 2, 4 of those sites)
+    const int w = e / 5, t = e - 5 * w;
+    int owner = w, term = t;
+    if (t == 2) term = 3;
+    else if (t == 3) { owner = ggf_shift(w, L, -1, 0); term = 2; }
+    else if (t == 4) { owner = ggf_shift(w, L, 0, -1); term = 4; }
+    int wr, y;
+    s_cc[e] = h_coef(cp, lk, L, group, owner, term, wr, y);
+    s_cy[e] = static_cast<int16_t>(y);
+  }
+  for (int ell = tid; ell < 2 * V; ell += blockDim.x) {
+    int u[4];
+    ggf_link_u(ell, L, u);
+    for (int k = 0; k < 4; ++k) s_lu[4 * ell + k] = static_cast<int16_t>(u[k]);
+  }
   __syncthreads();
   sens_sites<T>(cp, lk, L, group, G, n, Tn, s_Sa, s_Sb, s_SN);
   // final contraction: thread = (2 x 2 block of (p, q), one of 16 strided parts of m)
   const int part = tid & 15, blk = tid >> 4;
   const int p0 = 2 * (blk >> 2), q0 = 2 * (blk & 3);
   double sd00 = 0.0, sd01 = 0.0, sd10 = 0.0, sd11 = 0.0;
-  // stripe z + 1 is loaded into registers while stripe z is contracted (8 n <= 25 x 256 for V <= 100)
-  constexpr int kStripeRegs = 25;
-  double pf[kStripeRegs];
+  // stripe z + 1 is loaded into registers while stripe z is contracted: row r, columns tid + 256 k
+  // (n <= 800 for V <= 100, so 4 columns per row and thread)
+  const int pitch = n + 2;
+  constexpr int kCols = 4;
+  double pf[8 * kCols];
   auto load_stripe = [&](int z) {
     const T *src = G + static_cast<size_t>(8 * z) * n;
 #pragma unroll
-    for (int k = 0; k < kStripeRegs; ++k) {
-      const int e = tid + 256 * k;
-      pf[k] = e < 8 * n ? static_cast<double>(src[e]) : 0.0;
-    }
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int k = 0; k < kCols; ++k) {
+        const int col = tid + 256 * k;
+        pf[r * kCols + k] = col < n ? static_cast<double>(src[static_cast<size_t>(r) * n + col]) : 0.0;
+      }
   };
   load_stripe(0);
   for (int z = 0; z < V; ++z) {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kStripeRegs; ++k) {
-      const int e = tid + 256 * k;
-      if (e < 8 * n) s_G[e] = pf[k];
-    }
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int k = 0; k < kCols; ++k) {
+        const int col = tid + 256 * k;
+        if (col < n) s_G[r * pitch + col] = pf[r * kCols + k];
+      }
     if (z + 1 < V) load_stripe(z + 1);
     __syncthreads();
     for (int e = tid; e < 16 * V; e += blockDim.x) {
-      const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, a = col & 1;
-      const double *grow = s_G + i * n + 8 * w;
+      const int i = e & 7, col = e >> 3, w = col >> 1, a = col & 1;
+      const double *grow = s_G + i * pitch + 8 * w;
       double v = 0.0;
       for (int j = 0; j < 8; ++j) v += grow[j] * Tn.b[a * 8 + j];
-      s_U[i * 2 * V + col] = v;
+      s_U[e] = v;                            // U_z[2w + a][i]
     }
     __syncthreads();
     for (int e = tid; e < 8 * V; e += blockDim.x) {
       const int w = e >> 3, p = e & 7;
       double c0 = 0.0, c1 = 0.0;
+#pragma unroll
       for (int t = 0; t < 5; ++t) {
-        // the five blocks with row site w: on site, the hops to w + e1 and w + e2 (terms 1, 3 of w),
-        // the reverse hops from w - e1 and w - e2 (terms 2, 4 of those sites)
-        int owner = w, term = t;
-        if (t == 2) term = 3;
-        else if (t == 3) { owner = ggf_shift(w, L, -1, 0); term = 2; }
-        else if (t == 4) { owner = ggf_shift(w, L, 0, -1); term = 4; }
-        int wr, y;
-        double o[4];
-        h_term(cp, lk, L, group, owner, term, wr, y, o);
-        const double u0 = s_U[p * 2 * V + 2 * y], u1 = s_U[p * 2 * V + 2 * y + 1];
-        c0 += o[0] * u0 + o[1] * u1;
-        c1 += o[2] * u0 + o[3] * u1;
+        // block coef * (1/4) [[-i, 1], [-1, -i]] (real part), as coef_block
+        const double2 cf = s_cc[5 * w + t];
+        const int y = s_cy[5 * w + t];
+        const double u0 = s_U[(2 * y) * 8 + p], u1 = s_U[(2 * y + 1) * 8 + p];
+        c0 += cf.y * u0 + cf.x * u1;
+        c1 += cf.y * u1 - cf.x * u0;
       }
-      s_CU[(2 * w) * 8 + p] = c0;
-      s_CU[(2 * w + 1) * 8 + p] = c1;
+      s_CU[(2 * w) * 8 + p] = 0.25 * c0;
+      s_CU[(2 * w + 1) * 8 + p] = 0.25 * c1;
     }
     __syncthreads();
     for (int e = tid; e < 16 * V; e += blockDim.x) {
       const int ell = e >> 3, p = e & 7;
-      int u[4];
-      ggf_link_u(ell, L, u);
+      const int u[4] = {s_lu[4 * ell], s_lu[4 * ell + 1], s_lu[4 * ell + 2], s_lu[4 * ell + 3]};
       double q0 = 0.0, q1 = 0.0, q2 = 0.0;
       if (cp.ke != 0.0) {
         const double *R = s_R + 16 * lk[ell];
-        const double g1 = s_G[p * n + u[1]], g2 = s_G[p * n + u[2]], g3 = s_G[p * n + u[3]];
+        const double g1 = s_G[p * pitch + u[1]], g2 = s_G[p * pitch + u[2]], g3 = s_G[p * pitch + u[3]];
         q0 = cp.ke * (R[4] * g1 + R[8] * g2 + R[12] * g3);
         q1 = cp.ke * (R[9] * g2 + R[13] * g3);
         q2 = cp.ke * (R[14] * g3);
@@ -1341,7 +1368,7 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
     }
     __syncthreads();
     for (int m = part; m < n; m += 16) {
-      const double g0 = s_G[p0 * n + m], g1 = s_G[(p0 + 1) * n + m];
+      const double g0 = s_G[p0 * pitch + m], g1 = s_G[(p0 + 1) * pitch + m];
       const double2 t = *reinterpret_cast<const double2 *>(s_T + m * 8 + q0);
       sd00 += g0 * t.x;
       sd01 += g0 * t.y;
@@ -1704,10 +1731,13 @@ void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group) {
   const dim3 grid(lc.n_chains), block(256);
   if (max_sites <= 100) {
-    // two-stage stripe contraction: stripe, T_z (U_z inside), CU and the R table in LDS
-    const size_t lds = (static_cast<size_t>(144) * max_sites + 16 * max_group) * sizeof(double);
-    if (lc.precision == 64) hipLaunchKernelGGL(k_sens_t<double>, grid, block, lds, lc.stream, lc, cp, out, max_sites);
-    else hipLaunchKernelGGL(k_sens_t<float>, grid, block, lds, lc.stream, lc, cp, out, max_sites);
+    // two-stage stripe contraction: stripe, T_z (U_z inside), CU and the tables in LDS (80.8 KB at V = 64)
+    const size_t lds = (static_cast<size_t>(144) * max_sites + 16 + 16 * max_group) * sizeof(double) +
+                       static_cast<size_t>(5) * max_sites * sizeof(double2) + static_cast<size_t>(13) * max_sites * 2;
+    if (lc.precision == 64)
+      hipLaunchKernelGGL(k_sens_t<double>, grid, block, lds, lc.stream, lc, cp, out, max_sites, max_group);
+    else
+      hipLaunchKernelGGL(k_sens_t<float>, grid, block, lds, lc.stream, lc, cp, out, max_sites, max_group);
     return;
   }
   // stage each row stripe (8 n = 64 V float64) in LDS while it and U_z fit in 64 KB (V <= 102)
