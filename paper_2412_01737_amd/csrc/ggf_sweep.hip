@@ -1422,15 +1422,20 @@ __global__ __launch_bounds__(256) void k_form_pair(LaunchCtx lc, int pr, double2
   __syncthreads();
   double2 *out = Gab + static_cast<size_t>(c) * nmax * nmax;
   for (int r = threadIdx.x >> 5; r < n; r += blockDim.x >> 5) {
-    double2 ay[8];   // (G_S Y)[r][q]
-    for (int q = 0; q < s; ++q) {
+    double2 ay[8];   // (G_S Y)[r][q], zero for q >= s (fixed trip counts keep it in registers)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
       double2 v = make_double2(0.0, 0.0);
-      for (int p = 0; p < s; ++p) v = cadd(v, cscale(s_Y[pr][p * 8 + q], s_A[r * 8 + p]));
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < s && q < s) v = cadd(v, cscale(s_Y[pr][p * 8 + q], s_A[r * 8 + p]));
       ay[q] = v;
     }
     for (int col = threadIdx.x & 31; col < n; col += 32) {
       double2 v = make_double2(static_cast<double>(G[static_cast<size_t>(r) * n + col]), 0.0);
-      for (int q = 0; q < s; ++q) v = cadd(v, cscale(ay[q], s_A[col * 8 + q]));
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < s) v = cadd(v, cscale(ay[q], s_A[col * 8 + q]));
       out[static_cast<size_t>(r) * n + col] = v;
     }
   }
@@ -1474,10 +1479,17 @@ __device__ inline void h_term_c(const EnergyCp &cp, const int8_t *lk, int L, int
 // pr == 0 writes the row, later pairs add to it.  L <= 8.
 __global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, int pr, const double2 *Gab, int nmax,
                                                    const double *erows, double *out) {
-  __shared__ double2 s_U[16 * 64];        // U_z[i][2w + a], 8 x 2V
+  // dynamic LDS: T_z[m][p] (n x 8, U_z[2w + a][i] at its start), CU[2w + a][p] (2V x 8), the block
+  // coefficients of each row site (5 V, complex), their column sites (int16) and the links' Majoranas (int16)
+  extern __shared__ double2 s_dyn2[];
+  double2 *s_T = s_dyn2;
+  double2 *s_U = s_T;
+  double2 *s_CU = s_T + 8 * nmax;
+  double2 *s_cc = s_CU + 2 * nmax;
+  int16_t *s_cy = reinterpret_cast<int16_t *>(s_cc + 5 * (nmax / 8));
+  int16_t *s_lu = s_cy + 5 * (nmax / 8);
   __shared__ double2 s_sl[128][6];        // electric slopes of the pair per link
   __shared__ double2 s_Sa[4], s_Sb[16], s_SN[64];
-  __shared__ double2 s_red[4][64];
   __shared__ double2 s_wt[2];             // om/S, om/S (h - E)
   const int c = blockIdx.x;
   const ChainDev ch = lc.chains[c];
@@ -1520,6 +1532,21 @@ __global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, in
         s_sl[ell][k++] = row[i];
       }
     }
+    int u[4];
+    ggf_link_u(ell, L, u);
+    for (int q = 0; q < 4; ++q) s_lu[4 * ell + q] = static_cast<int16_t>(u[q]);
+  }
+  for (int e = tid; e < 5 * V; e += blockDim.x) {
+    // row site w: on site, the hops to w + e1 and w + e2 (terms 1, 3 of w), the reverse hops from
+    // w - e1 and w - e2 (terms 2, 4 of those sites)
+    const int w = e / 5, t = e - 5 * w;
+    int owner = w, term = t;
+    if (t == 2) term = 3;
+    else if (t == 3) { owner = ggf_shift(w, L, -1, 0); term = 2; }
+    else if (t == 4) { owner = ggf_shift(w, L, 0, -1); term = 4; }
+    int wr, y;
+    s_cc[e] = h_coef(cp, lk, L, group, owner, term, wr, y);
+    s_cy[e] = static_cast<int16_t>(y);
   }
   __syncthreads();
   for (int x = tid; x < V; x += blockDim.x) {
@@ -1580,58 +1607,92 @@ __global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, in
         atomicAdd(&s_SN[i * 8 + j].y, 0.5 * g.y);
       }
   }
-  const int ij = tid & 63, part = tid >> 6;
-  const int pi = ij >> 3, pj = ij & 7;
-  double2 sd = make_double2(0.0, 0.0);
+  // d-block in two contractions per row stripe z (as k_sens_t, complex):
+  //   CU = C U_z^T, T_z = b^T CU + the pair's electric slopes, acc(p, q) += sum_m M_ab^-1[8z + p][m] T_z[m][q]
+  const int part = tid & 15, blk = tid >> 4;
+  const int p0 = 2 * (blk >> 2), q0 = 2 * (blk & 3);
+  double2 sd[4];
+  for (int q = 0; q < 4; ++q) sd[q] = make_double2(0.0, 0.0);
   for (int z = 0; z < V; ++z) {
     __syncthreads();
-    for (int e = tid; e < 16 * V; e += blockDim.x) {
-      const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, al = col & 1;
-      const double2 *grow = Gc + static_cast<size_t>(8 * z + i) * n + 8 * w;
-      double2 v = make_double2(0.0, 0.0);
-      for (int j = 0; j < 8; ++j) v = cadd(v, cscale(grow[j], Tn.b[al * 8 + j]));
-      s_U[i * 2 * V + col] = v;
+    // U_z[2w + a][i]: 16 V <= 1024 items, four per thread with their loads issued together
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k;
+      if (e < 16 * V) {
+        const int i = e & 7, col = e >> 3, w = col >> 1, al = col & 1;
+        const double2 *grow = Gc + static_cast<size_t>(8 * z + i) * n + 8 * w;
+        double2 v = make_double2(0.0, 0.0);
+        for (int jj = 0; jj < 8; ++jj) v = cadd(v, cscale(grow[jj], Tn.b[al * 8 + jj]));
+        s_U[e] = v;
+      }
     }
     __syncthreads();
-    double2 acc = make_double2(0.0, 0.0);
-    for (int x = part; x < V; x += 4)
-      for (int term = 0; term < 5; ++term) {
-        int w, y;
+    for (int e = tid; e < 8 * V; e += blockDim.x) {
+      const int w = e >> 3, p = e & 7;
+      double2 c0 = make_double2(0.0, 0.0), c1 = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
         double2 o4[4];
-        h_term_c(cp, lk, L, group, x, term, w, y, o4);
-        const double2 ui0 = s_U[pi * 2 * V + 2 * w], ui1 = s_U[pi * 2 * V + 2 * w + 1];
-        const double2 uj0 = s_U[pj * 2 * V + 2 * y], uj1 = s_U[pj * 2 * V + 2 * y + 1];
-        acc = cadd(acc, cmul(ui0, cadd(cmul(o4[0], uj0), cmul(o4[1], uj1))));
-        acc = cadd(acc, cmul(ui1, cadd(cmul(o4[2], uj0), cmul(o4[3], uj1))));
+        coef_block_c(s_cc[5 * w + t], o4);
+        const int y = s_cy[5 * w + t];
+        const double2 u0 = s_U[(2 * y) * 8 + p], u1 = s_U[(2 * y + 1) * 8 + p];
+        c0 = cadd(c0, cadd(cmul(o4[0], u0), cmul(o4[1], u1)));
+        c1 = cadd(c1, cadd(cmul(o4[2], u0), cmul(o4[3], u1)));
       }
-    if (cp.ke != 0.0)
-      for (int ell = part; ell < 2 * V; ell += 4) {
-        int u[4];
-        ggf_link_u(ell, L, u);
-        double2 vp[4], vq[4];
-        for (int i = 0; i < 4; ++i) {
-          vp[i] = Gc[static_cast<size_t>(8 * z + pj) * n + u[i]];
-          vq[i] = Gc[static_cast<size_t>(8 * z + pi) * n + u[i]];
-        }
-        int k = 0;
-        for (int i = 0; i < 4; ++i)
-          for (int j = i + 1; j < 4; ++j) acc = cadd(acc, cscale(cmul(s_sl[ell][k++], cmul(vp[j], vq[i])), cp.ke));
+      s_CU[(2 * w) * 8 + p] = c0;
+      s_CU[(2 * w + 1) * 8 + p] = c1;
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * V; e += blockDim.x) {
+      const int ell = e >> 3, p = e & 7;
+      const int u[4] = {s_lu[4 * ell], s_lu[4 * ell + 1], s_lu[4 * ell + 2], s_lu[4 * ell + 3]};
+      double2 q0v = make_double2(0.0, 0.0), q1v = q0v, q2v = q0v;
+      if (cp.ke != 0.0) {
+        const double2 *grow = Gc + static_cast<size_t>(8 * z + p) * n;
+        const double2 g1 = grow[u[1]], g2 = grow[u[2]], g3 = grow[u[3]];
+        // s_sl[ell]: R[1][0], R[2][0], R[3][0], R[2][1], R[3][1], R[3][2]
+        q0v = cscale(cadd(cadd(cmul(s_sl[ell][0], g1), cmul(s_sl[ell][1], g2)), cmul(s_sl[ell][2], g3)), cp.ke);
+        q1v = cscale(cadd(cmul(s_sl[ell][3], g2), cmul(s_sl[ell][4], g3)), cp.ke);
+        q2v = cscale(cmul(s_sl[ell][5], g3), cp.ke);
       }
-    sd = cadd(sd, acc);
+      s_T[u[0] * 8 + p] = q0v;
+      s_T[u[1] * 8 + p] = q1v;
+      s_T[u[2] * 8 + p] = q2v;
+      s_T[u[3] * 8 + p] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = tid; e < 8 * n; e += blockDim.x) {
+      const int m = e >> 3, p = e & 7, w = m >> 3, jj = m & 7;
+      s_T[e] = cadd(s_T[e], cadd(cscale(s_CU[(2 * w) * 8 + p], Tn.b[jj]), cscale(s_CU[(2 * w + 1) * 8 + p], Tn.b[8 + jj])));
+    }
+    __syncthreads();
+    const double2 *r0 = Gc + static_cast<size_t>(8 * z + p0) * n, *r1 = r0 + n;
+    for (int m = part; m < n; m += 16) {
+      const double2 g0 = r0[m], g1 = r1[m], t0 = s_T[m * 8 + q0], t1 = s_T[m * 8 + q0 + 1];
+      sd[0] = cadd(sd[0], cmul(g0, t0));
+      sd[1] = cadd(sd[1], cmul(g0, t1));
+      sd[2] = cadd(sd[2], cmul(g1, t0));
+      sd[3] = cadd(sd[3], cmul(g1, t1));
+    }
   }
-  s_red[part][ij] = sd;
+  for (int off = 8; off > 0; off >>= 1)
+    for (int q = 0; q < 4; ++q) {
+      sd[q].x += __shfl_xor(sd[q].x, off, 64);
+      sd[q].y += __shfl_xor(sd[q].y, off, 64);
+    }
   __syncthreads();
   // combine: S_e^ab entries e and S_N^ab entries n: row += Re(om/S e + om/S (h - E) n), S_N += Re(om/S n)
   const double2 w0 = s_wt[0], w1 = s_wt[1];
   const bool first = pr == 0;
   auto put = [&](int idx, double v) { o[idx] = first ? v : o[idx] + v; };
-  if (tid < 64) {
-    const double2 v = cadd(cadd(s_red[0][tid], s_red[1][tid]), cadd(s_red[2][tid], s_red[3][tid]));
-    const double2 sn = s_SN[pj * 8 + pi];   // S_N^ab[2+pj][2+pi]
-    put((2 + pj) * 10 + 2 + pi, cmul(w0, v).x + cmul(w1, sn).x);
-    const double2 sn2 = s_SN[tid];
-    put(100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7), cmul(w0, sn2).x);
-  }
+  if (part == 0)
+    for (int q = 0; q < 4; ++q) {
+      // acc(p, q') is S_d^ab[q'][p]; S_N^ab[2 + q'][2 + p] = s_SN[q' * 8 + p]
+      const int pp = p0 + (q >> 1), qq = q0 + (q & 1);
+      put((2 + qq) * 10 + 2 + pp, cmul(w0, sd[q]).x + cmul(w1, s_SN[qq * 8 + pp]).x);
+    }
+  if (tid < 64) put(100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7), cmul(w0, s_SN[tid]).x);
   if (tid < 16) {
     const int al = tid >> 3, i = tid & 7;
     put((2 + i) * 10 + al, cmul(w0, s_Sb[tid]).x);
@@ -1756,12 +1817,15 @@ void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int m
 void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,
                            double *out, int kmax) {
   const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
+  // k_sens_pair: T_z (8 n), CU (2 n), coefficients (5 V) complex; column sites (5 V), Majoranas (n) int16
+  const size_t lds_s = (static_cast<size_t>(10) * nmax + 5 * (nmax / 8)) * sizeof(double2) +
+                       (static_cast<size_t>(5) * (nmax / 8) + nmax) * sizeof(int16_t);
   for (int pr = 0; pr < kmax * kmax; ++pr) {
     if (lc.precision == 64)
       hipLaunchKernelGGL(k_form_pair<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
     else
       hipLaunchKernelGGL(k_form_pair<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
-    hipLaunchKernelGGL(k_sens_pair, dim3(lc.n_chains), dim3(256), 0, lc.stream, lc, cp, pr, gab, nmax, erows, out);
+    hipLaunchKernelGGL(k_sens_pair, dim3(lc.n_chains), dim3(256), lds_s, lc.stream, lc, cp, pr, gab, nmax, erows, out);
   }
 }
 
