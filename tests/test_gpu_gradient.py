@@ -47,6 +47,21 @@ def test_sensitivity_rows(L, group, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("L,group", [(10, 2), (12, 3)])
+def test_sensitivity_rows_large(L, group):
+    """V = 100 (the largest lattice of the two-stage kernel, whose stripe and T_z fill its LDS) and
+    V = 144 (the one-stage kernel with rows read from global memory)."""
+    say(f"sensitivities L={L} Z{group} float64")
+    spec = spec_for(L, 1, group)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * 2, init=1)
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    for c in range(2):
+        _check_sens(rows[c], an, ctx.get_state(c)[0], 1e-10)
+    ctx.close()
+
+
 def test_sensitivity_full_size_sampled():
     """4096 chains of 8x8 Z2 (float64) in one launch; two chains checked, every row finite."""
     L, chains = 8, 4096
