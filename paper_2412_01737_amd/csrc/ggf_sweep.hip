@@ -1243,9 +1243,9 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
 // so the Hamiltonian's blocks are evaluated once per (site, row) rather than once per (site, row, column).
 // Dynamic LDS: stripe 8 (n + 2), T_z n x 8 (U_z 2V x 8 at its start), CU 2V x 8, R max_group x 16 (float64);
 // the 5 V block coefficients (complex), their column sites and the links' Majoranas (int16).
-// Launched with 256 threads.
+// Launched with 512 threads.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, double *out, int max_sites, int max_group) {
+__global__ __launch_bounds__(512, 4) void k_sens_t(LaunchCtx lc, EnergyCp cp, double *out, int max_sites, int max_group) {
   extern __shared__ double s_dyn[];
   double *s_G = s_dyn;                       // stripe z, 8 rows of pitch n + 2 (rows on distinct banks)
   double *s_T = s_G + 64 * max_sites + 16;   // T_z[m][p]
@@ -1290,14 +1290,14 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
   }
   __syncthreads();
   sens_sites<T>(cp, lk, L, group, G, n, Tn, s_Sa, s_Sb, s_SN);
-  // final contraction: thread = (2 x 2 block of (p, q), one of 16 strided parts of m)
-  const int part = tid & 15, blk = tid >> 4;
+  // final contraction: thread = (2 x 2 block of (p, q), one of 32 strided parts of m)
+  const int part = tid & 31, blk = tid >> 5;
   const int p0 = 2 * (blk >> 2), q0 = 2 * (blk & 3);
   double sd00 = 0.0, sd01 = 0.0, sd10 = 0.0, sd11 = 0.0;
-  // stripe z + 1 is loaded into registers while stripe z is contracted: row r, columns tid + 256 k
-  // (n <= 800 for V <= 100, so 4 columns per row and thread)
+  // stripe z + 1 is loaded into registers while stripe z is contracted: row r, columns tid + 512 k
+  // (n <= 800 for V <= 100, so 2 columns per row and thread)
   const int pitch = n + 2;
-  constexpr int kCols = 4;
+  constexpr int kCols = 2;
   double pf[8 * kCols];
   auto load_stripe = [&](int z) {
     const T *src = G + static_cast<size_t>(8 * z) * n;
@@ -1305,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
     for (int r = 0; r < 8; ++r)
 #pragma unroll
       for (int k = 0; k < kCols; ++k) {
-        const int col = tid + 256 * k;
+        const int col = tid + 512 * k;
         pf[r * kCols + k] = col < n ? static_cast<double>(src[static_cast<size_t>(r) * n + col]) : 0.0;
       }
   };
@@ -1316,7 +1316,7 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
     for (int r = 0; r < 8; ++r)
 #pragma unroll
       for (int k = 0; k < kCols; ++k) {
-        const int col = tid + 256 * k;
+        const int col = tid + 512 * k;
         if (col < n) s_G[r * pitch + col] = pf[r * kCols + k];
       }
     if (z + 1 < V) load_stripe(z + 1);
@@ -1367,7 +1367,7 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
       s_T[e] += Tn.b[j] * s_CU[(2 * w) * 8 + p] + Tn.b[8 + j] * s_CU[(2 * w + 1) * 8 + p];
     }
     __syncthreads();
-    for (int m = part; m < n; m += 16) {
+    for (int m = part; m < n; m += 32) {
       const double g0 = s_G[p0 * pitch + m], g1 = s_G[(p0 + 1) * pitch + m];
       const double2 t = *reinterpret_cast<const double2 *>(s_T + m * 8 + q0);
       sd00 += g0 * t.x;
@@ -1376,7 +1376,7 @@ __global__ __launch_bounds__(256) void k_sens_t(LaunchCtx lc, EnergyCp cp, doubl
       sd11 += g1 * t.y;
     }
   }
-  for (int off = 8; off > 0; off >>= 1) {
+  for (int off = 16; off > 0; off >>= 1) {
     sd00 += __shfl_xor(sd00, off, 64);
     sd01 += __shfl_xor(sd01, off, 64);
     sd10 += __shfl_xor(sd10, off, 64);
@@ -1792,13 +1792,14 @@ void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group) {
   const dim3 grid(lc.n_chains), block(256);
   if (max_sites <= 100) {
+    const dim3 block512(512);
     // two-stage stripe contraction: stripe, T_z (U_z inside), CU and the tables in LDS (80.8 KB at V = 64)
     const size_t lds = (static_cast<size_t>(144) * max_sites + 16 + 16 * max_group) * sizeof(double) +
                        static_cast<size_t>(5) * max_sites * sizeof(double2) + static_cast<size_t>(13) * max_sites * 2;
     if (lc.precision == 64)
-      hipLaunchKernelGGL(k_sens_t<double>, grid, block, lds, lc.stream, lc, cp, out, max_sites, max_group);
+      hipLaunchKernelGGL(k_sens_t<double>, grid, block512, lds, lc.stream, lc, cp, out, max_sites, max_group);
     else
-      hipLaunchKernelGGL(k_sens_t<float>, grid, block, lds, lc.stream, lc, cp, out, max_sites, max_group);
+      hipLaunchKernelGGL(k_sens_t<float>, grid, block512, lds, lc.stream, lc, cp, out, max_sites, max_group);
     return;
   }
   // stage each row stripe (8 n = 64 V float64) in LDS while it and U_z fit in 64 KB (V <= 102)
