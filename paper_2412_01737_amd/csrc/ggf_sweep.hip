@@ -1476,8 +1476,8 @@ __device__ inline void h_term_c(const EnergyCp &cp, const int8_t *lk, int L, int
 // k_sens with the complex M_ab^-1 of Gab and the pair's electric slopes), weighted by the
 // pair's om / S and combined with h_ab and E from the chain's energy row:
 //   S_e += Re (om/S) [S_e^ab + (h_ab - E) S_N^ab],   S_N += Re (om/S) S_N^ab.
-// pr == 0 writes the row, later pairs add to it.  L <= 8.
-__global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, int pr, const double2 *Gab, int nmax,
+// pr == 0 writes the row, later pairs add to it.  L <= 8; launched with 512 threads.
+__global__ __launch_bounds__(512, 2) void k_sens_pair(LaunchCtx lc, EnergyCp cp, int pr, const double2 *Gab, int nmax,
                                                    const double *erows, double *out) {
   // dynamic LDS: T_z[m][p] (n x 8, U_z[2w + a][i] at its start), CU[2w + a][p] (2V x 8), the block
   // coefficients of each row site (5 V, complex), their column sites (int16) and the links' Majoranas (int16)
@@ -1609,16 +1609,16 @@ __global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, in
   }
   // d-block in two contractions per row stripe z (as k_sens_t, complex):
   //   CU = C U_z^T, T_z = b^T CU + the pair's electric slopes, acc(p, q) += sum_m M_ab^-1[8z + p][m] T_z[m][q]
-  const int part = tid & 15, blk = tid >> 4;
+  const int part = tid & 31, blk = tid >> 5;
   const int p0 = 2 * (blk >> 2), q0 = 2 * (blk & 3);
   double2 sd[4];
   for (int q = 0; q < 4; ++q) sd[q] = make_double2(0.0, 0.0);
   for (int z = 0; z < V; ++z) {
     __syncthreads();
-    // U_z[2w + a][i]: 16 V <= 1024 items, four per thread with their loads issued together
+    // U_z[2w + a][i]: 16 V <= 1024 items, two per thread with their loads issued together
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = tid + 256 * k;
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + 512 * k;
       if (e < 16 * V) {
         const int i = e & 7, col = e >> 3, w = col >> 1, al = col & 1;
         const double2 *grow = Gc + static_cast<size_t>(8 * z + i) * n + 8 * w;
@@ -1668,7 +1668,7 @@ __global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, in
     }
     __syncthreads();
     const double2 *r0 = Gc + static_cast<size_t>(8 * z + p0) * n, *r1 = r0 + n;
-    for (int m = part; m < n; m += 16) {
+    for (int m = part; m < n; m += 32) {
       const double2 g0 = r0[m], g1 = r1[m], t0 = s_T[m * 8 + q0], t1 = s_T[m * 8 + q0 + 1];
       sd[0] = cadd(sd[0], cmul(g0, t0));
       sd[1] = cadd(sd[1], cmul(g0, t1));
@@ -1676,7 +1676,7 @@ __global__ __launch_bounds__(256) void k_sens_pair(LaunchCtx lc, EnergyCp cp, in
       sd[3] = cadd(sd[3], cmul(g1, t1));
     }
   }
-  for (int off = 8; off > 0; off >>= 1)
+  for (int off = 16; off > 0; off >>= 1)
     for (int q = 0; q < 4; ++q) {
       sd[q].x += __shfl_xor(sd[q].x, off, 64);
       sd[q].y += __shfl_xor(sd[q].y, off, 64);
@@ -1826,7 +1826,7 @@ void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab
       hipLaunchKernelGGL(k_form_pair<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
     else
       hipLaunchKernelGGL(k_form_pair<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
-    hipLaunchKernelGGL(k_sens_pair, dim3(lc.n_chains), dim3(256), lds_s, lc.stream, lc, cp, pr, gab, nmax, erows, out);
+    hipLaunchKernelGGL(k_sens_pair, dim3(lc.n_chains), dim3(512), lds_s, lc.stream, lc, cp, pr, gab, nmax, erows, out);
   }
 }
 
