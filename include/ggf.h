@@ -80,6 +80,8 @@ typedef struct {
   uint64_t sweeps;            /* sweeps done; the Philox counter word 1 of the next sweep */
   uint64_t accepts, proposals, refreshes, recoveries;
   double max_drift;           /* largest |log W_maintained - log W_fresh| seen at a refresh */
+  uint64_t near_ties;         /* Metropolis decisions (single-link and block) with |u - R| < 1e-9 R, where a
+                                 rounding change of R could flip the decision (Sec. 5.1 estimator) */
 } ggf_chain_info;
 
 /* Create a context on HIP device `device`. */
@@ -300,15 +302,23 @@ ggf_status ggf_update_timing(ggf_ctx *ctx, double *ms, int64_t *launches, int64_
  * is off), and the number of launches. */
 ggf_status ggf_ratio_timing(ggf_ctx *ctx, double *ms, int64_t *launches);
 
+/* Flags of ggf_autocorr_time. */
+#define GGF_TAU_FLOOR 1   /* the windowed sum fell to 1/2 or below and was clamped to 1/2 */
+#define GGF_TAU_SHORT 2   /* series too short for the estimate: n_t < 50 tau, a window above n_t / 4,
+                             or no window W >= c tau within the series */
+
 /* Integrated autocorrelation time of n_series Monte Carlo series sampled at
  * n_t times, series[t * n_series + s] (host float64).  Each series is centred
  * on its own mean; the autocovariance is averaged over series, normalised,
  * and summed with Sokal's automatic window (smallest W with W >= c tau(W),
- * tau(W) = 1/2 + sum_{t=1..W} rho(t)).  Outputs tau, its Madras-Sokal error
- * tau sqrt(2 (2W + 1) / (n_t n_series)) and W; effective samples =
- * n_t n_series / (2 tau).  Pure host computation; needs no context. */
+ * tau(W) = 1/2 + sum_{t=1..W} rho(t)).  Outputs tau (clamped below at 1/2),
+ * its Madras-Sokal error tau sqrt(2 (2W + 1) / (n_t n_series)), W and flags
+ * (GGF_TAU_FLOOR, GGF_TAU_SHORT; may be NULL): centring on the series mean
+ * biases short series towards 1/2, so a flagged tau is not a measurement.
+ * Effective samples = n_t n_series / (2 tau).  Pure host computation; needs
+ * no context.  GGF_EINVAL for n_t < 2, n_series < 1, c <= 0 or NULL series/tau. */
 ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series, double c, double *tau,
-                             double *tau_err, int64_t *window);
+                             double *tau_err, int64_t *window, int32_t *flags);
 
 /* ---- Learned block proposal --------------------------------------------
  * An exact Metropolis-Hastings move on a P x P patch of sites (2 P^2 links) of

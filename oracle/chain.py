@@ -8,6 +8,11 @@ a sweep visits links 0 .. 2V-1 in order; Z_N proposes k -> (k + 1 + (x2 mod (N-1
 A cold start has every k = 0; a hot start takes k = x0 mod N from Philox at
 counter (chain, 0xffffffff, link, 1).
 
+Near ties.  A decision with |u - R| < 1e-9 R could flip under a rounding
+change of R (the HIP path evaluates R through other, equally exact routes), so
+every chain counts them in ``ties``; parity tests compare decisions and report
+these counts instead of assuming them away.
+
 Two evaluators of the ratio:
 * ``DefinitionChain``: fresh log-determinant (and, for K > 1, full Pfaffians of
   every M_nm) of the current and proposed configuration -- the definition;
@@ -26,6 +31,12 @@ from . import philox
 from .model import Ansatz, rotation
 
 HOT_SWEEP = 0xFFFFFFFF
+TIE_REL = 1e-9
+
+
+def near_tie(u: float, R: float) -> bool:
+    """|u - R| < 1e-9 R: a decision that rounding of R could change."""
+    return abs(float(u) - R) < TIE_REL * R
 
 
 def hot_links(seed: int, chain: int, n_links: int, group: int) -> np.ndarray:
@@ -58,6 +69,7 @@ class DefinitionChain:
         self.sweep_idx = 0
         self.logn = self._logn(self.k)
         self.accepts = 0
+        self.ties = 0
 
     def _logn(self, k) -> float:
         lw = self.an.log_weight(k)
@@ -73,6 +85,7 @@ class DefinitionChain:
             knew[ell] = propose(int(self.k[ell]), int(step), an.group)
             ln_new = self._logn(knew)
             R = np.exp(ln_new - self.logn)
+            self.ties += near_tie(u, R)
             if float(u) < R:
                 self.k, self.logn = knew, ln_new
                 self.accepts += 1
@@ -90,6 +103,7 @@ class WoodburyChain:
         self.accepts = 0
         self.proposals = 0
         self.since_refresh = 0
+        self.ties = 0
         self.drifts = []
         self.refresh()
 
@@ -145,6 +159,7 @@ class WoodburyChain:
             k_new = propose(int(self.k[ell]), int(step), an.group)
             R, rho, s_new, dm = self.ratio(ell, k_new)
             self.proposals += 1
+            self.ties += near_tie(u, R)
             if float(u) < R:
                 self.accept(ell, k_new, rho, s_new, dm)
         self.sweep_idx += 1
@@ -157,21 +172,27 @@ class WoodburyChain:
         return self.an.observables(self.k)
 
 
-def block_move(ch: "WoodburyChain", params, P: int, patch: int):
+def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "def"):
     """One Metropolis-Hastings block move on a P x P patch (Z2), learned proposal.
 
     The proposal resamples the patch links from the network's factorised
     Bernoulli q(.|context) (logits from the float32 forward pass, uniforms
     from Philox at (chain, sweep, patch, 3 + j)); it is accepted iff
     u < N(G') q(x|ctx) / (N(G) q(x'|ctx)) with u from (chain, sweep, patch, 2).
-    N is evaluated from scratch for both configurations (fresh determinant; for
-    K > 1 the cross terms from a fresh inverse by the patch lemma) and an
-    accepted move refactorises G.  Returns (proposed, accepted, changed links).
+    N is evaluated from scratch for both configurations: W from a fresh
+    determinant and, for K > 1, N/W = sum_nm c_n^* c_m <B_m|B_n> Pf(M_nm)/Pf(M_00)
+    (Sec. 5) -- with ``route="def"`` from full Pfaffians of every M_nm (the
+    definition), with ``route="patch"`` from a fresh inverse by the patch lemma
+    (Pfaffians of order <= 16; for lattices where full Pfaffians are out of reach,
+    and pinned to the definition on every case both can run).  An accepted move
+    refactorises G.  Returns (proposed, accepted, changed links).
     """
     from . import nn
     an = ch.an
     if an.group != 2:
         raise ValueError("block moves are defined for Z2")
+    if route not in ("def", "patch"):
+        raise ValueError("route is 'def' or 'patch'")
     L = an.lat.Lx
     pl = nn.patch_links(L, P, patch)
     z, _ = nn.forward(params, nn.window(ch.k, L, P, patch), np.float32)
@@ -191,10 +212,13 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int):
         lw = 0.5 * ld - 4 * an.lat.V * np.log(2.0)
         if an.K == 1:
             return lw
-        G = np.linalg.inv(M)                  # fresh inverse; patch lemma for N/W (pinned to full Pfaffians)
+        if route == "def":
+            return lw + np.log(an.s_factor_def(k).real)
+        G = np.linalg.inv(M)
         return lw + np.log(an.s_factor_patch(G[np.ix_(an.S, an.S)], k).real)
 
     R = np.exp(log_n(k_new) - log_n(ch.k) + nn.log_q(zl, y_old) - nn.log_q(zl, y_new))
+    ch.ties += near_tie(u_acc, R)
     if u_acc < R:
         ch.k = k_new
         ch.refresh()
@@ -202,12 +226,12 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int):
     return True, False, m
 
 
-def block_sweep(ch: "WoodburyChain", params, P: int):
+def block_sweep(ch: "WoodburyChain", params, P: int, route: str = "def"):
     """Block moves on every patch in order, then the sweep counter advances (shared with link sweeps)."""
     L = ch.an.lat.Lx
     stats = [0, 0]
     for p in range((L // P) ** 2):
-        prop, acc, _ = block_move(ch, params, P, p)
+        prop, acc, _ = block_move(ch, params, P, p, route)
         stats[0] += prop
         stats[1] += acc
     ch.sweep_idx += 1

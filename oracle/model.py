@@ -311,37 +311,39 @@ class Ansatz:
         return tot / self.lat.n_links
 
     # ----- observables -----
+    def plaquette_value(self, links_k, x: int) -> complex:
+        """U(x,e1) U(x+e1,e2) U(x+e2,e1)^* U(x,e2)^* (Sec. 2.3), the plaquette with lower-left corner x."""
+        N = self.group
+        l1, l2, l3, l4 = self.lat.plaquette_links(x)
+        return (link_phase(links_k[l1], N) * link_phase(links_k[l2], N)
+                * np.conj(link_phase(links_k[l3], N)) * np.conj(link_phase(links_k[l4], N)))
+
     def plaquette(self, links_k) -> float:
+        """Lattice mean of Re of the plaquette (Sec. 2.3)."""
+        return sum(self.plaquette_value(links_k, x).real for x in range(self.lat.V)) / self.lat.V
+
+    def wilson2x2_value(self, links_k, x: int) -> complex:
+        """Oriented product of the 8 links around the 2x2 square with lower-left corner x (Sec. 5.1)."""
         lat, N = self.lat, self.group
-        tot = 0.0
-        for x in range(lat.V):
-            l1, l2, l3, l4 = lat.plaquette_links(x)
-            z = (link_phase(links_k[l1], N) * link_phase(links_k[l2], N)
-                 * np.conj(link_phase(links_k[l3], N)) * np.conj(link_phase(links_k[l4], N)))
-            tot += z.real
-        return tot / lat.V
+        z = 1.0 + 0j
+        p = x
+        for _ in range(2):                   # along +e1
+            z *= link_phase(links_k[lat.link(p, 0)], N)
+            p = lat.shift(p, 1, 0)
+        for _ in range(2):                   # along +e2
+            z *= link_phase(links_k[lat.link(p, 1)], N)
+            p = lat.shift(p, 0, 1)
+        for _ in range(2):                   # along -e1
+            p = lat.shift(p, -1, 0)
+            z *= np.conj(link_phase(links_k[lat.link(p, 0)], N))
+        for _ in range(2):                   # along -e2
+            p = lat.shift(p, 0, -1)
+            z *= np.conj(link_phase(links_k[lat.link(p, 1)], N))
+        return z
 
     def wilson2x2(self, links_k) -> float:
-        """Oriented product around the 2x2 square with lower-left corner x, lattice mean."""
-        lat, N = self.lat, self.group
-        tot = 0.0
-        for x in range(lat.V):
-            z = 1.0 + 0j
-            p = x
-            for _ in range(2):                   # along +e1
-                z *= link_phase(links_k[lat.link(p, 0)], N)
-                p = lat.shift(p, 1, 0)
-            for _ in range(2):                   # along +e2
-                z *= link_phase(links_k[lat.link(p, 1)], N)
-                p = lat.shift(p, 0, 1)
-            for _ in range(2):                   # along -e1
-                p = lat.shift(p, -1, 0)
-                z *= np.conj(link_phase(links_k[lat.link(p, 0)], N))
-            for _ in range(2):                   # along -e2
-                p = lat.shift(p, 0, -1)
-                z *= np.conj(link_phase(links_k[lat.link(p, 1)], N))
-            tot += z.real
-        return tot / lat.V
+        """Lattice mean of Re of the 2x2 Wilson loop."""
+        return sum(self.wilson2x2_value(links_k, x).real for x in range(self.lat.V)) / self.lat.V
 
     def density_from(self, gout: np.ndarray) -> complex:
         """Lattice mean of <psi_p^+ psi_p> = (1 + Gamma_out[2x, 2x+1]) / 2."""

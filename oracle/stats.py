@@ -36,6 +36,28 @@ def tau_int(x, c: float = 5.0):
     return tau, err, w
 
 
+def tau_int_chains(x, c: float = 5.0):
+    """(tau, tau_err, window) of several independent series x[t, s] of one chain ensemble: each
+    series centred on its own mean, the autocovariances averaged over series, then the same
+    windowed sum as ``tau_int``; the error uses all n_t * n_series samples."""
+    x = np.asarray(x, float)
+    n, m = x.shape
+    g = np.mean([autocov(x[:, s]) for s in range(m)], axis=0)
+    if g[0] <= 0:
+        return 0.5, 0.0, 0
+    rho = g / g[0]
+    tau = 0.5
+    w = 0
+    for t in range(1, n):
+        tau += rho[t]
+        w = t
+        if t >= c * tau:
+            break
+    tau = max(tau, 0.5)
+    err = tau * np.sqrt(2.0 * (2 * w + 1) / (n * m))
+    return tau, err, w
+
+
 def ess(x, c: float = 5.0) -> float:
     tau, _, _ = tau_int(x, c)
     return len(x) / (2.0 * tau)

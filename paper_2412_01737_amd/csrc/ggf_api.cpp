@@ -51,7 +51,7 @@ struct ggf_ctx {
   double *logw = nullptr, *max_drift = nullptr, *ldet = nullptr;
   double2 *sfac = nullptr;
   uint32_t *sweep = nullptr, *acc_since = nullptr;
-  unsigned long long *acc_total = nullptr, *prop_total = nullptr, *refreshes = nullptr;
+  unsigned long long *acc_total = nullptr, *prop_total = nullptr, *refreshes = nullptr, *ties = nullptr;
   int *flags = nullptr, *acc_list = nullptr, *acc_cnt = nullptr;
   double *scratch = nullptr;
   size_t scratch_elems = 0;
@@ -216,6 +216,7 @@ bool check_local(const double *g, std::string &why) {
 template <typename T>
 T *dalloc(ggf_ctx *ctx, size_t count, hipError_t &e) {
   void *p = nullptr;
+  if (e != hipSuccess) return nullptr;   // an earlier allocation of the batch failed: keep its error
   e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
   if (e == hipSuccess) {
     ctx->allocs.push_back(p);
@@ -260,6 +261,7 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.acc_total = ctx->acc_total;
   lc.prop_total = ctx->prop_total;
   lc.refreshes = ctx->refreshes;
+  lc.ties = ctx->ties;
   lc.max_drift = ctx->max_drift;
   lc.ldet = ctx->ldet;
   lc.flags = ctx->flags;
@@ -581,6 +583,8 @@ ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tenso
     }
   ctx->tensors.push_back(t);
   if (ctx->tensors.size() > ctx->tensors_cap) {
+    // a captured sweep graph holds the old table's address in its kernel arguments
+    if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
     if (ctx->tensors_dev) hipFree(ctx->tensors_dev);
     ctx->tensors_cap = std::max<size_t>(16, 2 * ctx->tensors.size());
     HIP_TRY(ctx, hipMalloc(&ctx->tensors_dev, ctx->tensors_cap * sizeof(TensorDev)));
@@ -676,6 +680,7 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
   ctx->acc_total = dalloc<unsigned long long>(ctx, n_chains, e);
   ctx->prop_total = dalloc<unsigned long long>(ctx, n_chains, e);
   ctx->refreshes = dalloc<unsigned long long>(ctx, n_chains, e);
+  ctx->ties = dalloc<unsigned long long>(ctx, n_chains, e);
   ctx->flags = dalloc<int>(ctx, n_chains, e);
   ctx->acc_list = dalloc<int>(ctx, n_chains, e);
   ctx->acc_cnt = dalloc<int>(ctx, 2, e);
@@ -1311,6 +1316,7 @@ ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_i
     HIP_TRY(ctx, hipMemcpy(&info->proposals, ctx->prop_total + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(&info->refreshes, ctx->refreshes + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(&info->max_drift, ctx->max_drift + chain, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&info->near_ties, ctx->ties + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
     info->s_re = sf.x;
     info->s_im = sf.y;
     info->sweeps = sw;
@@ -1480,7 +1486,7 @@ ggf_status ggf_ratio_timing(ggf_ctx *ctx, double *ms, int64_t *launches) {
 }
 
 ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series, double c, double *tau,
-                             double *tau_err, int64_t *window) {
+                             double *tau_err, int64_t *window, int32_t *flags) {
   if (!series || n_t < 2 || n_series < 1 || !(c > 0) || !tau) return GGF_EINVAL;
   std::vector<double> x(static_cast<size_t>(n_t) * n_series);
   for (int64_t s = 0; s < n_series; ++s) {
@@ -1498,18 +1504,27 @@ ggf_status ggf_autocorr_time(const double *series, int64_t n_t, int64_t n_series
   }
   double tv = 0.5, err = 0.0;
   int64_t w = 0;
+  int32_t fl = 0;
+  bool windowed = false;
   if (g[0] > 0) {
     for (int64_t t = 1; t < n_t; ++t) {
       tv += g[t] / g[0];
       w = t;
-      if (t >= c * tv) break;
+      if (t >= c * tv) { windowed = true; break; }
     }
+    if (tv <= 0.5) fl |= GGF_TAU_FLOOR;
     tv = std::max(tv, 0.5);
     err = tv * std::sqrt(2.0 * (2.0 * w + 1.0) / (static_cast<double>(n_t) * n_series));
+  } else {
+    fl |= GGF_TAU_FLOOR;
   }
+  // centring on each series' own mean biases the autocovariances low by O(tau / n_t): the estimate
+  // is only trusted when the series is long against tau and the window
+  if (!windowed || static_cast<double>(n_t) < 50.0 * tv || 4 * w > n_t) fl |= GGF_TAU_SHORT;
   *tau = tv;
   if (tau_err) *tau_err = err;
   if (window) *window = w;
+  if (flags) *flags = fl;
   return GGF_OK;
 }
 

@@ -22,6 +22,7 @@ struct LaunchCtx {
   unsigned long long *acc_total;
   unsigned long long *prop_total;
   unsigned long long *refreshes;
+  unsigned long long *ties;      // decisions with |u - R| < 1e-9 R (rounding of R could change them)
   double *max_drift;
   double *ldet;
   int *flags;

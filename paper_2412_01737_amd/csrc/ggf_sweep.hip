@@ -243,6 +243,7 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
     const double R = (rho > 0.0 ? sqrt(rho) : 0.0) * sratio;
     const bool accept = !bad && (s_u < R) && (a + 4 <= kDelayMax || !delayed);
     lc.prop_total[c] += 1;
+    if (!bad && fabs(s_u - R) < 1e-9 * R) lc.ties[c] += 1;
     if (bad) lc.flags[c] |= GGF_FLAG_NONFINITE;
     if (accept) {
       lk[ell] = static_cast<int8_t>(s_kn);

@@ -39,7 +39,7 @@ class ChainInfo(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("logw", ctypes.c_double), ("s_re", ctypes.c_double),
                 ("s_im", ctypes.c_double), ("sweeps", ctypes.c_uint64), ("accepts", ctypes.c_uint64),
                 ("proposals", ctypes.c_uint64), ("refreshes", ctypes.c_uint64), ("recoveries", ctypes.c_uint64),
-                ("max_drift", ctypes.c_double)]
+                ("max_drift", ctypes.c_double), ("near_ties", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,7 +82,7 @@ EXPORTS = {
                                          ctypes.POINTER(ctypes.c_int64)]),
     "ggf_ratio_timing": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "ggf_autocorr_time": (ctypes.c_int, [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _dp, _dp,
-                                         ctypes.POINTER(ctypes.c_int64)]),
+                                         ctypes.POINTER(ctypes.c_int64), _ip]),
     "ggf_nn_nparams": (ctypes.c_int32, []),
     "ggf_nn_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
     "ggf_nn_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
@@ -389,16 +389,22 @@ class Context:
         return ms.value, la.value, fl.value
 
 
-def autocorr_time(series, c: float = 5.0):
-    """(tau, tau_err, window) of series[t, s] (time-major) via ggf_autocorr_time."""
+TAU_FLOOR, TAU_SHORT = 1, 2
+
+
+def autocorr_time(series, c: float = 5.0, with_flags: bool = False):
+    """(tau, tau_err, window) of series[t, s] (time-major) via ggf_autocorr_time; with
+    with_flags also the flags (TAU_FLOOR: clamped at 1/2; TAU_SHORT: series too short)."""
     x = np.ascontiguousarray(np.asarray(series, np.float64))
     if x.ndim == 1:
         x = x[:, None]
-    tau, err, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    tau, err, w, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int32()
     st = load().ggf_autocorr_time(x.ctypes.data_as(_dp), x.shape[0], x.shape[1], float(c), ctypes.byref(tau),
-                                  ctypes.byref(err), ctypes.byref(w))
+                                  ctypes.byref(err), ctypes.byref(w), ctypes.byref(fl))
     if st != GGF_OK:
         raise GGFError(st, "ggf_autocorr_time: bad arguments")
+    if with_flags:
+        return tau.value, err.value, w.value, fl.value
     return tau.value, err.value, w.value
 
 

@@ -3,6 +3,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -45,3 +46,63 @@ def test_host_only_entry_points():
     assert abs(tau - 0.5) < 0.1 and w >= 1
     with pytest.raises(ggf.GGFError):
         ggf.autocorr_time(np.zeros((1, 1)))
+
+
+def _ar1(rng, phi, n_t, n_series):
+    x = np.zeros((n_t, n_series))
+    e = rng.standard_normal((n_t, n_series))
+    x[0] = e[0] / np.sqrt(1 - phi * phi)
+    for t in range(1, n_t):
+        x[t] = phi * x[t - 1] + e[t]
+    return x
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libggf.so not built")
+def test_native_tau_int_equals_the_oracle():
+    """ggf_autocorr_time (host code of the library) against oracle/stats on AR(1) series, an AR(1)
+    ensemble and a recorded plaquette series of an oracle chain; the flags mark the clamp at 1/2 and
+    series too short for the estimate."""
+    from oracle import stats
+    from oracle.chain import WoodburyChain
+    from oracle.lattice import Lattice
+    from oracle.model import Ansatz
+    import synth
+    from paper_2412_01737_amd import ggf
+    rng = np.random.default_rng(17)
+    for phi, n_t in ((0.9, 20000), (0.5, 5000), (0.0, 3000)):
+        x = _ar1(rng, phi, n_t, 1)[:, 0]
+        t0, e0, w0 = stats.tau_int(x)
+        t1, e1, w1, fl = ggf.autocorr_time(x, with_flags=True)
+        assert abs(t1 - t0) <= 1e-10 * t0 and abs(e1 - e0) <= 1e-10 * e0 and w1 == w0
+        if phi > 0:
+            assert fl == 0
+    x = _ar1(rng, 0.8, 600, 64)
+    t0, e0, w0 = stats.tau_int_chains(x)
+    t1, e1, w1, fl = ggf.autocorr_time(x, with_flags=True)
+    assert abs(t1 - t0) <= 1e-10 * t0 and abs(e1 - e0) <= 1e-10 * e0 and w1 == w0 and fl == 0
+    spec = synth.make_tensor(2)
+    an = Ansatz(Lattice(2, 2), spec.gamma_loc, spec.gamma_bond, 2)
+    ch = WoodburyChain(an, synth.SEED_CHAIN, 0)
+    series = []
+    for _ in range(1500):
+        ch.sweep()
+        series.append(an.plaquette(ch.k))
+    t0, e0, w0 = stats.tau_int(np.array(series))
+    t1, e1, w1 = ggf.autocorr_time(np.array(series))
+    assert abs(t1 - t0) <= 1e-10 * t0 and abs(e1 - e0) <= 1e-10 * e0 and w1 == w0
+    # a short series of a slow AR(1) process (true tau 19.5): biased towards 1/2 and flagged
+    t_short, _, _, fl = ggf.autocorr_time(_ar1(rng, 0.95, 8, 4), with_flags=True)
+    assert fl & ggf.TAU_SHORT and t_short < 5
+    _, _, _, fl = ggf.autocorr_time(np.array([1.0, -1.0, 1.0, -1.0, 1.0, -1.0]), with_flags=True)
+    assert fl & ggf.TAU_FLOOR
+
+
+def test_oracle_tau_int_chains_ar1_closed_form():
+    """An ensemble of AR(1) series has tau_int = (1 + phi) / (2 (1 - phi)); one series reduces to tau_int."""
+    from oracle import stats
+    rng = np.random.default_rng(23)
+    phi = 0.7
+    x = _ar1(rng, phi, 4000, 32)
+    tau, err, _ = stats.tau_int_chains(x)
+    assert abs(tau - (1 + phi) / (2 * (1 - phi))) < 4 * err
+    assert stats.tau_int_chains(x[:, :1]) == stats.tau_int(x[:, 0])

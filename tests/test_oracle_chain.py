@@ -128,3 +128,28 @@ def test_proposal_rule_table():
     counts = np.bincount(s5, minlength=6)
     assert counts[0] == 0 and counts[5] == 0
     assert np.all(np.abs(counts[1:5] - 2000) < 200)
+
+
+def _golden(name):
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_t14", os.path.join(here, "make_t14.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load(os.path.join(here, name))
+
+
+def test_t14_c1_stored_sequence_reproduced_by_the_woodbury_chain():
+    """The stored 10^4-sweep 2x2 decision sequence (fresh determinants) is reproduced sweep by sweep by
+    the oracle's independent Woodbury route (rank-4 updates of the maintained inverse)."""
+    ref = _golden("t14_c1.txt")[0]
+    codes = "".join(ref["lines"])
+    spec = synth.make_tensor(2)
+    an = Ansatz(Lattice(2, 2), spec.gamma_loc, spec.gamma_bond, 2)
+    ch = WoodburyChain(an, synth.SEED_CHAIN, 0, refresh_every=1024)
+    for s in range(len(codes) // 2):
+        ch.sweep()
+        assert "%02x" % int(sum(int(v) << i for i, v in enumerate(ch.k))) == codes[2 * s:2 * s + 2], s
+    assert ch.accepts == ref["accepts"] and ch.ties == ref["near_ties"] == 0
+    assert abs(ch.logw - ref["logw"]) < 1e-11 * abs(ref["logw"])

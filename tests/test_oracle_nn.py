@@ -16,7 +16,7 @@ import pytest
 
 import synth
 from oracle import nn
-from oracle.chain import WoodburyChain, block_sweep
+from oracle.chain import WoodburyChain, block_move, block_sweep
 from oracle.lattice import Lattice
 from oracle.model import Ansatz
 
@@ -181,3 +181,42 @@ def test_block_chain_matches_enumeration_2x2():
     err = np.std(series) * np.sqrt(2 * tau / len(series))
     assert acc[1] > 0.1 * acc[0]
     assert abs(series.mean() - exact) < 4 * err
+
+
+def _route_params(seed, bias):
+    rng = np.random.default_rng(seed)
+    p = (nn.init_params(seed) + 0.02 * rng.standard_normal(nn.n_params())).astype(np.float32)
+    p[-2:] = bias
+    return p
+
+
+@pytest.mark.parametrize("L,P,K,bias,sweeps", [
+    (4, 2, 2, 0.0, 3),    # K = 2 on a 4x4 lattice: proposals change about half of the 8 patch links
+    (4, 2, 3, -1.0, 3),
+    (4, 4, 4, -1.5, 2),   # one patch covering the lattice, every patch link of the superposition inside
+    (8, 4, 2, -3.0, 2),   # the shape of the GPU bit-exact block-move case with K = 2
+])
+def test_block_move_routes_agree(L, P, K, bias, sweeps):
+    """The K > 1 block-move weight by full Pfaffians of every M_nm (the definition) and by the
+    patch lemma on a fresh inverse take identical decisions and give N(G) within 1e-10: the
+    patch route is used only where full Pfaffians are out of reach (lattices above 8 x 8)."""
+    spec = synth.make_tensor(2, K=K)
+    lat = Lattice(L, L)
+    links, gk = synth.patch_bonds(lat.n_links, K)
+    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, 2, links, gk, spec.c)
+    params = _route_params(13, bias)
+    chains = {r: WoodburyChain(an, synth.SEED_CHAIN, 0) for r in ("def", "patch")}
+    moves = 0
+    for _ in range(sweeps):
+        for p in range((L // P) ** 2):
+            out = {r: block_move(ch, params, P, p, r) for r, ch in chains.items()}
+            assert out["def"] == out["patch"]
+            moves += out["def"][0]
+            assert np.array_equal(chains["def"].k, chains["patch"].k)
+        for ch in chains.values():
+            ch.sweep_idx += 1
+    assert moves > 0
+    assert chains["def"].ties == chains["patch"].ties == 0
+    k = chains["def"].k
+    s_def, s_patch = an.s_factor_def(k), an.s_factor_patch(np.linalg.inv(an.assemble_M(k))[np.ix_(an.S, an.S)], k)
+    assert abs(s_def - s_patch) < 1e-10 * abs(s_def)
