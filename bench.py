@@ -1,26 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: single-link Metropolis sweeps of gauged Gaussian fermionic PEPS on one MI355X.
+"""Benchmark of the gauged Gaussian fermionic PEPS Monte Carlo on one MI355X.
 
-Workload (default): Z2 gauge field on an 8x8 periodic lattice (128 links,
-n = 512 virtual Majoranas), the seeded Haar on-site Gaussian tensor, K = 1,
-4096 independent chains, float64 inverse with a float64 refactorisation every
-16384 accepted flips per chain (about 130 sweeps; the float64 drift over such
-an interval is below 1e-13 in log W).  Refactorisations are charged at their
-true rate: the timed sweeps are corrected by the difference between the
-refactorisations they contain and that rate, at the measured cost of one.  A step is one sweep of every chain (128
-proposals each: ratio and Metropolis decision on the current inverse, the
-Woodbury factors of an accepted flip kept pending, and one matrix-core flush
-of the pending flips per window of 16 link steps) followed by the plaquette /
-2x2 Wilson loop / density measurement.
+Default run (the headline): effective samples per second of the plaquette,
+estimated at a fixed observable error, of the learned block proposal with
+float32 updates and float64 refresh on the 32x32 Z2 K=2 workload (256
+chains), against the plain float64 single-link sampler on the same 256 chains
+and against the same block moves with an untrained (uniform) proposal.  A
+step is one block sweep of every chain (a Metropolis-Hastings move on each of
+the 64 4x4-site patches) followed by the plaquette / 2x2 Wilson loop / density
+measurement.  Effective samples come from the spread of the chain means
+(256 independent chains; ESS = var(O) / SE(mean)^2), which needs no estimate
+of the autocorrelation time; tau_int is reported beside it with its window and
+its flags (clamped at 1/2, series too short).
 
-Prints one JSON line: link-update proposals per second (value), effective
-samples per second of the lattice-mean plaquette, the HBM roofline of the
-dominant kernel (the window flush: per window, every chain's upper triangle of
-G read once and all of G written once, since G is antisymmetric; time: HIP
-events around every flush launch on its stream; with
---delay 0 the rank-4 update, 2 n^2 * 8 bytes per accepted flip), the time of
-the ratio kernels, and the CPU oracle timed on a bounded sample of the same
-workload.
+Sub-records: the plain float64 sampler on the 8x8 Z2 K=1 workload (4096
+chains; proposals/s, the HBM roofline of its window flush), the CPU oracle
+timed on bounded samples of both workloads (with the definitional per-proposal
+determinant mode), and the oracle's float64 observables of sampled final
+configurations against the float32 path.
+
+Other workloads: --workload c2 | c3 | c4 | c5 (one JSON line each).
 """
 from __future__ import annotations
 
@@ -41,8 +40,9 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2: 8x8 Z2 K=1 4096 chains float64 (default, the headline workload); "
+    ap.add_argument("--workload", default="north", choices=["north", "c2", "c3", "c4", "c5"],
+                    help="north (default): the c5 comparison with the c2 plain float64 leg and the CPU oracle; "
+                         "c2: 8x8 Z2 K=1 4096 chains float64; "
                          "c3: 16x16 Z2 K=3 2048 chains float32 + float64 refresh; "
                          "c4: 8192 chains, L in {6,8,12,16,20}, K in {1,2,4}, Z2/Z3, float32 + refresh, "
                          "graph-replayed autotuned sweeps; "
@@ -51,8 +51,11 @@ def parse():
     ap.add_argument("--train-chains", type=int, default=32, help="c5: chains of the plain sampler the net trains on")
     ap.add_argument("--train-sweeps", type=int, default=3, help="c5: plain-sampler sweeps of online training")
     ap.add_argument("--train-steps", type=int, default=40, help="c5: Adam steps after each training sweep")
-    ap.add_argument("--plain-chains", type=int, default=64, help="c5: chains of the float64 single-link comparison")
-    ap.add_argument("--plain-steps", type=int, default=4, help="c5: timed sweeps of the float64 single-link comparison")
+    ap.add_argument("--plain-chains", type=int, default=None,
+                    help="c5: chains of the float64 single-link comparison (default: the learned sampler's)")
+    ap.add_argument("--plain-steps", type=int, default=5, help="c5: timed sweeps of the float64 single-link comparison")
+    ap.add_argument("--untrained", type=int, default=1,
+                    help="c5: also time the block moves with an untrained (uniform) proposal (1 = yes)")
     ap.add_argument("--autotune", type=int, default=0, help="sweeps per autotuner candidate (0 = off)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
@@ -68,6 +71,7 @@ def parse():
     ap.add_argument("--delay", type=int, default=None,
                     help="window of delayed updates in link steps (0 = one rank-4 pass per accepted flip; "
                          "default: the library's)")
+    ap.add_argument("--flush-grid", type=int, default=0, help="workgroups of the window flush (0 = library default)")
     ap.add_argument("--update-grid", type=int, default=0)
     ap.add_argument("--update-tiles", type=int, default=0)
     ap.add_argument("--update-nt", type=int, default=1)
@@ -98,15 +102,54 @@ def parse():
                          "CSVs, write profiles/k_electric_traffic.json and exit (no GPU needed)")
     args = ap.parse_args()
     presets = {
+        "north": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
         "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384, delay=16),
         "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64, delay=16),
         "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64, delay=16),
-        "c5": dict(steps=8, warmup=1, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
+        "c5": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
     }
     for k, v in presets[args.workload].items():
         if getattr(args, k) is None:
             setattr(args, k, v)
+    if args.plain_chains is None:
+        args.plain_chains = args.chains
     return args
+
+
+def c2_args(args):
+    """The plain float64 8x8 leg of the default run (fixed counts: 20 timed sweeps after 3)."""
+    import copy
+    a = copy.copy(args)
+    a.workload = "c2"
+    for k, v in dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384,
+                     delay=16).items():
+        setattr(a, k, v)
+    return a
+
+
+def ess_between_chains(series):
+    """Effective samples of the grand mean of series[t, c] (independent chains c): the variance of
+    one sample over the squared standard error of the mean, the latter from the spread of the chain
+    means.  Returns (ess, standard error of the mean, variance of one sample)."""
+    x = np.asarray(series, np.float64)
+    n_t, n_c = x.shape
+    se2 = x.mean(axis=0).var(ddof=1) / n_c
+    var = x.var(ddof=1)
+    return (var / se2 if se2 > 0 else float("inf")), float(np.sqrt(se2)), float(var)
+
+
+def statistics(series, elapsed):
+    """ESS/s, the standard error after one second of sampling, and tau_int with its flags."""
+    from paper_2412_01737_amd.ggf import autocorr_time, TAU_FLOOR, TAU_SHORT
+    ess, se, var = ess_between_chains(series)
+    rec = {"effective_samples_per_s": ess / elapsed, "ess": ess, "samples": int(series.size),
+           "mean": float(np.mean(series)), "se_mean": se, "se_at_1s": float(np.sqrt(var * elapsed / ess))
+           if ess > 0 else None}
+    if series.shape[0] >= 2:
+        tau, err, w, fl = autocorr_time(series, with_flags=True)
+        rec.update(tau_int=tau, tau_int_err=err, tau_window=w, tau_at_floor=bool(fl & TAU_FLOOR),
+                   tau_series_too_short=bool(fl & TAU_SHORT))
+    return rec
 
 
 def traffic_from(args):
@@ -262,7 +305,9 @@ def copy_probe(nbytes: int):
     b = torch.empty_like(a)
     s = torch.cuda.current_stream()
     out = {"bytes": nbytes}
-    for mode, name, moved in ((0, "copy", 2), (1, "copy_nt", 2), (2, "rmw", 2), (3, "rmw_nt", 2)):
+    for mode, name, moved in ((0, "copy", 2), (1, "copy_nt", 2), (2, "rmw", 2), (3, "rmw_nt", 2),
+                              (4, "copy_unrolled", 2), (5, "rmw_unrolled", 2), (6, "read_unrolled", 1),
+                              (7, "write_unrolled", 1)):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         st = lib.ggf_stream_probe(mode, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nbytes, 0,
                                   ctypes.c_void_p(s.cuda_stream))
@@ -335,21 +380,49 @@ def refresh_correction(ctx, args, st0, stream):
             "correction_ms": (exp_mean - act_mean) * ms_all if args.refresh > 0 else 0.0}
 
 
+def host_info():
+    """CPU model and core count of the host, and the worker processes the oracle legs use (at most 16:
+    one GPU's share of the host)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return {"cpu_model": model, "nproc": nproc, "workers": max(1, min(16, nproc))}
+
+
 def cpu_baseline(args, budget_s: float):
-    """The oracle's Woodbury chain on host cores, one chain per worker process, bounded in time."""
+    """The oracle on host cores, bounded in time: its Woodbury chain (one chain per worker process, one
+    BLAS thread each), and its definitional mode (a fresh determinant per proposal) on one core."""
     import multiprocessing as mp
-    workers = max(1, min(16, os.cpu_count() or 1))
+    info = host_info()
+    workers = info["workers"]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(workers, initializer=_cpu_init) as pool:
-        res = pool.starmap(_cpu_chain, [(args.L, args.K, args.group, c, budget_s) for c in range(workers)])
-    wall = time.perf_counter() - t0
+        res = pool.starmap(_cpu_chain, [(args.L, args.K, args.group, c, budget_s, False) for c in range(workers)])
+        dres = pool.starmap(_cpu_chain, [(args.L, args.K, args.group, 0, min(budget_s, 5.0), True)])
+    wall = time.perf_counter() - t0 - min(budget_s, 5.0)
     props = sum(r[0] for r in res)
     sweeps = sum(r[1] for r in res)
-    return {"value": props / wall, "unit": "proposals/s", "cores": workers, "kind": "oracle",
-            "sample": f"{workers} chains x {sweeps // workers}-{max(r[1] for r in res)} sweeps of L={args.L} "
-                      f"K={args.K} Z{args.group} (Woodbury-mode oracle, float64, 1 BLAS thread per process), "
-                      f"{wall:.1f} s wall"}
+    rec = {"value": props / (wall if wall > 0 else budget_s), "unit": "proposals/s", "cores": workers,
+           "kind": "oracle",
+           "sample": f"{workers} chains x {min(r[1] for r in res)}-{max(r[1] for r in res)} sweeps of L={args.L} "
+                     f"K={args.K} Z{args.group} (Woodbury-mode oracle, float64, 1 BLAS thread per process), "
+                     f"{wall:.1f} s wall",
+           "o_def_proposals_per_s": dres[0][0] / dres[0][2],
+           "o_def_sample": f"1 chain, {dres[0][0]} proposals, each from a fresh determinant, {dres[0][2]:.1f} s"}
+    rec.update(info)
+    return rec
 
 
 def _cpu_init():
@@ -360,23 +433,98 @@ def _cpu_init():
         pass
 
 
-def _cpu_chain(L, K, group, chain, budget_s):
+def _cpu_chain(L, K, group, chain, budget_s, definitional):
     import synth
-    from oracle.chain import WoodburyChain
+    from oracle.chain import DefinitionChain, WoodburyChain
     from oracle.lattice import Lattice
     from oracle.model import Ansatz
     spec = synth.make_tensor(L, K=K, group=group)
     an = Ansatz(Lattice(L, L), spec.gamma_loc, spec.gamma_bond, group, spec.patch_link, spec.gamma_bond_k, spec.c)
-    ch = WoodburyChain(an, synth.SEED_CHAIN, chain, refresh_every=1024)
+    ch = (DefinitionChain(an, synth.SEED_CHAIN, chain) if definitional
+          else WoodburyChain(an, synth.SEED_CHAIN, chain, refresh_every=1024))
     t0 = time.perf_counter()
-    sweeps = 0
+    sweeps = props = 0
+    if definitional:
+        # proposals one at a time (a sweep of the definitional chain can outlast the budget)
+        from oracle import philox
+        from oracle.chain import propose
+        ell = 0
+        while time.perf_counter() - t0 < budget_s or props == 0:
+            u, step = philox.draw(ch.seed, ch.chain, ch.sweep_idx, ell, an.group)
+            knew = ch.k.copy()
+            knew[ell] = propose(int(ch.k[ell]), int(step), an.group)
+            ln_new = ch._logn(knew)
+            if float(u) < np.exp(ln_new - ch.logn):
+                ch.k, ch.logn = knew, ln_new
+            props += 1
+            ell = (ell + 1) % an.lat.n_links
+        return props, sweeps, time.perf_counter() - t0
     while time.perf_counter() - t0 < budget_s or sweeps == 0:
         ch.sweep()
         sweeps += 1
-    return ch.proposals, sweeps
+    return ch.proposals, sweeps, time.perf_counter() - t0
+
+
+def cpu_baseline_c5(args, budget_s: float, c5: dict):
+    """The oracle on the 32x32 K=2 learned-proposal workload, bounded in time, in one process with every
+    BLAS thread of one GPU's share of the host: hot start of chain 0, then block moves of the same
+    network (fresh LU factorisations of M(G) and M(G') per move) until the budget is spent.  Effective
+    samples per second = block sweeps per second / (2 tau), tau the GPU run's plaquette tau_int (at
+    least 1/2).  Also: the oracle's float64 observables of the GPU's final configuration of chain 0,
+    from a fresh inverse, against the float32 path's values."""
+    import threadpoolctl
+    info = host_info()
+    with threadpoolctl.threadpool_limits(info["workers"]):
+        return _cpu_baseline_c5(args, budget_s, c5, info)
+
+
+def _cpu_baseline_c5(args, budget_s, c5, info):
+    import synth
+    from oracle import nn
+    from oracle.chain import WoodburyChain, block_move, hot_links
+    from oracle.lattice import Lattice
+    from oracle.model import Ansatz
+    L, K, group, P = args.L, args.K, args.group, 4
+    spec = synth.make_tensor(L, K=K, group=group)
+    an = Ansatz(Lattice(L, L), spec.gamma_loc, spec.gamma_bond, group, spec.patch_link, spec.gamma_bond_k, spec.c)
+    t0 = time.perf_counter()
+    learned = c5["learned"]
+    k_gpu = np.array(learned["final_chain0"]["links"], np.int8)
+    G = np.linalg.inv(an.assemble_M(k_gpu))
+    ref = an.observables_from_inverse(k_gpu, G)
+    del G
+    gobs = np.array(learned["final_chain0"]["obs"])
+    err = np.abs(gobs - ref) / np.maximum(1.0, np.abs(ref))
+    t_check = time.perf_counter() - t0
+    params = c5.pop("_params", None)
+    if params is None:
+        params = nn.init_params(NN_SEED).astype(np.float32)
+    t0 = time.perf_counter()
+    ch = WoodburyChain(an, synth.SEED_CHAIN, 0, hot_links(synth.SEED_CHAIN, 0, an.lat.n_links, group))
+    moves = 0
+    npatch = (L // P) ** 2
+    while time.perf_counter() - t0 < budget_s or moves == 0:
+        block_move(ch, params, P, moves % npatch, route="patch")
+        moves += 1
+    wall = time.perf_counter() - t0
+    tau = max(0.5, learned["plaquette"].get("tau_int") or 0.5)
+    rec = {"value": moves / npatch / wall / (2.0 * tau), "unit": "effective samples/s", "cores": info["workers"],
+           "kind": "oracle",
+           "sample": f"1 chain of {L}x{L} Z{group} K={K}: hot start and {moves} learned block moves "
+                     f"({moves / npatch:.3f} block sweeps; fresh LU factorisations of M per move, "
+                     f"{info['workers']} BLAS threads) in {wall:.1f} s, divided by 2 tau_int "
+                     f"(tau = {tau:.3f} from the GPU run)",
+           "oracle_check": {"what": "float64 oracle observables of the float32 path's final configuration of "
+                                    "chain 0 (fresh inverse) against the path's values, |d| / max(1, |x|)",
+                            "max_error": float(err.max()), "worst_slot": int(err.argmax()),
+                            "errors": err.tolist(), "seconds": t_check}}
+    rec.update(info)
+    return rec
 
 
 NN_SEED = 7
+BETAS = (0.0, 0.25, 0.5, 0.75, 1.0)     # candidate scales of the network's output layer
+N_LAST = 2 * 32 * 9 + 2                 # output layer: W4 [2][32][3][3] and b4 [2], the last parameters
 MFMA_PEAK_F32_TFLOPS = 157.3
 
 
@@ -388,14 +536,18 @@ def run_c5(args):
        steps on (window, patch) examples of its current link fields.
     2. The learned sampler: --chains chains, one block sweep = one
        Metropolis-Hastings block move on every patch, float32 inverse with a
-       float64 refactorisation every --refresh changed links; the plaquette
-       is measured after every sweep.
-    3. The plain float64 single-link sampler on the same GPU (--plain-chains
-       chains, --plain-steps sweeps), measured the same way.
-    Effective samples per second = chains * sweeps / (2 tau_int) / wall time."""
+       float64 refactorisation every --refresh changed links; the plaquette and
+       the density are measured after every sweep.
+    3. The same block moves with an untrained network (all weights and biases
+       zero: every patch link proposed with probability 1/2), same chains.
+    4. The plain float64 single-link sampler on the same GPU (--plain-chains
+       chains, delayed updates, refactorisation every 16384 accepted flips,
+       --plain-steps sweeps), measured the same way.
+    Effective samples per second from the spread of the chain means (see
+    ess_between_chains), for the plaquette and the density."""
     import torch
     import synth
-    from paper_2412_01737_amd.ggf import Context, autocorr_time, OBS_LINK, GGF_NOBS
+    from paper_2412_01737_amd.ggf import Context, OBS_LINK, OBS_DENSITY, GGF_NOBS, load
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
@@ -406,6 +558,7 @@ def run_c5(args):
     L, K, group, P = args.L, args.K, args.group, 4
     n = 8 * L * L
     spec = synth.make_tensor(L, K=K, group=group)
+    nparams = load().ggf_nn_nparams()
 
     t0 = time.perf_counter()
     tr = Context(0)
@@ -419,56 +572,75 @@ def run_c5(args):
         tr.sweep(1, stream=stream)
         losses.append(tr.nn_train(args.train_steps, 512, 3e-3, NN_SEED + 1 + sw, stream=stream))
         log(f"c5 training sweep {sw + 1}/{args.train_sweeps}: loss {losses[-1]:.4f} nats/patch")
-    params = tr.nn_params()
+    trained = tr.nn_params()
+    # adaptation of the proposal's sharpness during burn-in, then frozen: the last layer scaled by
+    # beta (beta = 0 is the uniform proposal), beta chosen to maximise the links that accepted block
+    # moves change per block sweep on the training chains
+    scale_trials = []
+    for beta in BETAS:
+        p = trained.copy()
+        p[-N_LAST:] *= beta
+        tr.nn_params(p)
+        st0 = np.array([tr.block_stats(c) for c in range(args.train_chains)])
+        tr.block_sweep(2, stream=stream)
+        st1 = np.array([tr.block_stats(c) for c in range(args.train_chains)])
+        d = st1 - st0
+        scale_trials.append({"beta": beta, "acceptance": float(d[:, 1].sum() / max(1, d[:, 0].sum())),
+                             "accepted_links_per_sweep": float(d[:, 2].sum() / 2.0 / args.train_chains)})
+        log(f"c5 proposal scale {beta}: {scale_trials[-1]}")
+    beta = max(scale_trials, key=lambda t: t["accepted_links_per_sweep"])["beta"]
+    params = trained.copy()
+    params[-N_LAST:] *= beta
     tr.close()
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
-    def sampler(chains, precision, refresh, learned, steps, warmup):
+    def sampler(name, chains, precision, refresh, net, steps, warmup):
         ctx = Context(0)
         ctx.set_option("delay", args.delay)
         tid = ctx.set_tensor_spec(spec)
         ti = time.perf_counter()
         ctx.init_chains([L] * chains, tid, synth.SEED_CHAIN, init=1, precision=precision,
                         refresh_every=refresh, stream=stream)
-        if learned:
+        if net is not None:
             ctx.nn_init(P, NN_SEED)
-            ctx.nn_params(params)
+            ctx.nn_params(net)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - ti
-        step = (lambda: ctx.block_sweep(1, stream=stream)) if learned else (lambda: ctx.sweep(1, stream=stream))
+        block = net is not None
+        step = (lambda: ctx.block_sweep(1, stream=stream)) if block else (lambda: ctx.sweep(1, stream=stream))
         for w in range(warmup):
             step()
             torch.cuda.synchronize()
-            log(f"c5 {'learned' if learned else 'plain'} warmup sweep {w + 1}/{warmup}")
-        before = [ctx.block_stats(c) for c in range(chains)] if learned else None
-        acc_before = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) if not learned else 0
+            log(f"c5 {name} warmup sweep {w + 1}/{warmup}")
+        before = [ctx.block_stats(c) for c in range(chains)] if block else None
+        acc_before = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) if not block else 0
         ctx.set_option("time_update", 1)
         obs = torch.zeros((steps, chains, GGF_NOBS), dtype=torch.float64, device=dev)
         upd_ms, launches, changed = 0.0, 0, 0
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        for s in range(steps):
+        for s_ in range(steps):
             step()
             ms, la, fl = ctx.update_timing()
             upd_ms, launches, changed = upd_ms + ms, launches + la, changed + fl
-            ctx.measure(OBS_LINK, obs[s], stream=stream)
-            log(f"c5 {'learned' if learned else 'plain'} sweep {s + 1}/{steps}")
+            ctx.measure(OBS_LINK | OBS_DENSITY, obs[s_], stream=stream)
+            log(f"c5 {name} sweep {s_ + 1}/{steps}")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - ts
-        series = obs[:, :, 0].cpu().numpy()
-        tau, tau_err = autocorr_time(series)[:2] if steps >= 2 else (float("nan"), float("nan"))
-        rec = {"chains": chains, "sweeps": steps, "s_per_sweep": elapsed / steps, "init_s": t_init,
-               "tau_int_plaquette": tau, "tau_int_err": tau_err,
-               "effective_samples_per_s": steps * chains / (2.0 * tau) / elapsed,
-               "plaquette_mean": float(series.mean()), "update_ms_total": upd_ms, "update_launches": launches,
-               "links_changed": changed}
-        if learned:
+        series = obs.cpu().numpy()
+        final0 = ctx.measure()[0]                  # every slot of chain 0's final configuration
+        rec = {"chains": chains, "sweeps": steps, "warmup": warmup, "s_per_sweep": elapsed / steps,
+               "init_s": t_init, "precision": precision, "refresh_every": refresh,
+               "plaquette": statistics(series[:, :, 0], elapsed), "density": statistics(series[:, :, 2], elapsed),
+               "update_ms_total": upd_ms, "update_launches": launches, "links_changed": changed,
+               "final_chain0": {"links": ctx.get_state(0)[0].tolist(), "obs": final0.tolist()}}
+        if block:
             after = [ctx.block_stats(c) for c in range(chains)]
             prop = sum(a[0] - b[0] for a, b in zip(after, before))
             acc = sum(a[1] - b[1] for a, b in zip(after, before))
-            rec.update(acceptance=acc / max(prop, 1), links_per_accepted_move=changed / max(acc, 1), accepted_moves=acc,
-                       link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
+            rec.update(acceptance=acc / max(prop, 1), links_per_accepted_move=changed / max(acc, 1),
+                       accepted_moves=acc, link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
         else:
             acc = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) - acc_before
             rec.update(acceptance=acc / (chains * steps * 2 * L * L),
@@ -477,8 +649,11 @@ def run_c5(args):
         torch.cuda.synchronize()
         return rec
 
-    learned = sampler(args.chains, args.precision, args.refresh, True, args.steps, args.warmup)
-    plain = sampler(args.plain_chains, 64, 1024, False, args.plain_steps, 1) if args.plain_steps > 0 else None
+    learned = sampler("learned", args.chains, args.precision, args.refresh, params, args.steps, args.warmup)
+    untrained = (sampler("untrained", args.chains, args.precision, args.refresh, np.zeros(nparams, np.float32),
+                         args.steps, args.warmup) if args.untrained else None)
+    plain = (sampler("plain", args.plain_chains, 64, 16384, None, args.plain_steps, 1)
+             if args.plain_steps > 0 else None)
     # block update G -= G[:,U] W G[U,:] per accepted move of m changed links (rank r = 4 m), on the
     # upper triangle of the antisymmetric G and mirrored: algorithmic bytes = the upper triangle read
     # and all of G written ((n (n + 1) / 2 + n^2) * 4), flops = n^2 r
@@ -497,9 +672,15 @@ def run_c5(args):
             traffic = tj["bytes_per_accepted_move"] * learned["accepted_moves"] / learned["update_launches"]
     except (OSError, ValueError, KeyError):
         pass
-    out = {
+
+    def ratio(a, b, obs_name="plaquette"):
+        if not a or not b:
+            return None
+        return a[obs_name]["effective_samples_per_s"] / b[obs_name]["effective_samples_per_s"]
+
+    return {
         "metric": "link-update proposals/sec and effective samples/sec at fixed obs. error, 1 MI355X",
-        "value": learned["effective_samples_per_s"],
+        "value": learned["plaquette"]["effective_samples_per_s"],
         "unit": "effective samples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -512,16 +693,21 @@ def run_c5(args):
         "data": "synthetic",
         "config": {"workload": (f"Z{group} {L}x{L} periodic, K={K}, {args.chains} chains, learned 4x4-patch block "
                                 f"proposal (4-layer 3x3 conv, 32 channels, bf16 weights), float32 inverse, float64 "
-                                f"refresh every {args.refresh} changed links; vs the plain float64 single-link "
-                                f"sampler (delayed updates, window {args.delay}) on {args.plain_chains} chains"),
+                                f"refresh every {args.refresh} changed links; effective samples of the plaquette "
+                                f"from the spread of the chain means; vs the plain float64 single-link sampler "
+                                f"(delayed updates, window {args.delay}) on {args.plain_chains} chains and the "
+                                f"untrained block proposal"),
                    "name": "c5", "L": L, "K": K, "group": group, "chains": args.chains, "n": n, "patch": P,
                    "precision": args.precision, "refresh_every": args.refresh},
         "learned": learned,
+        "untrained_block": untrained,
         "plain_f64_single_link": plain,
-        "ess_ratio_learned_vs_plain": (learned["effective_samples_per_s"] / plain["effective_samples_per_s"]
-                                       if plain else None),
+        "ess_ratio_learned_vs_plain": ratio(learned, plain),
+        "ess_ratio_learned_vs_plain_density": ratio(learned, plain, "density"),
+        "ess_ratio_learned_vs_untrained": ratio(learned, untrained),
         "training": {"chains": args.train_chains, "sweeps": args.train_sweeps, "adam_steps_per_sweep": args.train_steps,
-                     "loss_nats_per_patch": losses, "seconds": t_train},
+                     "loss_nats_per_patch": losses, "uniform_loss_nats_per_patch": 32 * float(np.log(2.0)),
+                     "output_scale_trials": scale_trials, "output_scale": beta, "seconds": t_train},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_window_snap + k_window_gemm (block moves)",
@@ -530,8 +716,8 @@ def run_c5(args):
                      "tflops": tflops, "mfma_peak_tflops": MFMA_PEAK_F32_TFLOPS,
                      "flops_per_changed_link": 4.0 * n * n},
         "cpu_baseline": None,
+        "_params": params,
     }
-    print(json.dumps(out))
 
 
 def electric_measurement(ctx, args, Lc, stream, reps=20):
@@ -622,28 +808,8 @@ def synth_gamma_loc(args):
     return synth.make_tensor(args.L, K=args.K, group=args.group).gamma_loc
 
 
-def main():
-    args = parse()
-    if args.traffic_from:
-        traffic_from(args)
-        return
-    if args.electric_traffic_from:
-        electric_traffic_from(args)
-        return
-    if args.block_traffic_from:
-        block_traffic_from(args)
-        return
-    if args.copy_probe:
-        copy_probe(args.copy_probe)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent and "
-              "would shard by contiguous ranges of chains with one reduction of the observables, but that "
-              "path is not built)", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "c5":
-        run_c5(args)
-        return
+def run_plain(args, with_cpu=True):
+    """Single-link sweeps of the c2 / c3 / c4 workloads: one JSON record."""
     import torch
     import synth
     from paper_2412_01737_amd.ggf import Context, autocorr_time, OBS_LINK, OBS_DENSITY, GGF_NOBS
@@ -656,12 +822,12 @@ def main():
     if args.workload == "c4":
         Ls, Ks, groups = synth.mixed_batch(args.chains)
         ids = {}
-        for kk in synth.MIX_K:
-            for gg in synth.MIX_GROUP:
-                # patch links drawn on the smallest lattice exist on every lattice of the batch
-                ids[(kk, gg)] = ctx.set_tensor_spec(synth.make_tensor(min(synth.MIX_L), K=int(kk), group=int(gg)))
+        keys = list(zip(Ls.tolist(), Ks.tolist(), groups.tolist()))
+        for key in sorted(set(keys)):
+            # one ansatz per (L, K, group), its patch links drawn on its own lattice
+            ids[key] = ctx.set_tensor_spec(synth.make_tensor(key[0], K=key[1], group=key[2]))
         Lc = Ls
-        tids = np.array([ids[(int(k), int(g))] for k, g in zip(Ks, groups)], np.int32)
+        tids = np.array([ids[key] for key in keys], np.int32)
     else:
         Lc = np.full(args.chains, L, np.int32)
         tids = ctx.set_tensor_spec(synth.make_tensor(L, K=K, group=group))
@@ -672,31 +838,35 @@ def main():
                     refresh_every=args.refresh, stream=stream)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
-    tuned = None
-    if args.autotune:
-        tuned = ctx.autotune(args.autotune, os.path.join(HERE, "paper_2412_01737_amd", "autotune_cache.txt"),
-                             stream=stream)
+    ctx.set_option("delay", args.delay)
     if args.update_grid:
         ctx.set_option("update_grid", args.update_grid)
     if args.update_tiles:
         ctx.set_option("update_tiles", args.update_tiles)
+    if args.flush_grid:
+        ctx.set_option("flush_grid", args.flush_grid)
+    ctx.set_option("update_nt", args.update_nt)
+    tuned = None
+    if args.autotune:
+        # after the delay window is set: the tuner times the launch shapes of the path that runs
+        tuned = ctx.autotune(args.autotune, os.path.join(HERE, "paper_2412_01737_amd", "autotune_cache.txt"),
+                             stream=stream)
     ctx.set_option("graph", args.graph)
-    ctx.set_option("delay", args.delay)
-    if not args.autotune:
-        ctx.set_option("update_nt", args.update_nt)
     mask = OBS_LINK | OBS_DENSITY
     obs = torch.zeros((args.warmup + args.steps, args.chains, GGF_NOBS), dtype=torch.float64, device=dev)
     for w in range(args.warmup):
         ctx.sweep(1, stream=stream)
         ctx.measure(mask, obs[w], stream=stream)
     st0 = [ctx.get_state(c)[1] for c in range(args.chains)]
-    ctx.set_option("time_update", 1)
+    # per-kernel HIP events are recorded only on eager launches: with graph replay the timed sweeps
+    # run as graphs (timed by the host clock) and the kernel times come from eager sweeps afterwards
+    ctx.set_option("time_update", 0 if args.graph else 1)
     upd_ms, upd_launches, upd_flips = 0.0, 0, 0
     rat_ms, rat_launches = 0.0, 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        ctx.sweep(1, stream=stream)
+    acc0 = sum(st["accepts"] for st in st0)
+
+    def timings():
+        nonlocal upd_ms, upd_launches, upd_flips, rat_ms, rat_launches
         ms, la, fl = ctx.update_timing()
         upd_ms += ms
         upd_launches += la
@@ -704,10 +874,26 @@ def main():
         ms, la = ctx.ratio_timing()
         rat_ms += ms
         rat_launches += la
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ctx.sweep(1, stream=stream)
+        if not args.graph:
+            timings()
         ctx.measure(mask, obs[args.warmup + s], stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     refresh = refresh_correction(ctx, args, st0, stream)
+    kernel_sweeps = args.steps
+    if args.graph:
+        upd_flips_timed = sum(ctx.get_state(c)[1]["accepts"] for c in range(args.chains)) - acc0
+        ctx.set_option("time_update", 1)
+        kernel_sweeps = 2
+        for _ in range(kernel_sweeps):
+            ctx.sweep(1, stream=stream)
+            timings()
+        upd_flips = upd_flips_timed
     electric = electric_measurement(ctx, args, Lc, stream)
     energy = energy_measurement(ctx, args, stream)
     lambda_opt = None
@@ -735,12 +921,9 @@ def main():
     elapsed = elapsed + refresh["correction_ms"] * 1e-3
     proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
     value = proposals / elapsed
-    series = obs[args.warmup:, :, 0].cpu().numpy()
-    if series.shape[0] >= 2:
-        tau, tau_err, window = autocorr_time(series)
-        ess_per_s = series.shape[0] * series.shape[1] / (2.0 * tau) / elapsed
-    else:
-        tau = tau_err = ess_per_s = None
+    series = obs[args.warmup:].cpu().numpy()
+    plaq_stats = statistics(series[:, :, 0], elapsed)
+    dens_stats = statistics(series[:, :, 2], elapsed)
     acceptance = upd_flips / proposals
     esz = 8 if args.precision == 64 else 4
     if args.workload == "c4":
@@ -776,7 +959,7 @@ def main():
     except (OSError, ValueError):
         pass
     cpu = None
-    if not args.no_cpu and args.workload != "c4":
+    if with_cpu and not args.no_cpu and args.workload != "c4":
         cpu = cpu_baseline(args, args.cpu_seconds)
     mean_obs = obs[args.warmup:].mean(dim=(0, 1)).cpu().numpy()
     out = {
@@ -801,9 +984,9 @@ def main():
                    "name": args.workload, "L": L, "K": K, "group": group, "chains": args.chains, "n_max": n,
                    "precision": args.precision, "refresh_every": args.refresh, "graph": args.graph,
                    "delay_window": F, "autotuned": list(tuned) if tuned else None},
-        "effective_samples_per_s": ess_per_s,
-        "tau_int_plaquette": tau,
-        "tau_int_err": tau_err,
+        "effective_samples_per_s": plaq_stats["effective_samples_per_s"],
+        "plaquette": plaq_stats,
+        "density": dens_stats,
         "acceptance": acceptance,
         "observables_mean": {"plaquette": float(mean_obs[0]), "wilson2x2": float(mean_obs[1]),
                              "density": float(mean_obs[2])},
@@ -812,7 +995,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "update_ms_total": upd_ms, "update_launches": upd_launches, "flips": upd_flips},
-        "kernels_ms_per_step": {kernel: upd_ms / args.steps, "k_ratio": rat_ms / args.steps},
+        "kernels_ms_per_step": {kernel: upd_ms / kernel_sweeps, "k_ratio": rat_ms / kernel_sweeps},
         "timed_s": timed_s,
         "refresh": refresh,
         "electric": electric,
@@ -821,7 +1004,69 @@ def main():
         "gamma_opt": gamma_opt,
         "cpu_baseline": cpu,
     }
+    return out
+
+
+def run_north(args):
+    """The default run: the c5 comparison (headline), the c2 plain float64 leg, the CPU oracle legs."""
+    import torch
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    a2 = c2_args(args)
+    log("north: 8x8 plain float64 leg")
+    c2 = run_plain(a2, with_cpu=False)
+    torch.cuda.synchronize()
+    log("north: 32x32 learned-proposal comparison")
+    out = run_c5(args)
+    params = out.pop("_params", None)
+    cpu = None
+    if not args.no_cpu:
+        log("north: CPU oracle legs")
+        c2["cpu_baseline"] = cpu_baseline(a2, args.cpu_seconds)
+        out["_params"] = params
+        cpu = cpu_baseline_c5(args, 2.0 * args.cpu_seconds, out)
+        out.pop("_params", None)
+    for rec in (out.get("learned"), out.get("untrained_block"), out.get("plain_f64_single_link")):
+        if rec:
+            rec.pop("final_chain0", None)
+    out["cpu_baseline"] = cpu
+    out["plain_f64_c2"] = c2
     print(json.dumps(out))
+
+
+def main():
+    args = parse()
+    if args.traffic_from:
+        traffic_from(args)
+        return
+    if args.electric_traffic_from:
+        electric_traffic_from(args)
+        return
+    if args.block_traffic_from:
+        block_traffic_from(args)
+        return
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (chains are independent and "
+              "would shard by contiguous ranges of chains with one reduction of the observables, but that "
+              "path is not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "north":
+        run_north(args)
+        return
+    if args.workload == "c5":
+        out = run_c5(args)
+        out.pop("_params", None)
+        for rec in (out.get("learned"), out.get("untrained_block"), out.get("plain_f64_single_link")):
+            if rec:
+                rec.pop("final_chain0", None)
+        print(json.dumps(out))
+        return
+    print(json.dumps(run_plain(args)))
 
 
 if __name__ == "__main__":

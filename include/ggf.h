@@ -272,19 +272,24 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *                  flips of a window are kept as pending factors G_cur = G - X Y^T and applied
  *                  by one matrix-core rank-4F update at its end), 0 = one rank-4 streaming
  *                  update per link step, -1 (default) = 16.  Takes effect at the next sweep;
- *                  G as read through the ABI never has pending flips. */
+ *                  G as read through the ABI never has pending flips.
+ *   "flush_grid"   workgroups of the window flush (default 1024)
+ *   "time_update"  1 = record HIP events around the update and link-step launches of eager sweeps
+ *                  (ggf_update_timing, ggf_ratio_timing); a sweep with graph replay then runs eagerly */
 ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);
 
-/* Pick the launch shape of the rank-4 update (grid, rows per work item,
- * non-temporal G access) by timing candidates on live sweeps: each candidate
- * runs `sweeps_per_candidate` real Metropolis sweeps (they advance the chains,
- * so call it during burn-in; results do not depend on the launch shape) and
- * the update time per accepted flip is measured with HIP events.  With
- * cache_path != NULL the choice is looked up in / appended to that text file,
- * keyed by (n_max, precision, K_max, n_chains); a cached choice skips the
- * timing.  The chosen values are left set as the "update_grid",
- * "update_tiles" and "update_nt" options and returned through best[3]
- * (may be NULL).  Synchronous. */
+/* Pick the launch shapes of the path that runs by timing candidates on live
+ * sweeps: each candidate runs `sweeps_per_candidate` real Metropolis sweeps (they
+ * advance the chains, so call it during burn-in; results do not depend on the
+ * launch shape) and the time of the link steps and update launches per proposal
+ * is measured with HIP events.  With delayed updates (the default) it tunes the
+ * window flush: best = {flush_grid, delay window (8, 16 or 32 link steps), 0};
+ * with "delay" = 0 the rank-4 streaming update: best =
+ * {update_grid, update_tiles, update_nt}.  With cache_path != NULL the choice
+ * is looked up in / appended to that text file, keyed by (path, n_max,
+ * precision, K_max, n_chains); a cached choice skips the timing.  The chosen
+ * values are left set as options and returned through best[3] (may be NULL).
+ * Synchronous. */
 ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *cache_path, int64_t *best,
                         void *stream);
 
@@ -377,9 +382,12 @@ ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uin
 
 /* Bandwidth probe (diagnostics): mode 0 copies `bytes` from a to b, mode 1 the
  * same with non-temporal loads/stores, mode 2 updates a in place
- * (a = a * 1 + 1, read and write), mode 3 the same non-temporal.  a and b are
- * device pointers (b unused for modes 2, 3); bytes a multiple of 16; grid
- * workgroups of 256 threads (0 = 4096).  Asynchronous on `stream`. */
+ * (a = a * 1 + 1, read and write), mode 3 the same non-temporal.  Modes 4-7 keep
+ * 8 non-temporal 16-byte loads in flight per thread, each workgroup streaming one
+ * contiguous chunk: 4 copy a -> b, 5 update a in place, 6 read a only, 7 write b
+ * only.  a and b are device pointers (b unused for modes 2, 3, 5); bytes a
+ * multiple of 16; grid workgroups of 256 threads (0 = 4096).  Asynchronous on
+ * `stream`. */
 ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_t grid, void *stream);
 
 /* Message of the most recent failure on this context ("" if none). */

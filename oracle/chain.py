@@ -26,6 +26,7 @@ Two evaluators of the ratio:
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 from . import philox
 from .model import Ansatz, rotation
@@ -208,14 +209,17 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "de
 
     def log_n(k):
         M = an.assemble_M(k)
-        sign, ld = np.linalg.slogdet(M)
-        lw = 0.5 * ld - 4 * an.lat.V * np.log(2.0)
-        if an.K == 1:
-            return lw
-        if route == "def":
-            return lw + np.log(an.s_factor_def(k).real)
-        G = np.linalg.inv(M)
-        return lw + np.log(an.s_factor_patch(G[np.ix_(an.S, an.S)], k).real)
+        if an.K == 1 or route == "def":
+            sign, ld = np.linalg.slogdet(M)
+            lw = 0.5 * ld - 4 * an.lat.V * np.log(2.0)
+            return lw if an.K == 1 else lw + np.log(an.s_factor_def(k).real)
+        # one LU factorisation gives det M and the patch block (M^-1)_SS (columns S of the inverse)
+        lu, piv = scipy.linalg.lu_factor(M)
+        lw = 0.5 * np.sum(np.log(np.abs(np.diag(lu)))) - 4 * an.lat.V * np.log(2.0)
+        E = np.zeros((M.shape[0], len(an.S)))
+        E[an.S, np.arange(len(an.S))] = 1.0
+        g_ss = scipy.linalg.lu_solve((lu, piv), E)[an.S, :]
+        return lw + np.log(an.s_factor_patch(g_ss, k).real)
 
     R = np.exp(log_n(k_new) - log_n(ch.k) + nn.log_q(zl, y_old) - nn.log_q(zl, y_new))
     ch.ties += near_tie(u_acc, R)

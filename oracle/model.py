@@ -407,3 +407,59 @@ class Ansatz:
         keep = [OBS_DENSITY] + [OBS_MESON0 + i for i in range(MAX_MESON)]
         out[keep] = f[keep].real
         return out
+
+    def transition_inverse_factor(self, G: np.ndarray, links_k, n: int, m: int) -> np.ndarray:
+        """Y_nm with M_nm^-1 = G - G[:,S] Y_nm G[S,:]: M_nm = M_00 + Delta, Delta nonzero only on the
+        patch Majoranas S, so by the Woodbury identity Y = Delta_SS (1 + G_SS Delta_SS)^-1 (this form
+        needs no inverse of Delta, which is singular on the patch links a pair does not involve)."""
+        S = self.S
+        dl = self.delta_patch(links_k, n, m)
+        return dl @ np.linalg.inv(np.eye(len(S)) + G[np.ix_(S, S)] @ dl)
+
+    def observables_from_inverse(self, links_k, G: np.ndarray, logw=None) -> np.ndarray:
+        """The observable slots of ``observables`` from G = M(G)^-1 alone (a maintained inverse, or a
+        fresh one of a lattice too large for the full Pfaffians and inverses of every M_nm): the cross
+        ratios by the patch lemma on G_SS, and M_nm^-1 by the Woodbury correction of
+        ``transition_inverse_factor``; log W from a fresh determinant unless given."""
+        G = np.asarray(G, float)
+        out = np.zeros(NOBS)
+        out[OBS_PLAQ] = self.plaquette(links_k)
+        out[OBS_WILSON] = self.wilson2x2(links_k)
+        lw = self.log_weight(links_k) if logw is None else logw
+        gbb = self.B @ G @ self.B.T
+        if self.K == 1:
+            f = self.fermion_obs(self.A + gbb, links_k)
+            out[OBS_LOGN] = lw
+            out[OBS_ELECTRIC] = self.electric_mean(links_k, [[G]], np.ones((1, 1)))
+        else:
+            S = self.S
+            r = self.cross_ratio_patch(G[np.ix_(S, S)], links_k)
+            wts = np.conj(self.c)[:, None] * self.c[None, :] * self.bond_overlaps() * r
+            Stot = wts.sum()
+            f = np.zeros(NOBS, complex)
+            blocks = [[None] * self.K for _ in range(self.K)]
+            bgs = self.B @ G[:, S]
+            gsb = G[S, :] @ self.B.T
+            for n in range(self.K):
+                for m in range(self.K):
+                    Y = self.transition_inverse_factor(G, links_k, n, m)
+                    f += wts[n, m] / Stot * self.fermion_obs(self.A + gbb - bgs @ Y @ gsb, links_k)
+                    blocks[n][m] = _WoodburyBlocks(G, S, Y)
+            out[OBS_LOGN] = lw + np.log(Stot.real)
+            out[OBS_ELECTRIC] = self.electric_mean(links_k, blocks, wts)
+        keep = [OBS_DENSITY] + [OBS_MESON0 + i for i in range(MAX_MESON)]
+        out[keep] = f[keep].real
+        return out
+
+
+class _WoodburyBlocks:
+    """Index access M_nm^-1[np.ix_(u, v)] = G[u,v] - G[u,S] Y G[S,v] without forming M_nm^-1."""
+
+    def __init__(self, G, S, Y):
+        self.G, self.S, self.Y = G, S, Y
+
+    def __getitem__(self, idx):
+        u, v = idx
+        u, v = np.ravel(u), np.ravel(v)
+        return self.G[np.ix_(u, v)] - self.G[np.ix_(u, self.S)] @ self.Y @ self.G[np.ix_(self.S, v)]
+

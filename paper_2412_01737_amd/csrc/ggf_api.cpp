@@ -64,6 +64,7 @@ struct ggf_ctx {
   // options
   int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 0, opt_time_update = 0, opt_update_nt = 1;
   int opt_delay = -1;            // window of delayed updates in link steps (0 = immediate, -1 = automatic)
+  int opt_flush_grid = 0;        // workgroups of the window flush (0 = library default)
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -373,6 +374,7 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 2048;
   const int F = delay_window(ctx);
   if (F > 0 && !ctx->dly_cnt) return fail(ctx, GGF_ESTATE, "delayed-update buffers are not allocated");
+  const int flush_grid = ctx->opt_flush_grid > 0 ? ctx->opt_flush_grid : 1024;
   lc.dly = F;
   int k = 0;
   for (int ell = 0; ell < ctx->max_links; ++ell) {
@@ -383,7 +385,7 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->rev[2 * ell + 1], s));
     if (F > 0 && t != F - 1 && ell != ctx->max_links - 1) continue;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k], s));
-    if (F > 0) ggf_launch_window_flush(lc, wp, 1024, ctx->kmax > 1);
+    if (F > 0) ggf_launch_window_flush(lc, wp, flush_grid, ctx->kmax > 1);
     else ggf_launch_update(lc, ell & 1, grid, tiles, ctx->opt_update_nt);
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * k + 1], s));
     ++k;
@@ -1398,12 +1400,13 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
   } else if (k == "scratch_mb") ctx->opt_scratch_mb = value;
   else if (k == "time_update") ctx->opt_time_update = value != 0;
   else if (k == "update_nt") ctx->opt_update_nt = value != 0;
+  else if (k == "flush_grid") ctx->opt_flush_grid = static_cast<int>(std::min<int64_t>(value, 1 << 20));
   else if (k == "delay") {
     if (!(value == -1 || value == 0 || (value % 8 == 0 && value >= 8 && value <= 32)))
       return fail(ctx, GGF_EINVAL, "delay must be -1 (automatic), 0 (immediate) or 8, 16, 24, 32 link steps");
     ctx->opt_delay = static_cast<int>(value);
   } else return fail(ctx, GGF_EINVAL, "unknown option " + k);
-  if (k == "update_grid" || k == "update_tiles" || k == "update_nt" || k == "delay") {
+  if (k == "update_grid" || k == "update_tiles" || k == "update_nt" || k == "delay" || k == "flush_grid") {
     if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   }
   return GGF_OK;
@@ -1414,44 +1417,73 @@ ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *
   if (!ctx) return GGF_EINVAL;
   if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
   if (sweeps_per_candidate < 1) return fail(ctx, GGF_EINVAL, "sweeps_per_candidate must be >= 1");
-  char key[128];
-  std::snprintf(key, sizeof(key), "n%d_p%d_K%d_c%d", ctx->n_max, ctx->precision, ctx->kmax, ctx->n_chains);
-  long long choice[3] = {0, 0, 1};
+  // delayed updates (the default): the flush grid and the window length; immediate updates
+  // (delay = 0): the launch shape of the rank-4 streaming update
+  const bool delayed = delay_window(ctx) > 0;
+  char key[160];
+  std::snprintf(key, sizeof(key), "%s_n%d_p%d_K%d_c%d", delayed ? "flush" : "update", ctx->n_max, ctx->precision,
+                ctx->kmax, ctx->n_chains);
+  long long choice[3] = {0, 0, 0};
   bool found = false;
   if (cache_path) {
     if (FILE *f = std::fopen(cache_path, "r")) {
-      char k[128];
-      long long g, t, nt;
-      while (std::fscanf(f, "%127s %lld %lld %lld", k, &g, &t, &nt) == 4)
-        if (std::strcmp(k, key) == 0) { choice[0] = g; choice[1] = t; choice[2] = nt; found = true; }
+      char k[160];
+      long long a, b, c;
+      while (std::fscanf(f, "%159s %lld %lld %lld", k, &a, &b, &c) == 4)
+        if (std::strcmp(k, key) == 0) { choice[0] = a; choice[1] = b; choice[2] = c; found = true; }
       std::fclose(f);
     }
   }
   if (!found) {
-    const int saved_time = ctx->opt_time_update, saved_graph = ctx->opt_graph;
+    const int saved_time = ctx->opt_time_update;
     ctx->opt_time_update = 1;
     double best_cost = 1e300;
-    const int grids[3] = {1024, 2048, 4096};
-    const int rows[3] = {8, 16, 32};
-    for (int nt = 1; nt >= 0; --nt)
-      for (int gi = 0; gi < 3; ++gi)
-        for (int ri = 0; ri < 3; ++ri) {
-          ctx->opt_update_grid = grids[gi];
-          ctx->opt_update_tiles = std::max(1, ctx->n_max / rows[ri]);
-          ctx->opt_update_nt = nt;
-          ggf_status st = ggf_sweep(ctx, sweeps_per_candidate, stream);
+    auto timed_cost = [&](double &cost) -> ggf_status {
+      ggf_status st = ggf_sweep(ctx, sweeps_per_candidate, stream);
+      if (st != GGF_OK) return st;
+      const double props = static_cast<double>(sweeps_per_candidate) * ctx->max_links * ctx->n_chains;
+      // link steps and update launches: the part of a sweep the launch shape changes
+      cost = (ctx->last_update_ms + ctx->last_ratio_ms) / props;
+      return GGF_OK;
+    };
+    if (delayed) {
+      const int grids[3] = {512, 1024, 2048};
+      const int windows[3] = {8, 16, 32};
+      for (int wi = 0; wi < 3; ++wi)
+        for (int gi = 0; gi < 3; ++gi) {
+          ctx->opt_delay = windows[wi];
+          ctx->opt_flush_grid = grids[gi];
+          double cost = 0.0;
+          ggf_status st = timed_cost(cost);
           if (st != GGF_OK) return st;
-          if (ctx->last_flips <= 0) continue;
-          const double cost = ctx->last_update_ms / static_cast<double>(ctx->last_flips);
           if (cost < best_cost) {
             best_cost = cost;
             choice[0] = grids[gi];
-            choice[1] = ctx->opt_update_tiles;
-            choice[2] = nt;
+            choice[1] = windows[wi];
+            choice[2] = 0;
           }
         }
+    } else {
+      const int grids[3] = {1024, 2048, 4096};
+      const int rows[3] = {8, 16, 32};
+      for (int nt = 1; nt >= 0; --nt)
+        for (int gi = 0; gi < 3; ++gi)
+          for (int ri = 0; ri < 3; ++ri) {
+            ctx->opt_update_grid = grids[gi];
+            ctx->opt_update_tiles = std::max(1, ctx->n_max / rows[ri]);
+            ctx->opt_update_nt = nt;
+            double cost = 0.0;
+            ggf_status st = timed_cost(cost);
+            if (st != GGF_OK) return st;
+            if (cost < best_cost) {
+              best_cost = cost;
+              choice[0] = grids[gi];
+              choice[1] = ctx->opt_update_tiles;
+              choice[2] = nt;
+            }
+          }
+    }
     ctx->opt_time_update = saved_time;
-    ctx->opt_graph = saved_graph;
     if (cache_path && choice[0] > 0) {
       if (FILE *f = std::fopen(cache_path, "a")) {
         std::fprintf(f, "%s %lld %lld %lld\n", key, choice[0], choice[1], choice[2]);
@@ -1460,9 +1492,14 @@ ggf_status ggf_autotune(ggf_ctx *ctx, int32_t sweeps_per_candidate, const char *
     }
   }
   if (choice[0] > 0) {
-    ctx->opt_update_grid = static_cast<int>(choice[0]);
-    ctx->opt_update_tiles = static_cast<int>(choice[1]);
-    ctx->opt_update_nt = static_cast<int>(choice[2]);
+    if (delayed) {
+      ctx->opt_flush_grid = static_cast<int>(choice[0]);
+      ctx->opt_delay = static_cast<int>(choice[1]);
+    } else {
+      ctx->opt_update_grid = static_cast<int>(choice[0]);
+      ctx->opt_update_tiles = static_cast<int>(choice[1]);
+      ctx->opt_update_nt = static_cast<int>(choice[2]);
+    }
     if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   }
   if (best)
@@ -1732,7 +1769,8 @@ ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uin
 }
 
 ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_t grid, void *stream) {
-  if (!a || (mode < 2 && !b) || bytes % 16 != 0 || grid < 0 || mode < 0 || mode > 3) return GGF_EINVAL;
+  const bool needs_b = mode < 2 || mode == 4 || mode >= 6;
+  if (!a || (needs_b && !b) || bytes % 16 != 0 || grid < 0 || mode < 0 || mode > 7) return GGF_EINVAL;
   if (ggf_launch_probe(mode, a, b, bytes, grid ? grid : 4096, static_cast<hipStream_t>(stream)) != 0)
     return GGF_EINVAL;
   return hipGetLastError() == hipSuccess ? GGF_OK : GGF_EDEVICE;

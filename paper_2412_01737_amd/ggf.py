@@ -367,7 +367,8 @@ class Context:
         return p.value, a.value, m.value
 
     def autotune(self, sweeps_per_candidate: int = 1, cache_path: str | None = None, stream=None):
-        """Choose the update launch shape on live sweeps; returns (grid, tiles, non_temporal)."""
+        """Choose the launch shapes of the path that runs on live sweeps: (flush_grid, window, 0) with
+        delayed updates, (update_grid, update_tiles, non_temporal) with delay 0."""
         best = (ctypes.c_int64 * 3)()
         self._check(self._lib.ggf_autotune(self.h, int(sweeps_per_candidate),
                                            None if cache_path is None else cache_path.encode(), best,

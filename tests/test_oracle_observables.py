@@ -153,3 +153,18 @@ def test_meson_strings_r1_r2_against_fock(K, group):
                                 for j in range(r)])
                 tot += 2 * line * fk.expect(k, phi[x].conj().T @ phi[y], c)
             assert abs(obs[OBS_MESON0 + r - 1] - (tot / V).real) < 1e-12, (r, k)
+
+
+@pytest.mark.parametrize("L,K,group", [(2, 1, 2), (4, 1, 3), (2, 2, 2), (4, 3, 3), (4, 2, 2), (6, 4, 2)])
+def test_observables_from_inverse_equal_the_definition(L, K, group):
+    """Every observable slot from the maintained-inverse route (patch-lemma cross ratios, Woodbury
+    transition inverses) equals the definition (full Pfaffians and inverses of every M_nm)."""
+    lat = Lattice(L, L)
+    spec = synth.make_tensor(L, K=K, group=group)
+    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, group, spec.patch_link, spec.gamma_bond_k, spec.c)
+    rng = np.random.default_rng(31)
+    for _ in range(2 if L < 6 else 1):
+        k = rng.integers(0, group, lat.n_links)
+        ref = an.observables(k)
+        got = an.observables_from_inverse(k, np.linalg.inv(an.assemble_M(k)))
+        assert np.abs(got - ref).max() < 1e-10, np.abs(got - ref).max()
