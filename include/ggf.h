@@ -133,6 +133,19 @@ ggf_status ggf_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
 ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out_is_device,
                        void *stream);
 
+/* For callers that cannot allocate device memory (serving loops, harnesses that forbid
+ * hipMalloc, code that must not allocate between its set-up and its end): ggf_measure with a
+ * host output, staged through a fixed device array instead of a temporary allocation.
+ * obs_mask and the slots as in ggf_measure; host_out[n_chains][GGF_NOBS] float64, owned by
+ * the caller.  The staging array (GGF_STAGE_MAX_CHAINS x GGF_NOBS doubles, 2.6 MiB) is one
+ * per GPU, held until the process ends and shared by every context on that GPU: calls that
+ * overlap on one GPU (other host threads, or streams running concurrently) race on it.
+ * Allocates nothing; synchronises `stream`.  GGF_EINVAL when the context holds more than
+ * GGF_STAGE_MAX_CHAINS chains or host_out is NULL, GGF_EDEVICE when the array's address
+ * could not be obtained at ggf_create. */
+#define GGF_STAGE_MAX_CHAINS 16384
+ggf_status ggf_measure_staged(ggf_ctx *ctx, uint32_t obs_mask, double *host_out, void *stream);
+
 /* Couplings of the gauged Hamiltonian (Sec. 2 staggered fermions, Sec. 2.2
  * gauging, Sec. 2.3 plaquette and electric terms), one fermion mode per site:
  *   H = t  sum_{x,mu} [ i eta_mu(x) psi_x^+ D(g_{x,mu}) psi_{x+mu} + h.c. ]

@@ -20,6 +20,7 @@ static_assert(GGF_NOBS == GGF_NOBS_DEV, "observable slot counts of the ABI and t
 static_assert(GGF_KMAX == GGF_KMAX_DEV, "superposition sizes of the ABI and the kernels differ");
 static_assert(GGF_ENERGY_STRIDE == GGF_ENERGY_STRIDE_DEV, "energy row lengths of the ABI and the kernels differ");
 static_assert(GGF_SENS_STRIDE == GGF_SENS_STRIDE_DEV, "sensitivity row lengths of the ABI and the kernels differ");
+static_assert(GGF_STAGE_MAX_CHAINS == GGF_STAGE_MAX_CHAINS_DEV, "staging capacities of the ABI and the kernels differ");
 
 typedef std::complex<double> cplx;
 
@@ -35,6 +36,8 @@ struct Buf {
 struct ggf_ctx {
   int device = 0;
   std::string err;
+  double *stage = nullptr;       // this device's staging array of ggf_measure_staged (fixed, never freed)
+  hipError_t stage_err = hipSuccess;
   std::vector<TensorDev> tensors;
   TensorDev *tensors_dev = nullptr;
   size_t tensors_cap = 0;
@@ -510,6 +513,8 @@ ggf_status ggf_create(ggf_ctx **out, int device) {
   ggf_ctx *ctx = new (std::nothrow) ggf_ctx();
   if (!ctx) return GGF_ENOMEM;
   ctx->device = device;
+  // the staging array's address on this device, looked up once per device at set-up
+  ctx->stage_err = ggf_stage_address(device, &ctx->stage);
   *out = ctx;
   return GGF_OK;
 }
@@ -812,6 +817,26 @@ ggf_status ggf_measure(ggf_ctx *ctx, uint32_t obs_mask, double *out, int32_t out
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(tmp);
   if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+ggf_status ggf_measure_staged(ggf_ctx *ctx, uint32_t obs_mask, double *host_out, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (!host_out) return fail(ctx, GGF_EINVAL, "host_out is NULL");
+  if (ctx->n_chains > GGF_STAGE_MAX_CHAINS)
+    return fail(ctx, GGF_EINVAL, "ggf_measure_staged stages at most " + std::to_string(GGF_STAGE_MAX_CHAINS) +
+                                     " chains, the context has " + std::to_string(ctx->n_chains));
+  if (!ctx->stage)
+    return fail(ctx, GGF_EDEVICE, std::string("staging array unavailable: ") + hipGetErrorString(ctx->stage_err));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LaunchCtx lc = launch_ctx(ctx, s);
+  // every slot of every row is written by the measurement, so the array needs no clearing
+  ggf_launch_measure(lc, obs_mask, ctx->stage, ctx->kmax);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipMemcpyAsync(host_out, ctx->stage, static_cast<size_t>(ctx->n_chains) * GGF_NOBS * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
   return GGF_OK;
 }
 

@@ -79,3 +79,7 @@ void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int m
 void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,
                            double *out, int kmax);
 int ggf_launch_probe(int mode, void *a, void *b, size_t bytes, int grid, hipStream_t s);
+// Staging array of the allocation-free host measurement: GGF_STAGE_MAX_CHAINS x GGF_NOBS_DEV doubles per
+// GPU, a fixed device array; its address on `device` (looked up once per device).
+#define GGF_STAGE_MAX_CHAINS_DEV 16384
+hipError_t ggf_stage_address(int device, double **ptr);

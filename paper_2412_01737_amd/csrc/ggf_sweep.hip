@@ -25,6 +25,7 @@
 // rows and columns (Schur complement S = 1 + G_cur,UU dM, whose determinant is
 // rho).  At the end of the window the block-update kernels apply the whole
 // window as one rank-|A| matrix-core update of G.
+#include <mutex>
 #include <type_traits>
 
 #include "ggf_device.h"
@@ -1849,3 +1850,31 @@ void ggf_launch_measure(const LaunchCtx &lc, uint32_t mask, double *out, int kma
   else
     hipLaunchKernelGGL(k_measure<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, mask, out);
 }
+
+// Staging rows of the allocation-free host measurement (ggf_measure_staged): one fixed array per
+// GPU, held until the process ends.  Host code never names the array: it takes the address that
+// hipGetSymbolAddress returns on each device, once, and passes that to the kernels and copies.
+static __device__ __align__(256) double scratch[static_cast<size_t>(GGF_STAGE_MAX_CHAINS_DEV) * GGF_NOBS_DEV];
+
+hipError_t ggf_stage_address(int device, double **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex m;
+  static double *addr[kMaxDevices] = {};
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(m);
+  if (!addr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    double *p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch));
+    if (cur != device) hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+

@@ -19,6 +19,7 @@ GGF_OK, GGF_EINVAL, GGF_ENOMEM, GGF_ESINGULAR, GGF_ENONFINITE, GGF_EDEVICE, GGF_
 GGF_KMAX = 4
 GGF_NOBS = 21
 GGF_ENERGY_STRIDE = 1 + 4 * GGF_KMAX * GGF_KMAX
+GGF_STAGE_MAX_CHAINS = 16384
 GGF_SENS_STRIDE = 200
 OBS_LINK, OBS_DENSITY, OBS_MESON, OBS_ELECTRIC = 1, 2, 4, 8
 OBS_ALL = 15
@@ -58,6 +59,7 @@ EXPORTS = {
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "ggf_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "ggf_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_measure_staged": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, _dp, ctypes.c_void_p]),
     "ggf_measure_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Couplings), ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p]),
     "ggf_optimise_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Couplings), ctypes.c_int32,
@@ -221,6 +223,13 @@ class Context:
         ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
         self._check(self._lib.ggf_measure(self.h, int(mask), ctypes.c_void_p(ptr), 1, _stream_ptr(stream)))
         return out
+
+    def measure_staged(self, mask: int = OBS_ALL, stream=None) -> np.ndarray:
+        """Observables [n_chains, GGF_NOBS] into a new host array through ggf_measure_staged (no device
+        allocation; at most GGF_STAGE_MAX_CHAINS chains)."""
+        host = np.zeros((self.n_chains, GGF_NOBS))
+        self._check(self._lib.ggf_measure_staged(self.h, int(mask), host.ctypes.data_as(_dp), _stream_ptr(stream)))
+        return host
 
     def measure_energy(self, couplings, out=None, stream=None):
         """Local-energy rows [n_chains, GGF_ENERGY_STRIDE] (ggf_measure_energy); couplings is a
