@@ -403,6 +403,10 @@ ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uin
  * `stream`. */
 ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_t grid, void *stream);
 
+/* SHA-256 (hex) of the sources the library was built from (its C++/HIP sources and this
+ * header), or "unknown" for a build that did not record it.  Static string. */
+const char *ggf_source_digest(void);
+
 /* Message of the most recent failure on this context ("" if none). */
 const char *ggf_last_error(ggf_ctx *ctx);
 

@@ -2,7 +2,10 @@
 
 Objects are compiled in parallel into paper_2412_01737_amd/_build/ and linked
 into paper_2412_01737_amd/libggf.so.  Packed-FP32 instructions are disabled
-for the device code (the -packed-fp32-ops target feature).
+for the device code (the -packed-fp32-ops target feature).  The SHA-256 of the
+sources (csrc/ and include/ggf.h) is compiled into the library and read back by
+ggf_source_digest(), so a run can check that the library it loaded was built
+from the sources beside it.
 """
 from __future__ import annotations
 
@@ -22,6 +25,18 @@ ARCH = os.environ.get("GGF_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["ggf_api.cpp", "ggf_factor.hip", "ggf_sweep.hip", "ggf_probe.hip", "ggf_nn.hip"]
 
 
+def source_digest() -> str:
+    """SHA-256 over the library's sources: every file of csrc/ (sorted by name) and include/ggf.h."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if not f.startswith("."))
+    for path in files + [os.path.join(ROOT, "include", "ggf.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     p = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(p):
@@ -29,11 +44,13 @@ def hipcc() -> str:
     return p
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, digest: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [hipcc(), "-c", "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-Wall", "-Wno-unused-variable", "-Wno-unused-function"]
+    if src == "ggf_api.cpp":
+        cmd += [f"-DGGF_SOURCE_DIGEST=\"{digest}\""]
     if src.endswith(".hip"):
         cmd += ["-x", "hip", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-ffp-contract=fast"]
@@ -46,8 +63,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    digest = source_digest()
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, digest), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1803,6 +1803,11 @@ ggf_status ggf_stream_probe(int32_t mode, void *a, void *b, size_t bytes, int32_
 
 const char *ggf_last_error(ggf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+#ifndef GGF_SOURCE_DIGEST
+#define GGF_SOURCE_DIGEST "unknown"
+#endif
+const char *ggf_source_digest(void) { return GGF_SOURCE_DIGEST; }
+
 void ggf_destroy(ggf_ctx *ctx) {
   if (!ctx) return;
   free_chains(ctx);

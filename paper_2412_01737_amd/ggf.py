@@ -98,6 +98,7 @@ EXPORTS = {
     "ggf_stream_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_int32, ctypes.c_void_p]),
     "ggf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "ggf_source_digest": (ctypes.c_char_p, []),
     "ggf_destroy": (None, [ctypes.c_void_p]),
 }
 
@@ -397,6 +398,11 @@ class Context:
         fl = ctypes.c_int64()
         self._check(self._lib.ggf_update_timing(self.h, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(fl)))
         return ms.value, la.value, fl.value
+
+
+def library_digest() -> str:
+    """The source digest compiled into the loaded libggf.so."""
+    return load().ggf_source_digest().decode()
 
 
 TAU_FLOOR, TAU_SHORT = 1, 2

@@ -106,3 +106,11 @@ def test_oracle_tau_int_chains_ar1_closed_form():
     tau, err, _ = stats.tau_int_chains(x)
     assert abs(tau - (1 + phi) / (2 * (1 - phi))) < 4 * err
     assert stats.tau_int_chains(x[:, :1]) == stats.tau_int(x[:, 0])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libggf.so not built")
+def test_library_was_built_from_these_sources():
+    """The digest compiled into libggf.so equals the digest of the sources beside it (build() records it)."""
+    from paper_2412_01737_amd import build
+    from paper_2412_01737_amd.ggf import library_digest
+    assert library_digest() == build.source_digest()
