@@ -67,7 +67,9 @@ def parse():
     ap.add_argument("--refresh", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=None, help="1 = replay each sweep as a captured hipGraph")
+    ap.add_argument("--balance", type=int, default=None,
+                    help="1 = balanced sweeps (every chain steps its own link cursor; uneven batches)")
     ap.add_argument("--delay", type=int, default=None,
                     help="window of delayed updates in link steps (0 = one rank-4 pass per accepted flip; "
                          "default: the library's)")
@@ -103,14 +105,19 @@ def parse():
     args = ap.parse_args()
     presets = {
         "north": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
-        "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384, delay=16),
+        "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384, delay=16,
+                   graph=1),
         "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64, delay=16),
-        "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64, delay=16),
+        "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64, delay=16,
+                   graph=1, balance=1),
         "c5": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
     }
     for k, v in presets[args.workload].items():
         if getattr(args, k) is None:
             setattr(args, k, v)
+    for k in ("graph", "balance"):
+        if getattr(args, k) is None:
+            setattr(args, k, 0)
     if args.plain_chains is None:
         args.plain_chains = args.chains
     return args
@@ -122,7 +129,7 @@ def c2_args(args):
     a = copy.copy(args)
     a.workload = "c2"
     for k, v in dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384,
-                     delay=16).items():
+                     delay=16, graph=1, balance=0).items():
         setattr(a, k, v)
     return a
 
@@ -359,7 +366,7 @@ def refresh_rates(st0, st1, steps: int, refresh: int):
     return float(np.mean(expected)), float(np.mean(actual))
 
 
-def refresh_correction(ctx, args, st0, stream):
+def refresh_correction(ctx, args, st0, stream, st1=None):
     """Float64 refactorisations charged at their true rate.
 
     A chain is refactorised at the first sweep end after refresh_every accepted
@@ -368,7 +375,8 @@ def refresh_correction(ctx, args, st0, stream):
     difference to the true rate is charged (or credited) at the measured cost
     of refactorising all chains, timed here after the timed region."""
     import torch
-    st1 = [ctx.get_state(c)[1] for c in range(args.chains)]
+    if st1 is None:
+        st1 = [ctx.get_state(c)[1] for c in range(args.chains)]
     exp_mean, act_mean = refresh_rates(st0, st1, args.steps, args.refresh)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -852,6 +860,7 @@ def run_plain(args, with_cpu=True):
         tuned = ctx.autotune(args.autotune, os.path.join(HERE, "paper_2412_01737_amd", "autotune_cache.txt"),
                              stream=stream)
     ctx.set_option("graph", args.graph)
+    ctx.set_option("balance", args.balance)
     mask = OBS_LINK | OBS_DENSITY
     obs = torch.zeros((args.warmup + args.steps, args.chains, GGF_NOBS), dtype=torch.float64, device=dev)
     for w in range(args.warmup):
@@ -884,7 +893,21 @@ def run_plain(args, with_cpu=True):
         ctx.measure(mask, obs[args.warmup + s], stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    refresh = refresh_correction(ctx, args, st0, stream)
+    drift = None
+    st1 = [ctx.get_state(c)[1] for c in range(args.chains)]
+    if args.precision == 32:
+        # drift of every observable slot of the maintained float32 state: the measurement before and
+        # after a float64 refactorisation of every chain (largest |difference| / max(1, |value|))
+        from paper_2412_01737_amd.ggf import OBS_ALL
+        before = ctx.measure(OBS_ALL)
+        ctx.refresh_all(stream=stream)
+        after = ctx.measure(OBS_ALL)
+        rel = np.abs(before - after) / np.maximum(1.0, np.abs(after))
+        names = ["plaquette", "wilson2x2", "density", "log_n"] + [f"meson_{r}" for r in range(1, 17)] + ["electric"]
+        drift = {"what": "largest |maintained - refactorised| / max(1, |value|) over chains, after the timed "
+                         "sweeps", "per_observable": {nm: float(rel[:, q].max()) for q, nm in enumerate(names)
+                                                       if np.any(after[:, q] != 0)}}
+    refresh = refresh_correction(ctx, args, st0, stream, st1)
     kernel_sweeps = args.steps
     if args.graph:
         upd_flips_timed = sum(ctx.get_state(c)[1]["accepts"] for c in range(args.chains)) - acc0
@@ -919,7 +942,10 @@ def run_plain(args, with_cpu=True):
                      "grad_norm_per_round": gn_.tolist(), "couplings": BENCH_COUPLINGS}
     timed_s = elapsed
     elapsed = elapsed + refresh["correction_ms"] * 1e-3
-    proposals = int((2 * Lc.astype(np.int64) ** 2).sum()) * args.steps
+    # with balanced sweeps every chain proposes a link at every one of the max_links link steps
+    per_sweep = (int(2 * Lc.astype(np.int64).max() ** 2) * args.chains if args.balance
+                 else int((2 * Lc.astype(np.int64) ** 2).sum()))
+    proposals = per_sweep * args.steps
     value = proposals / elapsed
     series = obs[args.warmup:].cpu().numpy()
     plaq_stats = statistics(series[:, :, 0], elapsed)
@@ -941,7 +967,8 @@ def run_plain(args, with_cpu=True):
         # elements, copied by the link steps) are not counted
         nl_c = 2 * Lc.astype(np.int64) ** 2
         windows = -(-int(nl_c.max()) // F)
-        share = np.minimum(-(-nl_c // F), windows) / windows
+        # the fraction of windows in which a chain has link steps (all of them with balanced sweeps)
+        share = np.ones(len(nl_c)) if args.balance else np.minimum(-(-nl_c // F), windows) / windows
         nf_ = n_c.astype(np.float64)
         bytes_per_launch = float((share * (nf_ * (nf_ + 1) / 2 + nf_ ** 2) * esz).sum())
         kernel = "k_window_flush"
@@ -983,6 +1010,7 @@ def run_plain(args, with_cpu=True):
                     f"accepted flips"),
                    "name": args.workload, "L": L, "K": K, "group": group, "chains": args.chains, "n_max": n,
                    "precision": args.precision, "refresh_every": args.refresh, "graph": args.graph,
+                   "balance": args.balance,
                    "delay_window": F, "autotuned": list(tuned) if tuned else None},
         "effective_samples_per_s": plaq_stats["effective_samples_per_s"],
         "plaquette": plaq_stats,
@@ -998,6 +1026,7 @@ def run_plain(args, with_cpu=True):
         "kernels_ms_per_step": {kernel: upd_ms / kernel_sweeps, "k_ratio": rat_ms / kernel_sweeps},
         "timed_s": timed_s,
         "refresh": refresh,
+        "float32_drift": drift,
         "electric": electric,
         "energy": energy,
         "lambda_opt": lambda_opt,

@@ -82,6 +82,8 @@ typedef struct {
   double max_drift;           /* largest |log W_maintained - log W_fresh| seen at a refresh */
   uint64_t near_ties;         /* Metropolis decisions (single-link and block) with |u - R| < 1e-9 R, where a
                                  rounding change of R could flip the decision (Sec. 5.1 estimator) */
+  uint64_t link_cursor;       /* with balanced sweeps (option "balance"): the chain's next link within
+                                 its current sweep; 0 at a sweep boundary and without balanced sweeps */
 } ggf_chain_info;
 
 /* Create a context on HIP device `device`. */
@@ -258,7 +260,8 @@ ggf_status ggf_optimise_gamma(ggf_ctx *ctx, int32_t tensor_id, const ggf_couplin
 ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_info *info);
 
 /* Replace one chain's link field and sweep counter (checkpoint resume) and
- * refactorise it; synchronous. */
+ * refactorise it; the chain restarts at a sweep boundary (link cursor 0).
+ * Synchronous. */
 ggf_status ggf_set_state(ggf_ctx *ctx, int32_t chain, const int8_t *links, uint64_t sweeps);
 
 /* Copy one chain's maintained inverse G = M(G)^-1 (n x n, row-major) to host
@@ -287,6 +290,13 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *                  update per link step, -1 (default) = 16.  Takes effect at the next sweep;
  *                  G as read through the ABI never has pending flips.
  *   "flush_grid"   workgroups of the window flush (default 1024)
+ *   "balance"      1 = balanced sweeps for batches of different lattice sizes: a ggf_sweep sweep
+ *                  is max_links link steps at each of which every chain proposes its own next link
+ *                  (a per-chain cursor), so a chain with fewer links completes several of its own
+ *                  sweeps (links in order, Philox counters as always) instead of idling; its sweep
+ *                  counter advances when its cursor wraps, and the refactorisation check runs at
+ *                  the end of each ggf_sweep sweep.  0 (default) = link steps in lock-step.
+ *                  Switching it off needs every chain at a sweep boundary (GGF_ESTATE otherwise)
  *   "time_update"  1 = record HIP events around the update and link-step launches of eager sweeps
  *                  (ggf_update_timing, ggf_ratio_timing); a sweep with graph replay then runs eagerly */
 ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value);

@@ -55,6 +55,7 @@ struct ggf_ctx {
   double2 *sfac = nullptr;
   uint32_t *sweep = nullptr, *acc_since = nullptr;
   unsigned long long *acc_total = nullptr, *prop_total = nullptr, *refreshes = nullptr, *ties = nullptr;
+  int *cursor = nullptr;         // each chain's next link within its sweep (balanced sweeps)
   int *flags = nullptr, *acc_list = nullptr, *acc_cnt = nullptr;
   double *scratch = nullptr;
   size_t scratch_elems = 0;
@@ -68,6 +69,7 @@ struct ggf_ctx {
   int opt_update_grid = 0, opt_update_tiles = 0, opt_graph = 0, opt_gj_nb = 0, opt_time_update = 0, opt_update_nt = 1;
   int opt_delay = -1;            // window of delayed updates in link steps (0 = immediate, -1 = automatic)
   int opt_flush_grid = 0;        // workgroups of the window flush (0 = library default)
+  int opt_balance = 0;           // 1: balanced sweeps (every chain steps its own link cursor at every link step)
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -266,6 +268,7 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.prop_total = ctx->prop_total;
   lc.refreshes = ctx->refreshes;
   lc.ties = ctx->ties;
+  lc.cursor = ctx->opt_balance ? ctx->cursor : nullptr;
   lc.max_drift = ctx->max_drift;
   lc.ldet = ctx->ldet;
   lc.flags = ctx->flags;
@@ -688,6 +691,7 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
   ctx->prop_total = dalloc<unsigned long long>(ctx, n_chains, e);
   ctx->refreshes = dalloc<unsigned long long>(ctx, n_chains, e);
   ctx->ties = dalloc<unsigned long long>(ctx, n_chains, e);
+  ctx->cursor = dalloc<int>(ctx, n_chains, e);
   ctx->flags = dalloc<int>(ctx, n_chains, e);
   ctx->acc_list = dalloc<int>(ctx, n_chains, e);
   ctx->acc_cnt = dalloc<int>(ctx, 2, e);
@@ -1344,6 +1348,9 @@ ggf_status ggf_get_state(ggf_ctx *ctx, int32_t chain, int8_t *links, ggf_chain_i
     HIP_TRY(ctx, hipMemcpy(&info->refreshes, ctx->refreshes + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(&info->max_drift, ctx->max_drift + chain, sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(&info->near_ties, ctx->ties + chain, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    int cur = 0;
+    HIP_TRY(ctx, hipMemcpy(&cur, ctx->cursor + chain, sizeof(int), hipMemcpyDeviceToHost));
+    info->link_cursor = static_cast<uint64_t>(cur);
     info->s_re = sf.x;
     info->s_im = sf.y;
     info->sweeps = sw;
@@ -1366,6 +1373,7 @@ ggf_status ggf_set_state(ggf_ctx *ctx, int32_t chain, const int8_t *links, uint6
   HIP_TRY(ctx, hipMemcpy(ctx->sweep + chain, &sw, sizeof(uint32_t), hipMemcpyHostToDevice));
   const int zero = 0;
   HIP_TRY(ctx, hipMemcpy(ctx->flags + chain, &zero, sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->cursor + chain, &zero, sizeof(int), hipMemcpyHostToDevice));   // a sweep boundary
   return factorize(ctx, std::vector<int>{chain}, 0, nullptr);
 }
 
@@ -1426,12 +1434,27 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
   else if (k == "time_update") ctx->opt_time_update = value != 0;
   else if (k == "update_nt") ctx->opt_update_nt = value != 0;
   else if (k == "flush_grid") ctx->opt_flush_grid = static_cast<int>(std::min<int64_t>(value, 1 << 20));
+  else if (k == "balance") {
+    if (value > 1) return fail(ctx, GGF_EINVAL, "balance must be 0 or 1");
+    if (ctx->n_chains > 0 && !ctx->opt_balance && value) {
+      // chains enter balanced sweeps at the start of a sweep
+      HIP_TRY(ctx, hipMemset(ctx->cursor, 0, ctx->n_chains * sizeof(int)));
+    }
+    if (ctx->n_chains > 0 && ctx->opt_balance && !value) {
+      std::vector<int> cur(ctx->n_chains);
+      HIP_TRY(ctx, hipMemcpy(cur.data(), ctx->cursor, cur.size() * sizeof(int), hipMemcpyDeviceToHost));
+      for (int v : cur)
+        if (v != 0) return fail(ctx, GGF_ESTATE, "balanced sweeps can end only when every chain is at a sweep boundary");
+    }
+    ctx->opt_balance = static_cast<int>(value);
+  }
   else if (k == "delay") {
     if (!(value == -1 || value == 0 || (value % 8 == 0 && value >= 8 && value <= 32)))
       return fail(ctx, GGF_EINVAL, "delay must be -1 (automatic), 0 (immediate) or 8, 16, 24, 32 link steps");
     ctx->opt_delay = static_cast<int>(value);
   } else return fail(ctx, GGF_EINVAL, "unknown option " + k);
-  if (k == "update_grid" || k == "update_tiles" || k == "update_nt" || k == "delay" || k == "flush_grid") {
+  if (k == "update_grid" || k == "update_tiles" || k == "update_nt" || k == "delay" || k == "flush_grid" ||
+      k == "balance") {
     if (ctx->graph_exec) { hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
   }
   return GGF_OK;
@@ -1721,8 +1744,17 @@ ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   int max_np = 0;
   for (const ChainDev &c : ctx->chains) max_np = std::max(max_np, (c.L / ctx->nn_P) * (c.L / ctx->nn_P));
+  if (ctx->opt_balance) {
+    // block sweeps advance every chain's sweep counter: with balanced single-link sweeps they start
+    // only where every chain is at a sweep boundary
+    std::vector<int> cur(ctx->n_chains);
+    HIP_TRY(ctx, hipMemcpy(cur.data(), ctx->cursor, cur.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (int v : cur)
+      if (v != 0) return fail(ctx, GGF_ESTATE, "block sweep while a chain is inside a balanced sweep");
+  }
   BlockLaunch bl;
   bl.lc = launch_ctx(ctx, s);
+  bl.lc.cursor = nullptr;
   bl.nn = nn_args(ctx);
   bl.A = ctx->blk_A;
   bl.Wf = ctx->blk_W;

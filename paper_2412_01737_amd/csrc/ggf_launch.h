@@ -23,6 +23,7 @@ struct LaunchCtx {
   unsigned long long *prop_total;
   unsigned long long *refreshes;
   unsigned long long *ties;      // decisions with |u - R| < 1e-9 R (rounding of R could change them)
+  int *cursor;                   // balanced sweeps: each chain's next link (nullptr: lock-step link steps)
   double *max_drift;
   double *ldet;
   int *flags;

@@ -41,7 +41,7 @@ constexpr int kRatioThreads = 64;   // one wave per chain: the per-step work is 
 
 // PAIRS: some chain of the context has K > 1 (patch Pfaffians; index sets up to 16 Majoranas).
 template <typename T, bool PAIRS>
-__global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, int parity, int t, int wp) {
+__global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int step, int parity, int t, int wp) {
   extern __shared__ double2 s_work[];   // pair workspaces, then (delayed) G_IA, G_AI and a scratch block
   __shared__ double s_K[16], s_Ai[16], s_dM[16], s_Am[16];
   __shared__ double s_GI[(PAIRS ? 16 : 4) * 16];   // current inverse on the Majoranas I (U first), row stride 16
@@ -61,6 +61,10 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
   const int n = ch.n;
   const int a = (delayed && t > 0) ? lc.dr[c] : 0;  // pending Majoranas of this chain
   if (delayed && t == 0 && threadIdx.x == 0) lc.dr[c] = 0;
+  // the link of this step: the step itself (link steps in lock-step, chains past their last link
+  // idle), or with balanced sweeps the chain's own cursor (every chain steps every time and starts
+  // its next sweep when it wraps)
+  const int ell = lc.cursor ? lc.cursor[c] : step;
   if (ell >= ch.nlinks) return;
   const TensorDev &Tn = lc.tensors[ch.tensor];
   const T *G = static_cast<const T *>(lc.G) + ch.g_off;
@@ -263,6 +267,14 @@ __global__ __launch_bounds__(kRatioThreads) void k_ratio(LaunchCtx lc, int ell, 
       }
     }
     s_acc = accept ? 1 : 0;
+    if (lc.cursor) {
+      if (ell + 1 == ch.nlinks) {
+        lc.cursor[c] = 0;
+        lc.sweep[c] += 1;
+      } else {
+        lc.cursor[c] = ell + 1;
+      }
+    }
   }
   __syncthreads();
   if (!s_acc) return;
@@ -466,7 +478,7 @@ __global__ __launch_bounds__(256) void k_update(LaunchCtx lc, int parity, int ti
 
 __global__ void k_end_sweep(LaunchCtx lc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < lc.n_chains) lc.sweep[c] += 1u;
+  if (c < lc.n_chains && !lc.cursor) lc.sweep[c] += 1u;   // balanced sweeps advance it per chain
   if (c < 2) lc.acc_cnt[c] = 0;   // every sweep starts with both accepted counters cleared
   if (c < 2 && lc.dcnt) lc.dcnt[c] = 0;
 }

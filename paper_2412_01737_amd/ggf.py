@@ -40,7 +40,7 @@ class ChainInfo(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("logw", ctypes.c_double), ("s_re", ctypes.c_double),
                 ("s_im", ctypes.c_double), ("sweeps", ctypes.c_uint64), ("accepts", ctypes.c_uint64),
                 ("proposals", ctypes.c_uint64), ("refreshes", ctypes.c_uint64), ("recoveries", ctypes.c_uint64),
-                ("max_drift", ctypes.c_double), ("near_ties", ctypes.c_uint64)]
+                ("max_drift", ctypes.c_double), ("near_ties", ctypes.c_uint64), ("link_cursor", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
