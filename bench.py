@@ -104,13 +104,15 @@ def parse():
                          "CSVs, write profiles/k_electric_traffic.json and exit (no GPU needed)")
     args = ap.parse_args()
     presets = {
-        "north": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
+        # float64 refresh every 16384 changed links (about 16 block sweeps): the float32 drift of every
+        # observable after 10 sweeps without one is below 2e-7 (bench float32_drift)
+        "north": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=16384, delay=16),
         "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384, delay=16,
                    graph=1),
         "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64, delay=16),
         "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64, delay=16,
                    graph=1, balance=1),
-        "c5": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=4096, delay=16),
+        "c5": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=16384, delay=16),
     }
     for k, v in presets[args.workload].items():
         if getattr(args, k) is None:
@@ -253,9 +255,10 @@ def block_traffic_from(args):
     import csv
 
     def per_kernel(path, counter, match):
-        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
-                if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
-        return vals
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
+        if rows and "Dispatch_Id" in rows[0]:
+            rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return [float(r["Counter_Value"]) for r in rows]
 
     f_csv, w_csv, cf_csv, cw_csv, bench_json = args.block_traffic_from
     cfetch = sum(per_kernel(cf_csv, "FETCH_SIZE", "probe_copy")) / len(per_kernel(cf_csv, "FETCH_SIZE", "probe_copy"))
@@ -268,6 +271,10 @@ def block_traffic_from(args):
             rec = json.loads(line)
     learned = rec["learned"]
     moves_per_launch = learned["accepted_moves"] / learned["update_launches"]
+    # only the learned sampler's timed block sweeps: the last update_launches dispatches of each
+    # kernel (run with --untrained 0 --plain-steps 0, so nothing dispatches them afterwards; the
+    # training context's block sweeps of the output-scale trials come earlier)
+    last = int(learned["update_launches"])
     out = {"source_digest": source_digest(BLOCK_SOURCES), "moves_per_launch": moves_per_launch,
            "fetch_scale": sf, "write_scale": sw}
     total = 0.0
@@ -275,7 +282,7 @@ def block_traffic_from(args):
     # block moves only: k_window_snap and the <T, 8, true> instance of k_window_gemm (the training
     # sampler's window flushes run <T, 4, false>)
     for k in (f"k_window_snap<{tname}>", f"k_window_gemm<{tname}, 8, true>"):
-        fv, wv = per_kernel(f_csv, "FETCH_SIZE", k), per_kernel(w_csv, "WRITE_SIZE", k)
+        fv, wv = per_kernel(f_csv, "FETCH_SIZE", k)[-last:], per_kernel(w_csv, "WRITE_SIZE", k)[-last:]
         rd = sum(fv) / len(fv) * sf * 1024.0
         wr = sum(wv) / len(wv) * sw * 1024.0
         out[k.split("<")[0]] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
@@ -348,6 +355,19 @@ def source_digest(names=("ggf_sweep.hip",)) -> str:
         with open(os.path.join(HERE, "paper_2412_01737_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def float32_drift(ctx, stream):
+    """Drift of every observable slot of a maintained float32 state: the measurement before and after a
+    float64 refactorisation of every chain (largest |difference| / max(1, |value|) over chains)."""
+    from paper_2412_01737_amd.ggf import OBS_ALL
+    before = ctx.measure(OBS_ALL)
+    ctx.refresh_all(stream=stream)
+    after = ctx.measure(OBS_ALL)
+    rel = np.abs(before - after) / np.maximum(1.0, np.abs(after))
+    names = ["plaquette", "wilson2x2", "density", "log_n"] + [f"meson_{r}" for r in range(1, 17)] + ["electric"]
+    return {"what": "largest |maintained - refactorised| / max(1, |value|) over chains, after the timed sweeps",
+            "per_observable": {nm: float(rel[:, q].max()) for q, nm in enumerate(names) if np.any(after[:, q] != 0)}}
 
 
 def refresh_rates(st0, st1, steps: int, refresh: int):
@@ -638,11 +658,15 @@ def run_c5(args):
         elapsed = time.perf_counter() - ts
         series = obs.cpu().numpy()
         final0 = ctx.measure()[0]                  # every slot of chain 0's final configuration
+        st_end = [ctx.get_state(c)[1] for c in range(chains)]
+        refreshes = float(np.mean([st["refreshes"] for st in st_end]))
+        drift = float32_drift(ctx, stream) if precision == 32 else None
         rec = {"chains": chains, "sweeps": steps, "warmup": warmup, "s_per_sweep": elapsed / steps,
                "init_s": t_init, "precision": precision, "refresh_every": refresh,
                "plaquette": statistics(series[:, :, 0], elapsed), "density": statistics(series[:, :, 2], elapsed),
                "update_ms_total": upd_ms, "update_launches": launches, "links_changed": changed,
-               "final_chain0": {"links": ctx.get_state(0)[0].tolist(), "obs": final0.tolist()}}
+               "final_chain0": {"links": ctx.get_state(0)[0].tolist(), "obs": final0.tolist()},
+               "refreshes_per_chain": refreshes, "float32_drift": drift}
         if block:
             after = [ctx.block_stats(c) for c in range(chains)]
             prop = sum(a[0] - b[0] for a, b in zip(after, before))
@@ -893,20 +917,8 @@ def run_plain(args, with_cpu=True):
         ctx.measure(mask, obs[args.warmup + s], stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    drift = None
     st1 = [ctx.get_state(c)[1] for c in range(args.chains)]
-    if args.precision == 32:
-        # drift of every observable slot of the maintained float32 state: the measurement before and
-        # after a float64 refactorisation of every chain (largest |difference| / max(1, |value|))
-        from paper_2412_01737_amd.ggf import OBS_ALL
-        before = ctx.measure(OBS_ALL)
-        ctx.refresh_all(stream=stream)
-        after = ctx.measure(OBS_ALL)
-        rel = np.abs(before - after) / np.maximum(1.0, np.abs(after))
-        names = ["plaquette", "wilson2x2", "density", "log_n"] + [f"meson_{r}" for r in range(1, 17)] + ["electric"]
-        drift = {"what": "largest |maintained - refactorised| / max(1, |value|) over chains, after the timed "
-                         "sweeps", "per_observable": {nm: float(rel[:, q].max()) for q, nm in enumerate(names)
-                                                       if np.any(after[:, q] != 0)}}
+    drift = float32_drift(ctx, stream) if args.precision == 32 else None
     refresh = refresh_correction(ctx, args, st0, stream, st1)
     kernel_sweeps = args.steps
     if args.graph:
