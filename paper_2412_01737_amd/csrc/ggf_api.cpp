@@ -45,6 +45,7 @@ struct ggf_ctx {
   // chains
   int n_chains = 0, precision = 64, refresh_every = 0, kmax = 1, max_links = 0, n_max = 0;
   int nidx = 4;   // largest index set of a link step (Majoranas)
+  int tile_kinds = 0;            // bit 0: some n % GGF_WINDOW_TILE == 0, bit 1: some other n
   uint64_t seed = 0;
   std::vector<ChainDev> chains;
   std::vector<unsigned long long> recoveries;
@@ -287,6 +288,7 @@ LaunchCtx launch_ctx(ggf_ctx *ctx, hipStream_t s) {
   lc.key0 = static_cast<uint32_t>(ctx->seed & 0xFFFFFFFFu);
   lc.key1 = static_cast<uint32_t>(ctx->seed >> 32);
   lc.n_chains = ctx->n_chains;
+  lc.tile_kinds = ctx->tile_kinds;
   return lc;
 }
 
@@ -707,6 +709,8 @@ ggf_status ggf_init_chains(ggf_ctx *ctx, int32_t n_chains, const int32_t *L, con
   ctx->refresh_every = refresh_every;
   ctx->kmax = kmax;
   ctx->nidx = nidx;
+  ctx->tile_kinds = 0;
+  for (const ChainDev &c : ch) ctx->tile_kinds |= c.n % GGF_WINDOW_TILE == 0 ? 1 : 2;
   ctx->max_links = max_links;
   ctx->n_max = n_max;
   ctx->seed = seed;

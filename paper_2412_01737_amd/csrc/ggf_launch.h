@@ -46,7 +46,12 @@ struct LaunchCtx {
   const size_t *dP_off;
   uint32_t key0, key1;
   int n_chains;
+  // which chains the window-flush kernels meet: bit 0 some chain's n is a multiple of
+  // GGF_WINDOW_TILE (every tile full), bit 1 some chain's n is not
+  int tile_kinds;
 };
+
+#define GGF_WINDOW_TILE 64
 
 void ggf_launch_assemble(const LaunchCtx &lc, const int *list, int count, int max_sites);
 void ggf_launch_gj(const LaunchCtx &lc, const int *list, int count, int n_max, int nb, int *piv,
