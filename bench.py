@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=5, help="c5: timed sweeps of the float64 single-link comparison")
     ap.add_argument("--untrained", type=int, default=1,
                     help="c5: also time the block moves with an untrained (uniform) proposal (1 = yes)")
+    ap.add_argument("--bond-gradient", type=int, default=1,
+                    help="c5: time the gradient with respect to the patch bond states on the final "
+                         "configurations (1 = yes)")
     ap.add_argument("--autotune", type=int, default=0, help="sweeps per autotuner candidate (0 = off)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
@@ -661,12 +664,30 @@ def run_c5(args):
         st_end = [ctx.get_state(c)[1] for c in range(chains)]
         refreshes = float(np.mean([st["refreshes"] for st in st_end]))
         drift = float32_drift(ctx, stream) if precision == 32 else None
+        bond = None
+        if block and name == "learned" and K > 1 and args.bond_gradient:
+            # gradient of <H> with respect to the patch bond states on the sampled configurations
+            from paper_2412_01737_amd.ggf import bond_gradient
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            er = ctx.measure_energy(BENCH_COUPLINGS, stream=stream)
+            tr = time.perf_counter()
+            br = ctx.measure_bond_rows(BENCH_COUPLINGS, stream=stream)
+            tg = time.perf_counter()
+            gb = bond_gradient(spec, BENCH_COUPLINGS, er, br)
+            te = time.perf_counter()
+            bond = {"what": "d<H>/d theta for the six rotation generators of the patch bond, over the chains' "
+                            "final configurations", "couplings": BENCH_COUPLINGS, "mean_energy": float(er[:, 0].mean()),
+                    "grad": gb.tolist(), "energy_rows_s": tr - tb, "bond_rows_s": tg - tr, "host_gradient_s": te - tg}
+            log(f"c5 bond gradient: {te - tb:.3f} s")
         rec = {"chains": chains, "sweeps": steps, "warmup": warmup, "s_per_sweep": elapsed / steps,
                "init_s": t_init, "precision": precision, "refresh_every": refresh,
                "plaquette": statistics(series[:, :, 0], elapsed), "density": statistics(series[:, :, 2], elapsed),
                "update_ms_total": upd_ms, "update_launches": launches, "links_changed": changed,
                "final_chain0": {"links": ctx.get_state(0)[0].tolist(), "obs": final0.tolist()},
                "refreshes_per_chain": refreshes, "float32_drift": drift}
+        if bond is not None:
+            rec["bond_gradient"] = bond
         if block:
             after = [ctx.block_stats(c) for c in range(chains)]
             prop = sum(a[0] - b[0] for a, b in zip(after, before))

@@ -237,6 +237,59 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *couplings,
 ggf_status ggf_gamma_gradient(ggf_ctx *ctx, const double *gamma_loc, const double *energy_rows,
                               const double *sens_rows, int64_t n_rows, double *grad);
 
+/* Replace the bond state of B_k (1 <= k < K) on its patch link in tensor tensor_id (4 x 4, pure
+ * and even as in ggf_set_tensor; phase fixed by <b_0|b_k> > 0): the pair tables are recomputed
+ * and every chain that uses the tensor gets its S(G) = N(G) / W(G) again.  G = M(G)^-1 and
+ * log W do not involve the patch bonds, so nothing is refactorised.  Synchronous. */
+ggf_status ggf_set_bond(ggf_ctx *ctx, int32_t tensor_id, int32_t k, const double *gamma_bond_k, void *stream);
+
+#define GGF_BOND_SMAX 12      /* patch Majoranas of an ansatz: 4 per patch link, K <= GGF_KMAX */
+#define GGF_BOND_STRIDE (2 + GGF_BOND_SMAX + GGF_KMAX + 3 * GGF_BOND_SMAX * GGF_BOND_SMAX)
+
+/* Rows for the gradient with respect to the patch bond states Gamma_{B_k},
+ * k >= 1 (gradient descent on the bond states, the outlook of Sec. 6.3, for
+ * the superposition of Sec. 5).  The bond of B_k enters only through its patch
+ * link's transition covariances and overlaps, so per configuration the
+ * gradient needs G on the patch Majoranas S (the union over k >= 1 of the four
+ * Majoranas of link patch_link[k], in increasing order, s <= 12 of them) and
+ * the contraction of the linear part of the local energy with the rows G[S, :]:
+ *   R[a][b] = sum_ij C_ij G[i][S_a] G[S_b][j],
+ * where sum_ij C_ij X_ij is the part of the energy (Sec. 2 hopping, chemical
+ * and mass terms through Gamma_out = A + B X B^T, Sec. 2.3 electric term
+ * through the mixed occupation of every link with the reference bond's
+ * response) linear in X = M^-1.  Row c of out[n_chains][GGF_BOND_STRIDE]:
+ *   [0]                          s (0 for a chain with K = 1)
+ *   [1]                          L
+ *   [2 + q]                      S_q, q < s
+ *   [14 + k]                     value of link patch_link[k] (k >= 1)
+ *   [18 + 2 (12 a + b) + 0,1]    R[a][b] (complex)
+ *   [306 + 12 a + b]             G[S_a][S_b]
+ * (float64; device pointer when out_is_device != 0, else host pointer and
+ * synchronous).  GGF_EINVAL unless s L^2 <= 4096 for every chain with K > 1.
+ * Allocates out's size of device memory for a host out. */
+ggf_status ggf_measure_bond_rows(ggf_ctx *ctx, const ggf_couplings *couplings, double *out, int32_t out_is_device,
+                                 void *stream);
+
+/* Gradient of <H> with respect to the rotations of the patch bond states,
+ * Gamma_{B_k} -> exp(theta E) Gamma_{B_k} exp(-theta E) for the six generators
+ * E = e_ab - e_ba, (a, b) in order (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) of the
+ * link's Majoranas (out0, out1, in0, in1), the phase convention <b_0|b_k> > 0
+ * kept, from n_rows samples of p(G) of chains of one ansatz: host rows of
+ * ggf_measure_energy and ggf_measure_bond_rows of the same chains and
+ * configurations, and that ansatz's descriptor (as given to ggf_set_tensor).
+ * Per sample, with om_nm = lambda_n^* lambda_m rho_nm, S = sum om and
+ * e = sum om h / S: d log N = sum (om / S) d log rho, d e = sum (om / S) [d h +
+ * (h - e) d log rho], d log rho_nm = d log <B_m|B_n> + (1/2) tr(M_nm^-1 dM_nm),
+ * and d h_nm = -sum_ab dY_ab R_nm[a][b] + ke dX_nm, Y_nm = Delta (1 + G_SS
+ * Delta)^-1 the Woodbury factor of M_nm^-1 = G - G_S Y G_S^T, R_nm the rows'
+ * R with the pair's own electric response on its patch links and dX_nm the
+ * change of the mixed occupation of the varied link through its bond.  Then
+ * d<H>/d theta = mean Re d e + mean (Re e - mean Re e) d log N, written to
+ * grad[(k - 1) 6 + g] for k = 1 .. K - 1 and generator g.  Host only; ctx may
+ * be NULL.  GGF_EINVAL for K = 1 or rows of another size of S. */
+ggf_status ggf_bond_gradient(ggf_ctx *ctx, const ggf_tensor_desc *tensor, const ggf_couplings *couplings,
+                             const double *energy_rows, const double *bond_rows, int64_t n_rows, double *grad);
+
 /* Replace the on-site covariance of tensor tensor_id (10 x 10, checked as in
  * ggf_set_tensor) and refactorise every chain that uses it from its link field
  * (float64), so that G, log W and S follow the new tensor.  Synchronous. */

@@ -33,12 +33,15 @@ struct Buf {
 
 }  // namespace
 
+struct HostBonds;   // an ansatz's bonds, patch links and amplitudes on the host (defined below)
+
 struct ggf_ctx {
   int device = 0;
   std::string err;
   double *stage = nullptr;       // this device's staging array of ggf_measure_staged (fixed, never freed)
   hipError_t stage_err = hipSuccess;
   std::vector<TensorDev> tensors;
+  std::vector<HostBonds> bonds;  // host data of each tensor, for ggf_set_bond
   TensorDev *tensors_dev = nullptr;
   size_t tensors_cap = 0;
 
@@ -204,6 +207,52 @@ bool even_state(const double *g, Even2 &st, std::string &why) {
   transition_cov(st, st, back);
   for (int i = 0; i < 16; ++i)
     if (std::abs(back[i] - g[i]) > 1e-8) { why = "bond covariance is not a pure even-parity state"; return false; }
+  return true;
+}
+
+}  // namespace
+
+// Host copy of an ansatz's bonds (phase-fixed states), patch links and amplitudes, kept per tensor
+// so that a bond or lambda can be replaced later.
+struct HostBonds {
+  std::vector<Even2> bk;      // bk[0] = reference bond
+  std::vector<cplx> cc;       // lambda_k
+  std::vector<int> patch;     // patch_link[k]
+  double g0[16];              // reference bond covariance
+};
+
+namespace {
+
+// The pair tables of a tensor from its bonds: per (n, m) the involved patch links, the change of
+// their transition covariance from the reference bond, the electric responses, <B_m|B_n> and
+// lambda_n^* lambda_m <B_m|B_n>.
+bool fill_pairs(TensorDev &t, const HostBonds &hb, std::string &why) {
+  const int K = t.K;
+  store_response(hb.bk[0], hb.bk[0], t.en0, t.eq0);
+  for (int n = 0; n < K; ++n)
+    for (int m = 0; m < K; ++m) {
+      int links[2], cnt = 0;
+      if (n > 0) links[cnt++] = hb.patch[n];
+      if (m > 0 && !(cnt == 1 && links[0] == hb.patch[m])) links[cnt++] = hb.patch[m];
+      cplx ovl = 1.0;
+      t.nl[n][m] = cnt;
+      for (int l = 0; l < cnt; ++l) {
+        const Even2 &ket = (n > 0 && hb.patch[n] == links[l]) ? hb.bk[n] : hb.bk[0];
+        const Even2 &bra = (m > 0 && hb.patch[m] == links[l]) ? hb.bk[m] : hb.bk[0];
+        const cplx o = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
+        if (std::abs(o) < 1e-14) { why = "vanishing bond overlap"; return false; }
+        ovl *= o;
+        cplx g[16];
+        transition_cov(bra, ket, g);
+        t.lk[n][m][l] = links[l];
+        for (int q = 0; q < 16; ++q)
+          t.dg[n][m][l][q] = make_double2((g[q] - hb.g0[q]).real(), (g[q] - hb.g0[q]).imag());
+        store_response(bra, ket, t.en[n][m][l], t.eq[n][m][l]);
+      }
+      const cplx w = std::conj(hb.cc[n]) * hb.cc[m] * ovl;
+      t.w[n][m] = make_double2(w.real(), w.imag());
+      t.ov[n][m] = make_double2(ovl.real(), ovl.imag());
+    }
   return true;
 }
 
@@ -568,31 +617,14 @@ ggf_status ggf_set_tensor(ggf_ctx *ctx, const ggf_tensor_desc *d, int32_t *tenso
   }
   if (K > 1)
     for (int k = 0; k < K; ++k) cc[k] = cplx(d->c_re[k], d->c_im[k]);
-  const double *g0 = d->gamma_bond;
-  store_response(b0, b0, t.en0, t.eq0);
-  for (int n = 0; n < K; ++n)
-    for (int m = 0; m < K; ++m) {
-      int links[2], cnt = 0;
-      if (n > 0) links[cnt++] = d->patch_link[n];
-      if (m > 0 && !(cnt == 1 && links[0] == d->patch_link[m])) links[cnt++] = d->patch_link[m];
-      cplx ovl = 1.0;
-      t.nl[n][m] = cnt;
-      for (int l = 0; l < cnt; ++l) {
-        const Even2 &ket = (n > 0 && d->patch_link[n] == links[l]) ? bk[n] : bk[0];
-        const Even2 &bra = (m > 0 && d->patch_link[m] == links[l]) ? bk[m] : bk[0];
-        const cplx o = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
-        if (std::abs(o) < 1e-14) return fail(ctx, GGF_EINVAL, "vanishing bond overlap");
-        ovl *= o;
-        cplx g[16];
-        transition_cov(bra, ket, g);
-        t.lk[n][m][l] = links[l];
-        for (int q = 0; q < 16; ++q) t.dg[n][m][l][q] = make_double2((g[q] - g0[q]).real(), (g[q] - g0[q]).imag());
-        store_response(bra, ket, t.en[n][m][l], t.eq[n][m][l]);
-      }
-      const cplx w = std::conj(cc[n]) * cc[m] * ovl;
-      t.w[n][m] = make_double2(w.real(), w.imag());
-      t.ov[n][m] = make_double2(ovl.real(), ovl.imag());
-    }
+  HostBonds hb;
+  hb.bk = bk;
+  hb.cc = cc;
+  hb.patch.assign(d->patch_link ? d->patch_link : nullptr, d->patch_link ? d->patch_link + K : nullptr);
+  if (hb.patch.empty()) hb.patch.assign(K, -1);
+  for (int q = 0; q < 16; ++q) hb.g0[q] = d->gamma_bond[q];
+  if (!fill_pairs(t, hb, why)) return fail(ctx, GGF_EINVAL, why);
+  ctx->bonds.push_back(hb);
   ctx->tensors.push_back(t);
   if (ctx->tensors.size() > ctx->tensors_cap) {
     // a captured sweep graph holds the old table's address in its kernel arguments
@@ -868,6 +900,44 @@ ggf_status ggf_set_lambda(ggf_ctx *ctx, int32_t tensor_id, const double *c_re, c
                      cplx(t.ov[n][m].x, t.ov[n][m].y);
       t.w[n][m] = make_double2(w.real(), w.imag());
     }
+  for (int k = 0; k < K; ++k) ctx->bonds[tensor_id].cc[k] = cplx(c_re[k], c_im[k]);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->tensors_dev + tensor_id, &t, sizeof(TensorDev), hipMemcpyHostToDevice, s));
+  std::vector<int> which;
+  for (int c = 0; c < ctx->n_chains; ++c)
+    if (ctx->chains[c].tensor == tensor_id) which.push_back(c);
+  if (!which.empty()) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->list_dev, which.data(), which.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const LaunchCtx lc = launch_ctx(ctx, s);
+    ggf_launch_sfac(lc, ctx->list_dev, static_cast<int>(which.size()), ctx->kmax);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return GGF_OK;
+}
+
+ggf_status ggf_set_bond(ggf_ctx *ctx, int32_t tensor_id, int32_t k, const double *gamma_bond_k, void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(ctx->tensors.size()))
+    return fail(ctx, GGF_EINVAL, "bad tensor id");
+  TensorDev &t = ctx->tensors[tensor_id];
+  if (k < 1 || k >= t.K) return fail(ctx, GGF_EINVAL, "k must be in 1 .. K - 1");
+  if (!gamma_bond_k) return fail(ctx, GGF_EINVAL, "gamma_bond_k is required");
+  std::string why;
+  Even2 b;
+  if (!even_state(gamma_bond_k, b, why)) return fail(ctx, GGF_EINVAL, "gamma_bond_k: " + why);
+  HostBonds hb = ctx->bonds[tensor_id];
+  const cplx ov = std::conj(hb.bk[0].a) * b.a + std::conj(hb.bk[0].b) * b.b;
+  if (std::abs(ov) < 1e-12) return fail(ctx, GGF_EINVAL, "<b_0|b_k> = 0: phase convention undefined");
+  const cplx ph = ov / std::abs(ov);
+  b.a /= ph;
+  b.b /= ph;
+  hb.bk[k] = b;
+  TensorDev nt = t;
+  if (!fill_pairs(nt, hb, why)) return fail(ctx, GGF_EINVAL, why);
+  t = nt;
+  ctx->bonds[tensor_id] = hb;
+  // G = M_00^-1 and W(G) do not involve the patch bonds; only S(G) = N(G) / W(G) changes
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(ctx, hipMemcpyAsync(ctx->tensors_dev + tensor_id, &t, sizeof(TensorDev), hipMemcpyHostToDevice, s));
   std::vector<int> which;
@@ -908,6 +978,401 @@ ggf_status ggf_measure_energy(ggf_ctx *ctx, const ggf_couplings *cp, double *out
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(tmp);
   if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure_energy: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+ggf_status ggf_measure_bond_rows(ggf_ctx *ctx, const ggf_couplings *cp, double *out, int32_t out_is_device,
+                                 void *stream) {
+  if (!ctx) return GGF_EINVAL;
+  if (ctx->n_chains == 0) return fail(ctx, GGF_ESTATE, "ggf_init_chains has not been called");
+  if (!out || !cp) return fail(ctx, GGF_EINVAL, "out and couplings are required");
+  const double cv[5] = {cp->t, cp->mu, cp->m, cp->kb, cp->ke};
+  for (double v : cv)
+    if (!std::isfinite(v)) return fail(ctx, GGF_EINVAL, "couplings must be finite");
+  for (const ChainDev &ch : ctx->chains) {
+    if (ch.K < 2) continue;
+    const TensorDev &t = ctx->tensors[ch.tensor];
+    std::vector<int> S;
+    for (int k = 1; k < ch.K; ++k) {
+      const int ell = t.lk[k][0][0], i = ell >> 1, mu = ell & 1, L = ch.L;
+      const int j = mu == 0 ? (i / L) * L + (i % L + 1) % L : ((i / L + 1) % L) * L + i % L;
+      const int u[4] = {mu == 0 ? 8 * i + 4 : 8 * i + 2, mu == 0 ? 8 * i + 5 : 8 * i + 3,
+                        mu == 0 ? 8 * j + 0 : 8 * j + 6, mu == 0 ? 8 * j + 1 : 8 * j + 7};
+      for (int q : u)
+        if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
+    }
+    if (static_cast<int>(S.size()) * ch.L * ch.L > 4096)
+      return fail(ctx, GGF_EINVAL, "bond rows need s L^2 <= 4096 (s = 4 (K - 1) patch Majoranas)");
+  }
+  static_assert(GGF_BOND_STRIDE == GGF_BOND_STRIDE_DEV, "row size");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LaunchCtx lc = launch_ctx(ctx, s);
+  const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};
+  if (out_is_device) {
+    ggf_launch_bond_rows(lc, ec, out);
+    HIP_TRY(ctx, hipGetLastError());
+    return GGF_OK;
+  }
+  const size_t bytes = static_cast<size_t>(ctx->n_chains) * GGF_BOND_STRIDE * sizeof(double);
+  double *tmp = nullptr;
+  HIP_TRY(ctx, hipMalloc(&tmp, bytes));
+  ggf_launch_bond_rows(lc, ec, tmp);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(ctx, GGF_EDEVICE, std::string("measure_bond_rows: ") + hipGetErrorString(e));
+  return GGF_OK;
+}
+
+namespace {
+
+// ----- gradient with respect to the patch bond states (host) -----
+// Derivative of a bond state a|00> + b|11> along Gamma -> exp(theta E) Gamma exp(-theta E): the
+// state is the ground state of the even-sector H = [[h, z], [z^*, -h]] (even_state), so first-order
+// perturbation theory in that 2 x 2 block is exact: dv = -w <w|dH|v> / (2 e), w = (-b^*, a^*) the
+// excited state, e = sqrt(h^2 + |z|^2), dH from dGamma = [E, Gamma] by the same linear map; then the
+// phase convention <b_0|b_k> > 0 adds -i Im(<b_0|dv> / <b_0|v>) v.
+Even2 bond_state_derivative(const double *g, const double *E, const Even2 &v, const Even2 &b0) {
+  double dg[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double x = 0.0;
+      for (int q = 0; q < 4; ++q) x += E[i * 4 + q] * g[q * 4 + j] - g[i * 4 + q] * E[q * 4 + j];
+      dg[i * 4 + j] = x;
+    }
+  const double h = 0.5 * (g[0 * 4 + 1] + g[2 * 4 + 3]);
+  const cplx z(0.5 * (g[0 * 4 + 3] + g[1 * 4 + 2]), 0.5 * (g[0 * 4 + 2] - g[1 * 4 + 3]));
+  const double dh = 0.5 * (dg[0 * 4 + 1] + dg[2 * 4 + 3]);
+  const cplx dz(0.5 * (dg[0 * 4 + 3] + dg[1 * 4 + 2]), 0.5 * (dg[0 * 4 + 2] - dg[1 * 4 + 3]));
+  const double e = std::sqrt(h * h + std::norm(z));
+  const cplx wa = -std::conj(v.b), wb = std::conj(v.a);
+  // dH v and <w|dH v>
+  const cplx hva = dh * v.a + dz * v.b, hvb = std::conj(dz) * v.a - dh * v.b;
+  const cplx amp = std::conj(wa) * hva + std::conj(wb) * hvb;
+  Even2 dv{-wa * amp / (2.0 * e), -wb * amp / (2.0 * e)};
+  const cplx ov = std::conj(b0.a) * v.a + std::conj(b0.b) * v.b;
+  const cplx dov = std::conj(b0.a) * dv.a + std::conj(b0.b) * dv.b;
+  const cplx ph(0.0, -std::imag(dov / ov));
+  dv.a += ph * v.a;
+  dv.b += ph * v.b;
+  return dv;
+}
+
+// Derivatives of a link's transition quantities (transition_cov, occupation_response and the
+// overlap <bra|ket>) for bond vectors moving by (dbra, dket).
+void transition_derivative(const Even2 &bra, const Even2 &ket, const Even2 &dbra, const Even2 &dket, cplx dg[16],
+                           cplx &dov, cplx &den, cplx deq[16]) {
+  const cplx ov = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
+  dov = std::conj(dbra.a) * ket.a + std::conj(dbra.b) * ket.b + std::conj(bra.a) * dket.a + std::conj(bra.b) * dket.b;
+  cplx g[16], nb, q[16];
+  transition_cov(bra, ket, g);
+  occupation_response(bra, ket, nb, q);
+  den = (std::conj(dbra.b) * ket.b + std::conj(bra.b) * dket.b) / ov - nb * dov / ov;
+  for (int i = 0; i < 16; ++i) dg[i] = deq[i] = 0.0;
+  for (int p = 0; p < 4; ++p)
+    for (int r = p + 1; r < 4; ++r) {
+      cplx m[2][2];
+      bilinear(p, r, m);
+      auto mel = [&](const Even2 &x, const Even2 &y) {
+        return std::conj(x.a) * (m[0][0] * y.a + m[0][1] * y.b) + std::conj(x.b) * (m[1][0] * y.a + m[1][1] * y.b);
+      };
+      const cplx e = mel(bra, ket), de = mel(dbra, ket) + mel(bra, dket);
+      const cplx I(0.0, 1.0);
+      const cplx dgv = I * de / ov - I * e * dov / (ov * ov);
+      // Q_pr = i <bra|n_out c_p c_r|ket> / ov - Gamma_pr nbar, n_out = |11><11|
+      const cplx e1 = std::conj(bra.b) * (m[1][0] * ket.a + m[1][1] * ket.b);
+      const cplx de1 = std::conj(dbra.b) * (m[1][0] * ket.a + m[1][1] * ket.b) +
+                       std::conj(bra.b) * (m[1][0] * dket.a + m[1][1] * dket.b);
+      const cplx dqv = I * de1 / ov - I * e1 * dov / (ov * ov) - dgv * nb - g[p * 4 + r] * den;
+      dg[p * 4 + r] = dgv;
+      dg[r * 4 + p] = -dgv;
+      deq[p * 4 + r] = dqv;
+      deq[r * 4 + p] = -dqv;
+    }
+}
+
+// O X O^T for the link rotation O of value k (the out pair turned by 2 pi k / N).
+void rotate4(const cplx x[16], int k, int group, cplx y[16]) {
+  double c = 1.0, s = 0.0;
+  if (k != 0) {
+    if (group == 2) { c = -1.0; s = 0.0; }
+    else { c = std::cos(2.0 * M_PI * k / group); s = std::sin(2.0 * M_PI * k / group); }
+  }
+  const double o[16] = {c, s, 0, 0, -s, c, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+  cplx t[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      cplx v = 0.0;
+      for (int q = 0; q < 4; ++q) v += o[i * 4 + q] * x[q * 4 + j];
+      t[i * 4 + j] = v;
+    }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      cplx v = 0.0;
+      for (int q = 0; q < 4; ++q) v += t[i * 4 + q] * o[j * 4 + q];
+      y[i * 4 + j] = v;
+    }
+}
+
+// In-place inverse of an m x m complex matrix (m <= 8, leading dimension m) by Gauss-Jordan with
+// partial pivoting; false when singular.
+bool cinvert(std::vector<cplx> &a, int m) {
+  std::vector<cplx> inv(m * m, 0.0);
+  for (int i = 0; i < m; ++i) inv[i * m + i] = 1.0;
+  for (int col = 0; col < m; ++col) {
+    int p = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::abs(a[r * m + col]) > std::abs(a[p * m + col])) p = r;
+    if (!(std::abs(a[p * m + col]) > 0.0)) return false;
+    if (p != col)
+      for (int j = 0; j < m; ++j) {
+        std::swap(a[p * m + j], a[col * m + j]);
+        std::swap(inv[p * m + j], inv[col * m + j]);
+      }
+    const cplx d = 1.0 / a[col * m + col];
+    for (int j = 0; j < m; ++j) {
+      a[col * m + j] *= d;
+      inv[col * m + j] *= d;
+    }
+    for (int r = 0; r < m; ++r)
+      if (r != col) {
+        const cplx f = a[r * m + col];
+        if (f == 0.0) continue;
+        for (int j = 0; j < m; ++j) {
+          a[r * m + j] -= f * a[col * m + j];
+          inv[r * m + j] -= f * inv[col * m + j];
+        }
+      }
+  }
+  a = inv;
+  return true;
+}
+
+}  // namespace
+
+ggf_status ggf_bond_gradient(ggf_ctx *ctx, const ggf_tensor_desc *d, const ggf_couplings *cp,
+                             const double *energy_rows, const double *bond_rows, int64_t n_rows, double *grad) {
+  if (!d || !cp || !energy_rows || !bond_rows || n_rows <= 0 || !grad)
+    return fail(ctx, GGF_EINVAL, "tensor, couplings, rows, n_rows > 0 and grad are required");
+  const int K = d->K, group = d->group;
+  if (K < 2 || K > GGF_KMAX || !d->patch_link || !d->gamma_bond_k || !d->c_re || !d->c_im)
+    return fail(ctx, GGF_EINVAL, "the bond gradient needs a superposition (2 <= K <= GGF_KMAX) with its bonds");
+  std::string why;
+  std::vector<Even2> bk(K);
+  if (!even_state(d->gamma_bond, bk[0], why)) return fail(ctx, GGF_EINVAL, "gamma_bond: " + why);
+  for (int k = 1; k < K; ++k) {
+    if (!even_state(d->gamma_bond_k + 16 * k, bk[k], why))
+      return fail(ctx, GGF_EINVAL, "gamma_bond_k[" + std::to_string(k) + "]: " + why);
+    const cplx ov = std::conj(bk[0].a) * bk[k].a + std::conj(bk[0].b) * bk[k].b;
+    if (std::abs(ov) < 1e-12) return fail(ctx, GGF_EINVAL, "<b_0|b_k> = 0: phase convention undefined");
+    const cplx ph = ov / std::abs(ov);
+    bk[k].a /= ph;
+    bk[k].b /= ph;
+  }
+  std::vector<cplx> cc(K);
+  for (int k = 0; k < K; ++k) cc[k] = cplx(d->c_re[k], d->c_im[k]);
+  const int ng = 6, gens[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  const int nout = (K - 1) * ng;
+  // per-link transition data of pair (n, m): bra/ket bond vectors
+  auto vectors = [&](int ell, int n, int m, Even2 &ket, Even2 &bra) {
+    ket = (n > 0 && d->patch_link[n] == ell) ? bk[n] : bk[0];
+    bra = (m > 0 && d->patch_link[m] == ell) ? bk[m] : bk[0];
+  };
+  cplx g0c[16];
+  for (int i = 0; i < 16; ++i) g0c[i] = d->gamma_bond[i];
+  cplx en0, eq0[16];
+  occupation_response(bk[0], bk[0], en0, eq0);
+  // bond derivatives per (k, generator)
+  std::vector<Even2> dbk(nout);
+  for (int k = 1; k < K; ++k)
+    for (int gi = 0; gi < ng; ++gi) {
+      double E[16] = {0.0};
+      E[gens[gi][0] * 4 + gens[gi][1]] = 1.0;
+      E[gens[gi][1] * 4 + gens[gi][0]] = -1.0;
+      dbk[(k - 1) * ng + gi] = bond_state_derivative(d->gamma_bond_k + 16 * k, E, bk[k], bk[0]);
+    }
+  std::vector<double> es(n_rows), de(static_cast<size_t>(n_rows) * nout), dn(static_cast<size_t>(n_rows) * nout);
+  for (int64_t r = 0; r < n_rows; ++r) {
+    const double *er = energy_rows + r * GGF_ENERGY_STRIDE;
+    const double *br = bond_rows + r * GGF_BOND_STRIDE;
+    const int s = static_cast<int>(br[0]), L = static_cast<int>(br[1]);
+    if (s < 4 || s > GGF_BOND_SMAX) return fail(ctx, GGF_EINVAL, "bond row " + std::to_string(r) + " has no patch set");
+    std::vector<int> S(s);
+    for (int q = 0; q < s; ++q) S[q] = static_cast<int>(br[2 + q]);
+    auto link_pos = [&](int ell, int pos[4]) {
+      const int i = ell >> 1, mu = ell & 1;
+      const int j = mu == 0 ? (i / L) * L + (i % L + 1) % L : ((i / L + 1) % L) * L + i % L;
+      const int u[4] = {mu == 0 ? 8 * i + 4 : 8 * i + 2, mu == 0 ? 8 * i + 5 : 8 * i + 3,
+                        mu == 0 ? 8 * j + 0 : 8 * j + 6, mu == 0 ? 8 * j + 1 : 8 * j + 7};
+      for (int q = 0; q < 4; ++q) pos[q] = static_cast<int>(std::find(S.begin(), S.end(), u[q]) - S.begin());
+    };
+    auto R = [&](int a, int b) { return cplx(br[18 + 2 * (12 * a + b)], br[19 + 2 * (12 * a + b)]); };
+    auto gss = [&](int a, int b) { return br[306 + 12 * a + b]; };
+    // pair weights and energies
+    std::vector<cplx> om(K * K), h(K * K);
+    cplx e = 0.0, Ssum = 0.0;
+    for (int p = 0; p < K * K; ++p) {
+      const cplx rs(er[1 + 4 * p], er[2 + 4 * p]), rhs(er[3 + 4 * p], er[4 + 4 * p]);
+      om[p] = std::conj(cc[p / K]) * cc[p % K] * rs;   // om / S
+      h[p] = rhs / rs;
+      Ssum += om[p];
+      e += om[p] * h[p];
+    }
+    es[r] = e.real();
+    for (int k = 1; k < K; ++k) {
+      const int ellk = d->patch_link[k];
+      const int kv = static_cast<int>(br[14 + k]);
+      int uk[4];
+      link_pos(ellk, uk);
+      for (int gi = 0; gi < ng; ++gi) {
+        const Even2 &db = dbk[(k - 1) * ng + gi];
+        cplx dE = 0.0, dN = 0.0;
+        for (int n = 0; n < K; ++n)
+          for (int m = 0; m < K; ++m) {
+            if (n != k && m != k) continue;
+            const int p = n * K + m;
+            // the pair's patch links and their positions in S
+            int links[2], nl = 0;
+            if (n > 0) links[nl++] = d->patch_link[n];
+            if (m > 0 && !(nl == 1 && links[0] == d->patch_link[m])) links[nl++] = d->patch_link[m];
+            std::vector<int> P;
+            std::vector<int> lpos(nl * 4);
+            for (int l = 0; l < nl; ++l) {
+              int pos[4];
+              link_pos(links[l], pos);
+              for (int q = 0; q < 4; ++q) {
+                auto it = std::find(P.begin(), P.end(), pos[q]);
+                if (it == P.end()) { lpos[l * 4 + q] = static_cast<int>(P.size()); P.push_back(pos[q]); }
+                else lpos[l * 4 + q] = static_cast<int>(it - P.begin());
+              }
+            }
+            const int sp = static_cast<int>(P.size());
+            // Delta on P and its derivative (only link ellk moves)
+            std::vector<cplx> Dl(sp * sp, 0.0), dDl(sp * sp, 0.0), Rp(sp * sp, 0.0);
+            cplx dov = 0.0, ovk = 1.0, den = 0.0, deq[16], dgk[16];
+            int kl = -1;
+            for (int l = 0; l < nl; ++l) {
+              Even2 ket, bra;
+              vectors(links[l], n, m, ket, bra);
+              cplx g[16], dg[16], nb, q[16];
+              transition_cov(bra, ket, g);
+              occupation_response(bra, ket, nb, q);
+              const int lv = static_cast<int>(br[14 + (links[l] == d->patch_link[n] && n > 0 ? n : m)]);
+              cplx dgl[16], blk[16];
+              for (int i = 0; i < 16; ++i) dgl[i] = g[i] - g0c[i];
+              rotate4(dgl, lv, group, blk);
+              for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) Dl[lpos[l * 4 + i] * sp + lpos[l * 4 + j]] += blk[i * 4 + j];
+              // the pair's own electric response on this link replaces the reference one in R
+              if (cp->ke != 0.0) {
+                cplx dq[16], qr[16];
+                for (int i = 0; i < 16; ++i) dq[i] = q[i] - eq0[i];
+                rotate4(dq, lv, group, qr);
+                int pos[4];
+                link_pos(links[l], pos);
+                for (int a = 0; a < sp; ++a)
+                  for (int b = 0; b < sp; ++b) {
+                    cplx v = 0.0;
+                    for (int i = 0; i < 4; ++i)
+                      for (int j = 0; j < 4; ++j) v += qr[j * 4 + i] * gss(P[a], pos[i]) * gss(P[b], pos[j]);
+                    Rp[a * sp + b] -= 0.5 * cp->ke * v;
+                  }
+              }
+              if (links[l] == ellk) {
+                kl = l;
+                Even2 dket{0.0, 0.0}, dbra{0.0, 0.0};
+                if (n == k) dket = db;
+                if (m == k) dbra = db;
+                cplx dgr[16];
+                transition_derivative(bra, ket, dbra, dket, dg, dov, den, deq);
+                rotate4(dg, lv, group, dgr);
+                for (int i = 0; i < 16; ++i) dgk[i] = dgr[i];
+                for (int i = 0; i < 4; ++i)
+                  for (int j = 0; j < 4; ++j) dDl[lpos[l * 4 + i] * sp + lpos[l * 4 + j]] += dgr[i * 4 + j];
+                ovk = std::conj(bra.a) * ket.a + std::conj(bra.b) * ket.b;
+              }
+            }
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) Rp[a * sp + b] += R(P[a], P[b]);
+            // A = 1 + G_PP Delta, Y = Delta A^-1, M^-1_PP = G_PP - G_PP Y G_PP
+            std::vector<cplx> A(sp * sp), Ai;
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) {
+                cplx v = (a == b) ? 1.0 : 0.0;
+                for (int q = 0; q < sp; ++q) v += gss(P[a], P[q]) * Dl[q * sp + b];
+                A[a * sp + b] = v;
+              }
+            Ai = A;
+            if (!cinvert(Ai, sp)) return fail(ctx, GGF_ENONFINITE, "singular pair capacitance in row " + std::to_string(r));
+            std::vector<cplx> Y(sp * sp, 0.0), GY(sp * sp, 0.0), Mi(sp * sp, 0.0);
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b)
+                for (int q = 0; q < sp; ++q) Y[a * sp + b] += Dl[a * sp + q] * Ai[q * sp + b];
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b)
+                for (int q = 0; q < sp; ++q) GY[a * sp + b] += gss(P[a], P[q]) * Y[q * sp + b];
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) {
+                cplx v = gss(P[a], P[b]);
+                for (int q = 0; q < sp; ++q) v -= GY[a * sp + q] * gss(P[q], P[b]);
+                Mi[a * sp + b] = v;
+              }
+            // d log r = (1/2) tr(M^-1 dM)
+            cplx dlogr = 0.0;
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) dlogr += 0.5 * Mi[a * sp + b] * dDl[b * sp + a];
+            // dY = (1 - Y G_PP) dDelta A^-1
+            std::vector<cplx> T1(sp * sp, 0.0), dY(sp * sp, 0.0);
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) {
+                cplx v = 0.0;
+                for (int q = 0; q < sp; ++q) v += dDl[a * sp + q] * Ai[q * sp + b];
+                T1[a * sp + b] = v;
+              }
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) {
+                cplx v = T1[a * sp + b];
+                for (int q = 0; q < sp; ++q) {
+                  cplx yg = 0.0;
+                  for (int t = 0; t < sp; ++t) yg += Y[a * sp + t] * gss(P[t], P[q]);
+                  v -= yg * T1[q * sp + b];
+                }
+                dY[a * sp + b] = v;
+              }
+            cplx dh = 0.0;
+            for (int a = 0; a < sp; ++a)
+              for (int b = 0; b < sp; ++b) dh -= dY[a * sp + b] * Rp[a * sp + b];
+            if (cp->ke != 0.0 && kl >= 0) {
+              // explicit change of the varied link's mixed occupation: d en + (1/2) tr(M^-1_UU O deq O^T)
+              cplx dqr[16];
+              rotate4(deq, kv, group, dqr);
+              cplx x = den;
+              for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) x += 0.5 * Mi[lpos[kl * 4 + i] * sp + lpos[kl * 4 + j]] * dqr[j * 4 + i];
+              dh += cp->ke * x;
+            }
+            const cplx dlogrho = dov / ovk + dlogr;
+            dN += om[p] / Ssum * dlogrho;
+            dE += om[p] / Ssum * (dh + (h[p] - e / Ssum) * dlogrho);
+          }
+        de[r * nout + (k - 1) * ng + gi] = dE.real();
+        dn[r * nout + (k - 1) * ng + gi] = dN.real();
+      }
+    }
+  }
+  double ebar = 0.0;
+  for (int64_t r = 0; r < n_rows; ++r) {
+    if (!std::isfinite(es[r])) return fail(ctx, GGF_ENONFINITE, "non-finite energy in row " + std::to_string(r));
+    ebar += es[r];
+  }
+  ebar /= static_cast<double>(n_rows);
+  for (int q = 0; q < nout; ++q) {
+    double acc = 0.0;
+    for (int64_t r = 0; r < n_rows; ++r) acc += de[r * nout + q] + (es[r] - ebar) * dn[r * nout + q];
+    grad[q] = acc / static_cast<double>(n_rows);
+    if (!std::isfinite(grad[q])) return fail(ctx, GGF_ENONFINITE, "non-finite bond gradient");
+  }
   return GGF_OK;
 }
 

@@ -19,6 +19,7 @@
 #define GGF_ZN_MAX 64      // largest gauge group Z_N (link values are int8)
 #define GGF_ENERGY_STRIDE_DEV (1 + 4 * GGF_KMAX_DEV * GGF_KMAX_DEV)
 #define GGF_SENS_STRIDE_DEV 200
+#define GGF_BOND_STRIDE_DEV 450   // 2 + 12 + 4 + 3 * 12 * 12
 
 // Per-ansatz constants.  Pair (n, m) of the superposition involves at most
 // two patch links (those where B_n or B_m differ from B_0); for each of them

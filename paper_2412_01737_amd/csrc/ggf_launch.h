@@ -77,6 +77,7 @@ struct EnergyCp {
   double t, mu, m, kb, ke;
 };
 void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax);
+void ggf_launch_bond_rows(const LaunchCtx &lc, const EnergyCp &cp, double *out);
 // Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 16);
 // max_group: the largest link group among the chains.
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group);

@@ -996,6 +996,114 @@ __global__ __launch_bounds__(256) void k_energy(LaunchCtx lc, EnergyCp cp, doubl
   }
 }
 
+// Rows for the gradient with respect to the patch bond states (one workgroup per chain).  S is
+// the union of the patch links' Majoranas (ascending).  The part of the local energy linear in
+// X = M^-1 is sum_ij C_ij X_ij: the bilinear <phi_x^+ phi_y> (coefficient beta) contributes
+// -(beta / 4) i conj(z_p) z_q at X[8x + p][8y + q], z = b_0 + i b_1 (the rows of the
+// physical-virtual block), and the mixed occupation of link l with the reference bond's response,
+// X_l = en0 + (1/2) tr(X_UU O eq0 O^T), contributes (ke / 2) (O eq0 O^T)_ji at X[u_i][u_j].
+// With G real antisymmetric, V_b(y) = sum_q z_q G[S_b][8y + q] gives
+//   R[a][b] = sum_ij C_ij G[i][S_a] G[S_b][j]
+//           = (i / 4) sum beta_xy conj(V_a(x)) V_b(y) - (ke / 2) sum_l sum_ij Q_ji G[S_a][u_i] G[S_b][u_j].
+// V lives in LDS (s L^2 <= 4096 complex), O eq0 O^T per group element in a table.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bond_rows(LaunchCtx lc, EnergyCp cp, double *out) {
+  __shared__ double2 s_v[4096];
+  __shared__ double2 s_q[GGF_ZN_MAX][16];
+  __shared__ int s_S[12];
+  __shared__ int s_s;
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, K = ch.K, group = ch.group;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  double *o = out + static_cast<size_t>(c) * GGF_BOND_STRIDE_DEV;
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int k = 1; k < K; ++k) {
+      int u[4];
+      ggf_link_u(Tn.lk[k][0][0], L, u);
+      for (int i = 0; i < 4; ++i) {
+        bool seen = false;
+        for (int q = 0; q < m; ++q) seen = seen || s_S[q] == u[i];
+        if (!seen) s_S[m++] = u[i];
+      }
+    }
+    for (int i = 1; i < m; ++i)          // ascending
+      for (int j = i; j > 0 && s_S[j - 1] > s_S[j]; --j) {
+        const int t = s_S[j];
+        s_S[j] = s_S[j - 1];
+        s_S[j - 1] = t;
+      }
+    s_s = m;
+  }
+  for (int g = threadIdx.x; g < group * 4; g += blockDim.x) {
+    double2 row[4];
+    rotate_dg_row(Tn.eq0, g / 4, group, g % 4, row);   // row (g % 4) of O(g / 4) eq0 O(g / 4)^T
+    for (int j = 0; j < 4; ++j) s_q[g / 4][(g % 4) * 4 + j] = row[j];
+  }
+  __syncthreads();
+  const int s = s_s;
+  for (int q = threadIdx.x; q < GGF_BOND_STRIDE_DEV; q += blockDim.x) o[q] = 0.0;
+  __syncthreads();
+  if (s == 0) return;
+  for (int t = threadIdx.x; t < s * V; t += blockDim.x) {
+    const int b = t / V, y = t % V;
+    const T *row = G + static_cast<size_t>(s_S[b]) * n + 8 * y;
+    double2 v = make_double2(0.0, 0.0);
+    for (int q = 0; q < 8; ++q) {
+      const double gq = static_cast<double>(row[q]);
+      v = cadd(v, make_double2(Tn.b[q] * gq, Tn.b[8 + q] * gq));
+    }
+    s_v[b * V + y] = v;
+  }
+  __syncthreads();
+  const int a = threadIdx.x / s, b = threadIdx.x % s;
+  if (threadIdx.x < s * s) {
+    const double2 *va = s_v + a * V, *vb = s_v + b * V;
+    double2 fer = make_double2(0.0, 0.0), el = make_double2(0.0, 0.0);
+    for (int x = 0; x < V; ++x) {
+      const int x2 = x / L;
+      const double sgn = (((x % L) + x2) & 1) ? -1.0 : 1.0;
+      fer = cadd(fer, cscale(cmul(cconj(va[x]), vb[x]), cp.mu + sgn * cp.m));
+      for (int mu = 0; mu < 2; ++mu) {
+        const int ell = 2 * x + mu;
+        const int y = mu == 0 ? ggf_shift(x, L, 1, 0) : ggf_shift(x, L, 0, 1);
+        const double2 D = link_phase(lk[ell], group);
+        const double te = (mu == 0 && (x2 & 1)) ? -cp.t : cp.t;
+        // beta_xy = i te D on <phi_x^+ phi_y>, beta_yx = -i te D^* on <phi_y^+ phi_x>
+        const double2 bxy = make_double2(-te * D.y, te * D.x), byx = make_double2(-te * D.y, -te * D.x);
+        fer = cadd(fer, cmul(bxy, cmul(cconj(va[x]), vb[y])));
+        fer = cadd(fer, cmul(byx, cmul(cconj(va[y]), vb[x])));
+        if (cp.ke != 0.0) {
+          int u[4];
+          ggf_link_u(ell, L, u);
+          double ga[4], gb[4];
+          for (int i = 0; i < 4; ++i) {
+            ga[i] = static_cast<double>(G[static_cast<size_t>(s_S[a]) * n + u[i]]);
+            gb[i] = static_cast<double>(G[static_cast<size_t>(s_S[b]) * n + u[i]]);
+          }
+          const double2 *Q = s_q[lk[ell]];
+          for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) el = cadd(el, cscale(Q[j * 4 + i], ga[i] * gb[j]));
+        }
+      }
+    }
+    // R = (i / 4) fer - (ke / 2) el
+    const double2 r = make_double2(-0.25 * fer.y - 0.5 * cp.ke * el.x, 0.25 * fer.x - 0.5 * cp.ke * el.y);
+    o[18 + 2 * (12 * a + b)] = r.x;
+    o[19 + 2 * (12 * a + b)] = r.y;
+    o[306 + 12 * a + b] = static_cast<double>(G[static_cast<size_t>(s_S[a]) * n + s_S[b]]);
+  }
+  if (threadIdx.x == 0) {
+    o[0] = s;
+    o[1] = L;
+    for (int q = 0; q < s; ++q) o[2 + q] = s_S[q];
+    for (int k = 1; k < K; ++k) o[14 + k] = lk[Tn.lk[k][0][0]];
+  }
+}
+
 // Real part of Re(coef * Wc), Wc = (1/4) [[-i, 1], [-1, -i]]: the coefficient block of
 // Gamma_out[2x + a][2y + b] in coef <phi_x^+ phi_y> (with <c_p c_q> = -i Gamma_pq).
 __device__ inline void coef_block(double2 coef, double o[4]) {
@@ -1801,6 +1909,13 @@ void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int
     hipLaunchKernelGGL(k_energy<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
   else
     hipLaunchKernelGGL(k_energy<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, cp, out);
+}
+
+void ggf_launch_bond_rows(const LaunchCtx &lc, const EnergyCp &cp, double *out) {
+  if (lc.precision == 64)
+    hipLaunchKernelGGL(k_bond_rows<double>, dim3(lc.n_chains), dim3(256), 0, lc.stream, lc, cp, out);
+  else
+    hipLaunchKernelGGL(k_bond_rows<float>, dim3(lc.n_chains), dim3(256), 0, lc.stream, lc, cp, out);
 }
 
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group) {

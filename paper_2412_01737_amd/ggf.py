@@ -21,6 +21,8 @@ GGF_NOBS = 21
 GGF_ENERGY_STRIDE = 1 + 4 * GGF_KMAX * GGF_KMAX
 GGF_STAGE_MAX_CHAINS = 16384
 GGF_SENS_STRIDE = 200
+GGF_BOND_SMAX = 12
+GGF_BOND_STRIDE = 2 + GGF_BOND_SMAX + GGF_KMAX + 3 * GGF_BOND_SMAX * GGF_BOND_SMAX
 OBS_LINK, OBS_DENSITY, OBS_MESON, OBS_ELECTRIC = 1, 2, 4, 8
 OBS_ALL = 15
 _STATUS = {0: "GGF_OK", -1: "GGF_EINVAL", -2: "GGF_ENOMEM", -3: "GGF_ESINGULAR",
@@ -67,6 +69,11 @@ EXPORTS = {
     "ggf_measure_sensitivity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Couplings), ctypes.c_void_p,
                                                ctypes.c_int32, ctypes.c_void_p]),
     "ggf_gamma_gradient": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int64, _dp]),
+    "ggf_set_bond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_void_p]),
+    "ggf_measure_bond_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Couplings), ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_void_p]),
+    "ggf_bond_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(TensorDesc), ctypes.POINTER(Couplings), _dp,
+                                         _dp, ctypes.c_int64, _dp]),
     "ggf_set_gamma_loc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_void_p]),
     "ggf_optimise_gamma": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Couplings), ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp, ctypes.c_void_p]),
@@ -260,6 +267,26 @@ class Context:
                                                       _stream_ptr(stream)))
         return out
 
+    def set_bond(self, tensor_id: int, k: int, gamma_bond_k, stream=None):
+        """ggf_set_bond: new bond state of B_k on its patch link; the chains' S(G) are recomputed."""
+        g = np.ascontiguousarray(np.asarray(gamma_bond_k, np.float64).reshape(4, 4))
+        self._check(self._lib.ggf_set_bond(self.h, int(tensor_id), int(k), g.ctypes.data_as(_dp),
+                                           _stream_ptr(stream)))
+
+    def measure_bond_rows(self, couplings, out=None, stream=None):
+        """Rows [n_chains, GGF_BOND_STRIDE] for the gradient with respect to the patch bond states
+        (ggf_measure_bond_rows)."""
+        cp = couplings if isinstance(couplings, Couplings) else Couplings(**dict(couplings))
+        if out is None:
+            host = np.zeros((self.n_chains, GGF_BOND_STRIDE))
+            self._check(self._lib.ggf_measure_bond_rows(self.h, ctypes.byref(cp), host.ctypes.data_as(ctypes.c_void_p),
+                                                        0, _stream_ptr(stream)))
+            return host
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        self._check(self._lib.ggf_measure_bond_rows(self.h, ctypes.byref(cp), ctypes.c_void_p(ptr), 1,
+                                                    _stream_ptr(stream)))
+        return out
+
     def set_gamma_loc(self, tensor_id: int, gamma_loc, stream=None):
         """ggf_set_gamma_loc: new on-site covariance for a tensor; its chains are refactorised."""
         g = np.ascontiguousarray(np.asarray(gamma_loc, np.float64).reshape(10, 10))
@@ -436,6 +463,34 @@ def lambda_step(K: int, rows):
     if st != GGF_OK:
         raise GGFError(st, f"ggf_lambda_step failed ({_STATUS.get(st, st)})")
     return e.value, lr + 1j * li
+
+
+def bond_gradient(spec, couplings, energy_rows, bond_rows):
+    """ggf_bond_gradient on host rows of chains of the ansatz `spec` (group, gamma_loc, gamma_bond, K,
+    patch_link, gamma_bond_k, c): d<H>/d theta for bonds k = 1 .. K-1 and the six generators, shape
+    [K - 1, 6]."""
+    lib = load()
+    cp = couplings if isinstance(couplings, Couplings) else Couplings(**dict(couplings))
+    gl, gb = _f64(spec.gamma_loc), _f64(spec.gamma_bond)
+    pl = np.ascontiguousarray(np.asarray(spec.patch_link, np.int32))
+    gk = _f64(spec.gamma_bond_k)
+    cc = np.asarray(spec.c, complex)
+    cre, cim = _f64(cc.real), _f64(cc.imag)
+    d = TensorDesc()
+    d.group, d.K = int(spec.group), int(spec.K)
+    d.gamma_loc, d.gamma_bond = gl.ctypes.data_as(_dp), gb.ctypes.data_as(_dp)
+    d.patch_link, d.gamma_bond_k = pl.ctypes.data_as(_ip), gk.ctypes.data_as(_dp)
+    d.c_re, d.c_im = cre.ctypes.data_as(_dp), cim.ctypes.data_as(_dp)
+    er = np.ascontiguousarray(np.asarray(energy_rows, np.float64).reshape(-1, GGF_ENERGY_STRIDE))
+    br = np.ascontiguousarray(np.asarray(bond_rows, np.float64).reshape(-1, GGF_BOND_STRIDE))
+    if er.shape[0] != br.shape[0]:
+        raise ValueError("energy and bond rows must describe the same samples")
+    out = np.zeros((int(spec.K) - 1, 6))
+    st = lib.ggf_bond_gradient(None, ctypes.byref(d), ctypes.byref(cp), er.ctypes.data_as(_dp), br.ctypes.data_as(_dp),
+                               er.shape[0], out.ctypes.data_as(_dp))
+    if st != GGF_OK:
+        raise GGFError(st, f"ggf_bond_gradient failed ({_STATUS.get(st, st)})")
+    return out
 
 
 def gamma_gradient(gamma_loc, energy_rows, sens_rows):
