@@ -282,9 +282,9 @@ def block_traffic_from(args):
            "fetch_scale": sf, "write_scale": sw}
     total = 0.0
     tname = "float" if rec["config"]["precision"] == 32 else "double"
-    # block moves only: k_window_snap and the <T, 8, true> instance of k_window_gemm (the training
-    # sampler's window flushes run <T, 4, false>)
-    for k in (f"k_window_snap<{tname}>", f"k_window_gemm<{tname}, 8, true>"):
+    # block moves only: k_window_snap and the <T, 8, true, *> instances of k_window_gemm (the
+    # training sampler's window flushes run <T, 4, false, *>)
+    for k in (f"k_window_snap<{tname}>", f"k_window_gemm<{tname}, 8, true,"):
         fv, wv = per_kernel(f_csv, "FETCH_SIZE", k)[-last:], per_kernel(w_csv, "WRITE_SIZE", k)[-last:]
         rd = sum(fv) / len(fv) * sf * 1024.0
         wr = sum(wv) / len(wv) * sw * 1024.0

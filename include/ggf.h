@@ -342,7 +342,7 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *                  by one matrix-core rank-4F update at its end), 0 = one rank-4 streaming
  *                  update per link step, -1 (default) = 16.  Takes effect at the next sweep;
  *                  G as read through the ABI never has pending flips.
- *   "flush_grid"   workgroups of the window flush (default 1024)
+ *   "flush_grid"   workgroups of the window flush (default 512)
  *   "balance"      1 = balanced sweeps for batches of different lattice sizes: a ggf_sweep sweep
  *                  is max_links link steps at each of which every chain proposes its own next link
  *                  (a per-chain cursor), so a chain with fewer links completes several of its own

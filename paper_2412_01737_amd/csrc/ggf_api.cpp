@@ -431,7 +431,8 @@ ggf_status record_sweep(ggf_ctx *ctx, hipStream_t s, bool timed) {
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 2048;
   const int F = delay_window(ctx);
   if (F > 0 && !ctx->dly_cnt) return fail(ctx, GGF_ESTATE, "delayed-update buffers are not allocated");
-  const int flush_grid = ctx->opt_flush_grid > 0 ? ctx->opt_flush_grid : 1024;
+  // measured on the buffer-addressed flush: 512 workgroups beat 1024 by 2.5 % at 4096 chains of n = 128
+  const int flush_grid = ctx->opt_flush_grid > 0 ? ctx->opt_flush_grid : 512;
   lc.dly = F;
   int k = 0;
   for (int ell = 0; ell < ctx->max_links; ++ell) {
