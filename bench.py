@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=5, help="c5: timed sweeps of the float64 single-link comparison")
     ap.add_argument("--untrained", type=int, default=1,
                     help="c5: also time the block moves with an untrained (uniform) proposal (1 = yes)")
+    ap.add_argument("--block-pend", type=int, default=-1,
+                    help="c5: largest combined rank of pending block moves (-1 = library default, 0 = apply "
+                         "each accepted move at once)")
     ap.add_argument("--bond-gradient", type=int, default=1,
                     help="c5: time the gradient with respect to the patch bond states on the final "
                          "configurations (1 = yes)")
@@ -251,10 +254,10 @@ def electric_traffic_from(args):
 
 
 def block_traffic_from(args):
-    """HBM bytes per accepted block move of k_window_snap + k_window_gemm, from FETCH_SIZE / WRITE_SIZE.
+    """HBM bytes per block update of G (k_window_snap + k_window_gemm), from FETCH_SIZE / WRITE_SIZE.
 
     Counters are scaled by the copy calibration as in traffic_from; the number of
-    accepted moves per launch comes from the profiled run's own JSON line."""
+    updates of G per launch comes from the profiled run's own JSON line."""
     import csv
 
     def per_kernel(path, counter, match):
@@ -273,13 +276,13 @@ def block_traffic_from(args):
         if line.startswith("{") and '"learned"' in line:
             rec = json.loads(line)
     learned = rec["learned"]
-    moves_per_launch = learned["accepted_moves"] / learned["update_launches"]
+    updates_per_launch = learned["updates_of_G"] / learned["update_launches"]
     # only the learned sampler's timed block sweeps: the last update_launches dispatches of each
     # kernel (run with --untrained 0 --plain-steps 0, so nothing dispatches them afterwards; the
     # training context's block sweeps of the output-scale trials come earlier)
     last = int(learned["update_launches"])
-    out = {"source_digest": source_digest(BLOCK_SOURCES), "moves_per_launch": moves_per_launch,
-           "fetch_scale": sf, "write_scale": sw}
+    out = {"source_digest": source_digest(BLOCK_SOURCES), "updates_per_launch": updates_per_launch,
+           "moves_per_update": learned["moves_per_update"], "fetch_scale": sf, "write_scale": sw}
     total = 0.0
     tname = "float" if rec["config"]["precision"] == 32 else "double"
     # block moves only: k_window_snap and the <T, 8, true, *> instances of k_window_gemm (the
@@ -293,8 +296,8 @@ def block_traffic_from(args):
         total += rd + wr
     n = rec["config"]["n"]
     esz = 4 if rec["config"]["precision"] == 32 else 8
-    out["bytes_per_accepted_move"] = total / moves_per_launch
-    out["algorithmic_bytes_per_accepted_move"] = (n * (n + 1) / 2 + n * n) * esz
+    out["bytes_per_update"] = total / updates_per_launch
+    out["algorithmic_bytes_per_update"] = (n * (n + 1) / 2 + n * n) * esz
     key = f"L{rec['config']['L']}_K{rec['config']['K']}_Z{rec['config']['group']}_p{rec['config']['precision']}"
     path = os.path.join(HERE, "profiles", "k_block_traffic.json")
     try:
@@ -629,6 +632,8 @@ def run_c5(args):
     def sampler(name, chains, precision, refresh, net, steps, warmup):
         ctx = Context(0)
         ctx.set_option("delay", args.delay)
+        if args.block_pend >= 0:
+            ctx.set_option("block_pend", args.block_pend)
         tid = ctx.set_tensor_spec(spec)
         ti = time.perf_counter()
         ctx.init_chains([L] * chains, tid, synth.SEED_CHAIN, init=1, precision=precision,
@@ -692,8 +697,10 @@ def run_c5(args):
             after = [ctx.block_stats(c) for c in range(chains)]
             prop = sum(a[0] - b[0] for a, b in zip(after, before))
             acc = sum(a[1] - b[1] for a, b in zip(after, before))
+            upd = sum(a[3] - b[3] for a, b in zip(after, before))
             rec.update(acceptance=acc / max(prop, 1), links_per_accepted_move=changed / max(acc, 1),
-                       accepted_moves=acc, link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
+                       accepted_moves=acc, updates_of_G=upd, moves_per_update=acc / max(upd, 1),
+                       link_proposals_per_s=chains * steps * 2 * L * L / elapsed)
         else:
             acc = sum(ctx.get_state(c)[1]["accepts"] for c in range(chains)) - acc_before
             rec.update(acceptance=acc / (chains * steps * 2 * L * L),
@@ -707,12 +714,13 @@ def run_c5(args):
                          args.steps, args.warmup) if args.untrained else None)
     plain = (sampler("plain", args.plain_chains, 64, 16384, None, args.plain_steps, 1)
              if args.plain_steps > 0 else None)
-    # block update G -= G[:,U] W G[U,:] per accepted move of m changed links (rank r = 4 m), on the
-    # upper triangle of the antisymmetric G and mirrored: algorithmic bytes = the upper triangle read
-    # and all of G written ((n (n + 1) / 2 + n^2) * 4), flops = n^2 r
+    # block update G -= G[:,U] W G[U,:] per update of G (one accepted move, or several pending ones
+    # combined: rank r = 4 x their changed links), on the upper triangle of the antisymmetric G and
+    # mirrored: algorithmic bytes = the upper triangle read and all of G written
+    # ((n (n + 1) / 2 + n^2) * 4), flops = n^2 r
     esz = 4 if args.precision == 32 else 8
     upd_s = learned["update_ms_total"] * 1e-3
-    bytes_moved = (n * (n + 1) / 2 + n * n) * esz * learned["accepted_moves"]
+    bytes_moved = (n * (n + 1) / 2 + n * n) * esz * learned["updates_of_G"]
     flops = n * n * 4.0 * learned["links_changed"]
     achieved = bytes_moved / upd_s / 1e9 if upd_s > 0 else 0.0
     tflops = flops / upd_s / 1e12 if upd_s > 0 else 0.0
@@ -721,8 +729,8 @@ def run_c5(args):
         with open(os.path.join(HERE, "profiles", "k_block_traffic.json")) as f:
             tj = json.load(f).get(f"L{L}_K{K}_Z{group}_p{args.precision}")
         if tj and tj["source_digest"] == source_digest(BLOCK_SOURCES):
-            # measured bytes per accepted move x accepted moves per launch of this run
-            traffic = tj["bytes_per_accepted_move"] * learned["accepted_moves"] / learned["update_launches"]
+            # measured bytes per update of G x updates per launch of this run
+            traffic = tj["bytes_per_update"] * learned["updates_of_G"] / learned["update_launches"]
     except (OSError, ValueError, KeyError):
         pass
 
@@ -765,7 +773,7 @@ def run_c5(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_window_snap + k_window_gemm (block moves)",
                      "algorithmic_bytes_per_launch": bytes_moved / max(learned["update_launches"], 1),
-                     "bytes_per_accepted_move": (n * (n + 1) / 2 + n * n) * esz,
+                     "bytes_per_update": (n * (n + 1) / 2 + n * n) * esz,
                      "tflops": tflops, "mfma_peak_tflops": MFMA_PEAK_F32_TFLOPS,
                      "flops_per_changed_link": 4.0 * n * n},
         "cpu_baseline": None,

@@ -343,6 +343,9 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *                  update per link step, -1 (default) = 16.  Takes effect at the next sweep;
  *                  G as read through the ABI never has pending flips.
  *   "flush_grid"   workgroups of the window flush (default 512)
+ *   "block_pend"   block sweeps: largest combined rank of accepted block moves kept pending
+ *                  and applied to G together, 0 .. 128 (default 128; 0 = each accepted move
+ *                  updates G at once)
  *   "balance"      1 = balanced sweeps for batches of different lattice sizes: a ggf_sweep sweep
  *                  is max_links link steps at each of which every chain proposes its own next link
  *                  (a per-chain cursor), so a chain with fewer links completes several of its own
@@ -448,13 +451,20 @@ ggf_status ggf_nn_train(ggf_ctx *ctx, int32_t steps, int32_t batch, float lr, ui
  * counter advances (shared with ggf_sweep).  Philox counters: proposal
  * uniforms (chain, sweep, patch, 3 + l/4), word l mod 4, u = (x + 1/2) 2^-32;
  * acceptance (chain, sweep, patch, 2).  Requires ggf_nn_init and Z2 chains
- * whose side is a multiple of P. */
+ * whose side is a multiple of P.  With option "block_pend" > 0 (the default)
+ * accepted moves of consecutive patches are applied to G together, as one
+ * Woodbury update of rank up to "block_pend" (Sec. 4.2's update with the
+ * pending moves' U and W combined); each decision sees the inverse with every
+ * pending move applied, so the chain is the same; every move is applied by the
+ * end of the call. */
 ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream);
 
 /* Block moves proposed (at least one link changed) and accepted for a chain,
- * and the number of links the accepted moves changed.  Synchronous. */
+ * the number of links the accepted moves changed, and the number of updates of
+ * the chain's G that applied them (one per accepted move when "block_pend" is
+ * 0, fewer with delayed moves).  Any output may be NULL.  Synchronous. */
 ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uint64_t *accepts,
-                           uint64_t *links_changed);
+                           uint64_t *links_changed, uint64_t *updates);
 
 /* Bandwidth probe (diagnostics): mode 0 copies `bytes` from a to b, mode 1 the
  * same with non-temporal loads/stores, mode 2 updates a in place

@@ -74,6 +74,7 @@ struct ggf_ctx {
   int opt_delay = -1;            // window of delayed updates in link steps (0 = immediate, -1 = automatic)
   int opt_flush_grid = 0;        // workgroups of the window flush (0 = library default)
   int opt_balance = 0;           // 1: balanced sweeps (every chain steps its own link cursor at every link step)
+  int opt_block_pend = GGF_BLOCK_RMAX;   // delayed block moves: largest pending rank (0 = apply each move at once)
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -95,6 +96,9 @@ struct ggf_ctx {
   size_t *blk_doff = nullptr;
   int *blk_U = nullptr, *blk_r = nullptr;
   unsigned long long *blk_prop = nullptr, *blk_acc = nullptr;
+  // delayed block moves: the decision's move and its products with the pending moves
+  double *blk_E = nullptr, *blk_F = nullptr, *blk_Wn = nullptr;
+  int *blk_Un = nullptr, *blk_rn = nullptr, *blk_mode = nullptr;
 
   // delayed-update state (tied to the chains; with the block-move buffers): link changes of
   // the pending flips, window list counters
@@ -292,6 +296,8 @@ void free_chains(ggf_ctx *ctx) {
   ctx->blk_doff = nullptr;
   ctx->blk_U = ctx->blk_r = nullptr;
   ctx->blk_prop = ctx->blk_acc = nullptr;
+  ctx->blk_E = ctx->blk_F = ctx->blk_Wn = nullptr;
+  ctx->blk_Un = ctx->blk_rn = ctx->blk_mode = nullptr;
   ctx->n_chains = 0;
   ctx->chains.clear();
   ctx->G = ctx->F = nullptr;
@@ -539,8 +545,16 @@ ggf_status block_buffers(ggf_ctx *ctx) {
   ctx->blk_doff = dalloc<size_t>(ctx, ctx->n_chains, e);
   ctx->blk_U = dalloc<int>(ctx, static_cast<size_t>(GGF_BLOCK_RMAX) * ctx->n_chains, e);
   ctx->blk_r = dalloc<int>(ctx, ctx->n_chains, e);
-  ctx->blk_prop = dalloc<unsigned long long>(ctx, 3 * static_cast<size_t>(ctx->n_chains), e);   // proposed, accepted, links
+  // proposed, accepted, links changed, updates of G
+  ctx->blk_prop = dalloc<unsigned long long>(ctx, 4 * static_cast<size_t>(ctx->n_chains), e);
   ctx->blk_acc = ctx->blk_prop;
+  const size_t er = static_cast<size_t>(GGF_BLOCK_RMAX + 4 * (GGF_KMAX_DEV - 1)) * GGF_BLOCK_RMAX;
+  ctx->blk_E = dalloc<double>(ctx, er * ctx->n_chains, e);
+  ctx->blk_F = dalloc<double>(ctx, er * ctx->n_chains, e);
+  ctx->blk_Wn = dalloc<double>(ctx, rr * ctx->n_chains, e);
+  ctx->blk_Un = dalloc<int>(ctx, static_cast<size_t>(GGF_BLOCK_RMAX) * ctx->n_chains, e);
+  ctx->blk_rn = dalloc<int>(ctx, ctx->n_chains, e);
+  ctx->blk_mode = dalloc<int>(ctx, ctx->n_chains, e);
   for (void **dst : {&ctx->blk_D}) {
     if (e != hipSuccess) break;
     void *p = nullptr;
@@ -1904,6 +1918,10 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
   else if (k == "time_update") ctx->opt_time_update = value != 0;
   else if (k == "update_nt") ctx->opt_update_nt = value != 0;
   else if (k == "flush_grid") ctx->opt_flush_grid = static_cast<int>(std::min<int64_t>(value, 1 << 20));
+  else if (k == "block_pend") {
+    if (value > GGF_BLOCK_RMAX) return fail(ctx, GGF_EINVAL, "block_pend must be in 0..128");
+    ctx->opt_block_pend = static_cast<int>(value);
+  }
   else if (k == "balance") {
     if (value > 1) return fail(ctx, GGF_EINVAL, "balance must be 0 or 1");
     if (ctx->n_chains > 0 && !ctx->opt_balance && value) {
@@ -2235,21 +2253,33 @@ ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   bl.bprop = ctx->blk_prop;
   bl.bacc = ctx->blk_acc;
   bl.kmax = ctx->kmax;
+  bl.pend = ctx->opt_block_pend;
+  bl.E = ctx->blk_E;
+  bl.Fm = ctx->blk_F;
+  bl.Wn = ctx->blk_Wn;
+  bl.Un = ctx->blk_Un;
+  bl.rn = ctx->blk_rn;
+  bl.mode = ctx->blk_mode;
+  const bool pend = bl.pend > 0;
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 1024;
   const bool timed = ctx->opt_time_update != 0;
   ctx->last_update_ms = 0.0;
   ctx->last_launches = 0;
   ctx->last_flips = 0;
-  if (timed && ctx->tev.size() < static_cast<size_t>(2 * max_np)) {
+  const int nupd = max_np + (pend ? 1 : 0);   // update launches per sweep
+  if (timed && ctx->tev.size() < static_cast<size_t>(2 * nupd)) {
     for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
-    ctx->tev.assign(2 * max_np, nullptr);
+    ctx->tev.assign(2 * nupd, nullptr);
     for (auto &ev : ctx->tev) HIP_TRY(ctx, hipEventCreate(&ev));
   }
   std::vector<unsigned long long> chg0;
   if (timed) {
-    chg0.resize(3 * static_cast<size_t>(ctx->n_chains));
+    chg0.resize(4 * static_cast<size_t>(ctx->n_chains));
     HIP_TRY(ctx, hipMemcpy(chg0.data(), ctx->blk_prop, chg0.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
   }
+  // a block sweep starts and ends without pending moves (the delayed single-link updates
+  // share U and rcnt)
+  if (pend) ggf_block_pending_launch(bl, false, s);
   for (int sw = 0; sw < n_sweeps; ++sw) {
     for (int p = 0; p < max_np; ++p) {
       bl.patch = p;
@@ -2257,41 +2287,51 @@ ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
       ggf_block_decide_launch(bl, s);
       if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * p], s));
       ggf_block_update_launch(bl, grid, s);
+      if (pend) ggf_block_merge_launch(bl, s);
       if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * p + 1], s));
+    }
+    if (pend && max_np > 0) {
+      // apply every pending move; the last decision cleared counter max_np & 1
+      bl.parity = max_np & 1;
+      ggf_block_pending_launch(bl, true, s);
+      if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * max_np], s));
+      ggf_block_update_launch(bl, grid, s);
+      if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2 * max_np + 1], s));
+      ggf_block_pending_launch(bl, false, s);
     }
     ggf_launch_end_sweep(bl.lc);
     HIP_TRY(ctx, hipGetLastError());
     if (timed) {
       HIP_TRY(ctx, hipStreamSynchronize(s));
-      for (int p = 0; p < max_np; ++p) {
+      for (int p = 0; p < nupd; ++p) {
         float ms = 0.f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[2 * p], ctx->tev[2 * p + 1]));
         ctx->last_update_ms += ms;
       }
-      ctx->last_launches += max_np;
+      ctx->last_launches += nupd;
     }
     if ((st = after_sweep(ctx, s)) != GGF_OK) return st;
   }
   if (timed) {
     std::vector<unsigned long long> chg1(chg0.size());
     HIP_TRY(ctx, hipMemcpy(chg1.data(), ctx->blk_prop, chg1.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-    for (int c = 0; c < ctx->n_chains; ++c) ctx->last_flips += static_cast<long long>(chg1[3 * c + 2] - chg0[3 * c + 2]);
+    for (int c = 0; c < ctx->n_chains; ++c) ctx->last_flips += static_cast<long long>(chg1[4 * c + 2] - chg0[4 * c + 2]);
   }
   return GGF_OK;
 }
 
 ggf_status ggf_block_stats(ggf_ctx *ctx, int32_t chain, uint64_t *proposals, uint64_t *accepts,
-                           uint64_t *links_changed) {
+                           uint64_t *links_changed, uint64_t *updates) {
   if (!ctx) return GGF_EINVAL;
   if (chain < 0 || chain >= ctx->n_chains) return fail(ctx, GGF_EINVAL, "chain index out of range");
   HIP_TRY(ctx, hipDeviceSynchronize());
-  uint64_t v[3] = {0, 0, 0};
+  uint64_t v[4] = {0, 0, 0, 0};
   if (ctx->blk_prop)
-    for (int q = 0; q < 3; ++q)
-      HIP_TRY(ctx, hipMemcpy(&v[q], ctx->blk_prop + 3 * chain + q, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(v, ctx->blk_prop + 4 * chain, sizeof(v), hipMemcpyDeviceToHost));
   if (proposals) *proposals = v[0];
   if (accepts) *accepts = v[1];
   if (links_changed) *links_changed = v[2];
+  if (updates) *updates = v[3];
   return GGF_OK;
 }
 

@@ -24,8 +24,13 @@ struct BlockLaunch {
   void *D;
   const size_t *d_off;
   int *U, *rcnt;
-  unsigned long long *bprop, *bacc;
+  unsigned long long *bprop, *bacc;   // per chain: proposed, accepted, links changed, updates of G
   int patch, parity, kmax;
+  // delayed block moves: largest pending rank (0 = apply each accepted move at once) and the
+  // decision's move (Wn, Un, rn, mode) with its pending-move products (E, Fm)
+  int pend;
+  double *E, *Fm, *Wn;
+  int *Un, *rn, *mode;
 };
 
 void ggf_nn_forward_launch(const NNArgs &a, const int *ex_chain, const int *ex_patch, int n_ex, float *logits,
@@ -38,3 +43,5 @@ void ggf_nn_examples_launch(int *ex_chain, int *ex_patch, int n_ex, uint32_t t, 
                             int npatch, hipStream_t s);
 void ggf_block_decide_launch(const BlockLaunch &bl, hipStream_t s);
 void ggf_block_update_launch(const BlockLaunch &bl, int grid, hipStream_t s);
+void ggf_block_merge_launch(const BlockLaunch &bl, hipStream_t s);
+void ggf_block_pending_launch(const BlockLaunch &bl, bool list, hipStream_t s);

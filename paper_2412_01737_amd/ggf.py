@@ -101,7 +101,8 @@ EXPORTS = {
                                     _dp, ctypes.c_void_p]),
     "ggf_block_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "ggf_block_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
-                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
     "ggf_stream_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_int32, ctypes.c_void_p]),
     "ggf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -398,10 +399,11 @@ class Context:
         self._check(self._lib.ggf_block_sweep(self.h, int(n_sweeps), _stream_ptr(stream)))
 
     def block_stats(self, chain: int):
-        """(proposed, accepted, links changed by accepted moves) of one chain's block moves."""
-        p, a, m = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-        self._check(self._lib.ggf_block_stats(self.h, int(chain), ctypes.byref(p), ctypes.byref(a), ctypes.byref(m)))
-        return p.value, a.value, m.value
+        """(proposed, accepted, links changed by accepted moves, updates of G) of one chain's block moves."""
+        p, a, m, u = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._lib.ggf_block_stats(self.h, int(chain), ctypes.byref(p), ctypes.byref(a), ctypes.byref(m),
+                                              ctypes.byref(u)))
+        return p.value, a.value, m.value, u.value
 
     def autotune(self, sweeps_per_candidate: int = 1, cache_path: str | None = None, stream=None):
         """Choose the launch shapes of the path that runs on live sweeps: (flush_grid, window, 0) with

@@ -131,6 +131,60 @@ def test_block_moves_bit_exact(L, P, K, mix, bias, init):
     assert props > 0 and accs > 0
 
 
+@pytest.mark.parametrize("L,P,K,bias,pend,init", [
+    (8, 4, 2, 0.0, 128, 1),   # about 16 of 32 links change: pairs of moves merge or overflow the capacity
+    (8, 4, 1, -1.5, 128, 0),  # ranks ~24: several moves per update of G
+    (8, 2, 1, -0.5, 24, 1),   # capacity below some single moves
+    (6, 2, 2, 0.0, 64, 1),    # n = 288: ragged update tiles
+])
+def test_block_moves_delayed_equal_immediate(L, P, K, bias, pend, init):
+    """Delayed block moves (pending moves combined into one update of G, each decision on G_cur)
+    against immediate ones and the oracle's definitional moves: the same decisions after every
+    sweep, log W, S and G within float64 tolerance of each other and of the definitions, and
+    fewer updates of G than accepted moves."""
+    say(f"delayed block moves L={L} P={P} K={K} bias={bias} block_pend={pend}")
+    spec = synth.make_tensor(2, K=K)
+    ctxs = []
+    for pv in (0, pend):
+        ctx = gpu_context([spec], [L] * 3, init=init)
+        ctx.set_option("block_pend", pv)
+        ctx.nn_init(P, 21)
+        p = _params(13, 0.02)
+        p[-2:] = bias
+        params = ctx.nn_params(p)
+        ctxs.append(ctx)
+    orc = [oracle_chain(spec, L, c, init=init)[1] for c in range(3)]
+    for s in range(3):
+        for ctx in ctxs:
+            ctx.block_sweep(1)
+        for oc in orc:
+            # K > 1: the patch-lemma weight (decisions equal the definition's, test_block_move_routes_agree)
+            block_sweep(oc, params, P, route="patch" if K > 1 else "def")
+        for c, oc in enumerate(orc):
+            for ctx in ctxs:
+                assert np.array_equal(ctx.get_state(c)[0], oc.k), (s, c)
+    an = ansatz_for(spec, L)
+    imm, dly = ctxs
+    for c in range(3):
+        links, info = dly.get_state(c)
+        info0 = imm.get_state(c)[1]
+        assert abs(info["logw"] - an.log_weight(links)) < 1e-9 * abs(info["logw"])
+        assert abs(info["logw"] - info0["logw"]) < 1e-10 * abs(info["logw"])
+        Gt = np.linalg.inv(an.assemble_M(links))
+        G1 = dly.get_inverse(c)
+        assert np.abs(G1 - Gt).max() < 1e-9 * np.abs(Gt).max()
+        assert np.abs(G1 - imm.get_inverse(c)).max() < 1e-10 * np.abs(Gt).max()
+        if K > 1:
+            assert abs(info["s_re"] - an.s_factor_def(links).real) < 1e-8 * abs(info["s_re"])
+            assert abs(info["s_re"] - info0["s_re"]) < 1e-10 * abs(info["s_re"])
+    st0 = np.array([imm.block_stats(c) for c in range(3)])
+    st1 = np.array([dly.block_stats(c) for c in range(3)])
+    assert np.array_equal(st0[:, :3], st1[:, :3])
+    assert np.array_equal(st0[:, 3], st0[:, 1])              # immediate: one update per accepted move
+    assert st1[:, 1].sum() > 0 and st1[:, 3].sum() < st1[:, 1].sum()
+    say(f"accepted moves {st1[:, 1].tolist()}, updates of G {st1[:, 3].tolist()}")
+
+
 def test_block_moves_fp32_with_refresh():
     """Float32 inverse, matrix-core float32 block updates, float64 refactorisation every 8 changed links."""
     say("block moves fp32 L=12 P=4 K=2")
