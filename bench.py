@@ -634,6 +634,8 @@ def run_c5(args):
         ctx.set_option("delay", args.delay)
         if args.block_pend >= 0:
             ctx.set_option("block_pend", args.block_pend)
+        if args.update_grid:
+            ctx.set_option("update_grid", args.update_grid)
         tid = ctx.set_tensor_spec(spec)
         ti = time.perf_counter()
         ctx.init_chains([L] * chains, tid, synth.SEED_CHAIN, init=1, precision=precision,
