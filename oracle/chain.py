@@ -173,13 +173,18 @@ class WoodburyChain:
         return self.an.observables(self.k)
 
 
-def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "def"):
+def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "def", rho: float = 1.0):
     """One Metropolis-Hastings block move on a P x P patch (Z2), learned proposal.
 
     The proposal resamples the patch links from the network's factorised
     Bernoulli q(.|context) (logits from the float32 forward pass, uniforms
     from Philox at (chain, sweep, patch, 3 + j)); it is accepted iff
     u < N(G') q(x|ctx) / (N(G) q(x'|ctx)) with u from (chain, sweep, patch, 2).
+    With a move rate rho < 1 each patch link keeps its value with probability
+    1 - rho and is otherwise drawn from q(.|context) (link j becomes 1 iff its
+    uniform is below (1 - rho) x_j + rho sigmoid(z_j)), and the ratio uses the
+    proposal densities q(x|x', ctx) / q(x'|x, ctx) by their definition.  The
+    context masks the patch, so q does not depend on the patch links.
     N is evaluated from scratch for both configurations: W from a fresh
     determinant and, for K > 1, N/W = sum_nm c_n^* c_m <B_m|B_n> Pf(M_nm)/Pf(M_00)
     (Sec. 5) -- with ``route="def"`` from full Pfaffians of every M_nm (the
@@ -200,7 +205,7 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "de
     zl = nn.logits_patch_order(z).astype(np.float64)
     u_acc, u = nn.draw_block(ch.seed, ch.chain, ch.sweep_idx, patch, len(pl))
     y_old = ch.k[pl].astype(np.float64)
-    y_new = (u < nn.sigmoid(zl)).astype(np.float64)
+    y_new = (u < nn.propose_p1(zl, y_old, rho)).astype(np.float64)
     m = int(np.sum(y_new != y_old))
     if m == 0:
         return False, False, 0
@@ -221,7 +226,11 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "de
         g_ss = scipy.linalg.lu_solve((lu, piv), E)[an.S, :]
         return lw + np.log(an.s_factor_patch(g_ss, k).real)
 
-    R = np.exp(log_n(k_new) - log_n(ch.k) + nn.log_q(zl, y_old) - nn.log_q(zl, y_new))
+    if rho == 1.0:
+        log_qr = nn.log_q(zl, y_old) - nn.log_q(zl, y_new)
+    else:
+        log_qr = nn.log_q_move(zl, y_old, y_new, rho) - nn.log_q_move(zl, y_new, y_old, rho)
+    R = np.exp(log_n(k_new) - log_n(ch.k) + log_qr)
     ch.ties += near_tie(u_acc, R)
     if u_acc < R:
         ch.k = k_new
@@ -230,12 +239,12 @@ def block_move(ch: "WoodburyChain", params, P: int, patch: int, route: str = "de
     return True, False, m
 
 
-def block_sweep(ch: "WoodburyChain", params, P: int, route: str = "def"):
+def block_sweep(ch: "WoodburyChain", params, P: int, route: str = "def", rho: float = 1.0):
     """Block moves on every patch in order, then the sweep counter advances (shared with link sweeps)."""
     L = ch.an.lat.Lx
     stats = [0, 0]
     for p in range((L // P) ** 2):
-        prop, acc, _ = block_move(ch, params, P, p, route)
+        prop, acc, _ = block_move(ch, params, P, p, route, rho)
         stats[0] += prop
         stats[1] += acc
     ch.sweep_idx += 1

@@ -203,6 +203,23 @@ def log_q(z: np.ndarray, y: np.ndarray) -> float:
     return -bce_loss(z, y)
 
 
+def propose_p1(z: np.ndarray, y_from: np.ndarray, rho: float) -> np.ndarray:
+    """Probability that each patch link is 1 after a proposal with move rate rho: a link keeps its
+    value with probability 1 - rho and is otherwise drawn from q(.|context), so
+    P(y'_l = 1) = (1 - rho) y_l + rho sigmoid(z_l); rho = 1 is the factorised proposal q(.|context)."""
+    return (1.0 - rho) * np.asarray(y_from, np.float64) + rho * sigmoid(z)
+
+
+def log_q_move(z: np.ndarray, y_to: np.ndarray, y_from: np.ndarray, rho: float) -> float:
+    """log q(y_to | y_from, context) of the proposal with move rate rho (see propose_p1), by its
+    definition: sum over the patch links of log((1 - rho) [y_to = y_from] + rho q(y_to | context))."""
+    s = sigmoid(z)
+    y_to = np.asarray(y_to, np.float64)
+    q_to = np.where(y_to == 1.0, s, 1.0 - s)
+    same = (y_to == np.asarray(y_from, np.float64)).astype(np.float64)
+    return float(np.sum(np.log((1.0 - rho) * same + rho * q_to)))
+
+
 def draw_block(seed: int, chain: int, sweep: int, patch: int, n_links: int):
     """(u_accept, u_links) for a block move: accept word pair at counter (chain, sweep, patch, 2),
     link j's uniform (x + 1/2) 2^-32 from word j mod 4 of counter (chain, sweep, patch, 3 + j div 4)."""

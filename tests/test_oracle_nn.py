@@ -6,8 +6,9 @@
   do not either, window links do;
 * bf16 rounding and the Adam step against closed forms;
 * exact stationarity of the block-MH transition matrix on the 2x2 lattice
-  (p(G) from exhaustive enumeration is invariant under one patch move);
-* a long block-move chain reproduces exhaustive enumeration.
+  (p(G) from exhaustive enumeration is invariant under one patch move), also
+  with a move rate rho < 1, whose draw rule is checked against its density;
+* a long block-move chain reproduces exhaustive enumeration (rho = 1 and 1/2).
 """
 import itertools
 
@@ -115,6 +116,40 @@ def test_adam_first_step():
     assert np.abs(p1 - expect).max() < 1e-6
 
 
+def _exact_transition_rho(an, params, P, patch, weights, rho):
+    """Transition matrix of one block move with move rate rho, its proposal probabilities taken from
+    the oracle's draw rule (link l becomes 1 with probability propose_p1) and its acceptance from the
+    oracle's proposal densities log_q_move; also checks that the two agree."""
+    L = an.lat.Lx
+    n_links = an.lat.n_links
+    states = list(itertools.product(range(2), repeat=n_links))
+    index = {s: i for i, s in enumerate(states)}
+    T = np.zeros((len(states), len(states)))
+    pl = nn.patch_links(L, P, patch)
+    for i, s in enumerate(states):
+        k = np.array(s, np.int8)
+        z, _ = nn.forward(params, nn.window(k, L, P, patch), np.float32)
+        zl = nn.logits_patch_order(z).astype(np.float64)
+        y_old = k[pl].astype(float)
+        p1 = nn.propose_p1(zl, y_old, rho)
+        stay = 1.0
+        for ynew in itertools.product(range(2), repeat=len(pl)):
+            ynew = np.array(ynew, float)
+            q = float(np.prod(np.where(ynew == 1.0, p1, 1.0 - p1)))
+            assert abs(q - np.exp(nn.log_q_move(zl, ynew, y_old, rho))) < 1e-14
+            if np.array_equal(ynew, y_old):
+                continue
+            k2 = k.copy()
+            k2[pl] = ynew.astype(np.int8)
+            j = index[tuple(k2)]
+            back = np.exp(nn.log_q_move(zl, y_old, ynew, rho))
+            a = min(1.0, weights[j] * back / (weights[i] * q))
+            T[i, j] = q * a
+            stay -= q * a
+        T[i, i] = stay
+    return T
+
+
 def _exact_transition(an, params, P, patch, weights):
     """Transition matrix of one block move on `patch` over all configurations (Z2, small lattice)."""
     L = an.lat.Lx
@@ -158,8 +193,38 @@ def test_block_move_exact_stationarity_2x2():
         assert np.abs(pi @ T - pi).max() < 1e-14
 
 
+@pytest.mark.parametrize("rho", [0.5, 0.125])
+def test_block_move_rate_exact_stationarity_2x2(rho):
+    """Move rate rho < 1 (each patch link kept with probability 1 - rho): the oracle's draw rule
+    and its proposal density agree, and the block-MH transition matrix leaves p(G) invariant, on
+    2x2 with P = 1 (one link per patch) and P = 2 (every link of the lattice in one patch)."""
+    lat = Lattice(2, 2)
+    spec = synth.make_tensor(2)
+    an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, 2)
+    w = np.array([an.weight(np.array(s, np.int8)) for s in itertools.product(range(2), repeat=8)])
+    pi = w / w.sum()
+    params = nn.init_params(5)
+    params[-2:] = [0.4, -0.7]
+    for P, patches in ((1, range(4)), (2, range(1))):
+        for patch in patches:
+            T = _exact_transition_rho(an, params, P, patch, w, rho)
+            assert np.abs(T.sum(1) - 1).max() < 1e-12
+            assert np.abs(pi @ T - pi).max() < 1e-14
+
+
+def test_block_move_rate_one_is_the_factorised_proposal():
+    rng = np.random.default_rng(3)
+    z = rng.standard_normal(32)
+    y0 = (rng.random(32) < 0.5).astype(float)
+    y1 = (rng.random(32) < 0.5).astype(float)
+    assert np.array_equal(nn.propose_p1(z, y0, 1.0), nn.sigmoid(z))
+    a = nn.log_q_move(z, y0, y1, 1.0) - nn.log_q_move(z, y1, y0, 1.0)
+    assert abs(a - (nn.log_q(z, y0) - nn.log_q(z, y1))) < 1e-12
+
+
 @pytest.mark.slow
-def test_block_chain_matches_enumeration_2x2():
+@pytest.mark.parametrize("rho", [1.0, 0.5])
+def test_block_chain_matches_enumeration_2x2(rho):
     lat = Lattice(2, 2)
     spec = synth.make_tensor(2)
     an = Ansatz(lat, spec.gamma_loc, spec.gamma_bond, 2)
@@ -171,7 +236,7 @@ def test_block_chain_matches_enumeration_2x2():
     series = []
     acc = [0, 0]
     for _ in range(3000):
-        st = block_sweep(ch, params, 1)
+        st = block_sweep(ch, params, 1, rho=rho)
         acc[0] += st[0]
         acc[1] += st[1]
         series.append(an.plaquette(ch.k))
