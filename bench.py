@@ -560,6 +560,7 @@ def _cpu_baseline_c5(args, budget_s, c5, info):
 NN_SEED = 7
 BETAS = (0.0, 0.25, 0.5, 0.75, 1.0)     # candidate scales of the network's output layer
 N_LAST = 2 * 32 * 9 + 2                 # output layer: W4 [2][32][3][3] and b4 [2], the last parameters
+RHOS = (1.0, 0.5, 0.25, 0.125)         # candidate move rates of the block proposal
 MFMA_PEAK_F32_TFLOPS = 157.3
 
 
@@ -573,8 +574,11 @@ def run_c5(args):
        Metropolis-Hastings block move on every patch, float32 inverse with a
        float64 refactorisation every --refresh changed links (charged at its
        true rate); the plaquette and the density are measured after every sweep.
+       The output scale, then the move rate, are chosen on the training chains
+       (the most changed links of accepted moves per block sweep).
     3. The same block moves with an untrained network (all weights and biases
-       zero: every patch link proposed with probability 1/2), same chains.
+       zero: every patch link proposed with probability 1/2, move rate 1), same
+       chains.
     4. The plain float64 single-link sampler on the same GPU (--plain-chains
        chains, delayed updates, no refactorisation: its drift is negligible,
        --plain-steps sweeps), measured the same way.
@@ -623,16 +627,33 @@ def run_c5(args):
         scale_trials.append({"beta": beta, "acceptance": float(d[:, 1].sum() / max(1, d[:, 0].sum())),
                              "accepted_links_per_sweep": float(d[:, 2].sum() / 2.0 / args.train_chains)})
         log(f"c5 proposal scale {beta}: {scale_trials[-1]}")
-    beta = max(scale_trials, key=lambda t: t["accepted_links_per_sweep"])["beta"]
+    best = max(scale_trials, key=lambda t: t["accepted_links_per_sweep"])
+    beta = best["beta"]
     params = trained.copy()
     params[-N_LAST:] *= beta
+    # then the move rate at that scale (rho = 1 redraws every patch link; rho < 1 keeps each with
+    # probability 1 - rho), chosen the same way
+    tr.nn_params(params)
+    rate_trials = [{"rho": 1.0, "acceptance": best["acceptance"],
+                    "accepted_links_per_sweep": best["accepted_links_per_sweep"]}]
+    for rho in RHOS[1:]:
+        tr.set_option("block_rho", int(round(rho * 65536)))
+        st0 = np.array([tr.block_stats(c) for c in range(args.train_chains)])
+        tr.block_sweep(2, stream=stream)
+        st1 = np.array([tr.block_stats(c) for c in range(args.train_chains)])
+        d = st1 - st0
+        rate_trials.append({"rho": rho, "acceptance": float(d[:, 1].sum() / max(1, d[:, 0].sum())),
+                            "accepted_links_per_sweep": float(d[:, 2].sum() / 2.0 / args.train_chains)})
+        log(f"c5 move rate {rho}: {rate_trials[-1]}")
+    rho_best = max(rate_trials, key=lambda t: t["accepted_links_per_sweep"])["rho"]
     tr.close()
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
-    def sampler(name, chains, precision, refresh, net, steps, warmup):
+    def sampler(name, chains, precision, refresh, net, steps, warmup, rho=1.0):
         ctx = Context(0)
         ctx.set_option("delay", args.delay)
+        ctx.set_option("block_rho", int(round(rho * 65536)))
         if args.block_pend >= 0:
             ctx.set_option("block_pend", args.block_pend)
         if args.update_grid:
@@ -737,7 +758,8 @@ def run_c5(args):
         torch.cuda.synchronize()
         return rec
 
-    learned = sampler("learned", args.chains, args.precision, args.refresh, params, args.steps, args.warmup)
+    learned = sampler("learned", args.chains, args.precision, args.refresh, params, args.steps, args.warmup,
+                      rho=rho_best)
     untrained = (sampler("untrained", args.chains, args.precision, args.refresh, np.zeros(nparams, np.float32),
                          args.steps, args.warmup) if args.untrained else None)
     # the float64 comparison leg needs no refactorisation over its sweeps (float64 Woodbury
@@ -798,7 +820,8 @@ def run_c5(args):
         "ess_ratio_learned_vs_untrained": ratio(learned, untrained),
         "training": {"chains": args.train_chains, "sweeps": args.train_sweeps, "adam_steps_per_sweep": args.train_steps,
                      "loss_nats_per_patch": losses, "uniform_loss_nats_per_patch": 32 * float(np.log(2.0)),
-                     "output_scale_trials": scale_trials, "output_scale": beta, "seconds": t_train},
+                     "output_scale_trials": scale_trials, "output_scale": beta,
+                     "move_rate_trials": rate_trials, "move_rate": rho_best, "seconds": t_train},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_window_snap + k_window_gemm (block moves)",

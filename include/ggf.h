@@ -346,6 +346,11 @@ ggf_status ggf_refresh_all(ggf_ctx *ctx, void *stream);
  *   "block_pend"   block sweeps: largest combined rank of accepted block moves kept pending
  *                  and applied to G together, 0 .. 128 (default 128; 0 = each accepted move
  *                  updates G at once)
+ *   "block_rho"    move rate rho of the block proposal in units of 1/65536, 1 .. 65536 (default
+ *                  65536, rho = 1): each patch link keeps its value with probability 1 - rho and
+ *                  is otherwise drawn from the network's conditional; link l becomes 1 iff its
+ *                  uniform u_l < (1 - rho) y_l + rho sigmoid(z_l), and the acceptance uses the
+ *                  proposal densities of this rule
  *   "balance"      1 = balanced sweeps for batches of different lattice sizes: a ggf_sweep sweep
  *                  is max_links link steps at each of which every chain proposes its own next link
  *                  (a per-chain cursor), so a chain with fewer links completes several of its own

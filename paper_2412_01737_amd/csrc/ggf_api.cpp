@@ -75,6 +75,7 @@ struct ggf_ctx {
   int opt_flush_grid = 0;        // workgroups of the window flush (0 = library default)
   int opt_balance = 0;           // 1: balanced sweeps (every chain steps its own link cursor at every link step)
   int opt_block_pend = GGF_BLOCK_RMAX;   // delayed block moves: largest pending rank (0 = apply each move at once)
+  int opt_block_rho = 65536;     // move rate of the block proposal in units of 1/65536
   long long opt_scratch_mb = 0;
 
   // graph replay
@@ -1921,6 +1922,9 @@ ggf_status ggf_set_option(ggf_ctx *ctx, const char *key, int64_t value) {
   else if (k == "block_pend") {
     if (value > GGF_BLOCK_RMAX) return fail(ctx, GGF_EINVAL, "block_pend must be in 0..128");
     ctx->opt_block_pend = static_cast<int>(value);
+  } else if (k == "block_rho") {
+    if (value < 1 || value > 65536) return fail(ctx, GGF_EINVAL, "block_rho must be in 1..65536 (units of 1/65536)");
+    ctx->opt_block_rho = static_cast<int>(value);
   }
   else if (k == "balance") {
     if (value > 1) return fail(ctx, GGF_EINVAL, "balance must be 0 or 1");
@@ -2260,6 +2264,7 @@ ggf_status ggf_block_sweep(ggf_ctx *ctx, int32_t n_sweeps, void *stream) {
   bl.Un = ctx->blk_Un;
   bl.rn = ctx->blk_rn;
   bl.mode = ctx->blk_mode;
+  bl.rho = ctx->opt_block_rho / 65536.0;
   const bool pend = bl.pend > 0;
   const int grid = ctx->opt_update_grid > 0 ? ctx->opt_update_grid : 1024;
   const bool timed = ctx->opt_time_update != 0;

@@ -31,6 +31,7 @@ struct BlockLaunch {
   int pend;
   double *E, *Fm, *Wn;
   int *Un, *rn, *mode;
+  double rho;                  // move rate of the proposal
 };
 
 void ggf_nn_forward_launch(const NNArgs &a, const int *ex_chain, const int *ex_patch, int n_ex, float *logits,

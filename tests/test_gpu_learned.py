@@ -185,6 +185,45 @@ def test_block_moves_delayed_equal_immediate(L, P, K, bias, pend, init):
     say(f"accepted moves {st1[:, 1].tolist()}, updates of G {st1[:, 3].tolist()}")
 
 
+@pytest.mark.parametrize("L,P,K,bias,rho,pend,init", [
+    (8, 4, 1, 0.0, 0.25, 128, 0),     # about 4 of 32 patch links redrawn per move, delayed moves
+    (8, 2, 2, 0.0, 0.5, 128, 1),
+    (6, 2, 1, 0.5, 0.125, 0, 1),      # n = 288 (ragged tiles), each move applied at once
+])
+def test_block_moves_move_rate_bit_exact(L, P, K, bias, rho, pend, init):
+    """Move rate rho < 1 (option block_rho): decisions against the oracle's block moves with the same
+    rate after every sweep; log W, S and G within float64 tolerance of the definitions."""
+    say(f"block moves with move rate {rho}: L={L} P={P} K={K} bias={bias} block_pend={pend}")
+    spec = synth.make_tensor(2, K=K)
+    ctx = gpu_context([spec], [L] * 2, init=init)
+    ctx.set_option("block_pend", pend)
+    ctx.set_option("block_rho", int(rho * 65536))
+    ctx.nn_init(P, 21)
+    p = _params(13, 0.02)
+    p[-2:] = bias
+    params = ctx.nn_params(p)
+    orc = [oracle_chain(spec, L, c, init=init)[1] for c in range(2)]
+    for s in range(3):
+        ctx.block_sweep(1)
+        for oc in orc:
+            block_sweep(oc, params, P, route="patch" if K > 1 else "def", rho=rho)
+        for c, oc in enumerate(orc):
+            links, info = ctx.get_state(c)
+            assert np.array_equal(links, oc.k), (s, c)
+            assert info["sweeps"] == oc.sweep_idx
+    an = ansatz_for(spec, L)
+    for c in range(2):
+        links, info = ctx.get_state(c)
+        assert abs(info["logw"] - an.log_weight(links)) < 1e-9 * abs(info["logw"])
+        Gt = np.linalg.inv(an.assemble_M(links))
+        assert np.abs(ctx.get_inverse(c) - Gt).max() < 1e-9 * np.abs(Gt).max()
+        if K > 1:
+            assert abs(info["s_re"] - an.s_factor_def(links).real) < 1e-8 * abs(info["s_re"])
+    st = np.array([ctx.block_stats(c) for c in range(2)])
+    say(f"proposed {st[:, 0].tolist()}, accepted {st[:, 1].tolist()}, links changed {st[:, 2].tolist()}")
+    assert st[:, 1].sum() > 0
+
+
 def test_block_moves_fp32_with_refresh():
     """Float32 inverse, matrix-core float32 block updates, float64 refactorisation every 8 changed links."""
     say("block moves fp32 L=12 P=4 K=2")
@@ -258,10 +297,11 @@ def test_trained_network_gain_over_untrained(L, K, tensor_seed, precision):
     equal patch size and chain count: acceptance, links changed per accepted move and effective samples
     of the plaquette per block sweep (spread of the chain means), for the trained network as trained
     (output scale 1) and with its output layer scaled by the beta in {0, 1/4, 1/2, 3/4, 1} that changes
-    the most links per block sweep on the training chains (adapted during burn-in, then frozen; beta = 0
-    is the uniform proposal).  The gain is measured and reported; the test asserts that training lowered
-    the cross-entropy of the patch conditional, that the chosen scale changes at least as many links per
-    sweep on the training chains as the uniform proposal, and that every sampler moves."""
+    the most links per block sweep on the training chains, then the move rate rho in {1, 1/2, 1/4, 1/8}
+    chosen the same way (adapted during burn-in, then frozen; beta = 0 is the uniform proposal, which is
+    also run with its own best rate).  The gain is measured and reported; the test asserts that training
+    lowered the cross-entropy of the patch conditional, that each chosen setting changes at least as many
+    links per sweep on the training chains as the one it was chosen over, and that every sampler moves."""
     from oracle.stats import tau_int_chains
     P, nc, sweeps, n_last = 4, 128, 24, 2 * 32 * 9 + 2
     spec = synth.make_tensor(L, K=K, seed_tensor=tensor_seed)
@@ -274,21 +314,32 @@ def test_trained_network_gain_over_untrained(L, K, tensor_seed, precision):
         tr.nn_train(40, 256, 3e-3, 99 + s)
     loss1 = tr.nn_grad(list(range(64)), [0] * 64)[0]
     trained = tr.nn_params()
-    trials = {}
-    for beta in (0.0, 0.25, 0.5, 0.75, 1.0):
-        p = trained.copy()
-        p[-n_last:] *= beta
-        tr.nn_params(p)
+    def links_per_sweep(params, rho):
+        tr.nn_params(params)
+        tr.set_option("block_rho", int(rho * 65536))
         st0 = np.array([tr.block_stats(c) for c in range(64)])
         tr.block_sweep(2)
-        trials[beta] = (np.array([tr.block_stats(c) for c in range(64)]) - st0)[:, 2].sum() / 128.0
-    tr.close()
+        return (np.array([tr.block_stats(c) for c in range(64)]) - st0)[:, 2].sum() / 128.0
+
+    def scaled(beta):
+        p = trained.copy()
+        p[-n_last:] *= beta
+        return p
+
+    trials = {beta: links_per_sweep(scaled(beta), 1.0) for beta in (0.0, 0.25, 0.5, 0.75, 1.0)}
     beta = max(trials, key=trials.get)
-    tuned = trained.copy()
-    tuned[-n_last:] *= beta
+    rates = {1.0: trials[beta]}
+    rates.update({rho: links_per_sweep(scaled(beta), rho) for rho in (0.5, 0.25, 0.125)})
+    rho = max(rates, key=rates.get)
+    urates = {1.0: trials[0.0]}
+    urates.update({r: links_per_sweep(scaled(0.0), r) for r in (0.5, 0.25, 0.125)})
+    urho = max(urates, key=urates.get)
+    tr.close()
     res = {}
-    for name, params in (("trained", trained), ("tuned", tuned), ("untrained", np.zeros_like(trained))):
+    for name, params, r in (("trained", trained, 1.0), ("tuned", scaled(beta), rho),
+                            ("uniform tuned", scaled(0.0), urho), ("untrained", scaled(0.0), 1.0)):
         ctx = gpu_context([spec], [L] * nc, init=1, precision=precision, refresh_every=4096)
+        ctx.set_option("block_rho", int(r * 65536))
         ctx.nn_init(P, 3)
         ctx.nn_params(params)
         ctx.block_sweep(2)
@@ -307,13 +358,15 @@ def test_trained_network_gain_over_untrained(L, K, tensor_seed, precision):
     u = res["untrained"]
     msg = [f"L={L} K={K} tensor seed {tensor_seed}: cross-entropy {loss0:.3f} -> {loss1:.3f} nats/patch; "
            f"links per sweep on the training chains by beta {dict((b, round(v, 2)) for b, v in trials.items())}, "
-           f"chosen beta {beta}"]
+           f"chosen beta {beta}; by move rate at that beta {dict((q, round(v, 2)) for q, v in rates.items())}, "
+           f"chosen {rho}; uniform proposal by move rate {dict((q, round(v, 2)) for q, v in urates.items())}, "
+           f"chosen {urho}"]
     for name, r in res.items():
         msg.append(f"{name}: acceptance {r['acceptance']:.3f}, {r['links_per_move']:.2f} links/move, "
                    f"{r['ess_per_sweep']:.1f} ESS/sweep, tau {r['tau']:.2f}, "
                    f"gain x{r['ess_per_sweep'] / u['ess_per_sweep']:.2f}")
     say("; ".join(msg))
     assert loss1 < loss0
-    assert trials[beta] >= trials[0.0]
+    assert trials[beta] >= trials[0.0] and rates[rho] >= trials[beta] and urates[urho] >= trials[0.0]
     for r in res.values():
         assert r["acceptance"] > 0 and np.isfinite(r["ess_per_sweep"])
