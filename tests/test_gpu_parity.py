@@ -287,6 +287,12 @@ def test_invalid_inputs_rejected():
     for bad_delay in (12, 40, -2):
         with pytest.raises(GGFError):
             ctx.set_option("delay", bad_delay)
+    for key, bad in (("block_pend", 129), ("block_rho", 0), ("block_rho", 65537), ("no_such_option", 1)):
+        with pytest.raises(GGFError) as e:
+            ctx.set_option(key, bad)
+        assert e.value.status == GGF_EINVAL
+    ctx.set_option("block_pend", 0)
+    ctx.set_option("block_rho", 65536)
     ctx.init_chains([2], [tid], 1)
     ctx.sweep(0)
     with pytest.raises(GGFError):
