@@ -1003,13 +1003,18 @@ def run_plain(args, with_cpu=True):
     drift = float32_drift(ctx, stream) if args.precision == 32 else None
     refresh = refresh_correction(ctx, args, st0, stream, st1)
     kernel_sweeps = args.steps
+    kernel_flips = upd_flips                   # accepted flips of the sweeps whose kernels were timed
     if args.graph:
+        # graph replays are timed with host clocks; the kernels of two further eager sweeps with
+        # HIP events (their flips, not the timed sweeps', go with their launches)
         upd_flips_timed = sum(ctx.get_state(c)[1]["accepts"] for c in range(args.chains)) - acc0
         ctx.set_option("time_update", 1)
         kernel_sweeps = 2
+        upd_flips = 0
         for _ in range(kernel_sweeps):
             ctx.sweep(1, stream=stream)
             timings()
+        kernel_flips = upd_flips
         upd_flips = upd_flips_timed
     electric = electric_measurement(ctx, args, Lc, stream)
     energy = energy_measurement(ctx, args, stream)
@@ -1067,7 +1072,7 @@ def run_plain(args, with_cpu=True):
         bytes_per_launch = float((share * (nf_ * (nf_ + 1) / 2 + nf_ ** 2) * esz).sum())
         kernel = "k_window_flush"
     else:
-        bytes_per_launch = upd_flips * bytes_per_flip / max(upd_launches, 1)
+        bytes_per_launch = kernel_flips * bytes_per_flip / max(upd_launches, 1)
         kernel = "k_update"
     achieved = bytes_per_launch / (upd_ms / upd_launches * 1e-3) / 1e9 if upd_ms > 0 else 0.0
     traffic = None
@@ -1116,7 +1121,8 @@ def run_plain(args, with_cpu=True):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "update_ms_total": upd_ms, "update_launches": upd_launches, "flips": upd_flips},
+                     "update_ms_total": upd_ms, "update_launches": upd_launches, "flips": upd_flips,
+                     "kernel_timed_flips": kernel_flips},
         "kernels_ms_per_step": {kernel: upd_ms / kernel_sweeps, "k_ratio": rat_ms / kernel_sweeps},
         "timed_s": timed_s,
         "refresh": refresh,

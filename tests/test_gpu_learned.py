@@ -136,6 +136,7 @@ def test_block_moves_bit_exact(L, P, K, mix, bias, init):
     (8, 4, 1, -1.5, 128, 0),  # ranks ~24: several moves per update of G
     (8, 2, 1, -0.5, 24, 1),   # capacity below some single moves
     (6, 2, 2, 0.0, 64, 1),    # n = 288: ragged update tiles
+    (4, 2, 4, 0.0, 128, 1),   # K = 4: twelve patch Majoranas in the pending correction
 ])
 def test_block_moves_delayed_equal_immediate(L, P, K, bias, pend, init):
     """Delayed block moves (pending moves combined into one update of G, each decision on G_cur)
