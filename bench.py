@@ -101,7 +101,7 @@ def parse():
                          "workloads; --lambda-sweeps sweeps per round), reported under 'lambda_opt'")
     ap.add_argument("--lambda-sweeps", type=int, default=2)
     ap.add_argument("--gamma-iters", type=int, default=0,
-                    help="after the timed sweeps, rounds of gradient descent on Gamma_A (L <= 16 for K = 1, "
+                    help="after the timed sweeps, rounds of gradient descent on Gamma_A (L <= 32 for K = 1, "
                          "L <= 8 for K > 1; --lambda-sweeps sweeps per round, --gamma-step), reported under "
                          "'gamma_opt'")
     ap.add_argument("--gamma-step", type=float, default=0.01)
@@ -893,7 +893,7 @@ def energy_measurement(ctx, args, stream, reps=5):
     us = e0.elapsed_time(e1) * 1e3 / reps
     res = {"kernel": "k_energy", "bound": "latency", "us_per_launch": us, "couplings": BENCH_COUPLINGS,
            "mean_local_energy": float(out[:, 0].mean().item())}
-    if args.workload != "c4" and args.L <= (16 if args.K == 1 else 8):
+    if args.workload != "c4" and args.L <= (32 if args.K == 1 else 8):
         # sensitivities to the on-site covariance (gradient of <H> with respect to Gamma_A)
         from paper_2412_01737_amd.ggf import GGF_SENS_STRIDE, gamma_gradient
         sens = torch.zeros((args.chains, GGF_SENS_STRIDE), dtype=torch.float64, device=stream.device)
@@ -1030,7 +1030,7 @@ def run_plain(args, with_cpu=True):
                       "optimum_per_round": eo_.tolist(), "lambda_re": lam_.real.tolist(),
                       "lambda_im": lam_.imag.tolist(), "couplings": BENCH_COUPLINGS}
     gamma_opt = None
-    if args.gamma_iters > 0 and args.workload != "c4" and args.L <= (16 if args.K == 1 else 8):
+    if args.gamma_iters > 0 and args.workload != "c4" and args.L <= (32 if args.K == 1 else 8):
         torch.cuda.synchronize()
         t_opt = time.perf_counter()
         en_, gn_, _ = ctx.optimise_gamma(int(tids), BENCH_COUPLINGS, args.gamma_iters, args.lambda_sweeps,

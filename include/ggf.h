@@ -211,7 +211,7 @@ ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_coupli
 
 /* Sensitivities of every chain's local energy and log N(G) to the on-site
  * covariance Gamma_A (gradient descent on Gamma_A, the outlook of Sec. 6.3;
- * L <= 16 when every chain has K = 1, L <= 8 when any chain has K > 1, else
+ * L <= 32 when every chain has K = 1, L <= 8 when any chain has K > 1, else
  * GGF_EINVAL).  For a rotation
  * Gamma_A -> exp(theta E) Gamma_A exp(-theta E) (E real antisymmetric 10 x 10,
  * Delta = [E, Gamma_A]): d Re E_loc(G)/d theta = tr(Delta S_e) and

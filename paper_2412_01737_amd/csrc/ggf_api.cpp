@@ -1588,8 +1588,8 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
     max_group = std::max(max_group, ch.group);
   }
   for (const ChainDev &ch : ctx->chains)
-    if (ch.L > (pairs ? 8 : 16))
-      return fail(ctx, GGF_EINVAL, pairs ? "sensitivities of K > 1 chains need L <= 8" : "sensitivities need L <= 16");
+    if (ch.L > (pairs ? 8 : 32))
+      return fail(ctx, GGF_EINVAL, pairs ? "sensitivities of K > 1 chains need L <= 8" : "sensitivities need L <= 32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const LaunchCtx lc = launch_ctx(ctx, s);
   const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};

@@ -1268,13 +1268,15 @@ __device__ inline void sens_write_rest(double *o, const double *s_Sa, const doub
 //   S_e[b^T-block] from dB G B^T + B G dB^T (rows of G on the 5 neighbouring blocks),
 //   S_e[d-block]  = sum_z (P^T C P)[z, z]^T + ke sum_l sum_{i<j} R_k[j][i] G[z, u_j] (x) G[z, u_i],
 //   S_N[d-block]  = (1/2) sum_x G[x, x]  (log N = (1/2) log det M + const).
-// out[c][0..99] = Re S_e, out[c][100..199] = S_N (row-major 10 x 10).  L <= 16.
-// STAGE: the 8 rows of stripe z are staged in LDS (8 n float64 after U_z's 16 max_sites).
-template <typename T, bool STAGE>
+// out[c][0..99] = Re S_e, out[c][100..199] = S_N (row-major 10 x 10).  L <= 32.
+// Per row stripe z, the sites are taken in chunks of R whole lattice rows: the Hamiltonian blocks of
+// a site x pair it with x, x + e1 (same row) and x + e2 (next row), so U_z is formed on the chunk's
+// rows and the row after it, at most kSensSites sites (R = min(L, kSensSites / L - 1)).
+constexpr int kSensSites = 448;
+template <typename T>
 __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double *out, int max_sites) {
   extern __shared__ double s_dyn[];
-  double *s_U = s_dyn;                       // U_z[i][2w + a] = sum_j G[8z+i][8w+j] b[a][j], 8 x 2V
-  double *s_G = s_dyn + 16 * max_sites;      // stripe z, 8 x n (STAGE)
+  double *s_U = s_dyn;                       // U_z[i][2 ls + a] = sum_j G[8z+i][8w+j] b[a][j], w the chunk's ls-th site
   __shared__ double s_Sa[4], s_Sb[16], s_SN[64];
   __shared__ double s_R[GGF_ZN_MAX][16];
   __shared__ double s_red[4][64];
@@ -1292,57 +1294,53 @@ __global__ __launch_bounds__(256) void k_sens(LaunchCtx lc, EnergyCp cp, double 
   __syncthreads();
   // (1) per site: a-block, b-block and S_N
   sens_sites<T>(cp, lk, L, group, G, n, Tn, s_Sa, s_Sb, s_SN);
-  // (2) d-block: per row stripe z
+  // (2) d-block: per row stripe z, in chunks of R lattice rows
+  const int R = min(L, kSensSites / L - 1);
   const int ij = tid & 63, part = tid >> 6;
   const int pi = ij >> 3, pj = ij & 7;
+  // index of site s among the chunk's sites (rows r0 .. r0 + nr, the last taken mod L)
+  auto local = [&](int s_, int r0) { return (((s_ / L) - r0 + L) % L) * L + s_ % L; };
   double sd = 0.0;
   for (int z = 0; z < V; ++z) {
-    __syncthreads();
-    if (STAGE) {
-      for (int e = tid; e < 8 * n; e += blockDim.x)
-        s_G[e] = static_cast<double>(G[static_cast<size_t>(8 * z) * n + e]);
-      __syncthreads();
-    }
-    for (int e = tid; e < 16 * V; e += blockDim.x) {
-      const int i = e / (2 * V), col = e % (2 * V), w = col >> 1, a = col & 1;
-      double v = 0.0;
-      if (STAGE) {
-        const double *grow = s_G + i * n + 8 * w;
-        for (int j = 0; j < 8; ++j) v += grow[j] * Tn.b[a * 8 + j];
-      } else {
-        const T *grow = G + static_cast<size_t>(8 * z + i) * n + 8 * w;
-        for (int j = 0; j < 8; ++j) v += static_cast<double>(grow[j]) * Tn.b[a * 8 + j];
-      }
-      s_U[i * 2 * V + col] = v;
-    }
-    __syncthreads();
     double acc = 0.0;
-    for (int x = part; x < V; x += 4)
-      for (int term = 0; term < 5; ++term) {
-        int w, y;
-        double o[4];
-        h_term(cp, lk, L, group, x, term, w, y, o);
-        const double ui0 = s_U[pi * 2 * V + 2 * w], ui1 = s_U[pi * 2 * V + 2 * w + 1];
-        const double uj0 = s_U[pj * 2 * V + 2 * y], uj1 = s_U[pj * 2 * V + 2 * y + 1];
-        acc += ui0 * (o[0] * uj0 + o[1] * uj1) + ui1 * (o[2] * uj0 + o[3] * uj1);
+    for (int r0 = 0; r0 < L; r0 += R) {
+      const int nr = min(R, L - r0);
+      const int ns = (nr + 1) * L;
+      __syncthreads();                       // readers of the previous chunk's U_z are done
+      for (int e = tid; e < 16 * ns; e += blockDim.x) {
+        const int i = e / (2 * ns), col = e % (2 * ns), ls = col >> 1, a = col & 1;
+        const int w = ((r0 + ls / L) % L) * L + ls % L;
+        const T *grow = G + static_cast<size_t>(8 * z + i) * n + 8 * w;
+        double v = 0.0;
+        for (int j = 0; j < 8; ++j) v += static_cast<double>(grow[j]) * Tn.b[a * 8 + j];
+        s_U[i * 2 * ns + col] = v;
       }
+      __syncthreads();
+      for (int lx = part; lx < nr * L; lx += 4) {
+        const int x = (r0 + lx / L) * L + lx % L;
+        for (int term = 0; term < 5; ++term) {
+          int w, y;
+          double o[4];
+          h_term(cp, lk, L, group, x, term, w, y, o);
+          const int lw = local(w, r0), ly = local(y, r0);
+          const double ui0 = s_U[pi * 2 * ns + 2 * lw], ui1 = s_U[pi * 2 * ns + 2 * lw + 1];
+          const double uj0 = s_U[pj * 2 * ns + 2 * ly], uj1 = s_U[pj * 2 * ns + 2 * ly + 1];
+          acc += ui0 * (o[0] * uj0 + o[1] * uj1) + ui1 * (o[2] * uj0 + o[3] * uj1);
+        }
+      }
+    }
     if (cp.ke != 0.0)
       for (int ell = part; ell < 2 * V; ell += 4) {
         int u[4];
         ggf_link_u(ell, L, u);
-        const double *R = s_R[lk[ell]];
+        const double *Rk = s_R[lk[ell]];
         double vp[4], vq[4];   // G[8z + pj][u], G[8z + pi][u] (S_d[pj][pi] collects the sum)
         for (int i = 0; i < 4; ++i) {
-          if (STAGE) {
-            vp[i] = s_G[pj * n + u[i]];
-            vq[i] = s_G[pi * n + u[i]];
-          } else {
-            vp[i] = static_cast<double>(G[static_cast<size_t>(8 * z + pj) * n + u[i]]);
-            vq[i] = static_cast<double>(G[static_cast<size_t>(8 * z + pi) * n + u[i]]);
-          }
+          vp[i] = static_cast<double>(G[static_cast<size_t>(8 * z + pj) * n + u[i]]);
+          vq[i] = static_cast<double>(G[static_cast<size_t>(8 * z + pi) * n + u[i]]);
         }
         for (int i = 0; i < 4; ++i)
-          for (int j = i + 1; j < 4; ++j) acc += cp.ke * R[j * 4 + i] * vp[j] * vq[i];
+          for (int j = i + 1; j < 4; ++j) acc += cp.ke * Rk[j * 4 + i] * vp[j] * vq[i];
       }
     sd += acc;   // (P^T C P)[z][pi][pj] + electric part; S_d[pj][pi] collects it
   }
@@ -1931,17 +1929,10 @@ void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int m
       hipLaunchKernelGGL(k_sens_t<float>, grid, block512, lds, lc.stream, lc, cp, out, max_sites, max_group);
     return;
   }
-  // stage each row stripe (8 n = 64 V float64) in LDS while it and U_z fit in 64 KB (V <= 102)
-  const size_t lds_u = static_cast<size_t>(16) * max_sites * sizeof(double);
-  const size_t lds_g = static_cast<size_t>(64) * max_sites * sizeof(double);
-  const bool stage = lds_u + lds_g <= 65536;
-  if (lc.precision == 64) {
-    if (stage) hipLaunchKernelGGL((k_sens<double, true>), grid, block, lds_u + lds_g, lc.stream, lc, cp, out, max_sites);
-    else hipLaunchKernelGGL((k_sens<double, false>), grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
-  } else {
-    if (stage) hipLaunchKernelGGL((k_sens<float, true>), grid, block, lds_u + lds_g, lc.stream, lc, cp, out, max_sites);
-    else hipLaunchKernelGGL((k_sens<float, false>), grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
-  }
+  // one-stage kernel: U_z of a chunk of lattice rows in LDS (kSensSites sites, 56 KB)
+  const size_t lds_u = static_cast<size_t>(16) * kSensSites * sizeof(double);
+  if (lc.precision == 64) hipLaunchKernelGGL(k_sens<double>, grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
+  else hipLaunchKernelGGL(k_sens<float>, grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
 }
 
 void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,

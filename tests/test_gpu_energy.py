@@ -172,9 +172,7 @@ def test_energy_entry_points_reject_bad_input():
     big = Context(0)
     tb = big.set_tensor_spec(spec_for(18, 1, 2))
     big.init_chains([18], [tb], 1)
-    with pytest.raises(GGFError) as e:            # sensitivities need L <= 16
-        big.measure_sensitivity(CP)
-    assert e.value.status == GGF_EINVAL
+    assert np.all(np.isfinite(big.measure_sensitivity(CP)))   # K = 1: any L (up to 32)
     big.close()
     pairs = Context(0)
     tp = pairs.set_tensor_spec(spec_for(10, 2, 2))

@@ -62,6 +62,21 @@ def test_sensitivity_rows_large(L, group):
     ctx.close()
 
 
+@pytest.mark.parametrize("L", [24, 32])
+def test_sensitivity_rows_chunked(L):
+    """Lattices above the one-chunk size: U_z formed on chunks of lattice rows (L = 24: rows 0-16 and
+    17-23; L = 32: 0-12, 13-25, 26-31) with the next row as halo; one chain against the oracle."""
+    say(f"sensitivities L={L} Z2 float64, row chunks")
+    spec = spec_for(L, 1, 2)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L], init=1)
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    assert np.all(np.isfinite(rows))
+    _check_sens(rows[0], an, ctx.get_state(0)[0], 1e-10)
+    ctx.close()
+
+
 def test_sensitivity_full_size_sampled():
     """4096 chains of 8x8 Z2 (float64) in one launch; two chains checked, every row finite."""
     L, chains = 8, 4096
