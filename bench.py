@@ -101,9 +101,8 @@ def parse():
                          "workloads; --lambda-sweeps sweeps per round), reported under 'lambda_opt'")
     ap.add_argument("--lambda-sweeps", type=int, default=2)
     ap.add_argument("--gamma-iters", type=int, default=0,
-                    help="after the timed sweeps, rounds of gradient descent on Gamma_A (L <= 32 for K = 1, "
-                         "L <= 8 for K > 1; --lambda-sweeps sweeps per round, --gamma-step), reported under "
-                         "'gamma_opt'")
+                    help="after the timed sweeps, rounds of gradient descent on Gamma_A (--lambda-sweeps "
+                         "sweeps per round, --gamma-step), reported under 'gamma_opt'")
     ap.add_argument("--gamma-step", type=float, default=0.01)
     ap.add_argument("--electric-traffic-from", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -1030,7 +1029,7 @@ def run_plain(args, with_cpu=True):
                       "optimum_per_round": eo_.tolist(), "lambda_re": lam_.real.tolist(),
                       "lambda_im": lam_.imag.tolist(), "couplings": BENCH_COUPLINGS}
     gamma_opt = None
-    if args.gamma_iters > 0 and args.workload != "c4" and args.L <= (32 if args.K == 1 else 8):
+    if args.gamma_iters > 0 and args.workload != "c4":
         torch.cuda.synchronize()
         t_opt = time.perf_counter()
         en_, gn_, _ = ctx.optimise_gamma(int(tids), BENCH_COUPLINGS, args.gamma_iters, args.lambda_sweeps,

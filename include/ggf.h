@@ -211,8 +211,7 @@ ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_coupli
 
 /* Sensitivities of every chain's local energy and log N(G) to the on-site
  * covariance Gamma_A (gradient descent on Gamma_A, the outlook of Sec. 6.3;
- * L <= 32 when every chain has K = 1, L <= 8 when any chain has K > 1, else
- * GGF_EINVAL).  For a rotation
+ * any L <= 32).  For a rotation
  * Gamma_A -> exp(theta E) Gamma_A exp(-theta E) (E real antisymmetric 10 x 10,
  * Delta = [E, Gamma_A]): d Re E_loc(G)/d theta = tr(Delta S_e) and
  * d log N(G)/d theta = tr(Delta S_N), tr(Delta S) = sum_ij Delta_ij S_ji.
@@ -222,9 +221,10 @@ ggf_status ggf_optimise_lambda(ggf_ctx *ctx, int32_t tensor_id, const ggf_coupli
  * with om_ab = lambda_a^* lambda_b <B_b|B_a> r_ab, S = sum om, h_ab the pair's
  * transition energy and E the local energy, d log N = sum (om_ab / S) (1/2)
  * tr(M_ab^-1 dM) and d E = sum (om_ab / S) [d h_ab + (h_ab - E) (1/2)
- * tr(M_ab^-1 dM)], real parts.  Such a call is synchronous and allocates
- * n_chains x (GGF_ENERGY_STRIDE doubles + n^2 complex doubles) of device memory
- * for its duration (4 MiB per 8 x 8 chain). */
+ * tr(M_ab^-1 dM)], real parts.  Such a call is synchronous and allocates for
+ * its duration per chain GGF_ENERGY_STRIDE doubles and, with n the largest n of
+ * the context, M_ab^-1 as n^2 complex doubles when n <= 512 (4 MiB at L = 8),
+ * else the factors of M_ab^-1 - G (rank <= 8) as 26 n doubles (1.7 MiB at L = 32). */
 ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *couplings, double *out,
                                    int32_t out_is_device, void *stream);
 

@@ -1588,8 +1588,7 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
     max_group = std::max(max_group, ch.group);
   }
   for (const ChainDev &ch : ctx->chains)
-    if (ch.L > (pairs ? 8 : 32))
-      return fail(ctx, GGF_EINVAL, pairs ? "sensitivities of K > 1 chains need L <= 8" : "sensitivities need L <= 32");
+    if (ch.L > 32) return fail(ctx, GGF_EINVAL, "sensitivities need L <= 32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const LaunchCtx lc = launch_ctx(ctx, s);
   const EnergyCp ec{cp->t, cp->mu, cp->m, cp->kb, cp->ke};
@@ -1599,14 +1598,15 @@ ggf_status ggf_measure_sensitivity(ggf_ctx *ctx, const ggf_couplings *cp, double
     HIP_TRY(ctx, hipGetLastError());
     return GGF_OK;
   }
-  // K > 1: the chains' energy rows (pair weights, h_ab and E) and one complex n x n M_ab^-1 per chain
+  // K > 1: the chains' energy rows (pair weights, h_ab and E) and per chain the pair inverse M_ab^-1
+  // (complex n x n) or, for n > 512, the factors of its correction to G
   double *tmp = nullptr, *erows = nullptr;
-  double2 *gab = nullptr;
+  void *gab = nullptr;
   hipError_t e = out_is_device ? hipSuccess : hipMalloc(&tmp, bytes);
   if (e == hipSuccess && pairs)
     e = hipMalloc(&erows, static_cast<size_t>(ctx->n_chains) * GGF_ENERGY_STRIDE * sizeof(double));
   if (e == hipSuccess && pairs)
-    e = hipMalloc(&gab, static_cast<size_t>(ctx->n_chains) * max_n * max_n * sizeof(double2));
+    e = hipMalloc(&gab, ggf_sens_pairs_scratch(ctx->n_chains, max_n));
   double *dst = out_is_device ? out : tmp;
   if (e == hipSuccess) {
     if (pairs) {

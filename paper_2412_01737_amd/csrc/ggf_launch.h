@@ -78,12 +78,15 @@ struct EnergyCp {
 };
 void ggf_launch_energy(const LaunchCtx &lc, const EnergyCp &cp, double *out, int kmax);
 void ggf_launch_bond_rows(const LaunchCtx &lc, const EnergyCp &cp, double *out);
-// Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 16);
+// Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 32);
 // max_group: the largest link group among the chains.
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group);
 // K > 1 (L <= 8): per pair, M_ab^-1 formed into gab (n_chains x nmax^2 complex) and its weighted
 // contribution accumulated into out, using the chains' energy rows erows.
-void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,
+// Scratch bytes of ggf_launch_sens_pairs: the pair inverses M_ab^-1 (complex nmax x nmax per chain) when
+// nmax <= 512, else the correction tables (A, AY, Ab: 26 nmax doubles per chain).
+size_t ggf_sens_pairs_scratch(int n_chains, int nmax);
+void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, void *scratch, int nmax, const double *erows,
                            double *out, int kmax);
 int ggf_launch_probe(int mode, void *a, void *b, size_t bytes, int grid, hipStream_t s);
 // Staging array of the allocation-free host measurement: GGF_STAGE_MAX_CHAINS x GGF_NOBS_DEV doubles per

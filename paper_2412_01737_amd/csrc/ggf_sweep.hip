@@ -1115,9 +1115,8 @@ __device__ inline void coef_block(double2 coef, double o[4]) {
 
 // The five bilinear terms of H that involve site x: term 0 on-site (x, x), terms 1 + 2 mu
 // the hop (x, x + mu), terms 2 + 2 mu the reverse (x + mu, x); (row site, column site, complex
-// coefficient of <phi_w^+ phi_y>).
-__device__ inline double2 h_coef(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
-                                 int &y) {
+// coefficient of <phi_w^+ phi_y>), with D the phase of the term's link (unused by term 0).
+__device__ inline double2 h_coef_d(const EnergyCp &cp, int L, int x, int term, double2 D, int &w, int &y) {
   if (term == 0) {
     const int sgn = (((x % L) + x / L) & 1) ? -1 : 1;
     w = y = x;
@@ -1125,7 +1124,6 @@ __device__ inline double2 h_coef(const EnergyCp &cp, const int8_t *lk, int L, in
   }
   const int mu = (term - 1) >> 1;
   const int xn = mu == 0 ? ggf_shift(x, L, 1, 0) : ggf_shift(x, L, 0, 1);
-  const double2 D = link_phase(lk[2 * x + mu], group);
   const double te = (mu == 0 && ((x / L) & 1)) ? -cp.t : cp.t;
   if ((term & 1) == 1) {           // t i eta D <phi_x^+ phi_xn>
     w = x;
@@ -1135,6 +1133,13 @@ __device__ inline double2 h_coef(const EnergyCp &cp, const int8_t *lk, int L, in
   w = xn;                          // -t i eta D^* <phi_xn^+ phi_x>
   y = x;
   return make_double2(-te * D.y, -te * D.x);
+}
+
+// The same with the link phase taken from the link field.
+__device__ inline double2 h_coef(const EnergyCp &cp, const int8_t *lk, int L, int group, int x, int term, int &w,
+                                 int &y) {
+  const double2 D = term == 0 ? make_double2(1.0, 0.0) : link_phase(lk[2 * x + ((term - 1) >> 1)], group);
+  return h_coef_d(cp, L, x, term, D, w, y);
 }
 
 // The same terms as coefficient blocks of Gamma_out[2w + a][2y + b].
@@ -1174,12 +1179,14 @@ __device__ inline void sens_r_table(const TensorDev &Tn, int group, double *s_R)
 }
 
 // a-block, b-block and S_N of the K = 1 sensitivities: per site the rows of G on the 5
-// neighbouring blocks (accumulated into s_Sa, s_Sb, s_SN by LDS atomics).
+// neighbouring blocks (accumulated into s_Sa, s_Sb, s_SN by LDS atomics).  Only the first wave
+// takes part, so that the atomics of each sum come in a fixed order (rows reproducible bit for bit).
 template <typename T>
 __device__ inline void sens_sites(const EnergyCp &cp, const int8_t *lk, int L, int group, const T *G, int n,
                                   const TensorDev &Tn, double *s_Sa, double *s_Sb, double *s_SN) {
   const int V = L * L, tid = threadIdx.x;
-  for (int x = tid; x < V; x += blockDim.x) {
+  if (tid >= 64) return;
+  for (int x = tid; x < V; x += 64) {
     double sb[16];
     for (int q = 0; q < 16; ++q) sb[q] = 0.0;
     {
@@ -1592,84 +1599,85 @@ __device__ inline void h_term_c(const EnergyCp &cp, const int8_t *lk, int L, int
   }
 }
 
-// One pair's contribution to the K > 1 sensitivities of a chain (the K = 1 computation of
-// k_sens with the complex M_ab^-1 of Gab and the pair's electric slopes), weighted by the
-// pair's om / S and combined with h_ab and E from the chain's energy row:
-//   S_e += Re (om/S) [S_e^ab + (h_ab - E) S_N^ab],   S_N += Re (om/S) S_N^ab.
-// pr == 0 writes the row, later pairs add to it.  L <= 8; launched with 512 threads.
-__global__ __launch_bounds__(512, 2) void k_sens_pair(LaunchCtx lc, EnergyCp cp, int pr, const double2 *Gab, int nmax,
-                                                   const double *erows, double *out) {
-  // dynamic LDS: T_z[m][p] (n x 8, U_z[2w + a][i] at its start), CU[2w + a][p] (2V x 8), the block
-  // coefficients of each row site (5 V, complex), their column sites (int16) and the links' Majoranas (int16)
-  extern __shared__ double2 s_dyn2[];
-  double2 *s_T = s_dyn2;
-  double2 *s_U = s_T;
-  double2 *s_CU = s_T + 8 * nmax;
-  double2 *s_cc = s_CU + 2 * nmax;
-  int16_t *s_cy = reinterpret_cast<int16_t *>(s_cc + 5 * (nmax / 8));
-  int16_t *s_lu = s_cy + 5 * (nmax / 8);
-  __shared__ double2 s_sl[128][6];        // electric slopes of the pair per link
-  __shared__ double2 s_Sa[4], s_Sb[16], s_SN[64];
-  __shared__ double2 s_wt[2];             // om/S, om/S (h - E)
-  const int c = blockIdx.x;
-  const ChainDev ch = lc.chains[c];
-  const TensorDev &Tn = lc.tensors[ch.tensor];
-  const int n = ch.n, L = ch.L, V = L * L, group = ch.group, K = ch.K;
-  const int8_t *lk = lc.links + ch.link_off;
-  const int tid = threadIdx.x;
-  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
-  if (pr >= K * K) return;
+// Pair weights of one chain from its energy row: s_wt[0] = om_ab / S = lambda_a^* lambda_b rho_ab / S
+// (lambda_a^* lambda_b = w / ov), s_wt[1] = om_ab / S (h_ab - E), E = sum_p lambda^* lambda (rho h / S)_p.
+__device__ inline void pair_weights(const TensorDev &Tn, const double *row, int K, int pr, double2 *s_wt) {
   const int a = pr / K, b = pr % K;
-  const double2 *Gc = Gab + static_cast<size_t>(c) * nmax * nmax;
-  if (tid == 0) {
-    // om/S = lambda_a^* lambda_b rho/S, lambda_a^* lambda_b = w / ov; E = sum_p lambda^* lambda (rho h / S)_p
-    const double *row = erows + static_cast<size_t>(c) * GGF_ENERGY_STRIDE_DEV;
-    double2 E = make_double2(0.0, 0.0);
-    for (int p = 0; p < K * K; ++p) {
-      const int pa = p / K, pb = p % K;
-      const double2 ll = cdiv(Tn.w[pa][pb], Tn.ov[pa][pb]);
-      E = cadd(E, cmul(ll, make_double2(row[3 + 4 * p], row[4 + 4 * p])));
+  double2 E = make_double2(0.0, 0.0);
+  for (int p = 0; p < K * K; ++p) {
+    const int pa = p / K, pb = p % K;
+    const double2 ll = cdiv(Tn.w[pa][pb], Tn.ov[pa][pb]);
+    E = cadd(E, cmul(ll, make_double2(row[3 + 4 * p], row[4 + 4 * p])));
+  }
+  const double2 rho = make_double2(row[1 + 4 * pr], row[2 + 4 * pr]);
+  const double2 rh = make_double2(row[3 + 4 * pr], row[4 + 4 * pr]);
+  const double2 om = cmul(cdiv(Tn.w[a][b], Tn.ov[a][b]), rho);
+  s_wt[0] = om;
+  s_wt[1] = cmul(om, csub(cdiv(rh, rho), E));
+}
+
+// M_ab^-1 stored as a complex n x n matrix: entry (r, col), and t_a = sum_j M_ab^-1[r][8w + j] b[a][j].
+struct PairInvDense {
+  const double2 *Gc;
+  int n;
+  const double *b;
+  __device__ double2 operator()(int r, int col) const { return Gc[static_cast<size_t>(r) * n + col]; }
+  __device__ void bcols(int r, int w, double2 &t0, double2 &t1) const {
+    const double2 *grow = Gc + static_cast<size_t>(r) * n + 8 * w;
+    t0 = t1 = make_double2(0.0, 0.0);
+    for (int j = 0; j < 8; ++j) {
+      t0 = cadd(t0, cscale(grow[j], b[j]));
+      t1 = cadd(t1, cscale(grow[j], b[8 + j]));
     }
-    const double2 rho = make_double2(row[1 + 4 * pr], row[2 + 4 * pr]);
-    const double2 rh = make_double2(row[3 + 4 * pr], row[4 + 4 * pr]);
-    const double2 om = cmul(cdiv(Tn.w[a][b], Tn.ov[a][b]), rho);
-    s_wt[0] = om;
-    s_wt[1] = cmul(om, csub(cdiv(rh, rho), E));
   }
-  if (tid < 4) s_Sa[tid] = make_double2(0.0, 0.0);
-  if (tid < 16) s_Sb[tid] = make_double2(0.0, 0.0);
-  if (tid < 64) s_SN[tid] = make_double2(0.0, 0.0);
-  for (int ell = tid; ell < 2 * V; ell += blockDim.x) {
-    // slope of the pair's X along e_ij - e_ji: R[j][i], R = O eq_ab O^T of this link
-    const double2 *eq = Tn.eq0;
-    for (int l = 0; l < Tn.nl[a][b]; ++l)
-      if (Tn.lk[a][b][l] == ell) eq = Tn.eq[a][b][l];
-    int k = 0;
-    for (int i = 0; i < 4; ++i) {
-      for (int j = i + 1; j < 4; ++j) {
-        double2 row[4];
-        rotate_dg_row(eq, lk[ell], group, j, row);   // row j of O eq O^T
-        s_sl[ell][k++] = row[i];
-      }
+};
+
+// M_ab^-1 = G + AY A^T as the rank <= 8 correction of G: AY = G_S Y_ab (n x 8 complex), A = G[:, S]
+// (n x 8) and Ab[2w + a][q] = sum_j b[a][j] A[8w + j][q], the columns q >= s zero.
+template <typename T>
+struct PairInvRank {
+  const T *G;
+  int n;
+  const double *b;
+  const double2 *AY;
+  const double *A, *Ab;
+  __device__ double2 operator()(int r, int col) const {
+    double2 v = make_double2(static_cast<double>(G[static_cast<size_t>(r) * n + col]), 0.0);
+    const double2 *ay = AY + static_cast<size_t>(r) * 8;
+    const double *ac = A + static_cast<size_t>(col) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v = cadd(v, cscale(ay[q], ac[q]));
+    return v;
+  }
+  __device__ void bcols(int r, int w, double2 &t0, double2 &t1) const {
+    const T *grow = G + static_cast<size_t>(r) * n + 8 * w;
+    double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double g = static_cast<double>(grow[j]);
+      x0 += g * b[j];
+      x1 += g * b[8 + j];
     }
-    int u[4];
-    ggf_link_u(ell, L, u);
-    for (int q = 0; q < 4; ++q) s_lu[4 * ell + q] = static_cast<int16_t>(u[q]);
+    t0 = make_double2(x0, 0.0);
+    t1 = make_double2(x1, 0.0);
+    const double2 *ay = AY + static_cast<size_t>(r) * 8;
+    const double *ab = Ab + static_cast<size_t>(2 * w) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      t0 = cadd(t0, cscale(ay[q], ab[q]));
+      t1 = cadd(t1, cscale(ay[q], ab[8 + q]));
+    }
   }
-  for (int e = tid; e < 5 * V; e += blockDim.x) {
-    // row site w: on site, the hops to w + e1 and w + e2 (terms 1, 3 of w), the reverse hops from
-    // w - e1 and w - e2 (terms 2, 4 of those sites)
-    const int w = e / 5, t = e - 5 * w;
-    int owner = w, term = t;
-    if (t == 2) term = 3;
-    else if (t == 3) { owner = ggf_shift(w, L, -1, 0); term = 2; }
-    else if (t == 4) { owner = ggf_shift(w, L, 0, -1); term = 4; }
-    int wr, y;
-    s_cc[e] = h_coef(cp, lk, L, group, owner, term, wr, y);
-    s_cy[e] = static_cast<int16_t>(y);
-  }
-  __syncthreads();
-  for (int x = tid; x < V; x += blockDim.x) {
+};
+
+// Per-site part of one pair's sensitivities, the K = 1 computation of sens_sites with complex
+// blocks and M_ab^-1 read through mi: a-block, b-block and S_N (LDS sums, zeroed by the caller;
+// the first wave only, as in sens_sites).
+template <typename MI>
+__device__ inline void pair_sites(const EnergyCp &cp, const int8_t *lk, int L, int group, const MI &mi, double2 *s_Sa,
+                                  double2 *s_Sb, double2 *s_SN) {
+  if (threadIdx.x >= 64) return;
+  for (int x = threadIdx.x; x < L * L; x += 64) {
     double2 o4[4];
     int w, y;
     h_term_c(cp, lk, L, group, x, 0, w, y, o4);
@@ -1704,12 +1712,8 @@ __global__ __launch_bounds__(512, 2) void k_sens_pair(LaunchCtx lc, EnergyCp cp,
       if (nb == 0)
         for (int q = 0; q < 4; ++q) ocol[q] = orow[q];
       for (int i = 0; i < 8; ++i) {
-        const double2 *grow = Gc + static_cast<size_t>(8 * x + i) * n + 8 * yy;
-        double2 t0 = make_double2(0.0, 0.0), t1 = make_double2(0.0, 0.0);
-        for (int j = 0; j < 8; ++j) {
-          t0 = cadd(t0, cscale(grow[j], Tn.b[j]));
-          t1 = cadd(t1, cscale(grow[j], Tn.b[8 + j]));
-        }
+        double2 t0, t1;
+        mi.bcols(8 * x + i, yy, t0, t1);
         for (int aa = 0; aa < 2; ++aa) {
           sb[aa * 8 + i] = cadd(sb[aa * 8 + i], cadd(cmul(orow[aa * 2 + 0], t0), cmul(orow[aa * 2 + 1], t1)));
           sb[aa * 8 + i] = csub(sb[aa * 8 + i], cadd(cmul(ocol[0 * 2 + aa], t0), cmul(ocol[1 * 2 + aa], t1)));
@@ -1722,11 +1726,99 @@ __global__ __launch_bounds__(512, 2) void k_sens_pair(LaunchCtx lc, EnergyCp cp,
     }
     for (int i = 0; i < 8; ++i)
       for (int j = 0; j < 8; ++j) {
-        const double2 g = Gc[static_cast<size_t>(8 * x + i) * n + 8 * x + j];
+        const double2 g = mi(8 * x + i, 8 * x + j);
         atomicAdd(&s_SN[i * 8 + j].x, 0.5 * g.x);
         atomicAdd(&s_SN[i * 8 + j].y, 0.5 * g.y);
       }
   }
+}
+
+// Writes (pr == 0) or adds one pair's weighted a-block, b-block and S_N (thread tid < 100 its share):
+// S_e += Re (om/S) S_e^ab, S_N += Re (om/S) S_N^ab, and the zero entries.
+__device__ inline void pair_write_rest(double *o, bool first, double2 w0, const double2 *s_Sa, const double2 *s_Sb,
+                                       const double2 *s_SN) {
+  const int tid = threadIdx.x;
+  auto put = [&](int idx, double v) { o[idx] = first ? v : o[idx] + v; };
+  if (tid < 64) put(100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7), cmul(w0, s_SN[tid]).x);
+  if (tid < 16) {
+    const int al = tid >> 3, i = tid & 7;
+    put((2 + i) * 10 + al, cmul(w0, s_Sb[tid]).x);
+  }
+  if (tid < 4) put((tid >> 1) * 10 + (tid & 1), cmul(w0, s_Sa[tid]).x);
+  if (tid < 20) {
+    const int al = tid / 10, j = tid % 10;
+    if (j >= 2) put(al * 10 + j, 0.0);
+  }
+  if (tid < 100) {
+    const int i = tid / 10, j = tid % 10;
+    if (i < 2 || j < 2) put(100 + tid, 0.0);
+  }
+}
+
+// One pair's contribution to the K > 1 sensitivities of a chain (the K = 1 computation of
+// k_sens with the complex M_ab^-1 of Gab and the pair's electric slopes), weighted by the
+// pair's om / S and combined with h_ab and E from the chain's energy row:
+//   S_e += Re (om/S) [S_e^ab + (h_ab - E) S_N^ab],   S_N += Re (om/S) S_N^ab.
+// pr == 0 writes the row, later pairs add to it.  L <= 8; launched with 512 threads.
+__global__ __launch_bounds__(512, 2) void k_sens_pair(LaunchCtx lc, EnergyCp cp, int pr, const double2 *Gab, int nmax,
+                                                   const double *erows, double *out) {
+  // dynamic LDS: T_z[m][p] (n x 8, U_z[2w + a][i] at its start), CU[2w + a][p] (2V x 8), the block
+  // coefficients of each row site (5 V, complex), their column sites (int16) and the links' Majoranas (int16)
+  extern __shared__ double2 s_dyn2[];
+  double2 *s_T = s_dyn2;
+  double2 *s_U = s_T;
+  double2 *s_CU = s_T + 8 * nmax;
+  double2 *s_cc = s_CU + 2 * nmax;
+  int16_t *s_cy = reinterpret_cast<int16_t *>(s_cc + 5 * (nmax / 8));
+  int16_t *s_lu = s_cy + 5 * (nmax / 8);
+  __shared__ double2 s_sl[128][6];        // electric slopes of the pair per link
+  __shared__ double2 s_Sa[4], s_Sb[16], s_SN[64];
+  __shared__ double2 s_wt[2];             // om/S, om/S (h - E)
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group, K = ch.K;
+  const int8_t *lk = lc.links + ch.link_off;
+  const int tid = threadIdx.x;
+  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
+  if (pr >= K * K) return;
+  const int a = pr / K, b = pr % K;
+  const double2 *Gc = Gab + static_cast<size_t>(c) * nmax * nmax;
+  if (tid == 0) pair_weights(Tn, erows + static_cast<size_t>(c) * GGF_ENERGY_STRIDE_DEV, K, pr, s_wt);
+  if (tid < 4) s_Sa[tid] = make_double2(0.0, 0.0);
+  if (tid < 16) s_Sb[tid] = make_double2(0.0, 0.0);
+  if (tid < 64) s_SN[tid] = make_double2(0.0, 0.0);
+  for (int ell = tid; ell < 2 * V; ell += blockDim.x) {
+    // slope of the pair's X along e_ij - e_ji: R[j][i], R = O eq_ab O^T of this link
+    const double2 *eq = Tn.eq0;
+    for (int l = 0; l < Tn.nl[a][b]; ++l)
+      if (Tn.lk[a][b][l] == ell) eq = Tn.eq[a][b][l];
+    int k = 0;
+    for (int i = 0; i < 4; ++i) {
+      for (int j = i + 1; j < 4; ++j) {
+        double2 row[4];
+        rotate_dg_row(eq, lk[ell], group, j, row);   // row j of O eq O^T
+        s_sl[ell][k++] = row[i];
+      }
+    }
+    int u[4];
+    ggf_link_u(ell, L, u);
+    for (int q = 0; q < 4; ++q) s_lu[4 * ell + q] = static_cast<int16_t>(u[q]);
+  }
+  for (int e = tid; e < 5 * V; e += blockDim.x) {
+    // row site w: on site, the hops to w + e1 and w + e2 (terms 1, 3 of w), the reverse hops from
+    // w - e1 and w - e2 (terms 2, 4 of those sites)
+    const int w = e / 5, t = e - 5 * w;
+    int owner = w, term = t;
+    if (t == 2) term = 3;
+    else if (t == 3) { owner = ggf_shift(w, L, -1, 0); term = 2; }
+    else if (t == 4) { owner = ggf_shift(w, L, 0, -1); term = 4; }
+    int wr, y;
+    s_cc[e] = h_coef(cp, lk, L, group, owner, term, wr, y);
+    s_cy[e] = static_cast<int16_t>(y);
+  }
+  __syncthreads();
+  pair_sites(cp, lk, L, group, PairInvDense{Gc, n, Tn.b}, s_Sa, s_Sb, s_SN);
   // d-block in two contractions per row stripe z (as k_sens_t, complex):
   //   CU = C U_z^T, T_z = b^T CU + the pair's electric slopes, acc(p, q) += sum_m M_ab^-1[8z + p][m] T_z[m][q]
   const int part = tid & 31, blk = tid >> 5;
@@ -1812,20 +1904,272 @@ __global__ __launch_bounds__(512, 2) void k_sens_pair(LaunchCtx lc, EnergyCp cp,
       const int pp = p0 + (q >> 1), qq = q0 + (q & 1);
       put((2 + qq) * 10 + 2 + pp, cmul(w0, sd[q]).x + cmul(w1, s_SN[qq * 8 + pp]).x);
     }
-  if (tid < 64) put(100 + (2 + (tid >> 3)) * 10 + 2 + (tid & 7), cmul(w0, s_SN[tid]).x);
-  if (tid < 16) {
-    const int al = tid >> 3, i = tid & 7;
-    put((2 + i) * 10 + al, cmul(w0, s_Sb[tid]).x);
+  pair_write_rest(o, first, w0, s_Sa, s_Sb, s_SN);
+}
+
+// ---- Gamma_A sensitivities with K > 1 at any L <= 32: M_ab^-1 = G + AY A^T applied on the fly ----
+
+// Per chain and ordered pair pr, the factors of the rank <= 8 correction M_ab^-1 - G (PairInvRank):
+// A = G[:, S] and AY = A Y_ab at c * nmax * 8, Ab at c * (nmax / 4) * 8; s = 0 (all zero) for the
+// pair (0, 0) and for chains with K^2 <= pr.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_tables(LaunchCtx lc, int pr, double2 *AY, double *A, double *Ab,
+                                                     int nmax) {
+  __shared__ double2 s_Y[16][64];
+  __shared__ double2 s_om[16];
+  __shared__ int s_S[16][8];
+  __shared__ int s_s[16];
+  extern __shared__ double2 s_work[];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  pair_setup<T>(lc, c, ch, Tn, G, lk, s_Y, s_om, nullptr, s_S, s_s, s_work);
+  const int s = pr < ch.K * ch.K ? s_s[pr] : 0;
+  double2 *ay = AY + static_cast<size_t>(c) * nmax * 8;
+  double *ag = A + static_cast<size_t>(c) * nmax * 8;
+  double *ab = Ab + static_cast<size_t>(c) * (nmax / 4) * 8;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double g[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) g[q] = q < s ? static_cast<double>(G[static_cast<size_t>(r) * n + s_S[pr][q]]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < s && q < s) v = cadd(v, cscale(s_Y[pr][p * 8 + q], g[p]));
+      ay[static_cast<size_t>(r) * 8 + q] = v;
+      ag[static_cast<size_t>(r) * 8 + q] = g[q];
+    }
   }
-  if (tid < 4) put((tid >> 1) * 10 + (tid & 1), cmul(w0, s_Sa[tid]).x);
-  if (tid < 20) {
-    const int al = tid / 10, j = tid % 10;
-    if (j >= 2) put(al * 10 + j, 0.0);
+  for (int e = threadIdx.x; e < 2 * n; e += blockDim.x) {
+    // Ab[2w + al][q], e = (2w + al) * 8 + q
+    const int row = e >> 3, q = e & 7, w = row >> 1, al = row & 1;
+    double v = 0.0;
+    if (q < s)
+      for (int j = 0; j < 8; ++j) v += Tn.b[al * 8 + j] * static_cast<double>(G[static_cast<size_t>(8 * w + j) * n + s_S[pr][q]]);
+    ab[e] = v;
   }
-  if (tid < 100) {
-    const int i = tid / 10, j = tid % 10;
-    if (i < 2 || j < 2) put(100 + tid, 0.0);
+}
+
+// The d-block of one pair's contribution to the K > 1 sensitivities, om/S S_d^ab as in k_sens_pair (written
+// for pr == 0, else added), with M_ab^-1 = G + AY A^T read through the correction, per row stripe z in chunks
+// of lattice rows as in k_sens:
+//   hopping part: U_z[i][2w + a] = sum_j M_ab^-1[8z + i][8w + j] b[a][j] of the chunk's sites in LDS;
+//   electric part, with R_l the pair's slopes and the expansion of M_ab^-1 = G + AY A^T,
+//     sum_l sum_{i<j} R_l[j][i] M[P][u_j] M[Q][u_i] = sum_l sum_{i<j} R_l[j][i] G[P][u_j] G[Q][u_i]
+//       + sum_q AY[Q][q] Xa[P][q] + sum_q AY[P][q] Xb[Q][q] + sum_{q,q'} AY[P][q] Z[q][q'] AY[Q][q'],
+//     Xa[P][q] = sum R[j][i] G[P][u_j] A[u_i][q], Xb[Q][q] = sum R[j][i] A[u_j][q] G[Q][u_i] (per stripe) and
+//     Z[q][q'] = sum R[j][i] A[u_j][q] A[u_i][q'] (once per chain and pair).
+// At most kPairSites sites per chunk (R = min(L, kPairSites / L - 1) rows and the row after them).
+// Launched with 256 threads: thread (pi, pj) of each of the 4 parts sums the d-block entry (pi, pj).
+constexpr int kPairSites = 224;
+template <typename T>
+__global__ __launch_bounds__(256) void k_sens_pair_rows(LaunchCtx lc, EnergyCp cp, int pr, const double2 *AY,
+                                                        const double *A, const double *Ab, int nmax,
+                                                        const double *erows, double *out) {
+  extern __shared__ double2 s_dyn2[];
+  double2 *s_U = s_dyn2;                      // U_z[i][2 ls + a], ls the chunk's site
+  __shared__ double2 s_ph[GGF_ZN_MAX];        // link phases exp(2 pi i k / N)
+  __shared__ double2 s_Rg[GGF_ZN_MAX][6];     // slopes R[1][0], R[2][0], R[3][0], R[2][1], R[3][1], R[3][2] per link value
+  __shared__ double2 s_Rp[2][6];              // the same for the pair's patch links
+  __shared__ int s_pl[2];
+  __shared__ double2 s_wt[2], s_Z[64];
+  __shared__ double2 s_X[4][2][64];           // per part: Xa[P][q], Xb[Q][q] of the stripe
+  __shared__ double2 s_red[4][64];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int n = ch.n, L = ch.L, V = L * L, group = ch.group, K = ch.K;
+  if (pr >= K * K) return;
+  const int a = pr / K, b = pr % K;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const int8_t *lk = lc.links + ch.link_off;
+  const double2 *ay = AY + static_cast<size_t>(c) * nmax * 8;
+  const double *ag = A + static_cast<size_t>(c) * nmax * 8;
+  const PairInvRank<T> mi{G, n, Tn.b, ay, ag, Ab + static_cast<size_t>(c) * (nmax / 4) * 8};
+  const int tid = threadIdx.x;
+  if (tid == 0) pair_weights(Tn, erows + static_cast<size_t>(c) * GGF_ENERGY_STRIDE_DEV, K, pr, s_wt);
+  if (tid < 2) s_pl[tid] = tid < Tn.nl[a][b] ? Tn.lk[a][b][tid] : -1;
+  for (int k = tid; k < group; k += blockDim.x) s_ph[k] = link_phase(k, group);
+  for (int te = tid; te < 6 * (group + 2); te += blockDim.x) {
+    // entry idx of (i, j) = (0,1), (0,2), (0,3), (1,2), (1,3), (2,3): R[j][i], row j of O eq O^T
+    const int k = te / 6, idx = te - 6 * k;
+    const int i = idx < 3 ? 0 : (idx < 5 ? 1 : 2);
+    const int j = idx < 3 ? idx + 1 : (idx < 5 ? idx - 1 : 3);
+    double2 row[4];
+    if (k < group) {
+      rotate_dg_row(Tn.eq0, k, group, j, row);
+      s_Rg[k][idx] = row[i];
+    } else if (k - group < Tn.nl[a][b]) {
+      const int l = k - group;
+      rotate_dg_row(Tn.eq[a][b][l], lk[Tn.lk[a][b][l]], group, j, row);
+      s_Rp[l][idx] = row[i];
+    }
   }
+  __syncthreads();
+  // a link's slopes: a patch link of the pair (the later entry first), else the unpatched link's
+  auto slopes = [&](int ell) -> const double2 * {
+    if (ell == s_pl[1]) return s_Rp[1];
+    if (ell == s_pl[0]) return s_Rp[0];
+    return s_Rg[lk[ell]];
+  };
+  const int ij = tid & 63, part = tid >> 6;
+  const int pi = ij >> 3, pj = ij & 7;
+  if (cp.ke != 0.0) {
+    // Z[q][q'] with thread (pi, pj) taking q = pi, q' = pj
+    double2 zv = make_double2(0.0, 0.0);
+    for (int ell = part; ell < 2 * V; ell += 4) {
+      int u[4];
+      ggf_link_u(ell, L, u);
+      const double2 *R = slopes(ell);
+      double aq[4], ar[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        aq[k] = ag[static_cast<size_t>(u[k]) * 8 + pi];
+        ar[k] = ag[static_cast<size_t>(u[k]) * 8 + pj];
+      }
+      int k = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 4; ++j) zv = cadd(zv, cscale(R[k++], aq[j] * ar[i]));
+    }
+    s_red[part][ij] = zv;
+  }
+  __syncthreads();
+  if (tid < 64)
+    s_Z[tid] = cp.ke != 0.0 ? cscale(cadd(cadd(s_red[0][tid], s_red[1][tid]), cadd(s_red[2][tid], s_red[3][tid])), cp.ke)
+                            : make_double2(0.0, 0.0);
+  const int R = min(L, kPairSites / L - 1);
+  // index of site s among the chunk's sites (rows r0 .. r0 + nr, the last taken mod L)
+  auto local = [&](int s_, int r0) { return (((s_ / L) - r0 + L) % L) * L + s_ % L; };
+  double2 sd = make_double2(0.0, 0.0);
+  for (int z = 0; z < V; ++z) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int r0 = 0; r0 < L; r0 += R) {
+      const int nr = min(R, L - r0);
+      const int ns = (nr + 1) * L;
+      __syncthreads();                        // readers of the previous chunk's U_z (and s_X) are done
+      for (int e = tid; e < 8 * ns; e += blockDim.x) {
+        const int i = e / ns, ls = e - i * ns;
+        const int w = ((r0 + ls / L) % L) * L + ls % L;
+        double2 t0, t1;
+        mi.bcols(8 * z + i, w, t0, t1);
+        s_U[i * 2 * ns + 2 * ls] = t0;
+        s_U[i * 2 * ns + 2 * ls + 1] = t1;
+      }
+      __syncthreads();
+      for (int lx = part; lx < nr * L; lx += 4) {
+        const int x = (r0 + lx / L) * L + lx % L;
+#pragma unroll
+        for (int term = 0; term < 5; ++term) {
+          const double2 D = term == 0 ? make_double2(1.0, 0.0) : s_ph[lk[2 * x + ((term - 1) >> 1)]];
+          int w, y;
+          double2 o4[4];
+          coef_block_c(h_coef_d(cp, L, x, term, D, w, y), o4);
+          const int lw = local(w, r0), ly = local(y, r0);
+          const double2 ui0 = s_U[pi * 2 * ns + 2 * lw], ui1 = s_U[pi * 2 * ns + 2 * lw + 1];
+          const double2 uj0 = s_U[pj * 2 * ns + 2 * ly], uj1 = s_U[pj * 2 * ns + 2 * ly + 1];
+          acc = cadd(acc, cmul(ui0, cadd(cmul(o4[0], uj0), cmul(o4[1], uj1))));
+          acc = cadd(acc, cmul(ui1, cadd(cmul(o4[2], uj0), cmul(o4[3], uj1))));
+        }
+      }
+    }
+    if (cp.ke != 0.0) {
+      // P = 8z + pj (u_j), Q = 8z + pi (u_i)
+      const T *gp = G + static_cast<size_t>(8 * z + pj) * n, *gq = G + static_cast<size_t>(8 * z + pi) * n;
+      double2 ee = make_double2(0.0, 0.0), xa = ee, xb = ee;
+      for (int ell = part; ell < 2 * V; ell += 4) {
+        int u[4];
+        ggf_link_u(ell, L, u);
+        const double2 *Rl = slopes(ell);
+        double vp[4], vq[4], api[4], apj[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          vp[k] = static_cast<double>(gp[u[k]]);
+          vq[k] = static_cast<double>(gq[u[k]]);
+          api[k] = ag[static_cast<size_t>(u[k]) * 8 + pi];
+          apj[k] = ag[static_cast<size_t>(u[k]) * 8 + pj];
+        }
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = i + 1; j < 4; ++j) {
+            const double2 r = Rl[k++];
+            ee = cadd(ee, cscale(r, vp[j] * vq[i]));
+            xa = cadd(xa, cscale(r, vp[j] * api[i]));   // Xa[pj][pi]
+            xb = cadd(xb, cscale(r, apj[j] * vq[i]));   // Xb[pi][pj]
+          }
+      }
+      s_X[part][0][pj * 8 + pi] = cscale(xa, cp.ke);
+      s_X[part][1][pi * 8 + pj] = cscale(xb, cp.ke);
+      acc = cadd(acc, cscale(ee, cp.ke));
+      __syncthreads();
+      const double2 *ayq = ay + static_cast<size_t>(8 * z + pi) * 8, *ayp = ay + static_cast<size_t>(8 * z + pj) * 8;
+      double2 corr = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        corr = cadd(corr, cmul(ayq[q], s_X[part][0][pj * 8 + q]));
+        corr = cadd(corr, cmul(ayp[q], s_X[part][1][pi * 8 + q]));
+      }
+      if (part == 0)
+        for (int q = 0; q < 8; ++q) {
+          double2 zq = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int q2 = 0; q2 < 8; ++q2) zq = cadd(zq, cmul(s_Z[q * 8 + q2], ayq[q2]));
+          corr = cadd(corr, cmul(ayp[q], zq));
+        }
+      acc = cadd(acc, corr);
+    }
+    sd = cadd(sd, acc);
+  }
+  __syncthreads();
+  s_red[part][ij] = sd;
+  __syncthreads();
+  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
+  if (tid < 64) {
+    // thread (pi, pj) summed (U C U^T)[pi][pj] + electric part: S_d^ab[pj][pi]
+    const double2 v = cadd(cadd(s_red[0][tid], s_red[1][tid]), cadd(s_red[2][tid], s_red[3][tid]));
+    const int idx = (2 + pj) * 10 + 2 + pi;
+    const double add = cmul(s_wt[0], v).x;
+    o[idx] = pr == 0 ? add : o[idx] + add;
+  }
+}
+
+// The rest of one pair's contribution after k_sens_pair_rows: a-block, b-block and S_N with M_ab^-1 read
+// through the correction, and the S_N part of the d-block, om/S (h_ab - E) S_N^ab (added).  A kernel of
+// its own so that the per-site registers do not bound the occupancy of the stripe contraction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_sites(LaunchCtx lc, EnergyCp cp, int pr, const double2 *AY,
+                                                    const double *A, const double *Ab, int nmax, const double *erows,
+                                                    double *out) {
+  __shared__ double2 s_Sa[4], s_Sb[16], s_SN[64], s_wt[2];
+  const int c = blockIdx.x;
+  const ChainDev ch = lc.chains[c];
+  const TensorDev &Tn = lc.tensors[ch.tensor];
+  const int K = ch.K, tid = threadIdx.x;
+  if (pr >= K * K) return;
+  const T *G = static_cast<const T *>(lc.G) + ch.g_off;
+  const PairInvRank<T> mi{G, ch.n, Tn.b, AY + static_cast<size_t>(c) * nmax * 8, A + static_cast<size_t>(c) * nmax * 8,
+                          Ab + static_cast<size_t>(c) * (nmax / 4) * 8};
+  if (tid == 0) pair_weights(Tn, erows + static_cast<size_t>(c) * GGF_ENERGY_STRIDE_DEV, K, pr, s_wt);
+  if (tid < 4) s_Sa[tid] = make_double2(0.0, 0.0);
+  if (tid < 16) s_Sb[tid] = make_double2(0.0, 0.0);
+  if (tid < 64) s_SN[tid] = make_double2(0.0, 0.0);
+  __syncthreads();
+  pair_sites(cp, lc.links + ch.link_off, ch.L, ch.group, mi, s_Sa, s_Sb, s_SN);
+  __syncthreads();
+  double *o = out + static_cast<size_t>(c) * GGF_SENS_STRIDE_DEV;
+  if (tid < 64) {
+    const int pi = tid >> 3, pj = tid & 7;
+    o[(2 + pj) * 10 + 2 + pi] += cmul(s_wt[1], s_SN[pj * 8 + pi]).x;
+  }
+  pair_write_rest(o, pr == 0, s_wt[0], s_Sa, s_Sb, s_SN);
 }
 }  // namespace
 
@@ -1935,18 +2279,52 @@ void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int m
   else hipLaunchKernelGGL(k_sens<float>, grid, block, lds_u, lc.stream, lc, cp, out, max_sites);
 }
 
-void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, double2 *gab, int nmax, const double *erows,
+size_t ggf_sens_pairs_scratch(int n_chains, int nmax) {
+  const size_t per = nmax <= 512 ? static_cast<size_t>(nmax) * nmax * sizeof(double2)
+                                 : static_cast<size_t>(nmax) * 8 * (sizeof(double2) + sizeof(double)) +
+                                       static_cast<size_t>(nmax / 4) * 8 * sizeof(double);
+  return static_cast<size_t>(n_chains) * per;
+}
+
+void ggf_launch_sens_pairs(const LaunchCtx &lc, const EnergyCp &cp, void *scratch, int nmax, const double *erows,
                            double *out, int kmax) {
   const size_t lds = kmax > 1 ? 4 * (kPairLd * kPairLd + 64) * sizeof(double2) : 0;
+  const dim3 grid(lc.n_chains);
+  const bool f64 = lc.precision == 64;
+  if (nmax > 512) {
+    // per pair: the correction tables, the row-chunked contraction (U_z of kPairSites sites, 56 KB), the
+    // per-site part
+    double2 *AY = static_cast<double2 *>(scratch);
+    double *A = reinterpret_cast<double *>(AY + static_cast<size_t>(lc.n_chains) * nmax * 8);
+    double *Ab = A + static_cast<size_t>(lc.n_chains) * nmax * 8;
+    const size_t lds_u = static_cast<size_t>(16) * kPairSites * sizeof(double2);
+    for (int pr = 0; pr < kmax * kmax; ++pr) {
+      if (f64) {
+        hipLaunchKernelGGL(k_pair_tables<double>, grid, dim3(256), lds, lc.stream, lc, pr, AY, A, Ab, nmax);
+        hipLaunchKernelGGL(k_sens_pair_rows<double>, grid, dim3(256), lds_u, lc.stream, lc, cp, pr, AY, A, Ab, nmax,
+                           erows, out);
+        hipLaunchKernelGGL(k_pair_sites<double>, grid, dim3(256), 0, lc.stream, lc, cp, pr, AY, A, Ab, nmax, erows,
+                           out);
+      } else {
+        hipLaunchKernelGGL(k_pair_tables<float>, grid, dim3(256), lds, lc.stream, lc, pr, AY, A, Ab, nmax);
+        hipLaunchKernelGGL(k_sens_pair_rows<float>, grid, dim3(256), lds_u, lc.stream, lc, cp, pr, AY, A, Ab, nmax,
+                           erows, out);
+        hipLaunchKernelGGL(k_pair_sites<float>, grid, dim3(256), 0, lc.stream, lc, cp, pr, AY, A, Ab, nmax, erows,
+                           out);
+      }
+    }
+    return;
+  }
+  double2 *gab = static_cast<double2 *>(scratch);
   // k_sens_pair: T_z (8 n), CU (2 n), coefficients (5 V) complex; column sites (5 V), Majoranas (n) int16
   const size_t lds_s = (static_cast<size_t>(10) * nmax + 5 * (nmax / 8)) * sizeof(double2) +
                        (static_cast<size_t>(5) * (nmax / 8) + nmax) * sizeof(int16_t);
   for (int pr = 0; pr < kmax * kmax; ++pr) {
-    if (lc.precision == 64)
-      hipLaunchKernelGGL(k_form_pair<double>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
+    if (f64)
+      hipLaunchKernelGGL(k_form_pair<double>, grid, dim3(256), lds, lc.stream, lc, pr, gab, nmax);
     else
-      hipLaunchKernelGGL(k_form_pair<float>, dim3(lc.n_chains), dim3(256), lds, lc.stream, lc, pr, gab, nmax);
-    hipLaunchKernelGGL(k_sens_pair, dim3(lc.n_chains), dim3(512), lds_s, lc.stream, lc, cp, pr, gab, nmax, erows, out);
+      hipLaunchKernelGGL(k_form_pair<float>, grid, dim3(256), lds, lc.stream, lc, pr, gab, nmax);
+    hipLaunchKernelGGL(k_sens_pair, grid, dim3(512), lds_s, lc.stream, lc, cp, pr, gab, nmax, erows, out);
   }
 }
 

@@ -73,6 +73,7 @@ def test_sensitivity_rows_chunked(L):
     ctx.sweep(1)
     rows = ctx.measure_sensitivity(CP)
     assert np.all(np.isfinite(rows))
+    assert np.array_equal(ctx.measure_sensitivity(CP), rows)     # fixed summation order: reproducible
     _check_sens(rows[0], an, ctx.get_state(0)[0], 1e-10)
     ctx.close()
 
@@ -174,6 +175,35 @@ def test_sensitivity_rows_pairs(L, K, group, precision):
     tol = 1e-10 if precision == 64 else 2e-5
     for c in range(3):
         _check_sens(rows[c], an, ctx.get_state(c)[0], tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("L,K,group,precision", [(10, 2, 2, 64), (12, 2, 3, 64), (10, 3, 3, 64), (10, 2, 2, 32)])
+def test_sensitivity_rows_pairs_large(L, K, group, precision):
+    """K > 1 with n > 512: M_ab^-1 = G + (G_S Y_ab) G_S^T applied as a rank <= 8 correction of G,
+    the electric part through its expansion, the d-block in chunks of lattice rows."""
+    say(f"sensitivities K={K} L={L} Z{group} float{precision}, correction tables")
+    spec = spec_for(L, K, group)
+    an = ansatz_for(spec, L)
+    ctx = gpu_context([spec], [L] * 2, init=1, precision=precision, refresh_every=16 if precision == 32 else 0)
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    assert np.all(np.isfinite(rows))
+    assert np.array_equal(ctx.measure_sensitivity(CP), rows)     # fixed summation order: reproducible
+    _check_sens(rows[1], an, ctx.get_state(1)[0], 1e-10 if precision == 64 else 2e-5)
+    ctx.close()
+
+
+def test_sensitivity_rows_pairs_large_mixed():
+    """A K = 1 chain at L = 10 beside a K = 2 chain at L = 8 (n = 512 below the context's largest
+    n = 800): both through the correction tables, each to its oracle."""
+    say("sensitivities mixed K=1 L=10 / K=2 L=8 Z2, correction tables")
+    specs = [spec_for(10, 1, 2), spec_for(8, 2, 2)]
+    ctx = gpu_context(specs, [10, 8], init=1, tensor_ids=[0, 1])
+    ctx.sweep(1)
+    rows = ctx.measure_sensitivity(CP)
+    for c, (t, L) in enumerate([(0, 10), (1, 8)]):
+        _check_sens(rows[c], ansatz_for(specs[t], L), ctx.get_state(c)[0], 1e-10)
     ctx.close()
 
 
