@@ -194,6 +194,27 @@ def test_sensitivity_rows_pairs_large(L, K, group, precision):
     ctx.close()
 
 
+def test_sensitivity_rows_pairs_full_size_reduce_to_k1():
+    """32x32 (n = 8192, six row chunks of the correction-table kernel): a K = 2 ansatz whose second
+    amplitude is zero is the K = 1 ansatz of its reference bond.  Its rows, formed pair by pair through the
+    correction tables in complex arithmetic, equal those of the real K = 1 kernel, a separate code path,
+    on the same hot-start configuration, at a size the oracle does not reach."""
+    L = 32
+    say(f"sensitivities K=2 with lambda_1 = 0 against K=1, L={L} Z2 float64")
+    s2 = dataclasses.replace(spec_for(L, 2, 2), c=np.array([1.0, 0.0], complex))
+    s1 = dataclasses.replace(s2, K=1, patch_link=np.array([-1], np.int32), gamma_bond_k=np.zeros((1, 4, 4)),
+                             c=np.ones(1, complex))
+    ctx2 = gpu_context([s2], [L], init=1)
+    ctx1 = gpu_context([s1], [L], init=1)
+    assert np.array_equal(ctx2.get_state(0)[0], ctx1.get_state(0)[0])
+    r2 = ctx2.measure_sensitivity(CP)
+    r1 = ctx1.measure_sensitivity(CP)
+    assert np.all(np.isfinite(r2))
+    assert np.abs(r2 - r1).max() <= 1e-9 * max(1.0, np.abs(r1).max()), np.abs(r2 - r1).max()
+    ctx2.close()
+    ctx1.close()
+
+
 def test_sensitivity_rows_pairs_large_mixed():
     """A K = 1 chain at L = 10 beside a K = 2 chain at L = 8 (n = 512 below the context's largest
     n = 800): both through the correction tables, each to its oracle."""
