@@ -110,15 +110,16 @@ def parse():
                          "CSVs, write profiles/k_electric_traffic.json and exit (no GPU needed)")
     args = ap.parse_args()
     presets = {
-        # float64 refresh every 16384 changed links (about 16 block sweeps): the float32 drift of every
-        # observable after 10 sweeps without one is below 2e-7 (bench float32_drift)
-        "north": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=65536, delay=16),
+        # float64 refactorisation every 131072 changed links (about 130 block sweeps): after 135 block
+        # sweeps without one the float32 drift of every observable is at most 4.3e-7 and of log N 5.6e-7
+        # (bench float32_drift with --steps 130 --refresh 0), inside the 1e-6 target
+        "north": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=131072, delay=16),
         "c2": dict(steps=20, warmup=3, chains=4096, L=8, K=1, group=2, precision=64, refresh=16384, delay=16,
                    graph=1),
         "c3": dict(steps=3, warmup=1, chains=2048, L=16, K=3, group=2, precision=32, refresh=64, delay=16),
         "c4": dict(steps=2, warmup=1, chains=8192, L=0, K=0, group=0, precision=32, refresh=64, delay=16,
                    graph=1, balance=1),
-        "c5": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=65536, delay=16),
+        "c5": dict(steps=20, warmup=5, chains=256, L=32, K=2, group=2, precision=32, refresh=131072, delay=16),
     }
     for k, v in presets[args.workload].items():
         if getattr(args, k) is None:
