@@ -81,8 +81,9 @@ void ggf_launch_bond_rows(const LaunchCtx &lc, const EnergyCp &cp, double *out);
 // Sensitivities of Re E_loc and log N to the on-site covariance (K = 1 chains, L <= 32);
 // max_group: the largest link group among the chains.
 void ggf_launch_sens(const LaunchCtx &lc, const EnergyCp &cp, double *out, int max_sites, int max_group);
-// K > 1 (L <= 8): per pair, M_ab^-1 formed into gab (n_chains x nmax^2 complex) and its weighted
-// contribution accumulated into out, using the chains' energy rows erows.
+// K > 1: per pair, each chain's weighted contribution accumulated into out, using the chains' energy
+// rows erows; M_ab^-1 is formed explicitly in scratch when nmax <= 512, else applied as G plus the
+// rank <= 8 correction whose factors are kept in scratch.
 // Scratch bytes of ggf_launch_sens_pairs: the pair inverses M_ab^-1 (complex nmax x nmax per chain) when
 // nmax <= 512, else the correction tables (A, AY, Ab: 26 nmax doubles per chain).
 size_t ggf_sens_pairs_scratch(int n_chains, int nmax);
