@@ -20,4 +20,7 @@ Modules (each function cites the passage of the paper it follows):
   in a definitional mode (fresh determinant/Pfaffians per proposal) and an
   independent Woodbury mode.
 * ``stats``    -- integrated autocorrelation time and effective sample size.
+* ``nonabelian`` -- a non-abelian link group (Q8 in its 2-dimensional irrep) on
+  2-mode virtual legs: weight and link ratio in covariance form, pinned by the
+  Fock-space contraction on a 2 x 1 torus (Sec. 2.1, 3.2, 5; no kernel yet).
 """
