@@ -116,6 +116,29 @@ class NonAbelianAnsatz:
             raise ValueError("det M <= 0: the configuration has zero weight")
         return 0.5 * ld
 
+    def element_index(self, u: np.ndarray) -> int:
+        return min(range(len(self.elements)), key=lambda k: np.abs(self.elements[k] - u).max())
+
+    def plaquette_trace(self, links: np.ndarray, i: int) -> complex:
+        """(1/d) tr D(g_{x,x+e1} g_{x+e1,x+e1+e2} g_{x+e2,x+e1+e2}^-1 g_{x,x+e2}^-1) at site x = i
+        (the plaquette operator's expectation in a configuration, Sec. 2.3)."""
+        x1, x2 = i % self.lx, i // self.lx
+        a = self.site(x1 + 1, x2)
+        b = self.site(x1, x2 + 1)
+        e = self.elements
+        u = (e[int(links[2 * i])] @ e[int(links[2 * a + 1])] @ e[int(links[2 * b])].conj().T
+             @ e[int(links[2 * i + 1])].conj().T)
+        return complex(np.trace(u)) / self.d
+
+    def gauge_transform(self, links: np.ndarray, h: np.ndarray) -> np.ndarray:
+        """g_{x -> y} -> h_x g h_y^-1 for site elements h (indices), the link field's gauge action."""
+        out = links.copy()
+        for ell in range(self.n_links):
+            i, _, j, _ = self.link_sites(ell)
+            u = self.elements[int(h[i])] @ self.elements[int(links[ell])] @ self.elements[int(h[j])].conj().T
+            out[ell] = self.element_index(u)
+        return out
+
     def link_ratio(self, ginv: np.ndarray, links: np.ndarray, ell: int, k_new: int) -> float:
         """W(G with g_ell -> element k_new) / W(G) from M^-1 on the link's 4d Majoranas."""
         u = self.link_majoranas(ell)

@@ -7,7 +7,9 @@
   <psi(G)|psi(G)> of the PEPS on a 2 x 1 torus with 2-mode legs (20 fermionic modes), for random
   link configurations of Q8 elements (Sec. 3.2, 5; the link space of Sec. 2.1);
 * a link change's weight ratio from M^-1 on the link's Majoranas (determinant lemma) equals the ratio
-  of fresh determinants.
+  of fresh determinants;
+* the plaquette trace is invariant under gauge transformations of the link field (which fixes the
+  orientation of its four links) and is not a class function of any single link.
 """
 import numpy as np
 
@@ -100,3 +102,31 @@ def test_link_ratio_by_determinant_lemma():
         new[ell] = k_new
         ref = np.exp(an.log_weight(new) - lw)
         assert abs(an.link_ratio(ginv, links, ell, k_new) - ref) <= 1e-10 * ref
+
+
+def test_plaquette_trace_is_gauge_invariant():
+    rng = np.random.default_rng(13)
+    gl = _random_pure_even(2 * (2 + 8), rng)
+    gb = ga.covariance_of_state(_bond_state(2), 4).real
+    an = na.NonAbelianAnsatz(3, 3, gl, gb, na.quaternion_group(), 2)
+    for _ in range(5):
+        links = rng.integers(0, 8, size=an.n_links)
+        h = rng.integers(0, 8, size=an.V)
+        moved = an.gauge_transform(links, h)
+        for i in range(an.V):
+            assert abs(an.plaquette_trace(moved, i) - an.plaquette_trace(links, i)) < 1e-14
+    # a wrong orientation (one link not inverted) is not invariant for this non-abelian group: on a
+    # configuration whose wrong loop has a nonzero trace, some gauge transformation flips its sign
+    e = an.elements
+
+    def wrong(lk, i):
+        x1, x2 = i % an.lx, i // an.lx
+        a, b = an.site(x1 + 1, x2), an.site(x1, x2 + 1)
+        u = e[int(lk[2 * i])] @ e[int(lk[2 * a + 1])] @ e[int(lk[2 * b])] @ e[int(lk[2 * i + 1])].conj().T
+        return np.trace(u) / 2
+    links = rng.integers(0, 8, size=an.n_links)
+    while abs(wrong(links, 0)) < 0.5:
+        links = rng.integers(0, 8, size=an.n_links)
+    diffs = [abs(wrong(an.gauge_transform(links, rng.integers(0, 8, size=an.V)), 0) - wrong(links, 0))
+             for _ in range(40)]
+    assert max(diffs) > 0.5
